@@ -1,0 +1,282 @@
+"""Python face of the CPU oracle (test infrastructure only).
+
+Only tests, the smoke check and the benchmark's CPU-baseline leg may import
+this module.  It loads oracle/liboracle_rt.so (built by
+oracle/build_oracle.py) through ctypes and adds the per-image reductions of
+Sec. 6 written out in numpy.  Nothing here imports the HIP package except
+its seeded input generator (paper_2605_05635_amd.workloads), which holds no
+ray-tracing arithmetic.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboracle_rt.so")
+
+METRIC_ID = {"kerr": 0, "einasto": 1, "cnfw": 2}
+STATUS = {"running": 0, "captured": 1, "escaped": 2, "step_limit": 3, "nonfinite": 4}
+
+
+class OrcParams(C.Structure):
+    _fields_ = [
+        ("metric", C.c_int32), ("max_attempts", C.c_int32),
+        ("spin", C.c_double), ("halo0", C.c_double), ("halo1", C.c_double),
+        ("incl", C.c_double), ("r_obs", C.c_double),
+        ("nx", C.c_int32), ("ny", C.c_int32),
+        ("x_min", C.c_double), ("x_max", C.c_double), ("y_min", C.c_double), ("y_max", C.c_double),
+        ("rtol", C.c_double), ("atol", C.c_double),
+        ("r_stop_fac", C.c_double), ("r_esc_fac", C.c_double),
+        ("r_in", C.c_double), ("r_out", C.c_double), ("emis_pow", C.c_double),
+        ("sigma_in", C.c_double), ("sigma_out", C.c_double), ("h0", C.c_double),
+    ]
+
+
+class OrcRay(C.Structure):
+    _fields_ = [
+        ("status", C.c_int32), ("ncross", C.c_int32), ("attempts", C.c_int32),
+        ("accepted", C.c_int32), ("filtered", C.c_int32), ("pad", C.c_int32),
+        ("E", C.c_double), ("L", C.c_double),
+        ("r_em", C.c_double * 3), ("phi_em", C.c_double * 3), ("t_em", C.c_double * 3),
+        ("g_em", C.c_double * 3), ("i_n", C.c_double * 3),
+        ("intensity", C.c_double), ("lambda_end", C.c_double),
+        ("max_constraint", C.c_double), ("carter_drift", C.c_double),
+        ("y_end", C.c_double * 6),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded oracle library (built on first use if missing)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            from oracle.build_oracle import build  # noqa: WPS433 (local import by design)
+            build()
+        L = C.CDLL(LIB_PATH)
+        P = C.POINTER(OrcParams)
+        D = C.POINTER(C.c_double)
+        I32 = C.POINTER(C.c_int32)
+        I64 = C.POINTER(C.c_int64)
+        L.orc_radial.argtypes = [P, C.c_double, D]
+        L.orc_metric.argtypes = [P, C.c_double, C.c_double, D]
+        L.orc_two_hamiltonian.argtypes = [P, C.c_double, C.c_double, D]
+        L.orc_two_hamiltonian.restype = C.c_double
+        L.orc_rhs.argtypes = [P, C.c_double, C.c_double, D, D]
+        L.orc_horizon.argtypes = [P, D]
+        L.orc_extremal_spin.argtypes = [P, D, D]
+        L.orc_observer.argtypes = [P, D]
+        L.orc_initial_momentum.argtypes = [P, C.c_double, C.c_double, D, D]
+        L.orc_redshift.argtypes = [P, C.c_double, C.c_double, C.c_double]
+        L.orc_redshift.restype = C.c_double
+        L.orc_trace_ray.argtypes = [P, C.c_double, C.c_double, C.POINTER(OrcRay), D, C.c_int,
+                                    C.POINTER(C.c_int)]
+        L.orc_trace_pixels.argtypes = [P, I64, C.c_int64, I32, I32, I32, D, D, D, D, D, D]
+        L.orc_image_setup.argtypes = [P, D]
+        assert L.orc_sizeof_params() == C.sizeof(OrcParams)
+        assert L.orc_sizeof_ray() == C.sizeof(OrcRay)
+        _lib = L
+    return _lib
+
+
+def params(img: dict) -> OrcParams:
+    """Oracle parameter struct of a workload dict (paper_2605_05635_amd.workloads)."""
+    return OrcParams(
+        metric=METRIC_ID[img["metric"]], max_attempts=int(img["max_attempts"]),
+        spin=img["spin"], halo0=img["halo"][0], halo1=img["halo"][1],
+        incl=img["incl"], r_obs=img["r_obs"], nx=int(img["nx"]), ny=int(img["ny"]),
+        x_min=img["x_min"], x_max=img["x_max"], y_min=img["y_min"], y_max=img["y_max"],
+        rtol=img["rtol"], atol=img["atol"], r_stop_fac=img["r_stop_fac"],
+        r_esc_fac=img["r_esc_fac"], r_in=img["r_in"], r_out=img["r_out"],
+        emis_pow=img["emis_pow"], sigma_in=img["sigma_in"], sigma_out=img["sigma_out"],
+        h0=img["h0"])
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def radial(img: dict, R: float) -> dict:
+    out = np.zeros(6)
+    lib().orc_radial(C.byref(params(img)), R, _dp(out))
+    return dict(zip(("H", "dH", "mu", "dmu", "F", "dF"), out))
+
+
+METRIC_KEYS = ("F", "dF", "Delta", "dDelta", "Sigma",
+               "g_TT", "g_Tph", "g_RR", "g_thth", "g_phph",
+               "u_TT", "u_Tph", "u_RR", "u_thth", "u_phph",
+               "dR_TT", "dR_Tph", "dR_RR", "dR_thth", "dR_phph",
+               "dt_TT", "dt_Tph", "dt_RR", "dt_thth", "dt_phph")
+
+
+def metric(img: dict, R: float, th: float) -> dict:
+    out = np.zeros(25)
+    lib().orc_metric(C.byref(params(img)), R, th, _dp(out))
+    return dict(zip(METRIC_KEYS, out))
+
+
+def two_hamiltonian(img: dict, E: float, L: float, y) -> float:
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    return lib().orc_two_hamiltonian(C.byref(params(img)), E, L, _dp(y))
+
+
+def rhs(img: dict, E: float, L: float, y) -> np.ndarray:
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    dy = np.zeros(6)
+    lib().orc_rhs(C.byref(params(img)), E, L, _dp(y), _dp(dy))
+    return dy
+
+
+def horizon(img: dict) -> float | None:
+    r = C.c_double()
+    rc = lib().orc_horizon(C.byref(params(img)), C.byref(r))
+    return r.value if rc == 0 else None
+
+
+def extremal_spin(img: dict):
+    """(chi_e, R_e), or None when no horizon exists at any spin."""
+    chi, r = C.c_double(), C.c_double()
+    rc = lib().orc_extremal_spin(C.byref(params(img)), C.byref(chi), C.byref(r))
+    return (chi.value, r.value) if rc == 0 else None
+
+
+def observer(img: dict) -> dict:
+    out = np.zeros(23)
+    lib().orc_observer(C.byref(params(img)), _dp(out))
+    return dict(omega=out[0], N=out[1], u=out[2:6], eR=out[6:10], eth=out[10:14],
+                eph=out[14:18], g=out[18:23])
+
+
+def initial_momentum(img: dict, X: float, Y: float):
+    up, dn = np.zeros(4), np.zeros(4)
+    lib().orc_initial_momentum(C.byref(params(img)), X, Y, _dp(up), _dp(dn))
+    return up, dn
+
+
+def redshift(img: dict, R: float, E: float, L: float) -> float:
+    return lib().orc_redshift(C.byref(params(img)), R, E, L)
+
+
+def image_setup(img: dict) -> dict | None:
+    out = np.zeros(4)
+    rc = lib().orc_image_setup(C.byref(params(img)), _dp(out))
+    if rc != 0:
+        return None
+    return dict(r_plus=out[0], r_stop=out[1], r_esc=out[2], r_in=out[3])
+
+
+def trace_ray(img: dict, X: float, Y: float, log_cap: int = 0):
+    """Trace one screen point.  Returns (OrcRay, step_log) where step_log is an
+    (n, 8) array of accepted steps (lambda, h, y[6]) when log_cap > 0."""
+    ray = OrcRay()
+    n = C.c_int(0)
+    log = np.zeros((max(log_cap, 1), 8))
+    rc = lib().orc_trace_ray(C.byref(params(img)), X, Y, C.byref(ray),
+                             _dp(log) if log_cap > 0 else None, log_cap, C.byref(n))
+    if rc != 0:
+        raise ValueError("no horizon for these parameters")
+    return ray, log[: n.value]
+
+
+def pixel_xy(img: dict, idx: np.ndarray):
+    idx = np.asarray(idx, dtype=np.int64)
+    ix, iy = idx % img["nx"], idx // img["nx"]
+    X = img["x_min"] + (ix + 0.5) * ((img["x_max"] - img["x_min"]) / img["nx"])
+    Y = img["y_min"] + (iy + 0.5) * ((img["y_max"] - img["y_min"]) / img["ny"])
+    return X, Y
+
+
+def trace_pixels(img: dict, idx=None, threads: int | None = None, chunk: int = 64) -> dict:
+    """Trace the listed pixels (default: the whole screen) on `threads` host
+    threads (ctypes releases the GIL during each call).  Returns numpy arrays
+    indexed like `idx`: ncross, status, attempts (int32); r_em, phi_em, t_em,
+    g_em, i_n with shape (3, n); intensity (n)."""
+    if idx is None:
+        idx = np.arange(img["nx"] * img["ny"], dtype=np.int64)
+    idx = np.ascontiguousarray(idx, dtype=np.int64)
+    n = idx.size
+    out = dict(ncross=np.zeros(n, np.int32), status=np.zeros(n, np.int32),
+               attempts=np.zeros(n, np.int32),
+               r_em=np.zeros((3, n)), phi_em=np.zeros((3, n)), t_em=np.zeros((3, n)),
+               g_em=np.zeros((3, n)), i_n=np.zeros((3, n)), intensity=np.zeros(n))
+    p = params(img)
+    L = lib()
+    threads = threads or os.cpu_count() or 1
+
+    def work(lo: int) -> int:
+        hi = min(lo + chunk, n)
+        m = hi - lo
+        loc = {k: (np.zeros(m, np.int32) if v.ndim == 1 and v.dtype == np.int32
+                   else np.zeros((3, m)) if v.ndim == 2 else np.zeros(m))
+               for k, v in out.items()}
+        sub = np.ascontiguousarray(idx[lo:hi])
+        i32 = lambda a: a.ctypes.data_as(C.POINTER(C.c_int32))  # noqa: E731
+        rc = L.orc_trace_pixels(C.byref(p), sub.ctypes.data_as(C.POINTER(C.c_int64)), m,
+                                i32(loc["ncross"]), i32(loc["status"]), i32(loc["attempts"]),
+                                _dp(loc["r_em"]), _dp(loc["phi_em"]), _dp(loc["t_em"]),
+                                _dp(loc["g_em"]), _dp(loc["i_n"]), _dp(loc["intensity"]))
+        if rc != 0:
+            raise ValueError("no horizon for these parameters")
+        for k, v in loc.items():
+            if v.ndim == 2:
+                out[k][:, lo:hi] = v
+            else:
+                out[k][lo:hi] = v
+        return m
+
+    starts = list(range(0, n, chunk))
+    if threads == 1 or len(starts) == 1:
+        for s in starts:
+            work(s)
+    else:
+        with ThreadPoolExecutor(max_workers=threads) as ex:
+            list(ex.map(work, starts))
+    return out
+
+
+def trace_image(img: dict, threads: int | None = None) -> dict:
+    """Whole screen; arrays reshaped to [ny][nx] (maps to [3][ny][nx])."""
+    o = trace_pixels(img, None, threads)
+    ny, nx = img["ny"], img["nx"]
+    for k, v in o.items():
+        o[k] = v.reshape((3, ny, nx)) if v.ndim == 2 else v.reshape((ny, nx))
+    return o
+
+
+# ------------------------------------------------ Sec. 6.2 and 6.4, in numpy
+def screen_axes(img: dict):
+    dx = (img["x_max"] - img["x_min"]) / img["nx"]
+    dy = (img["y_max"] - img["y_min"]) / img["ny"]
+    X = img["x_min"] + (np.arange(img["nx"]) + 0.5) * dx
+    Y = img["y_min"] + (np.arange(img["ny"]) + 0.5) * dy
+    return X, Y, dx, dy
+
+
+def flux_centroid(img: dict, intensity: np.ndarray):
+    """Flux F = int I dX dY and centroid (X_c, Y_c) (Sec. 6.2), midpoint rule."""
+    X, Y, dx, dy = screen_axes(img)
+    I = np.asarray(intensity, dtype=np.float64).reshape(img["ny"], img["nx"])
+    F = I.sum() * dx * dy
+    Xc = (I * X[None, :]).sum() * dx * dy / F
+    Yc = (I * Y[:, None]).sum() * dx * dy / F
+    return F, Xc, Yc
+
+
+def visibility_amplitude(img: dict, intensity: np.ndarray, uv: np.ndarray) -> np.ndarray:
+    """|V(u,v)| / |V(0,0)| with V = int I exp(-2 pi i (uX + vY)) dX dY (Sec. 6.4),
+    as a direct sum over pixel centres."""
+    X, Y, dx, dy = screen_axes(img)
+    I = np.asarray(intensity, dtype=np.float64).reshape(img["ny"], img["nx"])
+    out = np.zeros(len(uv))
+    V0 = abs(I.sum() * dx * dy)
+    for k, (u, v) in enumerate(np.asarray(uv, dtype=np.float64)):
+        ex = np.exp(-2j * math.pi * u * X)[None, :] * np.exp(-2j * math.pi * v * Y)[:, None]
+        out[k] = abs((I * ex).sum() * dx * dy) / V0
+    return out

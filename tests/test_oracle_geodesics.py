@@ -1,0 +1,351 @@
+"""Truth pins of the oracle's traced rays (paper Sec. 3-5).
+
+Checks that the oracle integrates the right equations to the accuracy its
+tolerance allows: Hamilton's equations against numerical derivatives of the
+Hamiltonian, the separated (Carter-like) form, conservation laws, the
+finite-distance Schwarzschild shadow (Synge), the finite-distance Kerr
+critical curve (Bardeen's spherical photon orbits), the Schwarzschild transfer
+map by orbit quadrature, scipy's Dormand-Prince stepping, mirror symmetries and
+closed-form Keplerian redshifts.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy.integrate import RK45, quad
+from scipy.optimize import brentq
+
+from paper_2605_05635_amd import workloads as W
+
+HALF_PI = math.pi / 2
+
+METRICS = [W.image(metric="kerr", spin=0.5),
+           W.image(metric="einasto", spin=0.9, halo=(0.15, 0.0), incl=math.radians(60)),
+           W.image(metric="cnfw", spin=0.94, halo=(0.02, 10.0), incl=math.radians(163))]
+
+
+# --------------------------------------------------------- equations of motion
+def test_hamiltonian_equals_separated_form(orc):
+    """Sec. 3.1: Sigma * 2H = Delta p_R^2 - P^2/Delta + p_theta^2 + (l/s - chi E s)^2."""
+    rng = np.random.default_rng(3)
+    for img in METRICS:
+        chi = img["spin"]
+        for _ in range(30):
+            R, th = rng.uniform(2.0, 80), rng.uniform(0.1, 3.0)
+            E, L, pR, pth = rng.uniform(0.5, 1.5), rng.uniform(-6, 6), rng.normal(), rng.normal(0, 4)
+            m = orc.metric(img, R, th)
+            D, S, s = m["Delta"], m["Sigma"], math.sin(th)
+            P = (R * R + chi * chi) * E - chi * L
+            sep = D * pR ** 2 - P * P / D + pth ** 2 + (L / s - chi * E * s) ** 2
+            h2 = orc.two_hamiltonian(img, E, L, [0, R, th, 0, pR, pth])
+            scale = D * pR ** 2 + P * P / D + pth ** 2 + (L / s - chi * E * s) ** 2
+            assert abs(S * h2 - sep) < 1e-13 * scale
+
+
+def test_rhs_is_hamiltons_equations(orc):
+    """eqs. (46)-(47): dq/dlambda = dH/dp and dp/dlambda = -dH/dq, with H from eq. (54),
+    checked by numerical differentiation of the oracle's Hamiltonian."""
+    rng = np.random.default_rng(4)
+
+    def dnum(f, x, h):
+        return (8 * (f(x + h) - f(x - h)) - (f(x + 2 * h) - f(x - 2 * h))) / (12 * h)
+
+    for img in METRICS:
+        for _ in range(10):
+            R, th = rng.uniform(2.5, 40), rng.uniform(0.3, 2.8)
+            E, L, pR, pth = rng.uniform(0.5, 1.5), rng.uniform(-5, 5), rng.normal(), rng.normal(0, 3)
+            y = np.array([0.0, R, th, 0.0, pR, pth])
+            H = lambda **kw: 0.5 * orc.two_hamiltonian(  # noqa: E731
+                img, kw.get("E", E), kw.get("L", L),
+                [0, kw.get("R", R), kw.get("th", th), 0, kw.get("pR", pR), kw.get("pth", pth)])
+            dy = orc.rhs(img, E, L, y)
+            want = [-dnum(lambda v: H(E=v), E, 1e-4),         # dT = dH/dp_T = -dH/dE
+                    dnum(lambda v: H(pR=v), pR, 1e-4),
+                    dnum(lambda v: H(pth=v), pth, 1e-4),
+                    dnum(lambda v: H(L=v), L, 1e-4),
+                    -dnum(lambda v: H(R=v), R, 1e-4),
+                    -dnum(lambda v: H(th=v), th, 1e-4)]
+            for i in range(6):
+                assert dy[i] == pytest.approx(want[i], rel=1e-7, abs=1e-10), i
+
+
+@pytest.mark.parametrize("img", METRICS)
+def test_conservation_along_rays(orc, img):
+    """Sec. 3.1: the null constraint and the Carter-like constant stay fixed along
+    each ray to the integration tolerance (1e-8); E and l are constants by design."""
+    rng = np.random.default_rng(5)
+    for X, Y in rng.uniform(-9, 9, size=(12, 2)):
+        ray, _ = orc.trace_ray(img, X, Y)
+        assert ray.status in (1, 2)
+        assert ray.max_constraint < 1e-6
+        assert ray.carter_drift < 1e-6
+
+
+# ------------------------------------------------------ shadow and critical curve
+def _bisect_edge(orc, img, inside, outside, iters=42):
+    """Capture/escape boundary on the segment inside -> outside (Sec. 4.1)."""
+    a, b = np.array(inside, float), np.array(outside, float)
+    assert orc.trace_ray(img, *a)[0].status == 1
+    assert orc.trace_ray(img, *b)[0].status == 2
+    for _ in range(iters):
+        m = 0.5 * (a + b)
+        if orc.trace_ray(img, *m)[0].status == 1:
+            a = m
+        else:
+            b = m
+    return 0.5 * (a + b)
+
+
+def test_schwarzschild_shadow_synge(orc):
+    """Shadow radius at finite R_o: sin(alpha) = sqrt(27) sqrt(1 - 2/R_o)/R_o with
+    rho = R_o tan(alpha) on the screen (-> sqrt(27) as R_o -> infinity)."""
+    img = W.image(metric="kerr", spin=0.0, incl=1.0, rtol=1e-11, atol=1e-11)
+    Ro = img["r_obs"]
+    alpha = math.asin(math.sqrt(27) * math.sqrt(1 - 2 / Ro) / Ro)
+    want = Ro * math.tan(alpha)
+    for psi in (0.0, 1.1, 2.5):
+        d = np.array([math.cos(psi), math.sin(psi)])
+        edge = _bisect_edge(orc, img, 4.0 * d, 6.0 * d)
+        assert np.hypot(*edge) == pytest.approx(want, abs=2e-8)
+
+
+def _critical_points_on_y0(Ro, th_o, chi, Delta, dDelta, g_obs):
+    """Screen points (X, 0) of the critical curve at finite R_o for a Kerr-like
+    Delta(r): spherical photon orbits of the separated radial potential
+    (P^2 - Delta K = 0 and its r-derivative) give xi = l/E and eta_C = K - (xi-chi)^2;
+    the screen direction follows from inverting the tetrad map of Sec. 3.2."""
+    def xi(r):
+        return chi + r * r / chi - 4 * r * Delta(r) / (chi * dDelta(r))
+
+    def etaC(r):
+        return r * r * (16 * chi * chi * Delta(r) - (4 * Delta(r) - r * dDelta(r)) ** 2) / (
+            chi * chi * dDelta(r) ** 2)
+
+    def pth2(r):
+        return etaC(r) + chi * chi * math.cos(th_o) ** 2 - xi(r) ** 2 / math.tan(th_o) ** 2
+
+    gTT, gTp, gRR, gtt, gpp = g_obs
+    N = math.sqrt(-(gTT - gTp * gTp / gpp))
+    rs = np.linspace(1.05, 6.0, 5000)
+    vals = [pth2(r) for r in rs]
+    roots = [brentq(pth2, rs[i], rs[i + 1], xtol=1e-15, rtol=1e-15)
+             for i in range(len(rs) - 1) if vals[i] * vals[i + 1] < 0 and etaC(rs[i]) > -1]
+    X = []
+    for r in roots:
+        x = xi(r)
+        nph = x * N / (math.sqrt(gpp) + x * gTp / math.sqrt(gpp))
+        nR = -math.sqrt(1 - nph * nph)
+        X.append(Ro * nph / nR)
+    return sorted(X)
+
+
+def kerr_obs_metric(Ro, th, a):
+    S = Ro * Ro + a * a * math.cos(th) ** 2
+    D = Ro * Ro - 2 * Ro + a * a
+    s2 = math.sin(th) ** 2
+    return (-(1 - 2 * Ro / S), -2 * a * Ro * s2 / S, S / D, S,
+            (Ro * Ro + a * a + 2 * a * a * Ro * s2 / S) * s2)
+
+
+def test_kerr_critical_curve_bardeen(orc):
+    """Fig. 5 parameters (chi = 0.5, theta_o = 60 deg): the capture/escape boundary
+    traced by the oracle matches the analytic Kerr critical curve on Y = 0, including
+    the flattened prograde edge at X < 0."""
+    chi, th = 0.5, math.radians(60)
+    img = W.image(metric="kerr", spin=chi, incl=th, rtol=1e-11, atol=1e-11)
+    Ro = img["r_obs"]
+    Xs = _critical_points_on_y0(Ro, th, chi, lambda r: r * r - 2 * r + chi * chi,
+                                lambda r: 2 * r - 2, kerr_obs_metric(Ro, th, chi))
+    assert len(Xs) == 2 and Xs[0] < 0 < Xs[1] and abs(Xs[0]) < abs(Xs[1])
+    left = _bisect_edge(orc, img, (0.0, 0.0), (-8.0, 0.0))
+    right = _bisect_edge(orc, img, (0.0, 0.0), (8.0, 0.0))
+    assert left[0] == pytest.approx(Xs[0], abs=3e-8)
+    assert right[0] == pytest.approx(Xs[1], abs=3e-8)
+
+
+@pytest.mark.parametrize("img0", [W.image(metric="einasto", halo=(0.3, 0.0)),
+                                  W.image(metric="cnfw", halo=(0.02, 10.0))])
+def test_halo_critical_curve_from_separated_potential(orc, img0):
+    """Fig. 5's dark-matter cases: the same spherical-photon-orbit construction with
+    the metric's own Delta(r) matches the oracle's traced shadow edge on Y = 0."""
+    chi, th = 0.5, math.radians(60)
+    img = dict(img0, spin=chi, incl=th, rtol=1e-11, atol=1e-11)
+    m_obs = orc.metric(img, img["r_obs"], th)
+    g_obs = (m_obs["g_TT"], m_obs["g_Tph"], m_obs["g_RR"], m_obs["g_thth"], m_obs["g_phph"])
+    Xs = _critical_points_on_y0(img["r_obs"], th, chi,
+                                lambda r: orc.metric(img, r, HALF_PI)["Delta"],
+                                lambda r: orc.metric(img, r, HALF_PI)["dDelta"], g_obs)
+    assert len(Xs) == 2
+    left = _bisect_edge(orc, img, (0.0, 0.0), (-9.0, 0.0))
+    right = _bisect_edge(orc, img, (0.0, 0.0), (9.0, 0.0))
+    assert left[0] == pytest.approx(Xs[0], abs=3e-8)
+    assert right[0] == pytest.approx(Xs[1], abs=3e-8)
+
+
+# ----------------------------------------------- Schwarzschild transfer map
+def _schwarzschild_crossings(Ro, th_o, X, Y, r_stop, r_esc, n_max=3):
+    """Radii of the first n_max equatorial crossings of the backward ray of screen
+    point (X, Y) in Schwarzschild, from the orbit equation
+    (du/dpsi)^2 = 1/b^2 - u^2 + 2u^3 (u = 1/r, psi the angle in the orbit plane)."""
+    rho = math.hypot(X, Y)
+    b = Ro * (rho / math.hypot(Ro, rho)) / math.sqrt(1 - 2 / Ro)
+    psi_c = math.atan2(math.cos(th_o), -Y * math.sin(th_o) / rho) % math.pi
+    targets = [psi_c + n * math.pi for n in range(n_max)]
+    uo, ustop, uesc = 1 / Ro, 1 / r_stop, 1 / r_esc
+    roots = np.roots([2.0, -1.0, 0.0, 1 / b ** 2])
+    real = sorted(r.real for r in roots if abs(r.imag) < 1e-12)
+    pos = [r for r in real if r > 0]
+    G = lambda u: 1 / b ** 2 - u * u + 2 * u ** 3  # noqa: E731
+    opts = dict(epsabs=0, epsrel=1e-13, limit=200)
+    if len(pos) == 2 and pos[0] > uo:           # periapsis at u_p: escapes
+        u1, up, u3 = real[0], pos[0], pos[1]
+        smooth = lambda w: 2 / math.sqrt(2 * (up - w * w - u1) * (u3 - up + w * w))  # noqa: E731
+
+        def I(ua):  # int_{ua}^{up} du / sqrt(G)
+            return quad(smooth, 0.0, math.sqrt(up - ua), **opts)[0]
+        psi_p = I(uo)
+        total = psi_p + I(uesc)
+        out = []
+        for t in targets:
+            if t >= total:
+                break
+            if t <= psi_p:
+                u = brentq(lambda v: (psi_p - I(v)) - t, uo, up, xtol=1e-16, rtol=1e-15)
+            else:
+                u = brentq(lambda v: psi_p + I(v) - t, uesc, up, xtol=1e-16, rtol=1e-15)
+            out.append(1 / u)
+        return out, "escaped"
+    psi = lambda u: quad(lambda v: 1 / math.sqrt(G(v)), uo, u, **opts)[0]  # noqa: E731
+    total = psi(ustop)
+    out = []
+    for t in targets:
+        if t >= total:
+            break
+        out.append(1 / brentq(lambda v: psi(v) - t, uo, ustop, xtol=1e-16, rtol=1e-15))
+    return out, "captured"
+
+
+@pytest.mark.parametrize("th_deg", [17.0, 60.0, 163.0])
+@pytest.mark.parametrize("tol,bound", [(1e-12, 2e-8), (1e-8, 1e-4)])
+def test_schwarzschild_transfer_map_quadrature(orc, th_deg, tol, bound):
+    """Crossing radii R_em^(n) (Sec. 4.3) converge to the exact orbit as the
+    tolerance shrinks: within 2e-8 M at tol 1e-12; the global error at tol 1e-8
+    stays below 1e-4 M."""
+    img = W.image(metric="kerr", spin=0.0, incl=math.radians(th_deg), rtol=tol, atol=tol)
+    setup = orc.image_setup(img)
+    pts = [(3.1, 4.2), (-6.5, 1.0), (0.4, -5.3), (2.0, 7.9), (-9.0, -9.0), (5.25, -5.5)]
+    checked = 0
+    for X, Y in pts:
+        want, fate = _schwarzschild_crossings(img["r_obs"], img["incl"], X, Y,
+                                              setup["r_stop"], setup["r_esc"])
+        ray, _ = orc.trace_ray(img, X, Y)
+        assert ray.status == (1 if fate == "captured" else 2)
+        assert ray.ncross == len(want)
+        for n, r in enumerate(want[:3]):
+            assert abs(ray.r_em[n] - r) < bound, (X, Y, n)
+            checked += 1
+    assert checked >= 6
+
+
+# ---------------------------------------------------------- library integrator
+def test_step_sequence_matches_scipy_rk45(orc):
+    """scipy's RK45 is the same Dormand-Prince pair with the same controller; with
+    first_step = h0 its accepted steps and dense output match the oracle's."""
+    img = W.image(metric="cnfw", spin=0.94, halo=(0.02, 10.0), incl=math.radians(60))
+    X, Y = 3.3, -2.2
+    ray, log = orc.trace_ray(img, X, Y, log_cap=5000)
+    up, dn = orc.initial_momentum(img, X, Y)
+    E, L = -dn[0], dn[3]
+    y0 = np.array([0.0, img["r_obs"], img["incl"], 0.0, dn[1], dn[2]])
+    sol = RK45(lambda t, y: orc.rhs(img, E, L, y), 0.0, y0, t_bound=1e9, rtol=img["rtol"],
+               atol=img["atol"], first_step=img["h0"])
+    crossings = []
+    for k in range(len(log)):
+        sol.step()
+        # The embedded error estimate is a difference of O(|y|) terms that cancel
+        # to O(tol |y|), so it carries ~1e-9 relative rounding noise that depends on
+        # summation order; step sizes therefore agree to ~1e-9, not to the last bit.
+        assert sol.t == pytest.approx(log[k, 0], rel=1e-7)
+        assert np.allclose(sol.y, log[k, 2:], rtol=1e-6, atol=1e-6)
+        dense = sol.dense_output()
+        if (dense(sol.t_old)[2] - HALF_PI >= 0) != (sol.y[2] - HALF_PI >= 0):
+            tc = brentq(lambda t: dense(t)[2] - HALF_PI, sol.t_old, sol.t, xtol=1e-14)
+            crossings.append(dense(tc)[1])
+    assert len(crossings) == ray.ncross >= 1
+    assert sol.status == "running" and len(log) == ray.accepted
+    for n, r in enumerate(crossings[:3]):
+        assert ray.r_em[n] == pytest.approx(r, rel=1e-9)
+
+
+# ------------------------------------------------------------------ symmetries
+def _same(a, b, rel):
+    a, b = np.asarray(a, float), np.asarray(b, float)
+    both_nan = np.isnan(a) & np.isnan(b)
+    return bool(np.all(both_nan | np.isclose(a, b, rtol=rel, atol=rel)))
+
+
+def _bitwise(a, b):
+    a, b = np.asarray(a, float), np.asarray(b, float)
+    return bool(np.all((np.isnan(a) & np.isnan(b)) | (a == b)))
+
+
+def test_exact_mirror_symmetries(orc):
+    """The metric is invariant under (chi, phi) -> (-chi, -phi), and the screen map
+    sends X -> -X with it; the geodesic quantities are then mirrored exactly (same
+    magnitudes, same rounding): chi -> -chi mirrors the transfer maps in X bit for
+    bit, and chi = 0 makes N_cross and R_em even in X."""
+    rng = np.random.default_rng(9)
+    base = W.image(metric="cnfw", spin=0.6, halo=(0.02, 10.0), incl=math.radians(50))
+    neg = dict(base, spin=-base["spin"])
+    zero = dict(base, spin=0.0)
+    for X, Y in rng.uniform(-9, 9, size=(8, 2)):
+        a, _ = orc.trace_ray(base, X, Y)
+        c, _ = orc.trace_ray(neg, -X, Y)
+        assert (a.ncross, a.status, a.attempts) == (c.ncross, c.status, c.attempts)
+        assert _bitwise(a.r_em, c.r_em) and _bitwise(a.phi_em, -np.asarray(c.phi_em))
+        assert _bitwise(a.t_em, c.t_em)
+        # (the intensity is not mirrored: eq. (91) takes the root with Omega > 0, so the
+        # disc keeps its sense of rotation when chi changes sign)
+        d1, _ = orc.trace_ray(zero, X, Y)
+        d2, _ = orc.trace_ray(zero, -X, Y)
+        assert d1.ncross == d2.ncross and _bitwise(d1.r_em, d2.r_em)
+
+
+def test_equatorial_reflection_symmetry(orc):
+    """theta_o -> pi - theta_o maps Y -> -Y.  The error norm weighs |theta|, which
+    is not reflection invariant, so mirrored rays take different steps and agree
+    only to the integration error: checked at tolerance 1e-12."""
+    rng = np.random.default_rng(9)
+    base = W.image(metric="cnfw", spin=0.6, halo=(0.02, 10.0), incl=math.radians(50),
+                   rtol=1e-12, atol=1e-12)
+    flip = dict(base, incl=math.pi - base["incl"])
+    for X, Y in rng.uniform(-9, 9, size=(8, 2)):
+        a, _ = orc.trace_ray(base, X, Y)
+        b, _ = orc.trace_ray(flip, X, -Y)
+        assert (a.ncross, a.status) == (b.ncross, b.status)
+        assert _same(a.r_em, b.r_em, 1e-8) and _same(a.phi_em, b.phi_em, 1e-8)
+        assert _same(a.t_em, b.t_em, 1e-8)
+        assert a.intensity == pytest.approx(b.intensity, rel=1e-7, abs=1e-300)
+
+
+# ------------------------------------------------------------------- redshift
+def test_kerr_keplerian_redshift_closed_form(orc):
+    """Sec. 5.2 in the Kerr limit: Omega = 1/(R^{3/2} + chi) and
+    u^T = (R^{3/2}+chi) / (R^{3/4} sqrt(R^{3/2} - 3 R^{1/2} + 2 chi)), g = 1/(u^T (E - Omega l));
+    no circular orbit (g = 0) inside the prograde photon orbit."""
+    for chi in (0.0, 0.5, 0.94, -0.7):
+        img = W.image(metric="kerr", spin=chi)
+        for R in (2.9, 4.0, 6.5, 12.0, 19.0):
+            q = R ** 1.5 - 3 * R ** 0.5 + 2 * chi
+            for E, L in ((1.0, 0.0), (0.97, 2.5), (1.02, -3.0)):
+                g = orc.redshift(img, R, E, L)
+                if q <= 0:
+                    assert g == 0.0
+                    continue
+                uT = (R ** 1.5 + chi) / (R ** 0.75 * math.sqrt(q))
+                Om = 1 / (R ** 1.5 + chi)
+                assert g == pytest.approx(1 / (uT * (E - Om * L)), rel=1e-13)
+    # Schwarzschild, zero angular momentum: g = sqrt(1 - 3/R)/E
+    img = W.image(metric="kerr", spin=0.0)
+    assert orc.redshift(img, 7.0, 1.0, 0.0) == pytest.approx(math.sqrt(1 - 3 / 7.0), rel=1e-14)
+    assert orc.redshift(img, 2.5, 1.0, 0.0) == 0.0

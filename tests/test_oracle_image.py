@@ -1,0 +1,48 @@
+"""Pins of the oracle's per-image reductions (paper Sec. 6.2 and 6.4) against
+closed forms for Gaussian images, and of the screen pixel convention."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2605_05635_amd import workloads as W
+
+
+def gaussian_image(img, x0, y0, s):
+    X = img["x_min"] + (np.arange(img["nx"]) + 0.5) * (img["x_max"] - img["x_min"]) / img["nx"]
+    Y = img["y_min"] + (np.arange(img["ny"]) + 0.5) * (img["y_max"] - img["y_min"]) / img["ny"]
+    return np.exp(-((X[None, :] - x0) ** 2 + (Y[:, None] - y0) ** 2) / (2 * s * s))
+
+
+def test_flux_and_centroid_of_gaussian(orc):
+    img = W.image(nx=201, ny=173, x_min=-14, x_max=14, y_min=-15, y_max=13)
+    I = gaussian_image(img, 1.3, -2.1, 1.2)
+    F, Xc, Yc = orc.flux_centroid(img, I)
+    assert F == pytest.approx(2 * math.pi * 1.2 ** 2, rel=1e-10)
+    assert Xc == pytest.approx(1.3, abs=1e-10) and Yc == pytest.approx(-2.1, abs=1e-10)
+
+
+def test_visibility_of_gaussian(orc):
+    """|V(u,v)|/|V(0,0)| of a Gaussian of width s is exp(-2 pi^2 s^2 q^2), and a
+    shift only changes the phase."""
+    img = W.image(nx=160, ny=150, x_min=-12, x_max=12, y_min=-12, y_max=12)
+    s = 1.6
+    I = gaussian_image(img, 0.7, 0.4, s)
+    uv = W.uv_points(11, 40)
+    amp = orc.visibility_amplitude(img, I, uv)
+    q2 = (uv ** 2).sum(1)
+    assert np.allclose(amp, np.exp(-2 * math.pi ** 2 * s * s * q2), rtol=0, atol=1e-10)
+
+
+def test_pixel_centres_and_workloads():
+    img = W.kerr_small()
+    assert (img["x_max"] - img["x_min"]) / img["nx"] == 0.375
+    from oracle import oracle as O
+    X, Y = O.pixel_xy(img, np.array([0, 63, 64, 4095]))
+    assert X[0] == -12 + 0.1875 and X[1] == 12 - 0.1875 and Y[2] == -12 + 0.375 + 0.1875
+    assert Y[3] == 12 - 0.1875
+    a, b = W.einasto_512(), W.einasto_512()
+    assert a == b and 0.10 <= a["halo"][0] <= 0.18
+    batch = W.batch_64()
+    assert len(batch) == 64 and {d["metric"] for d in batch} == {"kerr", "einasto", "cnfw"}
+    assert all(d["nx"] in (128, 256, 512, 768) for d in batch)
