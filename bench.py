@@ -1,0 +1,152 @@
+"""Throughput benchmark of the backward geodesic ray tracer on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+
+One step = one full trace of the 1024x1024 cored-NFW screen (chi = 0.94,
+(eta, lambda_c) = (0.02, 10), theta_o = 163 deg, R_o = 1000, +-10 M, FP64
+Dormand-Prince at rtol = atol = 1e-8, up to three crossings, thin-disc
+intensity, flux and centroid) through the C ABI, with the outputs resident in
+HBM.  Prints one JSON line: whole-job rays/s, the trace kernel's algorithmic
+FLOP rate against the FP64 vector peak, and the CPU oracle's rate on a
+strided sample of the same screen.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "geodesic rays/s at 1024² (FP64 vs mixed); adjoint image-gradient ms"
+FP64_VECTOR_PEAK_TFLOPS = 78.6   # MI355X: 256 CUs x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
+TRACE_SOURCES = ("paper_2605_05635_amd/csrc/rt_trace.hip", "paper_2605_05635_amd/csrc/rt_device.h")
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def trace_source_hash() -> str:
+    h = hashlib.sha256()
+    for p in TRACE_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel_hash: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or None
+    when it is missing or was taken on a different kernel source."""
+    path = os.path.join(ROOT, "profiles", "trace_kernel_cnfw_1024_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("kernel_source_hash") != kernel_hash:
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(img: dict, stride: int) -> dict:
+    from oracle import oracle as O
+    from paper_2605_05635_amd import workloads as W
+    threads = max(1, min(16, os.cpu_count() or 1))
+    idx = W.subsample_indices(img["nx"], img["ny"], stride)
+    log(f"cpu baseline: oracle on {idx.size} pixels with {threads} threads")
+    t0 = time.perf_counter()
+    O.trace_pixels(img, idx, threads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": idx.size / dt, "unit": "rays/s", "cores": threads, "kind": "oracle",
+            "sample": f"every {stride}th pixel in x and y of the same screen "
+                      f"({idx.size} rays, {dt:.1f} s)"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-stride", type=int, default=2)
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: the ray tracer runs on a single MI355X "
+              "(rays are independent; see DESIGN.md for how the screen would shard)",
+              file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    from paper_2605_05635_amd import census, rt, workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    img = W.cnfw_1024("fp64")
+    n_rays = img["nx"] * img["ny"]
+    outs = rt.alloc_outputs(img)
+    params, o = [rt.params_from(img)], [rt.out_from(outs)]
+    stream = torch.cuda.current_stream()
+
+    log(f"warmup {args.warmup} steps")
+    for _ in range(args.warmup):
+        rt.rt_trace_image(params, o, stream)
+    torch.cuda.synchronize()
+
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    stops = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    log(f"timing {args.steps} steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        rt.rt_set_kernel_timing(starts[k], stops[k])
+        rt.rt_trace_image(params, o, stream)
+    rt.rt_set_kernel_timing(None, None)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kernel_ms = [a.elapsed_time(b) for a, b in zip(starts, stops)]
+    ms_per_step = 1e3 * wall / args.steps
+    value = n_rays * args.steps / wall
+    log(f"{ms_per_step:.3f} ms/step, trace kernel {np.mean(kernel_ms):.3f} ms")
+
+    attempts = outs["attempts"].double().sum().item()
+    crossings = outs["ncross"].double().sum().item()
+    flops = (attempts * (6 * census.flops_rhs(img["metric"]) + census.flops_step_overhead())
+             + crossings * census.flops_crossing(img["metric"])
+             + n_rays * (20 + census.flops_rhs(img["metric"])))
+    k_s = float(np.mean(kernel_ms)) * 1e-3
+    achieved = flops / k_s / 1e12
+    khash = trace_source_hash()
+    roofline = {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
+                "traffic": measured_traffic(khash),
+                "kernel": "trace_kernel<cNFW>", "kernel_ms": float(np.mean(kernel_ms)),
+                "flops_per_launch": flops, "kernel_source_hash": khash}
+
+    line = {
+        "metric": METRIC, "value": value, "unit": "rays/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "cored-NFW 1024x1024 screen, FP64 trace", "metric": img["metric"],
+                   "spin": img["spin"], "eta": img["halo"][0], "lambda_c": img["halo"][1],
+                   "incl_deg": 163.0, "r_obs": img["r_obs"], "screen": "+-10 M",
+                   "rtol": img["rtol"], "atol": img["atol"], "rays": n_rays},
+        "fp64_rays_per_s": value,
+        "attempts_per_ray": attempts / n_rays,
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(img, args.cpu_stride)
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

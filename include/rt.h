@@ -1,0 +1,153 @@
+/*
+ * rt.h -- C ABI of the MI355X (gfx950) backward null-geodesic ray tracer.
+ *
+ * The library traces one null geodesic per observer-screen pixel backward
+ * through a stationary, axisymmetric, Kerr-like rotating spacetime and returns
+ * the equatorial-crossing (lensing-band) counts, the transfer maps of the first
+ * three crossings and the redshifted thin-disc intensity, following
+ * M. Fathi, "Adaptive ray tracing, image diagnostics, and photon ring
+ * signatures of rotating dark-matter-dressed black holes":
+ *   - spacetimes: Sec. 2, eqs. (9), (13), (23)-(31) (Kerr, Einasto-type and
+ *     cored-NFW seeds in Kerr-like Boyer-Lindquist form);
+ *   - geodesics: Sec. 3.1, Hamilton's equations (46)-(47), eqs. (57)-(62);
+ *   - screen: Sec. 3.2, ZAMO tetrad eqs. (63)-(68), screen map eqs. (70)-(74);
+ *   - events: Sec. 3.3, eqs. (75)-(77); lensing bands Sec. 4.2, eqs. (80)-(81);
+ *     transfer maps Sec. 4.3, eq. (82);
+ *   - emission: Sec. 5.1-5.2, eqs. (85)-(91);
+ *   - image reductions: Sec. 6.2, flux and centroid; Sec. 6.4, eq. (108)-(109).
+ *
+ * Units: M = 1 throughout (eq. (1)).
+ *
+ * Conventions shared by every entry point
+ *   - All array arguments are DEVICE pointers on the current HIP device, owned
+ *     by the caller; the library never frees them.  Parameter structs are host
+ *     memory, read before the call returns.
+ *   - Every call is asynchronous on `hip_stream` (a hipStream_t; NULL means the
+ *     null stream).  Outputs are valid once that stream has reached the point
+ *     of the call.  Scratch memory (a work-queue counter per image) is
+ *     allocated stream-ordered and released before the work completes.
+ *   - Return value: RT_OK (0) on success, a negative RT_ERR_* code otherwise;
+ *     rt_last_error() then describes the failure (thread-local string).  On an
+ *     error nothing has been launched.  The library never aborts or prints.
+ *   - Screen layout: pixel (ix, iy), 0 <= ix < nx, 0 <= iy < ny, sits at the
+ *     centre X = x_min + (ix + 1/2)(x_max - x_min)/nx,
+ *                Y = y_min + (iy + 1/2)(y_max - y_min)/ny,
+ *     and per-pixel arrays are row-major [ny][nx] (index iy*nx + ix);
+ *     per-crossing arrays are [3][ny][nx] (index n*nx*ny + iy*nx + ix).
+ */
+#ifndef RT_MI355X_RT_H
+#define RT_MI355X_RT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RT_VERSION 1
+
+/* Spacetime (Sec. 2.1, eqs. (4), (9), (13)). */
+enum { RT_KERR = 0, RT_EINASTO = 1, RT_CNFW = 2 };
+
+/* Arithmetic of the trace. */
+enum { RT_FP64 = 0 };
+
+/* Return codes. */
+enum {
+  RT_OK = 0,
+  RT_ERR_ARG = -1,        /* invalid argument (null pointer, bad range, NaN)      */
+  RT_ERR_NO_HORIZON = -2, /* Delta(R) has no root in (0.05, 50]: no outer horizon */
+  RT_ERR_HIP = -3,        /* HIP runtime or launch failure                        */
+  RT_ERR_ALLOC = -4       /* stream-ordered scratch allocation failed             */
+};
+
+/* Per-ray termination status (Sec. 3.3). */
+enum {
+  RT_RAY_CAPTURED = 1,    /* R <= r_stop_fac * R_+ at the end of an accepted step */
+  RT_RAY_ESCAPED = 2,     /* R >= r_esc_fac * R_o at the end of an accepted step  */
+  RT_RAY_STEP_LIMIT = 3   /* max_attempts step attempts used                      */
+};
+
+/* Parameters of one image (host memory). */
+typedef struct rt_image_params {
+  int32_t metric;        /* RT_KERR, RT_EINASTO or RT_CNFW                            */
+  int32_t precision;     /* RT_FP64                                                   */
+  double spin;           /* chi = a/M (eq. (1)); the spacetime must have a horizon    */
+  double halo[2];        /* RT_EINASTO: {lambda_E > 0 (eq. (10)), ignored};
+                            RT_CNFW: {eta >= 0 (eq. (14)), lambda_c > 0 (eq. (12))};
+                            RT_KERR: ignored                                          */
+  double incl;           /* theta_o [rad], 0 < theta_o < pi (Sec. 3.2)                */
+  double r_obs;          /* R_o, observer radius; > r_out and outside the horizon     */
+  int32_t nx, ny;        /* screen pixels, >= 1 each, nx*ny < 2^31                    */
+  double x_min, x_max;   /* screen extent in X, x_min < x_max                         */
+  double y_min, y_max;   /* screen extent in Y, y_min < y_max                         */
+  double rtol, atol;     /* Dormand-Prince 5(4) tolerances, > 0                       */
+  double r_stop_fac;     /* capture at R <= r_stop_fac * R_+ (eq. (75)), > 1          */
+  double r_esc_fac;      /* escape at R >= r_esc_fac * R_o, > 1                       */
+  double r_in;           /* inner disc edge (eq. (77)); <= 0 means R_+                */
+  double r_out;          /* outer disc edge, > r_in                                   */
+  double emis_pow;       /* thin-disc emissivity R^-emis_pow                          */
+  double sigma_in;       /* taper widths of eqs. (85)-(86); both > 0 selects the      */
+  double sigma_out;      /*   tanh tapers, otherwise hard edges r_in <= R <= r_out    */
+  double h0;             /* first trial affine step, > 0                              */
+  int32_t max_attempts;  /* step attempts per ray (accepted + rejected), >= 1         */
+  int32_t reserved;      /* must be 0                                                 */
+} rt_image_params;
+
+/* Outputs of one image: device pointers, any of which may be NULL (not wanted).
+ * Crossing records n >= min(N_cross, 3) are NaN. */
+typedef struct rt_image_out {
+  uint8_t *ncross;       /* [ny][nx] trusted equatorial crossings, saturating at 255  */
+  uint8_t *status;       /* [ny][nx] RT_RAY_*                                         */
+  double *r_em;          /* [3][ny][nx] R at crossing n (eq. (82))                    */
+  double *phi_em;        /* [3][ny][nx] phi at crossing n (traced ray, phi_0 = 0)     */
+  double *t_em;          /* [3][ny][nx] T at crossing n (traced ray, T_0 = 0)         */
+  double *g_em;          /* [3][ny][nx] redshift g at crossing n (eq. (89)); 0 where
+                            no timelike circular orbit exists                         */
+  double *intensity;     /* [ny][nx] I = sum_n I_n                                    */
+  double *intensity_n;   /* [3][ny][nx] I_n = w(R_n) g_n^3 R_n^-emis_pow              */
+  int32_t *attempts;     /* [ny][nx] step attempts used by the ray                    */
+  double *reduce;        /* [3] {F, X_c, Y_c} of `intensity` (Sec. 6.2): the flux by
+                            the midpoint rule and the intensity-weighted centroid;
+                            requires `intensity` (RT_ERR_ARG otherwise)               */
+} rt_image_out;
+
+/* Trace n_images images (params[i] -> out[i]).  Every pixel's ray is
+ * integrated with Hamilton's equations and the adaptive Dormand-Prince 5(4)
+ * controller; equatorial crossings are located on the continuous extension
+ * of each step; the thin-disc intensity uses the Keplerian emitter of
+ * eqs. (89)-(91).  Returns RT_ERR_NO_HORIZON if any image has no outer
+ * horizon, RT_ERR_ARG for invalid parameters or n_images < 1. */
+int rt_trace_image(const rt_image_params *params, int32_t n_images, const rt_image_out *out,
+                   void *hip_stream);
+
+/* The transfer maps only (Sec. 4.2-4.3): like rt_trace_image but the emission
+ * outputs (g_em, intensity, intensity_n, reduce) are ignored and not computed. */
+int rt_transfer_maps(const rt_image_params *params, int32_t n_images, const rt_image_out *out,
+                     void *hip_stream);
+
+/* Outer horizon R_+ (largest root of Delta, eq. (33)) and the image setup the
+ * trace uses, on the host: setup[0..3] = {R_+, capture radius, escape radius,
+ * inner disc edge}.  `setup` is host memory.  Synchronous. */
+int rt_image_setup(const rt_image_params *params, double *setup);
+
+/* Profiling hook.  When both are non-NULL hipEvent_t handles, every later
+ * rt_trace_image / rt_transfer_maps call made on this thread records
+ * `start_event` on its stream just before the first trace kernel and
+ * `stop_event` just after the last one (the work-queue reset before and the
+ * reductions after are outside the bracket).  NULL, NULL switches it off.
+ * The events stay owned by the caller.  Returns RT_ERR_ARG if exactly one is
+ * NULL. */
+int rt_set_kernel_timing(void *start_event, void *stop_event);
+
+/* Thread-local description of the last error on this thread ("" if none). */
+const char *rt_last_error(void);
+
+/* RT_VERSION of the library. */
+int rt_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RT_MI355X_RT_H */

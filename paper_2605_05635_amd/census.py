@@ -1,0 +1,160 @@
+"""Algorithmic operation census of the trace (for roofline accounting).
+
+Counts the floating-point operations one right-hand-side evaluation, one
+Dormand-Prince step attempt and one recorded crossing must perform, by
+executing the kernel's formulas (rt_trace.hip) once with a counting scalar.
+Convention: every +, -, *, / , sqrt, fabs/fmax/fmin and every special-function
+value (sin, cos, exp, expm1, log1p, pow, tanh) counts as one flop; common
+subexpressions are counted once, as the kernel computes them; comparisons and
+integer bookkeeping are not counted.
+
+Used only to turn measured per-ray step counts into FLOP/s; it computes nothing
+the trace returns.  tests/test_census.py checks that the formulas below give
+the same numbers as the oracle's right-hand side, so the census counts a
+correct evaluation.
+"""
+from __future__ import annotations
+
+import math
+
+
+class Num:
+    """A float that counts the arithmetic done on it."""
+    ops = 0
+
+    def __init__(self, v):
+        self.v = float(v.v if isinstance(v, Num) else v)
+
+    @staticmethod
+    def _v(x):
+        return x.v if isinstance(x, Num) else float(x)
+
+    def _op(self, r):
+        Num.ops += 1
+        return Num(r)
+
+    def __add__(self, o): return self._op(self.v + self._v(o))
+    def __radd__(self, o): return self._op(self._v(o) + self.v)
+    def __sub__(self, o): return self._op(self.v - self._v(o))
+    def __rsub__(self, o): return self._op(self._v(o) - self.v)
+    def __mul__(self, o): return self._op(self.v * self._v(o))
+    def __rmul__(self, o): return self._op(self._v(o) * self.v)
+    def __truediv__(self, o): return self._op(self.v / self._v(o))
+    def __rtruediv__(self, o): return self._op(self._v(o) / self.v)
+    def __neg__(self): return Num(-self.v)      # sign flips are free
+    def __float__(self): return self.v
+
+
+def f(name, *x):
+    Num.ops += 1
+    return Num(getattr(math, name)(*(Num._v(a) for a in x)))
+
+
+def mass_function(metric: str, c: dict, R):
+    if metric == "kerr":
+        return 2.0 * R, Num(2.0)
+    if metric == "einasto":
+        x = R * c["inv_lam"]
+        e = f("exp", -x)
+        mu = 1.0 - e * (1.0 + x * (1.0 + 0.5 * x))
+        dmu = 0.5 * e * x * x * c["inv_lam"]
+        return 2.0 * R * mu, 2.0 * (mu + R * dmu)
+    iR = 1.0 / R
+    iRl = 1.0 / (R + c["lam_c"])
+    lg = f("log1p", R / c["lam_c"])
+    ex = c["eta_lc"] * (iRl - 2.0 * iR * lg)
+    dex = c["eta_lc"] * (2.0 * iR * (iR * lg - iRl) - iRl * iRl)
+    em1 = f("expm1", ex)
+    F = R * (2.0 - R * em1)
+    dF = 2.0 - R * (2.0 * em1 + R * (em1 + 1.0) * dex)
+    return F, dF
+
+
+def rhs(metric: str, c: dict, E, L, R, th, pR, pth):
+    s, co = f("sin", th), f("cos", th)
+    F, dF = mass_function(metric, c, R)
+    chi, chi2 = c["chi"], c["chi2"]
+    R2 = R * R
+    R2c = R2 + chi2
+    Sig = R2 + chi2 * co * co
+    Del = R2c - F
+    dDel = 2.0 * R - dF
+    iS, iD, is_ = 1.0 / Sig, 1.0 / Del, 1.0 / s
+    P = R2c * E - chi * L
+    PiD = P * iD
+    Lis2 = L * is_ * is_
+    chiE = chi * E
+    W = L * is_ - chiE * s
+    pR2 = pR * pR
+    N = Del * pR2 + pth * pth - P * PiD + W * W
+    dN = dDel * (pR2 + PiD * PiD) - 4.0 * R * E * PiD
+    return [(PiD * R2c + chi * (L - chiE * s * s)) * iS,
+            Del * pR * iS,
+            pth * iS,
+            (chi * PiD + Lis2 - chiE) * iS,
+            (N * R * iS - 0.5 * dN) * iS,
+            co * iS * (W * (Lis2 + chiE) - chi2 * s * N * iS)]
+
+
+def _consts(metric, chi=0.5, halo=(0.1, 10.0)):
+    return dict(chi=chi, chi2=chi * chi, inv_lam=1.0 / halo[0], lam_c=halo[1],
+                eta_lc=halo[0] * halo[1])
+
+
+def flops_rhs(metric: str) -> int:
+    Num.ops = 0
+    c = _consts(metric)
+    rhs(metric, c, Num(1.0), Num(2.0), Num(7.0), Num(1.1), Num(0.3), Num(2.0))
+    return Num.ops
+
+
+def flops_step_overhead() -> int:
+    """Everything in one attempt except the six right-hand sides: stage inputs
+    of the four dynamical components (T and phi do not feed back), the 5th-order
+    update, the RMS error norm and the step-size factor."""
+    n = 0
+    for j in range(2, 7):        # stages 2..6: y + h * sum_{i<j} a_ji k_i
+        n += 4 * (2 * j - 1)
+    n += 6 * 11                  # y_new = y + h * (5 weighted k's)
+    n += 6 * (12 + 5 + 3)        # error term, scale atol + rtol max(|y|,|y_new|), q^2 sum
+    n += 2 + 4                   # sqrt(mean), pow, safety, min/max
+    return n
+
+
+def flops_crossing(metric: str, bisections: int = 60) -> int:
+    """Locating and recording one crossing: dense coefficients for theta, R,
+    p_theta, phi and T; the bisection on theta(s); the evaluations at the root;
+    the Keplerian redshift and the disc emission."""
+    dense_coeffs = 5 * (3 + 12 + 1)      # r2, r3, r4 and r5 = h sum d_i k_i
+    per_eval = 9                          # y0 + s (r2 + (1-s)(r3 + s (r4 + (1-s) r5)))
+    bis = bisections * (per_eval + 3)     # midpoint, evaluation, compare offset
+    at_root = 4 * per_eval + 4            # R, p_theta, phi, T; affine position
+    Num.ops = 0
+    c = _consts(metric)
+    R = Num(7.0)
+    F, dF = mass_function(metric, c, R)
+    iR = 1.0 / R
+    FoR2 = F * iR * iR
+    G = (dF - 2.0 * F * iR) * iR * iR
+    disc = -2.0 * R * G
+    Om = (c["chi"] * G + f("sqrt", disc)) / (2.0 * R + c["chi2"] * G)
+    gTT, gTp = -(1.0 - FoR2), -c["chi"] * FoR2
+    gpp = R * R + c["chi2"] + c["chi2"] * FoR2
+    A = -(gTT + Om * (2.0 * gTp + Om * gpp))
+    g = f("sqrt", A) / (1.0 - Om * 2.0)
+    In = g * g * g * f("pow", R, -3.0)
+    _ = In + 1.0
+    return dense_coeffs + bis + at_root + Num.ops
+
+
+def flops_per_ray(metric: str, attempts: float, crossings: float) -> float:
+    """Algorithmic flops of a ray with the given step attempts and recorded
+    crossings (plus its start: screen map and one right-hand side)."""
+    return (attempts * (6 * flops_rhs(metric) + flops_step_overhead())
+            + crossings * flops_crossing(metric) + 20 + flops_rhs(metric))
+
+
+if __name__ == "__main__":
+    for m in ("kerr", "einasto", "cnfw"):
+        print(m, "rhs", flops_rhs(m), "step", flops_step_overhead(), "crossing",
+              flops_crossing(m), "attempt", 6 * flops_rhs(m) + flops_step_overhead())

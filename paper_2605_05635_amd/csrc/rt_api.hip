@@ -1,0 +1,342 @@
+// rt_api.hip -- the C ABI (include/rt.h): argument validation, per-image
+// setup on the host (outer horizon, observer tetrad, screen, stop radii) and
+// the stream-ordered launches of the gfx950 kernels.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "rt.h"
+#include "rt_device.h"
+#include "rt_kernels.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+thread_local hipEvent_t g_timing_start = nullptr, g_timing_stop = nullptr;
+
+int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+    return fail(RT_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool finite_all(std::initializer_list<double> v) {
+    for (double x : v)
+        if (!std::isfinite(x)) return false;
+    return true;
+}
+
+// Delta(R) = R^2 - F(R) + chi^2 (eq. (25)) and its R-derivative.
+void delta(const rt::ImageConst& c, double R, double* D, double* dD) {
+    double F, dF;
+    rt::mass_function_any(c, R, F, dF);
+    *D = R * R - F + c.chi2;
+    *dD = 2.0 * R - dF;
+}
+
+// Outer horizon: the largest root of Delta (eq. (33)) in (0.05, 50].  Delta is
+// sampled downward on a grid of spacing 1e-2; an interval counts when Delta
+// changes sign across it, or when Delta has an interior minimum <= 0 (two
+// close roots, near extremality).  The root is refined by bisection to the
+// last representable bracket.
+bool outer_horizon(const rt::ImageConst& c, double* r_plus) {
+    const double top = 50.0, step = 1e-2;
+    double D_hi, dD_hi;
+    delta(c, top, &D_hi, &dD_hi);
+    if (!(D_hi > 0.0)) return false;
+    for (int k = 1; top - k * step >= 0.05 - 1e-12; ++k) {
+        const double hi = top - (k - 1) * step, lo = top - k * step;
+        double D_lo, dD_lo;
+        delta(c, lo, &D_lo, &dD_lo);
+        double a = lo, b = hi;  // want Delta(a) <= 0 < Delta(b)
+        bool bracket = D_lo <= 0.0;
+        if (!bracket && dD_lo < 0.0 && dD_hi > 0.0) {
+            // interior minimum: locate it where dDelta/dR = 0
+            double u = lo, v = hi;
+            for (int it = 0; it < 200; ++it) {
+                const double m = 0.5 * (u + v);
+                if (m <= u || m >= v) break;
+                double Dm, dDm;
+                delta(c, m, &Dm, &dDm);
+                if (dDm < 0.0) u = m; else v = m;
+            }
+            double Dm, dDm;
+            delta(c, 0.5 * (u + v), &Dm, &dDm);
+            if (Dm <= 0.0) {
+                a = 0.5 * (u + v);
+                bracket = true;
+            }
+        }
+        if (bracket) {
+            for (int it = 0; it < 200; ++it) {
+                const double m = 0.5 * (a + b);
+                if (m <= a || m >= b) break;
+                double Dm, dDm;
+                delta(c, m, &Dm, &dDm);
+                if (Dm > 0.0) b = m; else a = m;
+            }
+            *r_plus = 0.5 * (a + b);
+            return true;
+        }
+        D_hi = D_lo;
+        dD_hi = dD_lo;
+    }
+    return false;
+}
+
+// Validates p and fills the image constants.  Returns RT_OK or an error code.
+int setup_image(const rt_image_params* p, int index, bool emission, rt::ImageConst* c,
+                double* r_plus_out) {
+    if (!p) return fail(RT_ERR_ARG, "image %d: null parameter pointer", index);
+    if (p->metric < RT_KERR || p->metric > RT_CNFW)
+        return fail(RT_ERR_ARG, "image %d: unknown metric %d", index, p->metric);
+    if (p->precision != RT_FP64)
+        return fail(RT_ERR_ARG, "image %d: unsupported precision %d", index, p->precision);
+    if (p->reserved != 0) return fail(RT_ERR_ARG, "image %d: reserved field must be 0", index);
+    if (!finite_all({p->spin, p->halo[0], p->halo[1], p->incl, p->r_obs, p->x_min, p->x_max,
+                     p->y_min, p->y_max, p->rtol, p->atol, p->r_stop_fac, p->r_esc_fac, p->r_in,
+                     p->r_out, p->emis_pow, p->sigma_in, p->sigma_out, p->h0}))
+        return fail(RT_ERR_ARG, "image %d: non-finite parameter", index);
+    if (p->nx < 1 || p->ny < 1 || static_cast<int64_t>(p->nx) * p->ny >= (int64_t(1) << 31))
+        return fail(RT_ERR_ARG, "image %d: bad screen size %d x %d", index, p->nx, p->ny);
+    if (!(p->x_min < p->x_max) || !(p->y_min < p->y_max))
+        return fail(RT_ERR_ARG, "image %d: empty screen extent", index);
+    if (!(p->incl > 0.0) || !(p->incl < M_PI))
+        return fail(RT_ERR_ARG, "image %d: inclination must lie in (0, pi)", index);
+    if (!(p->rtol > 0.0) || !(p->atol > 0.0) || !(p->h0 > 0.0))
+        return fail(RT_ERR_ARG, "image %d: rtol, atol and h0 must be positive", index);
+    if (!(p->r_stop_fac > 1.0) || !(p->r_esc_fac > 1.0))
+        return fail(RT_ERR_ARG, "image %d: stop factors must exceed 1", index);
+    if (p->max_attempts < 1) return fail(RT_ERR_ARG, "image %d: max_attempts < 1", index);
+    if (p->metric == RT_EINASTO && !(p->halo[0] > 0.0))
+        return fail(RT_ERR_ARG, "image %d: Einasto lambda_E must be positive", index);
+    if (p->metric == RT_CNFW && (!(p->halo[0] >= 0.0) || !(p->halo[1] > 0.0)))
+        return fail(RT_ERR_ARG, "image %d: cored-NFW needs eta >= 0, lambda_c > 0", index);
+
+    std::memset(c, 0, sizeof *c);
+    c->metric = p->metric;
+    c->max_attempts = p->max_attempts;
+    c->nx = p->nx;
+    c->ny = p->ny;
+    c->n_pix = static_cast<int64_t>(p->nx) * p->ny;
+    c->chi = p->spin;
+    c->chi2 = p->spin * p->spin;
+    if (p->metric == RT_EINASTO) c->inv_lam = 1.0 / p->halo[0];
+    if (p->metric == RT_CNFW) {
+        c->lam_c = p->halo[1];
+        c->eta_lc = p->halo[0] * p->halo[1];
+    }
+    double r_plus = 0.0;
+    if (!outer_horizon(*c, &r_plus))
+        return fail(RT_ERR_NO_HORIZON, "image %d: Delta(R) has no root in (0.05, 50]", index);
+    if (r_plus_out) *r_plus_out = r_plus;
+    c->r_stop = p->r_stop_fac * r_plus;
+    c->r_esc = p->r_esc_fac * p->r_obs;
+    c->r_in = p->r_in > 0.0 ? p->r_in : r_plus;
+    c->r_out = p->r_out;
+    if (!(c->r_out > c->r_in)) return fail(RT_ERR_ARG, "image %d: need r_out > r_in", index);
+    if (!(p->r_obs > c->r_stop) || !(p->r_obs > c->r_out))
+        return fail(RT_ERR_ARG, "image %d: observer must lie outside the disc and horizon", index);
+
+    // Observer metric at (R_o, theta_o), eqs. (27)-(31), and the ZAMO (63)-(65).
+    const double R = p->r_obs, th = p->incl;
+    double F, dF;
+    rt::mass_function_any(*c, R, F, dF);
+    const double s = std::sin(th), co = std::cos(th), s2 = s * s;
+    const double Sig = R * R + c->chi2 * co * co;
+    const double Del = R * R - F + c->chi2;
+    const double gTT = -(1.0 - F / Sig);
+    const double gTp = -c->chi * F * s2 / Sig;
+    const double gRR = Sig / Del;
+    const double gthth = Sig;
+    const double gpp = s2 * (R * R + c->chi2 + c->chi2 * F * s2 / Sig);
+    const double N2 = gTp * gTp / gpp - gTT;  // -(g_TT + 2 w g_Tphi + w^2 g_phiphi), w = -g_Tphi/g_phiphi
+    if (!(Del > 0.0) || !(N2 > 0.0) || !(gpp > 0.0))
+        return fail(RT_ERR_ARG, "image %d: no static observer frame at R_o", index);
+    c->r_obs = R;
+    c->incl = th;
+    c->obs_N = std::sqrt(N2);
+    c->obs_sq_gphph = std::sqrt(gpp);
+    c->obs_gTph_over_sq_gphph = gTp / c->obs_sq_gphph;
+    c->obs_sq_gRR = std::sqrt(gRR);
+    c->obs_sq_gthth = std::sqrt(gthth);
+
+    c->dx = (p->x_max - p->x_min) / p->nx;
+    c->dy = (p->y_max - p->y_min) / p->ny;
+    c->x0 = p->x_min;
+    c->y0 = p->y_min;
+    c->rtol = p->rtol;
+    c->atol = p->atol;
+    c->h0 = p->h0;
+    c->emis_pow = p->emis_pow;
+    c->sigma_in = p->sigma_in;
+    c->sigma_out = p->sigma_out;
+    c->taper = (p->sigma_in > 0.0 && p->sigma_out > 0.0) ? 1 : 0;
+    c->emission = emission ? 1 : 0;
+    return RT_OK;
+}
+
+struct DeviceInfo {
+    int cus = 0;
+    int blocks_per_cu[3] = {0, 0, 0};
+};
+
+int device_info(DeviceInfo* info) {
+    static DeviceInfo cache[64];
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= 64) return fail(RT_ERR_HIP, "device index %d out of range", dev);
+    DeviceInfo& d = cache[dev];
+    if (d.cus == 0) {
+        int cus = 0;
+        e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute");
+        for (int m = 0; m < 3; ++m) d.blocks_per_cu[m] = rt::max_blocks_per_cu(m);
+        d.cus = cus;
+    }
+    *info = d;
+    return RT_OK;
+}
+
+template <class T>
+int check_device_ptr(const T* ptr, const char* name, int index) {
+    if (!ptr) return RT_OK;
+    hipPointerAttribute_t attr;
+    hipError_t e = hipPointerGetAttributes(&attr, ptr);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(RT_ERR_ARG, "image %d: %s is not device-accessible memory", index, name);
+    }
+    if (attr.type != hipMemoryTypeDevice && attr.type != hipMemoryTypeManaged)
+        return fail(RT_ERR_ARG, "image %d: %s is not device memory", index, name);
+    return RT_OK;
+}
+
+int trace_common(const rt_image_params* params, int32_t n_images, const rt_image_out* out,
+                 void* hip_stream, bool emission) {
+    g_last_error.clear();
+    if (!params || !out) return fail(RT_ERR_ARG, "null params or out");
+    if (n_images < 1) return fail(RT_ERR_ARG, "n_images must be >= 1");
+    std::vector<rt::ImageConst> consts(n_images);
+    for (int i = 0; i < n_images; ++i) {
+        const int rc = setup_image(&params[i], i, emission, &consts[i], nullptr);
+        if (rc != RT_OK) return rc;
+        if (emission && out[i].reduce && !out[i].intensity)
+            return fail(RT_ERR_ARG, "image %d: reduce needs the intensity output", i);
+    }
+    DeviceInfo info;
+    int rc = device_info(&info);
+    if (rc != RT_OK) return rc;
+    for (int i = 0; i < n_images; ++i) {
+        const rt_image_out& o = out[i];
+        if ((rc = check_device_ptr(o.ncross, "ncross", i)) || (rc = check_device_ptr(o.status, "status", i)) ||
+            (rc = check_device_ptr(o.r_em, "r_em", i)) || (rc = check_device_ptr(o.phi_em, "phi_em", i)) ||
+            (rc = check_device_ptr(o.t_em, "t_em", i)) || (rc = check_device_ptr(o.g_em, "g_em", i)) ||
+            (rc = check_device_ptr(o.intensity, "intensity", i)) ||
+            (rc = check_device_ptr(o.intensity_n, "intensity_n", i)) ||
+            (rc = check_device_ptr(o.attempts, "attempts", i)) ||
+            (rc = check_device_ptr(o.reduce, "reduce", i)))
+            return rc;
+    }
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    unsigned long long* queue = nullptr;
+    hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&queue),
+                                  sizeof(unsigned long long) * n_images, stream);
+    if (e != hipSuccess || !queue) {
+        (void)hipGetLastError();
+        return fail(RT_ERR_ALLOC, "stream-ordered allocation of the work queue failed");
+    }
+    e = rt::launch_zero(queue, n_images, stream);
+    if (e != hipSuccess) {
+        (void)hipFreeAsync(queue, stream);
+        return hip_fail(e, "queue reset launch");
+    }
+    if (g_timing_start) (void)hipEventRecord(g_timing_start, stream);
+    for (int i = 0; i < n_images; ++i) {
+        const rt::ImageConst& c = consts[i];
+        rt::OutPtrs o{out[i].ncross, out[i].status, out[i].r_em, out[i].phi_em, out[i].t_em,
+                      emission ? out[i].g_em : nullptr, emission ? out[i].intensity : nullptr,
+                      emission ? out[i].intensity_n : nullptr, out[i].attempts};
+        const int64_t waves = (c.n_pix + 63) / 64;
+        const int64_t want_blocks = (waves + 3) / 4;
+        const int64_t resident = static_cast<int64_t>(info.cus) * info.blocks_per_cu[c.metric];
+        const int32_t grid = static_cast<int32_t>(want_blocks < resident ? want_blocks : resident);
+        const int32_t chunk = 64;
+        e = rt::launch_trace(c, o, queue + i, chunk, grid, stream);
+        if (e != hipSuccess) {
+            (void)hipFreeAsync(queue, stream);
+            return hip_fail(e, "trace kernel launch");
+        }
+    }
+    if (g_timing_stop) (void)hipEventRecord(g_timing_stop, stream);
+    for (int i = 0; i < n_images; ++i) {
+        if (emission && out[i].reduce) {
+            e = rt::launch_reduce(consts[i], out[i].intensity, out[i].reduce, stream);
+            if (e != hipSuccess) {
+                (void)hipFreeAsync(queue, stream);
+                return hip_fail(e, "reduce kernel launch");
+            }
+        }
+    }
+    e = hipFreeAsync(queue, stream);
+    if (e != hipSuccess) return hip_fail(e, "hipFreeAsync");
+    return RT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int rt_trace_image(const rt_image_params* params, int32_t n_images, const rt_image_out* out,
+                   void* hip_stream) {
+    return trace_common(params, n_images, out, hip_stream, true);
+}
+
+int rt_transfer_maps(const rt_image_params* params, int32_t n_images, const rt_image_out* out,
+                     void* hip_stream) {
+    return trace_common(params, n_images, out, hip_stream, false);
+}
+
+int rt_image_setup(const rt_image_params* params, double* setup) {
+    g_last_error.clear();
+    if (!setup) return fail(RT_ERR_ARG, "null setup pointer");
+    rt::ImageConst c;
+    double r_plus = 0.0;
+    const int rc = setup_image(params, 0, true, &c, &r_plus);
+    if (rc != RT_OK) return rc;
+    setup[0] = r_plus;
+    setup[1] = c.r_stop;
+    setup[2] = c.r_esc;
+    setup[3] = c.r_in;
+    return RT_OK;
+}
+
+int rt_set_kernel_timing(void* start_event, void* stop_event) {
+    g_last_error.clear();
+    if ((start_event == nullptr) != (stop_event == nullptr))
+        return fail(RT_ERR_ARG, "timing events must both be set or both be null");
+    g_timing_start = static_cast<hipEvent_t>(start_event);
+    g_timing_stop = static_cast<hipEvent_t>(stop_event);
+    return RT_OK;
+}
+
+const char* rt_last_error(void) { return g_last_error.c_str(); }
+
+int rt_version(void) { return RT_VERSION; }
+
+}  // extern "C"

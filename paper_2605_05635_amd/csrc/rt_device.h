@@ -1,0 +1,87 @@
+// rt_device.h -- spacetime functions and per-image constants of the MI355X
+// ray tracer, usable from host setup code and from the gfx950 kernels.
+//
+// Paper: M. Fathi, "Adaptive ray tracing, image diagnostics, and photon ring
+// signatures of rotating dark-matter-dressed black holes".  Units M = 1.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+namespace rt {
+
+enum : int32_t { KERR = 0, EINASTO = 1, CNFW = 2 };
+enum : int32_t { RAY_CAPTURED = 1, RAY_ESCAPED = 2, RAY_STEP_LIMIT = 3 };
+
+// Everything a kernel needs to know about one image.  Passed by value as a
+// kernel argument (it lands in the kernarg segment and is read through the
+// scalar cache), or gathered from a device table in a batched launch.
+struct ImageConst {
+    int32_t metric;
+    int32_t max_attempts;
+    int32_t nx, ny;
+    int64_t n_pix;
+    // spacetime
+    double chi, chi2;
+    double inv_lam;      // Einasto: 1/lambda_E
+    double lam_c;        // cored NFW: lambda_c
+    double eta_lc;       // cored NFW: eta * lambda_c
+    // observer (Sec. 3.2): ZAMO normalisation and tetrad scale factors at (R_o, theta_o)
+    double r_obs, incl;
+    double obs_N;        // N_o, eq. (65)
+    double obs_gTph_over_sq_gphph;   // g_Tphi / sqrt(g_phiphi)
+    double obs_sq_gRR, obs_sq_gthth, obs_sq_gphph;
+    // screen: X = x0 + (ix + 1/2) dx, Y = y0 + (iy + 1/2) dy
+    double x0, dx, y0, dy;
+    // integrator and events
+    double rtol, atol, h0;
+    double r_stop, r_esc;
+    // emission
+    double r_in, r_out, emis_pow, sigma_in, sigma_out;
+    int32_t taper;       // 1: tanh tapers of eqs. (85)-(86); 0: hard window, eq. (77)
+    int32_t emission;    // 0: transfer maps only
+};
+
+// F(R) = 2 R mu(R) (eq. (24)) and dF/dR for the chosen seed.  The mass
+// functions mu_E (from eq. (9)) and mu_cNFW (from eq. (13)) are written in
+// cancellation-free forms: mu_E = 1 - e^{-x}(1 + x + x^2/2) with x = R/lambda_E,
+// mu_cNFW = 1 - (R/2) expm1(Ex) with Ex the exponent of eq. (13).
+template <int METRIC>
+__host__ __device__ inline void mass_function(const ImageConst& c, double R, double& F,
+                                              double& dF) {
+    if constexpr (METRIC == KERR) {
+        F = 2.0 * R;
+        dF = 2.0;
+    } else if constexpr (METRIC == EINASTO) {
+        const double x = R * c.inv_lam;
+        const double e = exp(-x);
+        const double mu = 1.0 - e * (1.0 + x * (1.0 + 0.5 * x));
+        const double dmu = 0.5 * e * x * x * c.inv_lam;
+        F = 2.0 * R * mu;
+        dF = 2.0 * (mu + R * dmu);
+    } else {
+        const double iR = 1.0 / R;
+        const double iRl = 1.0 / (R + c.lam_c);
+        const double lg = log1p(R / c.lam_c);
+        const double ex = c.eta_lc * (iRl - 2.0 * iR * lg);
+        const double dex = c.eta_lc * (2.0 * iR * (iR * lg - iRl) - iRl * iRl);
+        const double em1 = expm1(ex);
+        F = R * (2.0 - R * em1);
+        dF = 2.0 - R * (2.0 * em1 + R * (em1 + 1.0) * dex);
+    }
+}
+
+// Runtime dispatch of mass_function (host setup and the batched kernel).
+__host__ __device__ inline void mass_function_any(const ImageConst& c, double R, double& F,
+                                                  double& dF) {
+    if (c.metric == EINASTO)
+        mass_function<EINASTO>(c, R, F, dF);
+    else if (c.metric == CNFW)
+        mass_function<CNFW>(c, R, F, dF);
+    else
+        mass_function<KERR>(c, R, F, dF);
+}
+
+}  // namespace rt

@@ -1,0 +1,383 @@
+// rt_trace.hip -- gfx950 kernels of the backward null-geodesic ray tracer.
+//
+// One wavefront lane integrates one ray (one screen pixel) from the observer
+// toward the hole with Hamilton's equations (Sec. 3.1, eqs. (46)-(47) and
+// (57)-(62)) and an adaptive Dormand-Prince 5(4) step controller, detects
+// equatorial crossings on the step's continuous extension (Sec. 3.3, 4.2),
+// records the transfer maps of the first three crossings (Sec. 4.3, eq. (82))
+// and the redshifted thin-disc intensity (Sec. 5.2, eqs. (89)-(91)).
+//
+// Launch shape: a persistent grid.  Each wavefront claims chunks of pixels
+// from a global counter with one atomic per chunk; a lane whose ray ends takes
+// the next pixel of its wave's chunk at the next refill point, so lanes stay
+// busy while rays of very different lengths are in flight (wavefront-level
+// compaction of terminated rays).
+#include "rt_device.h"
+#include "rt_kernels.h"
+
+namespace rt {
+namespace {
+
+constexpr double kHalfPi = 1.5707963267948966;
+
+// ---------------------------------------------------------------- the RHS
+// Hamilton's equations for H = g^{ab} p_a p_b / 2 with p_T = -E, p_phi = l.
+// The inverse metric of eqs. (49)-(53) is used through the algebraically
+// identical separated form of Sec. 3.1 (the Hamilton-Jacobi equation
+// multiplied by Sigma):
+//   2 Sigma H = N = Delta p_R^2 + p_theta^2 - P^2/Delta + W^2,
+//   P = (R^2 + chi^2) E - chi l,   W = l/sin(theta) - chi E sin(theta),
+// so that, with Sigma = R^2 + chi^2 cos^2(theta) (eq. (23)),
+//   dT/dl   = [P (R^2+chi^2)/Delta + chi (l - chi E sin^2)] / Sigma     (57)
+//   dR/dl   = Delta p_R / Sigma                                         (59)
+//   dth/dl  = p_theta / Sigma                                           (60)
+//   dphi/dl = [chi P/Delta + l/sin^2 - chi E] / Sigma                   (58)
+//   dp_R/dl = -dH/dR = (N R/Sigma - dN/dR / 2) / Sigma                  (61)
+//   dp_th/dl= -dH/dth = cos/Sigma [W (l/sin^2 + chi E) - chi^2 sin N/Sigma]  (62)
+// The N dSigma terms keep the full derivative of H off the constraint shell.
+template <int METRIC>
+__device__ __forceinline__ void rhs(const ImageConst& c, double E, double L, double R, double th,
+                                    double pR, double pth, double d[6]) {
+    double s, co;
+    sincos(th, &s, &co);
+    double F, dF;
+    mass_function<METRIC>(c, R, F, dF);
+    const double R2 = R * R;
+    const double R2c = R2 + c.chi2;
+    const double Sig = R2 + c.chi2 * co * co;
+    const double Del = R2c - F;
+    const double dDel = 2.0 * R - dF;
+    const double iS = 1.0 / Sig;
+    const double iD = 1.0 / Del;
+    const double is = 1.0 / s;
+    const double P = R2c * E - c.chi * L;
+    const double PiD = P * iD;
+    const double Lis2 = L * is * is;
+    const double W = L * is - c.chi * E * s;
+    const double N = Del * pR * pR + pth * pth - P * PiD + W * W;
+    const double dN = dDel * (pR * pR + PiD * PiD) - 4.0 * R * E * PiD;
+    d[0] = (PiD * R2c + c.chi * (L - c.chi * E * s * s)) * iS;
+    d[1] = Del * pR * iS;
+    d[2] = pth * iS;
+    d[3] = (c.chi * PiD + Lis2 - c.chi * E) * iS;
+    d[4] = (N * R * iS - 0.5 * dN) * iS;
+    d[5] = co * iS * (W * (Lis2 + c.chi * E) - c.chi2 * s * N * iS);
+}
+
+// ------------------------------------------------ Dormand-Prince 5(4) tableau
+// Dormand & Prince (1980), first-same-as-last.
+constexpr double a21 = 0.2;
+constexpr double a31 = 3.0 / 40.0, a32 = 9.0 / 40.0;
+constexpr double a41 = 44.0 / 45.0, a42 = -56.0 / 15.0, a43 = 32.0 / 9.0;
+constexpr double a51 = 19372.0 / 6561.0, a52 = -25360.0 / 2187.0, a53 = 64448.0 / 6561.0,
+                 a54 = -212.0 / 729.0;
+constexpr double a61 = 9017.0 / 3168.0, a62 = -355.0 / 33.0, a63 = 46732.0 / 5247.0,
+                 a64 = 49.0 / 176.0, a65 = -5103.0 / 18656.0;
+constexpr double b1 = 35.0 / 384.0, b3 = 500.0 / 1113.0, b4 = 125.0 / 192.0,
+                 b5 = -2187.0 / 6784.0, b6 = 11.0 / 84.0;
+// Error weights: 5th-order minus embedded 4th-order weights.
+constexpr double e1 = 71.0 / 57600.0, e3 = -71.0 / 16695.0, e4 = 71.0 / 1920.0,
+                 e5 = -17253.0 / 339200.0, e6 = 22.0 / 525.0, e7 = -1.0 / 40.0;
+// Continuous extension in Hairer's form (Solving ODEs I, II.6):
+//   y(s) = y0 + s (r2 + (1-s)(r3 + s (r4 + (1-s) r5))),
+//   r2 = y1 - y0, r3 = h k1 - r2, r4 = r2 - h k7 - r3, r5 = h sum_i d_i k_i.
+constexpr double d1 = -12715105075.0 / 11282082432.0, d3 = 87487479700.0 / 32700410799.0,
+                 d4 = -10690763975.0 / 1880347072.0, d5 = 701980252875.0 / 199316789632.0,
+                 d6 = -1453857185.0 / 822651844.0, d7 = 69997945.0 / 29380423.0;
+
+struct DenseComp {
+    double y0, r2, r3, r4, r5;
+    __device__ __forceinline__ double at(double s) const {
+        return y0 + s * (r2 + (1.0 - s) * (r3 + s * (r4 + (1.0 - s) * r5)));
+    }
+};
+
+__device__ __forceinline__ DenseComp dense_comp(double h, double y0, double y1, double k1,
+                                                double k3, double k4, double k5, double k6,
+                                                double k7) {
+    DenseComp o;
+    o.y0 = y0;
+    o.r2 = y1 - y0;
+    o.r3 = h * k1 - o.r2;
+    o.r4 = o.r2 - h * k7 - o.r3;
+    o.r5 = h * (d1 * k1 + d3 * k3 + d4 * k4 + d5 * k5 + d6 * k6 + d7 * k7);
+    return o;
+}
+
+// ------------------------------------------------------------ emission
+// Keplerian equatorial emitter (eqs. (90)-(91)) and redshift (eq. (89)) for a
+// photon with constants (E, l) and unit observer-frame energy.  At theta =
+// pi/2, Sigma = R^2 and with G = d(F/R^2)/dR the metric derivatives are
+// dg_TT = G, dg_Tphi = -chi G, dg_phiphi = 2R + chi^2 G, so eq. (91) reads
+// Omega = (chi G + sqrt(-2 R G)) / (2R + chi^2 G).  g = 0 where no timelike
+// circular orbit exists.
+template <int METRIC>
+__device__ __forceinline__ double redshift(const ImageConst& c, double R, double E, double L) {
+    double F, dF;
+    mass_function<METRIC>(c, R, F, dF);
+    const double iR = 1.0 / R;
+    const double FoR2 = F * iR * iR;
+    const double G = (dF - 2.0 * F * iR) * iR * iR;
+    const double disc = -2.0 * R * G;
+    if (!(disc >= 0.0)) return 0.0;
+    const double Om = (c.chi * G + sqrt(disc)) / (2.0 * R + c.chi2 * G);
+    const double gTT = -(1.0 - FoR2);
+    const double gTp = -c.chi * FoR2;
+    const double gpp = R * R + c.chi2 + c.chi2 * FoR2;
+    const double A = -(gTT + Om * (2.0 * gTp + Om * gpp));
+    if (!(A > 0.0)) return 0.0;
+    const double den = E - Om * L;
+    if (!(den > 0.0)) return 0.0;
+    return sqrt(A) / den;
+}
+
+__device__ __forceinline__ double disc_window(const ImageConst& c, double R) {
+    if (c.taper) {
+        const double tin = 0.5 * (1.0 + tanh((R - c.r_in) / c.sigma_in));
+        const double tout = 0.5 * (1.0 - tanh((R - c.r_out) / c.sigma_out));
+        return tin * tout;
+    }
+    return (R >= c.r_in && R <= c.r_out) ? 1.0 : 0.0;
+}
+
+// ------------------------------------------------------------- ray state
+struct Ray {
+    double y[6];    // T, R, theta, phi, p_R, p_theta
+    double k1[6];   // f(y), first-same-as-last
+    double E, L;
+    double h, lam, last_cross, intensity;
+    int32_t attempts, ncross;
+    int32_t after_reject;
+    int64_t pix;
+};
+
+// Screen pixel -> initial state (Sec. 3.2, eqs. (70)-(74) with E_loc = 1):
+// with n = -(R_o, Y, X)/sqrt(R_o^2 + X^2 + Y^2) in the ZAMO triad, lowering
+// p^mu = u_o + n^(a) e_(a) with the observer metric gives
+// E = N_o - g_Tphi n^(phi)/sqrt(g_phiphi), l = sqrt(g_phiphi) n^(phi),
+// p_R = sqrt(g_RR) n^(R), p_theta = sqrt(g_thth) n^(theta).
+template <int METRIC>
+__device__ __forceinline__ void start_ray(const ImageConst& c, int64_t pix, Ray& r) {
+    const int64_t iy = pix / c.nx;
+    const int64_t ix = pix - iy * c.nx;
+    const double X = c.x0 + (static_cast<double>(ix) + 0.5) * c.dx;
+    const double Y = c.y0 + (static_cast<double>(iy) + 0.5) * c.dy;
+    const double inv = 1.0 / sqrt(c.r_obs * c.r_obs + X * X + Y * Y);
+    const double nR = -c.r_obs * inv, nth = -Y * inv, nph = -X * inv;
+    r.E = c.obs_N - c.obs_gTph_over_sq_gphph * nph;
+    r.L = c.obs_sq_gphph * nph;
+    r.y[0] = 0.0;
+    r.y[1] = c.r_obs;
+    r.y[2] = c.incl;
+    r.y[3] = 0.0;
+    r.y[4] = c.obs_sq_gRR * nR;
+    r.y[5] = c.obs_sq_gthth * nth;
+    rhs<METRIC>(c, r.E, r.L, r.y[1], r.y[2], r.y[4], r.y[5], r.k1);
+    r.h = c.h0;
+    r.lam = 0.0;
+    r.last_cross = -INFINITY;
+    r.intensity = 0.0;
+    r.attempts = 0;
+    r.ncross = 0;
+    r.after_reject = 0;
+    r.pix = pix;
+}
+
+// One step attempt.  Returns 0 while the ray runs, else its final status.
+template <int METRIC>
+__device__ __forceinline__ int32_t attempt(const ImageConst& c, const OutPtrs& o, Ray& r) {
+    if (r.attempts >= c.max_attempts) return RAY_STEP_LIMIT;
+    ++r.attempts;
+    const double h = r.h;
+    double k2[6], k3[6], k4[6], k5[6], k6[6], k7[6], t[6], yn[6];
+#define RT_STAGE(expr, out)                                                      \
+    for (int i = 0; i < 6; ++i) t[i] = r.y[i] + h * (expr);                       \
+    rhs<METRIC>(c, r.E, r.L, t[1], t[2], t[4], t[5], out);
+    RT_STAGE(a21 * r.k1[i], k2)
+    RT_STAGE(a31 * r.k1[i] + a32 * k2[i], k3)
+    RT_STAGE(a41 * r.k1[i] + a42 * k2[i] + a43 * k3[i], k4)
+    RT_STAGE(a51 * r.k1[i] + a52 * k2[i] + a53 * k3[i] + a54 * k4[i], k5)
+    RT_STAGE(a61 * r.k1[i] + a62 * k2[i] + a63 * k3[i] + a64 * k4[i] + a65 * k5[i], k6)
+#undef RT_STAGE
+    for (int i = 0; i < 6; ++i)
+        yn[i] = r.y[i] + h * (b1 * r.k1[i] + b3 * k3[i] + b4 * k4[i] + b5 * k5[i] + b6 * k6[i]);
+    rhs<METRIC>(c, r.E, r.L, yn[1], yn[2], yn[4], yn[5], k7);
+    double acc = 0.0;
+    for (int i = 0; i < 6; ++i) {
+        const double ei = h * (e1 * r.k1[i] + e3 * k3[i] + e4 * k4[i] + e5 * k5[i] + e6 * k6[i]
+                               + e7 * k7[i]);
+        const double sc = c.atol + c.rtol * fmax(fabs(r.y[i]), fabs(yn[i]));
+        const double q = ei / sc;
+        acc += q * q;
+    }
+    const double err = sqrt(acc * (1.0 / 6.0));
+    if (!(err < 1.0)) {  // reject; NaN lands here too
+        r.h = h * (isfinite(err) ? fmax(0.2, 0.9 * pow(err, -0.2)) : 0.2);
+        r.after_reject = 1;
+        return 0;
+    }
+    double factor = err == 0.0 ? 10.0 : fmin(10.0, 0.9 * pow(err, -0.2));
+    if (r.after_reject) factor = fmin(1.0, factor);
+    r.after_reject = 0;
+
+    // Equatorial crossing (Sec. 3.3): the sign of theta - pi/2 changes.
+    const bool up0 = (r.y[2] - kHalfPi) >= 0.0;
+    const bool up1 = (yn[2] - kHalfPi) >= 0.0;
+    if (up0 != up1) {
+        const DenseComp dth = dense_comp(h, r.y[2], yn[2], r.k1[2], k3[2], k4[2], k5[2], k6[2], k7[2]);
+        double lo = 0.0, hi = 1.0;
+        for (int it = 0; it < 60; ++it) {
+            const double mid = 0.5 * (lo + hi);
+            if (((dth.at(mid) - kHalfPi) >= 0.0) == up0) lo = mid; else hi = mid;
+        }
+        const double s = 0.5 * (lo + hi);
+        const double Rc = dense_comp(h, r.y[1], yn[1], r.k1[1], k3[1], k4[1], k5[1], k6[1], k7[1]).at(s);
+        const double pthc = dense_comp(h, r.y[5], yn[5], r.k1[5], k3[5], k4[5], k5[5], k6[5], k7[5]).at(s);
+        const double lc = r.lam + s * h;
+        // trusted crossing (Sec. 4.2): |dtheta/dlambda| = |p_theta|/R^2 bounded away
+        // from zero and not a repeat within a tiny affine interval
+        if (fabs(pthc) >= 1e-12 * Rc * Rc && (lc - r.last_cross) >= 1e-10) {
+            const int n = r.ncross;
+            if (n < 3) {
+                const int64_t off = static_cast<int64_t>(n) * c.n_pix + r.pix;
+                if (o.r_em) o.r_em[off] = Rc;
+                if (o.phi_em)
+                    o.phi_em[off] = dense_comp(h, r.y[3], yn[3], r.k1[3], k3[3], k4[3], k5[3],
+                                               k6[3], k7[3]).at(s);
+                if (o.t_em)
+                    o.t_em[off] = dense_comp(h, r.y[0], yn[0], r.k1[0], k3[0], k4[0], k5[0],
+                                             k6[0], k7[0]).at(s);
+                if (c.emission) {
+                    const double g = redshift<METRIC>(c, Rc, r.E, r.L);
+                    const double In = disc_window(c, Rc) * g * g * g * pow(Rc, -c.emis_pow);
+                    r.intensity += In;
+                    if (o.g_em) o.g_em[off] = g;
+                    if (o.intensity_n) o.intensity_n[off] = In;
+                }
+            }
+            if (r.ncross < 255) ++r.ncross;
+            r.last_cross = lc;
+        }
+    }
+
+    for (int i = 0; i < 6; ++i) {
+        r.y[i] = yn[i];
+        r.k1[i] = k7[i];
+    }
+    r.lam += h;
+    r.h = h * factor;
+    if (r.y[1] <= c.r_stop) return RAY_CAPTURED;   // eq. (75)
+    if (r.y[1] >= c.r_esc) return RAY_ESCAPED;
+    return 0;
+}
+
+__device__ __forceinline__ void finish_ray(const ImageConst& c, const OutPtrs& o, const Ray& r,
+                                           int32_t status) {
+    const int64_t p = r.pix;
+    if (o.ncross) o.ncross[p] = static_cast<uint8_t>(r.ncross);
+    if (o.status) o.status[p] = static_cast<uint8_t>(status);
+    if (o.attempts) o.attempts[p] = r.attempts;
+    if (c.emission && o.intensity) o.intensity[p] = r.intensity;
+    const double nan = __builtin_nan("");
+    for (int n = r.ncross < 3 ? r.ncross : 3; n < 3; ++n) {
+        const int64_t off = static_cast<int64_t>(n) * c.n_pix + p;
+        if (o.r_em) o.r_em[off] = nan;
+        if (o.phi_em) o.phi_em[off] = nan;
+        if (o.t_em) o.t_em[off] = nan;
+        if (c.emission) {
+            if (o.g_em) o.g_em[off] = nan;
+            if (o.intensity_n) o.intensity_n[off] = nan;
+        }
+    }
+}
+
+// Persistent trace kernel for one image.
+template <int METRIC>
+__global__ __launch_bounds__(kBlock) void trace_kernel(ImageConst c, OutPtrs o,
+                                                       unsigned long long* queue, int32_t chunk) {
+    const int lane = __lane_id();
+    Ray r;
+    bool active = false;
+    // Wave-uniform chunk cursor: pixels [next, end) are claimed but not yet started.
+    int64_t next = 0, end = 0;
+    bool exhausted = false;
+    for (;;) {
+        // --- refill point: every lane of the wave is converged here
+        if (!exhausted) {
+            unsigned long long need = __ballot(!active);
+            while (need != 0ull) {
+                if (next >= end) {
+                    unsigned long long base = 0;
+                    if (lane == 0) base = atomicAdd(queue, static_cast<unsigned long long>(chunk));
+                    base = __shfl(base, 0);
+                    if (static_cast<int64_t>(base) >= c.n_pix) { exhausted = true; break; }
+                    next = static_cast<int64_t>(base);
+                    end = next + chunk < c.n_pix ? next + chunk : c.n_pix;
+                }
+                const int64_t avail = end - next;
+                const int nneed = __popcll(need);
+                const int take = avail < nneed ? static_cast<int>(avail) : nneed;
+                const int rank = __popcll(need & ((1ull << lane) - 1ull));
+                if (!active && rank < take) {
+                    start_ray<METRIC>(c, next + rank, r);
+                    active = true;
+                }
+                next += take;
+                need = __ballot(!active);
+            }
+        }
+        if (__ballot(active) == 0ull) break;
+        if (active) {
+            const int32_t st = attempt<METRIC>(c, o, r);
+            if (st != 0) {
+                finish_ray(c, o, r, st);
+                active = false;
+            }
+        }
+    }
+}
+
+__global__ void zero_counters(unsigned long long* q, int32_t n) {
+    const int32_t i = static_cast<int32_t>(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i < n) q[i] = 0ull;
+}
+
+}  // namespace
+
+hipError_t launch_zero(unsigned long long* queue, int32_t n, hipStream_t stream) {
+    hipLaunchKernelGGL(zero_counters, dim3((n + 255) / 256), dim3(256), 0, stream, queue, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_trace(const ImageConst& c, const OutPtrs& o, unsigned long long* queue,
+                        int32_t chunk, int32_t grid, hipStream_t stream) {
+    switch (c.metric) {
+        case KERR:
+            hipLaunchKernelGGL(trace_kernel<KERR>, dim3(grid), dim3(kBlock), 0, stream, c, o,
+                               queue, chunk);
+            break;
+        case EINASTO:
+            hipLaunchKernelGGL(trace_kernel<EINASTO>, dim3(grid), dim3(kBlock), 0, stream, c, o,
+                               queue, chunk);
+            break;
+        default:
+            hipLaunchKernelGGL(trace_kernel<CNFW>, dim3(grid), dim3(kBlock), 0, stream, c, o,
+                               queue, chunk);
+            break;
+    }
+    return hipGetLastError();
+}
+
+int max_blocks_per_cu(int metric) {
+    int n = 0;
+    hipError_t e;
+    if (metric == KERR)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, trace_kernel<KERR>, kBlock, 0);
+    else if (metric == EINASTO)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, trace_kernel<EINASTO>, kBlock, 0);
+    else
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, trace_kernel<CNFW>, kBlock, 0);
+    return (e == hipSuccess && n > 0) ? n : 1;
+}
+
+}  // namespace rt

@@ -1,0 +1,209 @@
+"""Python binding of the C ABI in include/rt.h (argument marshalling only).
+
+Every entry point of the library has a function of the same name here that
+takes ctypes structures (or workload dicts) and device tensors, and calls the
+shared library; the computation happens in the gfx950 kernels.  PyTorch is
+used only for device buffers and the current stream.
+
+If the shared library is missing this module raises ImportError: there is no
+fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libgeodesic_rt.so")
+
+RT_KERR, RT_EINASTO, RT_CNFW = 0, 1, 2
+RT_FP64 = 0
+RT_OK, RT_ERR_ARG, RT_ERR_NO_HORIZON, RT_ERR_HIP, RT_ERR_ALLOC = 0, -1, -2, -3, -4
+RT_RAY_CAPTURED, RT_RAY_ESCAPED, RT_RAY_STEP_LIMIT = 1, 2, 3
+METRIC_ID = {"kerr": RT_KERR, "einasto": RT_EINASTO, "cnfw": RT_CNFW}
+PRECISION_ID = {"fp64": RT_FP64}
+
+
+class rt_image_params(C.Structure):
+    _fields_ = [
+        ("metric", C.c_int32), ("precision", C.c_int32),
+        ("spin", C.c_double), ("halo", C.c_double * 2),
+        ("incl", C.c_double), ("r_obs", C.c_double),
+        ("nx", C.c_int32), ("ny", C.c_int32),
+        ("x_min", C.c_double), ("x_max", C.c_double),
+        ("y_min", C.c_double), ("y_max", C.c_double),
+        ("rtol", C.c_double), ("atol", C.c_double),
+        ("r_stop_fac", C.c_double), ("r_esc_fac", C.c_double),
+        ("r_in", C.c_double), ("r_out", C.c_double), ("emis_pow", C.c_double),
+        ("sigma_in", C.c_double), ("sigma_out", C.c_double), ("h0", C.c_double),
+        ("max_attempts", C.c_int32), ("reserved", C.c_int32),
+    ]
+
+
+class rt_image_out(C.Structure):
+    _fields_ = [
+        ("ncross", C.c_void_p), ("status", C.c_void_p),
+        ("r_em", C.c_void_p), ("phi_em", C.c_void_p), ("t_em", C.c_void_p),
+        ("g_em", C.c_void_p), ("intensity", C.c_void_p), ("intensity_n", C.c_void_p),
+        ("attempts", C.c_void_p), ("reduce", C.c_void_p),
+    ]
+
+
+class RTError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"rt error {code}: {msg}")
+        self.code = code
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is missing: build it with `python -m paper_2605_05635_amd.build` "
+            "(there is no non-GPU fallback)")
+    lib = C.CDLL(LIB_PATH)
+    P, O = C.POINTER(rt_image_params), C.POINTER(rt_image_out)
+    for name in ("rt_trace_image", "rt_transfer_maps"):
+        f = getattr(lib, name)
+        f.argtypes = [P, C.c_int32, O, C.c_void_p]
+        f.restype = C.c_int
+    lib.rt_image_setup.argtypes = [P, C.POINTER(C.c_double)]
+    lib.rt_image_setup.restype = C.c_int
+    lib.rt_set_kernel_timing.argtypes = [C.c_void_p, C.c_void_p]
+    lib.rt_set_kernel_timing.restype = C.c_int
+    lib.rt_last_error.argtypes = []
+    lib.rt_last_error.restype = C.c_char_p
+    lib.rt_version.argtypes = []
+    lib.rt_version.restype = C.c_int
+    return lib
+
+
+_lib = _load()
+
+
+def lib():
+    return _lib
+
+
+def _check(rc: int) -> None:
+    if rc != RT_OK:
+        raise RTError(rc, _lib.rt_last_error().decode())
+
+
+def params_from(img: dict) -> rt_image_params:
+    """rt_image_params of a workload dict (paper_2605_05635_amd.workloads)."""
+    p = rt_image_params()
+    p.metric = METRIC_ID[img["metric"]]
+    p.precision = PRECISION_ID[img.get("precision", "fp64")]
+    p.spin = img["spin"]
+    p.halo[0], p.halo[1] = img["halo"]
+    for k in ("incl", "r_obs", "x_min", "x_max", "y_min", "y_max", "rtol", "atol",
+              "r_stop_fac", "r_esc_fac", "r_in", "r_out", "emis_pow", "sigma_in",
+              "sigma_out", "h0"):
+        setattr(p, k, float(img[k]))
+    p.nx, p.ny = int(img["nx"]), int(img["ny"])
+    p.max_attempts = int(img["max_attempts"])
+    p.reserved = 0
+    return p
+
+
+def out_from(tensors: dict) -> rt_image_out:
+    o = rt_image_out()
+    for name, _ in rt_image_out._fields_:
+        t = tensors.get(name)
+        setattr(o, name, None if t is None else t.data_ptr())
+    return o
+
+
+def _stream_handle(stream):
+    """hipStream_t of `stream`: a torch stream, a raw handle (int), or None for
+    torch's current stream."""
+    if isinstance(stream, int):
+        return C.c_void_p(stream)
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _array(cls, items):
+    arr = (cls * len(items))()
+    for i, it in enumerate(items):
+        arr[i] = it
+    return arr
+
+
+def rt_trace_image(params: list, outs: list, stream=None) -> None:
+    """Calls rt_trace_image on lists of rt_image_params / rt_image_out."""
+    _check(_lib.rt_trace_image(_array(rt_image_params, params), len(params),
+                               _array(rt_image_out, outs), _stream_handle(stream)))
+
+
+def rt_transfer_maps(params: list, outs: list, stream=None) -> None:
+    _check(_lib.rt_transfer_maps(_array(rt_image_params, params), len(params),
+                                 _array(rt_image_out, outs), _stream_handle(stream)))
+
+
+def rt_image_setup(params: rt_image_params) -> dict:
+    buf = (C.c_double * 4)()
+    _check(_lib.rt_image_setup(C.byref(params), buf))
+    return dict(r_plus=buf[0], r_stop=buf[1], r_esc=buf[2], r_in=buf[3])
+
+
+def rt_set_kernel_timing(start_event, stop_event) -> None:
+    """Bracket the trace kernels of later calls on this thread with two
+    torch.cuda.Event objects (or raw hipEvent_t ints); None, None switches off."""
+    def h(ev):
+        if ev is None:
+            return None
+        return C.c_void_p(ev if isinstance(ev, int) else ev.cuda_event)
+    _check(_lib.rt_set_kernel_timing(h(start_event), h(stop_event)))
+
+
+def rt_version() -> int:
+    return _lib.rt_version()
+
+
+def rt_last_error() -> str:
+    return _lib.rt_last_error().decode()
+
+
+# --------------------------------------------------------------- conveniences
+def alloc_outputs(img: dict, device="cuda", emission: bool = True, reduce: bool = True) -> dict:
+    """Device tensors for every output of one image."""
+    import torch
+    ny, nx = int(img["ny"]), int(img["nx"])
+    d = dict(
+        ncross=torch.empty((ny, nx), dtype=torch.uint8, device=device),
+        status=torch.empty((ny, nx), dtype=torch.uint8, device=device),
+        r_em=torch.empty((3, ny, nx), dtype=torch.float64, device=device),
+        phi_em=torch.empty((3, ny, nx), dtype=torch.float64, device=device),
+        t_em=torch.empty((3, ny, nx), dtype=torch.float64, device=device),
+        attempts=torch.empty((ny, nx), dtype=torch.int32, device=device),
+    )
+    if emission:
+        d.update(g_em=torch.empty((3, ny, nx), dtype=torch.float64, device=device),
+                 intensity=torch.empty((ny, nx), dtype=torch.float64, device=device),
+                 intensity_n=torch.empty((3, ny, nx), dtype=torch.float64, device=device))
+        if reduce:
+            d["reduce"] = torch.empty(3, dtype=torch.float64, device=device)
+    return d
+
+
+def trace(img: dict, device="cuda", stream=None, emission: bool = True) -> dict:
+    """Trace one image (workload dict) and return its outputs as device tensors."""
+    outs = alloc_outputs(img, device, emission)
+    f = rt_trace_image if emission else rt_transfer_maps
+    f([params_from(img)], [out_from(outs)], stream)
+    return outs
+
+
+def trace_many(imgs: list, device="cuda", stream=None) -> list:
+    outs = [alloc_outputs(i, device) for i in imgs]
+    rt_trace_image([params_from(i) for i in imgs], [out_from(o) for o in outs], stream)
+    return outs
+
+
+__all__ = ["rt_trace_image", "rt_transfer_maps", "rt_image_setup", "rt_set_kernel_timing",
+           "rt_version",
+           "rt_last_error", "trace", "trace_many", "params_from", "out_from", "alloc_outputs",
+           "RTError"]

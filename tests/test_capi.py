@@ -1,0 +1,131 @@
+"""Host-side checks of the C ABI library (no GPU needed): it loads, exports every
+function include/rt.h declares, its structs match the header's layout, and
+invalid arguments are rejected before any device work."""
+import ctypes as C
+import math
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_2605_05635_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rt.h")
+
+
+@pytest.fixture(scope="module")
+def rt():
+    from paper_2605_05635_amd import rt as mod
+    return mod
+
+
+def declared_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(rt_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_every_declared_symbol_is_exported(rt):
+    names = declared_functions()
+    assert {"rt_trace_image", "rt_transfer_maps", "rt_last_error", "rt_version"} <= set(names)
+    lib = C.CDLL(rt.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), n
+    out = subprocess.run(["nm", "-D", "--defined-only", rt.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (rt_[a-z0-9_]+)\b", out))
+    assert set(names) <= exported
+
+
+def test_version(rt):
+    m = re.search(r"#define RT_VERSION (\d+)", open(HEADER).read())
+    assert rt.rt_version() == int(m.group(1))
+
+
+def test_struct_layout_matches_header(rt, tmp_path):
+    """ctypes mirrors of rt_image_params / rt_image_out have the C layout."""
+    fields_p = [f for f, _ in rt.rt_image_params._fields_]
+    fields_o = [f for f, _ in rt.rt_image_out._fields_]
+    src = ['#include <stdio.h>', '#include <stddef.h>', '#include "rt.h"', "int main(void){",
+           'printf("%zu\\n", sizeof(rt_image_params));',
+           'printf("%zu\\n", sizeof(rt_image_out));']
+    src += [f'printf("%zu\\n", offsetof(rt_image_params, {f}));' for f in fields_p]
+    src += [f'printf("%zu\\n", offsetof(rt_image_out, {f}));' for f in fields_o]
+    src += ["return 0;}"]
+    c = tmp_path / "layout.c"
+    c.write_text("\n".join(src))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(c), "-o", str(exe)],
+                   check=True)
+    vals = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True,
+                                           check=True).stdout.split()]
+    assert vals[0] == C.sizeof(rt.rt_image_params)
+    assert vals[1] == C.sizeof(rt.rt_image_out)
+    offs_p = [getattr(rt.rt_image_params, f).offset for f in fields_p]
+    offs_o = [getattr(rt.rt_image_out, f).offset for f in fields_o]
+    assert vals[2:] == offs_p + offs_o
+
+
+def _err(rt, img_or_params, n=None, outs=None):
+    p = img_or_params if isinstance(img_or_params, rt.rt_image_params) else rt.params_from(img_or_params)
+    with pytest.raises(rt.RTError) as e:
+        rt.rt_trace_image([p] if n is None else [p] * n, outs or [rt.rt_image_out()], 0)
+    return e.value.code
+
+
+@pytest.mark.parametrize("change", [
+    dict(incl=0.0), dict(incl=math.pi), dict(spin=float("nan")), dict(nx=0), dict(ny=-3),
+    dict(rtol=0.0), dict(atol=-1.0), dict(h0=0.0), dict(r_stop_fac=1.0), dict(r_esc_fac=0.5),
+    dict(max_attempts=0), dict(x_min=1.0, x_max=1.0), dict(r_obs=15.0),
+    dict(metric="einasto", halo=(0.0, 0.0)), dict(metric="cnfw", halo=(0.02, 0.0)),
+    dict(metric="cnfw", halo=(-0.1, 10.0)), dict(r_in=25.0),
+])
+def test_invalid_arguments_rejected(rt, change):
+    assert _err(rt, W.image(**change)) == rt.RT_ERR_ARG
+    assert rt.rt_last_error()
+
+
+def test_bad_enum_and_reserved_fields(rt):
+    for field, value in (("metric", 7), ("precision", 5), ("reserved", 1)):
+        p = rt.params_from(W.kerr_small())
+        setattr(p, field, value)
+        assert _err(rt, p) == rt.RT_ERR_ARG
+
+
+def test_null_pointers_and_counts(rt):
+    lib = rt.lib()
+    p = rt.params_from(W.kerr_small())
+    o = rt.rt_image_out()
+    assert lib.rt_trace_image(None, 1, C.byref(o), None) == rt.RT_ERR_ARG
+    assert lib.rt_trace_image(C.byref(p), 1, None, None) == rt.RT_ERR_ARG
+    assert lib.rt_trace_image(C.byref(p), 0, C.byref(o), None) == rt.RT_ERR_ARG
+    assert lib.rt_transfer_maps(C.byref(p), -1, C.byref(o), None) == rt.RT_ERR_ARG
+    assert lib.rt_image_setup(C.byref(p), None) == rt.RT_ERR_ARG
+
+
+def test_no_horizon_beyond_extremal_spin(rt):
+    """Einasto lambda_E = 0.3 has extremal spin 0.640 (Sec. 2.2, Fig. 2)."""
+    assert _err(rt, W.image(metric="einasto", halo=(0.3, 0.0), spin=0.65)) == rt.RT_ERR_NO_HORIZON
+    assert _err(rt, W.image(metric="kerr", spin=1.01)) == rt.RT_ERR_NO_HORIZON
+    assert _err(rt, W.image(metric="einasto", halo=(0.5, 0.0), spin=0.0)) == rt.RT_ERR_NO_HORIZON
+    # a batch fails as a whole when any image has no horizon
+    good, bad = rt.params_from(W.kerr_small()), rt.params_from(W.image(spin=1.2))
+    with pytest.raises(rt.RTError) as e:
+        rt.rt_trace_image([good, bad], [rt.rt_image_out()] * 2, 0)
+    assert e.value.code == rt.RT_ERR_NO_HORIZON and "image 1" in str(e.value)
+
+
+def test_image_setup_matches_oracle(rt, orc):
+    """The library's host setup finds the same outer horizon as the oracle."""
+    cases = [(W.kerr_small(), 1e-14), (W.einasto_512(), 1e-14), (W.cnfw_1024(), 1e-14),
+             (W.cnfw_adjoint_256(), 1e-14)] + [(b, 1e-14) for b in W.batch_64()[:12]]
+    # 1e-4 below the extremal spin Delta is nearly a double root, and rounding
+    # noise in Delta moves its zero by ~sqrt(eps) relative
+    cases.append((W.image(metric="einasto", halo=(0.3, 0.0), spin=0.6395), 1e-7))
+    for img, tol in cases:
+        mine = rt.rt_image_setup(rt.params_from(img))
+        ref = orc.image_setup(img)
+        for k in ("r_plus", "r_stop", "r_esc", "r_in"):
+            assert mine[k] == pytest.approx(ref[k], rel=tol, abs=0), (img["metric"], k)
