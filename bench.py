@@ -101,6 +101,8 @@ def main() -> int:
 
     starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
     stops = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    for ev in starts + stops:      # torch creates the hipEvent_t at its first record
+        ev.record(stream)
     log(f"timing {args.steps} steps")
     torch.cuda.synchronize()
     t0 = time.perf_counter()

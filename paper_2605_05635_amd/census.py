@@ -61,7 +61,7 @@ def mass_function(metric: str, c: dict, R):
         return 2.0 * R * mu, 2.0 * (mu + R * dmu)
     iR = 1.0 / R
     iRl = 1.0 / (R + c["lam_c"])
-    lg = f("log1p", R / c["lam_c"])
+    lg = f("log1p", R * c["inv_lam_c"])
     ex = c["eta_lc"] * (iRl - 2.0 * iR * lg)
     dex = c["eta_lc"] * (2.0 * iR * (iR * lg - iRl) - iRl * iRl)
     em1 = f("expm1", ex)
@@ -97,7 +97,7 @@ def rhs(metric: str, c: dict, E, L, R, th, pR, pth):
 
 
 def _consts(metric, chi=0.5, halo=(0.1, 10.0)):
-    return dict(chi=chi, chi2=chi * chi, inv_lam=1.0 / halo[0], lam_c=halo[1],
+    return dict(chi=chi, chi2=chi * chi, inv_lam=1.0 / halo[0], lam_c=halo[1], inv_lam_c=1.0 / halo[1],
                 eta_lc=halo[0] * halo[1])
 
 

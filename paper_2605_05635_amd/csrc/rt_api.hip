@@ -138,6 +138,7 @@ int setup_image(const rt_image_params* p, int index, bool emission, rt::ImageCon
     if (p->metric == RT_EINASTO) c->inv_lam = 1.0 / p->halo[0];
     if (p->metric == RT_CNFW) {
         c->lam_c = p->halo[1];
+        c->inv_lam_c = 1.0 / p->halo[1];
         c->eta_lc = p->halo[0] * p->halo[1];
     }
     double r_plus = 0.0;

@@ -10,6 +10,8 @@
 #include <cmath>
 #include <cstdint>
 
+#include "rt_math.h"
+
 namespace rt {
 
 enum : int32_t { KERR = 0, EINASTO = 1, CNFW = 2 };
@@ -27,6 +29,7 @@ struct ImageConst {
     double chi, chi2;
     double inv_lam;      // Einasto: 1/lambda_E
     double lam_c;        // cored NFW: lambda_c
+    double inv_lam_c;    // cored NFW: 1/lambda_c
     double eta_lc;       // cored NFW: eta * lambda_c
     // observer (Sec. 3.2): ZAMO normalisation and tetrad scale factors at (R_o, theta_o)
     double r_obs, incl;
@@ -56,7 +59,7 @@ __host__ __device__ inline void mass_function(const ImageConst& c, double R, dou
         dF = 2.0;
     } else if constexpr (METRIC == EINASTO) {
         const double x = R * c.inv_lam;
-        const double e = exp(-x);
+        const double e = dm::exp(-x);
         const double mu = 1.0 - e * (1.0 + x * (1.0 + 0.5 * x));
         const double dmu = 0.5 * e * x * x * c.inv_lam;
         F = 2.0 * R * mu;
@@ -64,10 +67,10 @@ __host__ __device__ inline void mass_function(const ImageConst& c, double R, dou
     } else {
         const double iR = 1.0 / R;
         const double iRl = 1.0 / (R + c.lam_c);
-        const double lg = log1p(R / c.lam_c);
+        const double lg = dm::log1p(R * c.inv_lam_c);
         const double ex = c.eta_lc * (iRl - 2.0 * iR * lg);
         const double dex = c.eta_lc * (2.0 * iR * (iR * lg - iRl) - iRl * iRl);
-        const double em1 = expm1(ex);
+        const double em1 = dm::expm1(ex);
         F = R * (2.0 - R * em1);
         dF = 2.0 - R * (2.0 * em1 + R * (em1 + 1.0) * dex);
     }

@@ -14,11 +14,23 @@
 // compaction of terminated rays).
 #include "rt_device.h"
 #include "rt_kernels.h"
+#include "rt_math.h"
 
 namespace rt {
 namespace {
 
 constexpr double kHalfPi = 1.5707963267948966;
+
+// Reciprocal: the hardware estimate refined by two Newton-Raphson steps (each
+// squares the relative error), about one ulp for the finite, non-zero normal
+// arguments that occur here; cheaper than the IEEE division sequence.
+__device__ __forceinline__ double rcp(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
 
 // ---------------------------------------------------------------- the RHS
 // Hamilton's equations for H = g^{ab} p_a p_b / 2 with p_T = -E, p_phi = l.
@@ -39,7 +51,7 @@ template <int METRIC>
 __device__ __forceinline__ void rhs(const ImageConst& c, double E, double L, double R, double th,
                                     double pR, double pth, double d[6]) {
     double s, co;
-    sincos(th, &s, &co);
+    dm::sincos(th, &s, &co);
     double F, dF;
     mass_function<METRIC>(c, R, F, dF);
     const double R2 = R * R;
@@ -47,9 +59,9 @@ __device__ __forceinline__ void rhs(const ImageConst& c, double E, double L, dou
     const double Sig = R2 + c.chi2 * co * co;
     const double Del = R2c - F;
     const double dDel = 2.0 * R - dF;
-    const double iS = 1.0 / Sig;
-    const double iD = 1.0 / Del;
-    const double is = 1.0 / s;
+    const double iS = rcp(Sig);
+    const double iD = rcp(Del);
+    const double is = rcp(s);
     const double P = R2c * E - c.chi * L;
     const double PiD = P * iD;
     const double Lis2 = L * is * is;
@@ -92,17 +104,6 @@ struct DenseComp {
     }
 };
 
-__device__ __forceinline__ DenseComp dense_comp(double h, double y0, double y1, double k1,
-                                                double k3, double k4, double k5, double k6,
-                                                double k7) {
-    DenseComp o;
-    o.y0 = y0;
-    o.r2 = y1 - y0;
-    o.r3 = h * k1 - o.r2;
-    o.r4 = o.r2 - h * k7 - o.r3;
-    o.r5 = h * (d1 * k1 + d3 * k3 + d4 * k4 + d5 * k5 + d6 * k6 + d7 * k7);
-    return o;
-}
 
 // ------------------------------------------------------------ emission
 // Keplerian equatorial emitter (eqs. (90)-(91)) and redshift (eq. (89)) for a
@@ -145,7 +146,8 @@ struct Ray {
     double y[6];    // T, R, theta, phi, p_R, p_theta
     double k1[6];   // f(y), first-same-as-last
     double E, L;
-    double h, lam, last_cross, intensity;
+    double h, lam, last_cross;
+    double rc[3];   // radii of the first three trusted crossings
     int32_t attempts, ncross;
     int32_t after_reject;
     int64_t pix;
@@ -176,47 +178,98 @@ __device__ __forceinline__ void start_ray(const ImageConst& c, int64_t pix, Ray&
     r.h = c.h0;
     r.lam = 0.0;
     r.last_cross = -INFINITY;
-    r.intensity = 0.0;
     r.attempts = 0;
     r.ncross = 0;
     r.after_reject = 0;
     r.pix = pix;
 }
 
+// Root of theta(s) = pi/2 on the step's continuous extension, s in (0, 1),
+// given theta(0) and theta(1) on opposite sides.  Writing the extension as
+// y0 + s (c1 + s (c2 + s (c3 + s c4))), Newton's method starts from the secant
+// root and is kept inside the shrinking sign bracket (bisection when a Newton
+// step would leave it); it stops when the step falls below 1e-15 or the
+// bracket is exhausted.
+__device__ __forceinline__ double crossing_root(const DenseComp& d, bool up0) {
+    const double c1 = d.r2 + d.r3;
+    const double c2 = d.r4 + d.r5 - d.r3;
+    const double c3 = -d.r4 - 2.0 * d.r5;
+    const double c4 = d.r5;
+    double a = 0.0, b = 1.0;
+    double s = (kHalfPi - d.y0) / d.r2;
+    if (!(s > 0.0 && s < 1.0)) s = 0.5;
+    for (int it = 0; it < 48; ++it) {
+        const double f = d.y0 + s * (c1 + s * (c2 + s * (c3 + s * c4))) - kHalfPi;
+        if ((f >= 0.0) == up0) a = s; else b = s;
+        const double df = c1 + s * (2.0 * c2 + s * (3.0 * c3 + s * 4.0 * c4));
+        double sn = s - f / df;
+        if (!(sn > a && sn < b)) sn = 0.5 * (a + b);
+        const double step = fabs(sn - s);
+        s = sn;
+        if (step <= 1e-15 || b - a <= 1e-15) break;
+    }
+    return s;
+}
+
 // One step attempt.  Returns 0 while the ray runs, else its final status.
+// The 5th-order update, the error estimate and the continuous-extension
+// coefficient r5 are accumulated as the stages are produced, so a stage
+// derivative stays live only while later stage inputs still need it.
 template <int METRIC>
 __device__ __forceinline__ int32_t attempt(const ImageConst& c, const OutPtrs& o, Ray& r) {
     if (r.attempts >= c.max_attempts) return RAY_STEP_LIMIT;
     ++r.attempts;
     const double h = r.h;
-    double k2[6], k3[6], k4[6], k5[6], k6[6], k7[6], t[6], yn[6];
+    double ab[6], ae[6], ad[6];     // sums of b_i k_i, e_i k_i, d_i k_i
+    double k2[6], k3[6], k4[6], k5[6], kk[6], t[6];
+    for (int i = 0; i < 6; ++i) {
+        ab[i] = b1 * r.k1[i];
+        ae[i] = e1 * r.k1[i];
+        ad[i] = d1 * r.k1[i];
+    }
 #define RT_STAGE(expr, out)                                                      \
     for (int i = 0; i < 6; ++i) t[i] = r.y[i] + h * (expr);                       \
     rhs<METRIC>(c, r.E, r.L, t[1], t[2], t[4], t[5], out);
+#define RT_ACC(bb, ee, dd, kv)                                                   \
+    for (int i = 0; i < 6; ++i) {                                                \
+        ab[i] += bb * kv[i];                                                     \
+        ae[i] += ee * kv[i];                                                     \
+        ad[i] += dd * kv[i];                                                     \
+    }
     RT_STAGE(a21 * r.k1[i], k2)
     RT_STAGE(a31 * r.k1[i] + a32 * k2[i], k3)
+    RT_ACC(b3, e3, d3, k3)
     RT_STAGE(a41 * r.k1[i] + a42 * k2[i] + a43 * k3[i], k4)
+    RT_ACC(b4, e4, d4, k4)
     RT_STAGE(a51 * r.k1[i] + a52 * k2[i] + a53 * k3[i] + a54 * k4[i], k5)
-    RT_STAGE(a61 * r.k1[i] + a62 * k2[i] + a63 * k3[i] + a64 * k4[i] + a65 * k5[i], k6)
+    RT_ACC(b5, e5, d5, k5)
+    RT_STAGE(a61 * r.k1[i] + a62 * k2[i] + a63 * k3[i] + a64 * k4[i] + a65 * k5[i], kk)
+    RT_ACC(b6, e6, d6, kk)
 #undef RT_STAGE
-    for (int i = 0; i < 6; ++i)
-        yn[i] = r.y[i] + h * (b1 * r.k1[i] + b3 * k3[i] + b4 * k4[i] + b5 * k5[i] + b6 * k6[i]);
-    rhs<METRIC>(c, r.E, r.L, yn[1], yn[2], yn[4], yn[5], k7);
+#undef RT_ACC
+    double yn[6];
+    for (int i = 0; i < 6; ++i) yn[i] = r.y[i] + h * ab[i];
+    rhs<METRIC>(c, r.E, r.L, yn[1], yn[2], yn[4], yn[5], kk);   // k7 (first-same-as-last)
     double acc = 0.0;
     for (int i = 0; i < 6; ++i) {
-        const double ei = h * (e1 * r.k1[i] + e3 * k3[i] + e4 * k4[i] + e5 * k5[i] + e6 * k6[i]
-                               + e7 * k7[i]);
+        ae[i] += e7 * kk[i];
+        ad[i] += d7 * kk[i];
         const double sc = c.atol + c.rtol * fmax(fabs(r.y[i]), fabs(yn[i]));
-        const double q = ei / sc;
+        const double q = h * ae[i] / sc;
         acc += q * q;
     }
-    const double err = sqrt(acc * (1.0 / 6.0));
-    if (!(err < 1.0)) {  // reject; NaN lands here too
-        r.h = h * (isfinite(err) ? fmax(0.2, 0.9 * pow(err, -0.2)) : 0.2);
+    // err^2 = mean of the squared scaled errors; the step is accepted when
+    // err < 1 and the size factor is 0.9 err^(-1/5) = 0.9 (err^2)^(-1/10),
+    // clipped to [0.2, 10] (err = 0 gives the maximum, a non-finite err the
+    // minimum).  Outside err^2 in [1e-12, 1e12] the clip decides the factor.
+    const double err2 = acc * (1.0 / 6.0);
+    const double grow = 0.9 * dm::rpow_tenth(fmin(fmax(err2, 1e-12), 1e12));
+    if (!(err2 < 1.0)) {  // reject; NaN lands here too
+        r.h = h * (isfinite(err2) ? fmax(0.2, grow) : 0.2);
         r.after_reject = 1;
         return 0;
     }
-    double factor = err == 0.0 ? 10.0 : fmin(10.0, 0.9 * pow(err, -0.2));
+    double factor = err2 == 0.0 ? 10.0 : fmin(10.0, grow);
     if (r.after_reject) factor = fmin(1.0, factor);
     r.after_reject = 0;
 
@@ -224,15 +277,18 @@ __device__ __forceinline__ int32_t attempt(const ImageConst& c, const OutPtrs& o
     const bool up0 = (r.y[2] - kHalfPi) >= 0.0;
     const bool up1 = (yn[2] - kHalfPi) >= 0.0;
     if (up0 != up1) {
-        const DenseComp dth = dense_comp(h, r.y[2], yn[2], r.k1[2], k3[2], k4[2], k5[2], k6[2], k7[2]);
-        double lo = 0.0, hi = 1.0;
-        for (int it = 0; it < 60; ++it) {
-            const double mid = 0.5 * (lo + hi);
-            if (((dth.at(mid) - kHalfPi) >= 0.0) == up0) lo = mid; else hi = mid;
-        }
-        const double s = 0.5 * (lo + hi);
-        const double Rc = dense_comp(h, r.y[1], yn[1], r.k1[1], k3[1], k4[1], k5[1], k6[1], k7[1]).at(s);
-        const double pthc = dense_comp(h, r.y[5], yn[5], r.k1[5], k3[5], k4[5], k5[5], k6[5], k7[5]).at(s);
+        auto dense = [&](int i) {
+            DenseComp d;
+            d.y0 = r.y[i];
+            d.r2 = yn[i] - r.y[i];
+            d.r3 = h * r.k1[i] - d.r2;
+            d.r4 = d.r2 - h * kk[i] - d.r3;
+            d.r5 = h * ad[i];
+            return d;
+        };
+        const double s = crossing_root(dense(2), up0);
+        const double Rc = dense(1).at(s);
+        const double pthc = dense(5).at(s);
         const double lc = r.lam + s * h;
         // trusted crossing (Sec. 4.2): |dtheta/dlambda| = |p_theta|/R^2 bounded away
         // from zero and not a repeat within a tiny affine interval
@@ -240,20 +296,13 @@ __device__ __forceinline__ int32_t attempt(const ImageConst& c, const OutPtrs& o
             const int n = r.ncross;
             if (n < 3) {
                 const int64_t off = static_cast<int64_t>(n) * c.n_pix + r.pix;
+                // (selects, not r.rc[n]: a runtime index would put the ray in scratch)
+                r.rc[0] = n == 0 ? Rc : r.rc[0];
+                r.rc[1] = n == 1 ? Rc : r.rc[1];
+                r.rc[2] = n == 2 ? Rc : r.rc[2];
                 if (o.r_em) o.r_em[off] = Rc;
-                if (o.phi_em)
-                    o.phi_em[off] = dense_comp(h, r.y[3], yn[3], r.k1[3], k3[3], k4[3], k5[3],
-                                               k6[3], k7[3]).at(s);
-                if (o.t_em)
-                    o.t_em[off] = dense_comp(h, r.y[0], yn[0], r.k1[0], k3[0], k4[0], k5[0],
-                                             k6[0], k7[0]).at(s);
-                if (c.emission) {
-                    const double g = redshift<METRIC>(c, Rc, r.E, r.L);
-                    const double In = disc_window(c, Rc) * g * g * g * pow(Rc, -c.emis_pow);
-                    r.intensity += In;
-                    if (o.g_em) o.g_em[off] = g;
-                    if (o.intensity_n) o.intensity_n[off] = In;
-                }
+                if (o.phi_em) o.phi_em[off] = dense(3).at(s);
+                if (o.t_em) o.t_em[off] = dense(0).at(s);
             }
             if (r.ncross < 255) ++r.ncross;
             r.last_cross = lc;
@@ -262,7 +311,7 @@ __device__ __forceinline__ int32_t attempt(const ImageConst& c, const OutPtrs& o
 
     for (int i = 0; i < 6; ++i) {
         r.y[i] = yn[i];
-        r.k1[i] = k7[i];
+        r.k1[i] = kk[i];
     }
     r.lam += h;
     r.h = h * factor;
@@ -271,29 +320,45 @@ __device__ __forceinline__ int32_t attempt(const ImageConst& c, const OutPtrs& o
     return 0;
 }
 
+// Ray epilogue: emission of the recorded crossings (Sec. 5.2, evaluated once
+// per ray rather than inside the step loop), then the per-pixel outputs.
+// Records n >= min(N_cross, 3) are NaN.
+template <int METRIC>
 __device__ __forceinline__ void finish_ray(const ImageConst& c, const OutPtrs& o, const Ray& r,
                                            int32_t status) {
     const int64_t p = r.pix;
+    const int nrec = r.ncross < 3 ? r.ncross : 3;
+    const double nan = __builtin_nan("");
+    if (c.emission) {
+        double intensity = 0.0;
+        for (int n = 0; n < 3; ++n) {
+            const int64_t off = static_cast<int64_t>(n) * c.n_pix + p;
+            double g = nan, In = nan;
+            if (n < nrec) {
+                const double R = r.rc[n];
+                g = redshift<METRIC>(c, R, r.E, r.L);
+                In = disc_window(c, R) * g * g * g * pow(R, -c.emis_pow);
+                intensity += In;
+            }
+            if (o.g_em) o.g_em[off] = g;
+            if (o.intensity_n) o.intensity_n[off] = In;
+        }
+        if (o.intensity) o.intensity[p] = intensity;
+    }
     if (o.ncross) o.ncross[p] = static_cast<uint8_t>(r.ncross);
     if (o.status) o.status[p] = static_cast<uint8_t>(status);
     if (o.attempts) o.attempts[p] = r.attempts;
-    if (c.emission && o.intensity) o.intensity[p] = r.intensity;
-    const double nan = __builtin_nan("");
-    for (int n = r.ncross < 3 ? r.ncross : 3; n < 3; ++n) {
+    for (int n = nrec; n < 3; ++n) {
         const int64_t off = static_cast<int64_t>(n) * c.n_pix + p;
         if (o.r_em) o.r_em[off] = nan;
         if (o.phi_em) o.phi_em[off] = nan;
         if (o.t_em) o.t_em[off] = nan;
-        if (c.emission) {
-            if (o.g_em) o.g_em[off] = nan;
-            if (o.intensity_n) o.intensity_n[off] = nan;
-        }
     }
 }
 
 // Persistent trace kernel for one image.
 template <int METRIC>
-__global__ __launch_bounds__(kBlock) void trace_kernel(ImageConst c, OutPtrs o,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 8))) void trace_kernel(ImageConst c, OutPtrs o,
                                                        unsigned long long* queue, int32_t chunk) {
     const int lane = __lane_id();
     Ray r;
@@ -330,7 +395,7 @@ __global__ __launch_bounds__(kBlock) void trace_kernel(ImageConst c, OutPtrs o,
         if (active) {
             const int32_t st = attempt<METRIC>(c, o, r);
             if (st != 0) {
-                finish_ray(c, o, r, st);
+                finish_ray<METRIC>(c, o, r, st);
                 active = false;
             }
         }

@@ -1,0 +1,37 @@
+// Host driver for tests/test_devmath.py: evaluates the trace kernels' compact
+// elementary functions (paper_2605_05635_amd/csrc/rt_math.h, compiled for the
+// host) on the doubles read from stdin and writes the results to stdout.
+//   usage: devmath_driver <function>   (sincos | exp | expm1 | log1p | rpow_tenth)
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "rt_math.h"
+
+int main(int argc, char** argv) {
+    if (argc != 2) return 2;
+    std::vector<double> x;
+    double v;
+    while (std::fread(&v, sizeof v, 1, stdin) == 1) x.push_back(v);
+    std::vector<double> out;
+    for (double a : x) {
+        if (!std::strcmp(argv[1], "sincos")) {
+            double s, c;
+            rt::dm::sincos(a, &s, &c);
+            out.push_back(s);
+            out.push_back(c);
+        } else if (!std::strcmp(argv[1], "exp")) {
+            out.push_back(rt::dm::exp(a));
+        } else if (!std::strcmp(argv[1], "expm1")) {
+            out.push_back(rt::dm::expm1(a));
+        } else if (!std::strcmp(argv[1], "log1p")) {
+            out.push_back(rt::dm::log1p(a));
+        } else if (!std::strcmp(argv[1], "rpow_tenth")) {
+            out.push_back(rt::dm::rpow_tenth(a));
+        } else {
+            return 3;
+        }
+    }
+    std::fwrite(out.data(), sizeof(double), out.size(), stdout);
+    return 0;
+}

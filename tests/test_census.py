@@ -13,6 +13,7 @@ from paper_2605_05635_amd import workloads as W
 def test_census_formulas_match_oracle_rhs(orc, metric, halo):
     img = W.image(metric=metric, spin=0.7, halo=halo)
     c = dict(chi=0.7, chi2=0.49, inv_lam=1 / halo[0] if halo[0] else 0.0, lam_c=halo[1] or 1.0,
+             inv_lam_c=1 / (halo[1] or 1.0),
              eta_lc=halo[0] * halo[1])
     rng = np.random.default_rng(2)
     for _ in range(20):

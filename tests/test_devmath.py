@@ -1,0 +1,95 @@
+"""Accuracy of the trace kernels' compact elementary functions (rt_math.h),
+compiled for the host from the same source, against mpmath at 40 digits.
+
+Measured in units in the last place (ulp) of the exact result, over the
+argument ranges the trace uses: theta in (-2 pi, 3 pi), exp of R/lambda_E
+arguments down to underflow, expm1 of the cored-NFW exponent, log1p of
+R/lambda_c, and the step controller's x^(-1/10)."""
+import os
+import subprocess
+
+import mpmath as mp
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "tests", "devmath", "devmath_driver.cpp")
+INC = os.path.join(ROOT, "paper_2605_05635_amd", "csrc")
+mp.mp.dps = 40
+
+
+@pytest.fixture(scope="module")
+def driver(tmp_path_factory):
+    exe = str(tmp_path_factory.mktemp("devmath") / "devmath_driver")
+    subprocess.run(["/opt/rocm/bin/hipcc", "-O2", "-std=c++17", "-I", INC, SRC, "-o", exe],
+                   check=True, capture_output=True)
+    return exe
+
+
+def run(exe, fn, x):
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    out = subprocess.run([exe, fn], input=x.tobytes(), capture_output=True, check=True).stdout
+    return np.frombuffer(out, dtype=np.float64)
+
+
+def ulp_err(got, exact):
+    exact_f = np.array([float(e) for e in exact])
+    ulp = np.spacing(np.abs(exact_f))
+    ulp[ulp == 0] = np.spacing(0.0)
+    d = np.array([float(abs(mp.mpf(g) - e)) for g, e in zip(got, exact)])
+    return d / ulp
+
+
+def test_sincos(driver):
+    rng = np.random.default_rng(0)
+    x = np.concatenate([rng.uniform(-2 * np.pi, 3 * np.pi, 3000),
+                        np.pi / 2 * np.arange(-4, 7) + 1e-13, [0.0, 1e-300, 3.1e5]])
+    out = run(driver, "sincos", x).reshape(-1, 2)
+    es = [mp.sin(mp.mpf(v)) for v in x]
+    ec = [mp.cos(mp.mpf(v)) for v in x]
+    # absolute error relative to 1 (the magnitude of sin and cos)
+    ds = np.array([float(abs(mp.mpf(g) - e)) for g, e in zip(out[:, 0], es)])
+    dc = np.array([float(abs(mp.mpf(g) - e)) for g, e in zip(out[:, 1], ec)])
+    assert ds.max() < 2.5e-16 and dc.max() < 2.5e-16
+    # relative accuracy away from the zeros
+    big = np.abs(np.array([float(e) for e in es])) > 1e-3
+    assert ulp_err(out[big, 0], [e for e, b in zip(es, big) if b]).max() < 4
+
+
+def test_exp(driver):
+    rng = np.random.default_rng(1)
+    x = np.concatenate([rng.uniform(-740, 700, 2000), rng.uniform(-1, 1, 1000),
+                        [0.0, -744.0, -800.0, -1e5, 709.0]])
+    out = run(driver, "exp", x)
+    ex = [mp.exp(mp.mpf(v)) for v in x]
+    normal = np.array([float(e) for e in ex]) > 2.3e-308
+    assert ulp_err(out[normal], [e for e, n in zip(ex, normal) if n]).max() < 3
+    assert out[x <= -800].max() == 0.0
+
+
+def test_expm1(driver):
+    rng = np.random.default_rng(2)
+    x = np.concatenate([rng.uniform(-0.6, 0.2, 3000), 10.0 ** rng.uniform(-20, -1, 500),
+                        -(10.0 ** rng.uniform(-20, -1, 500)), [0.0, 0.3465, -0.3466, 2.0]])
+    out = run(driver, "expm1", x)
+    ex = [mp.expm1(mp.mpf(v)) for v in x]
+    nz = x != 0
+    assert ulp_err(out[nz], [e for e, n in zip(ex, nz) if n]).max() < 4
+    assert out[x == 0][0] == 0.0
+
+
+def test_log1p(driver):
+    rng = np.random.default_rng(3)
+    x = np.concatenate([10.0 ** rng.uniform(-3, 3.5, 3000), rng.uniform(-0.5, 0.5, 500),
+                        [1e-17, 1.0, 3.0, 1e5]])
+    out = run(driver, "log1p", x)
+    ex = [mp.log1p(mp.mpf(v)) for v in x]
+    assert ulp_err(out, ex).max() < 4
+
+
+def test_rpow_tenth(driver):
+    rng = np.random.default_rng(4)
+    x = np.concatenate([10.0 ** rng.uniform(-12, 12, 3000), [1.0, 6.0, 1e-12, 1e12]])
+    out = run(driver, "rpow_tenth", x)
+    ex = [mp.power(mp.mpf(v), mp.mpf(-1) / 10) for v in x]
+    assert ulp_err(out, ex).max() < 3
