@@ -73,7 +73,10 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-stride", type=int, default=2)
+    ap.add_argument("--cpu-stride", type=int, default=1)
+    ap.add_argument("--calibration-copy-mib", type=int, default=0,
+                    help="after the timed steps, run one plain device-to-device copy of this "
+                         "many MiB (the reference kernel for HBM byte counters) and report it")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -144,6 +147,15 @@ def main() -> int:
         "attempts_per_ray": attempts / n_rays,
         "roofline": roofline,
     }
+    if args.calibration_copy_mib > 0:
+        nbytes = args.calibration_copy_mib << 20
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        line["calibration_copy_bytes"] = nbytes
+        log(f"calibration copy: {nbytes} bytes read and {nbytes} bytes written")
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(img, args.cpu_stride)
     print(json.dumps(line), flush=True)

@@ -21,11 +21,18 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # never forms them from scalar float code with this feature turned off.
 DEVICE_FLAGS = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang",
                 "-packed-fp32-ops"]
+# The trace kernels use ~100 distinct binary64 constants (integrator tableau,
+# series coefficients).  Machine-level loop-invariant code motion hoists all
+# of their materialisations out of the persistent ray loop, which overflows
+# the scalar registers and spills them to vector-register lanes (one VALU
+# read per use inside the loop).  Without that pass the constants are
+# rematerialised by scalar moves next to their uses.
+CODEGEN_FLAGS = ["-mllvm", "-disable-machine-licm"]
 
 
 def build(verbose: bool = False, extra: list[str] | None = None) -> str:
     srcs = sorted(glob.glob(os.path.join(PKG, "csrc", "*.hip")))
-    cmd = [HIPCC, *DEVICE_FLAGS, "-O3", "-std=c++17", "-fPIC", "-shared", "-Wall",
+    cmd = [HIPCC, *DEVICE_FLAGS, *CODEGEN_FLAGS, "-O3", "-std=c++17", "-fPIC", "-shared", "-Wall",
            "-I", os.path.join(ROOT, "include"), "-I", os.path.join(PKG, "csrc"),
            *(extra or []), "-o", LIB + ".tmp", *srcs]
     if verbose:

@@ -255,16 +255,24 @@ int trace_common(const rt_image_params* params, int32_t n_images, const rt_image
             return rc;
     }
     hipStream_t stream = static_cast<hipStream_t>(hip_stream);
-    unsigned long long* queue = nullptr;
-    hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&queue),
-                                  sizeof(unsigned long long) * n_images, stream);
-    if (e != hipSuccess || !queue) {
+    // scratch: one work-queue counter per image, then the reduction partials
+    bool any_reduce = false;
+    for (int i = 0; i < n_images; ++i) any_reduce |= emission && out[i].reduce != nullptr;
+    const size_t queue_bytes = (sizeof(unsigned long long) * n_images + 255) / 256 * 256;
+    const size_t scratch_bytes =
+        queue_bytes + (any_reduce ? sizeof(double) * 3 * rt::kReduceBlocks : 0);
+    void* scratch = nullptr;
+    hipError_t e = hipMallocAsync(&scratch, scratch_bytes, stream);
+    if (e != hipSuccess || !scratch) {
         (void)hipGetLastError();
-        return fail(RT_ERR_ALLOC, "stream-ordered allocation of the work queue failed");
+        return fail(RT_ERR_ALLOC, "stream-ordered allocation of %zu scratch bytes failed",
+                    scratch_bytes);
     }
+    unsigned long long* queue = static_cast<unsigned long long*>(scratch);
+    double* partials = reinterpret_cast<double*>(static_cast<char*>(scratch) + queue_bytes);
     e = rt::launch_zero(queue, n_images, stream);
     if (e != hipSuccess) {
-        (void)hipFreeAsync(queue, stream);
+        (void)hipFreeAsync(scratch, stream);
         return hip_fail(e, "queue reset launch");
     }
     if (g_timing_start) (void)hipEventRecord(g_timing_start, stream);
@@ -280,21 +288,21 @@ int trace_common(const rt_image_params* params, int32_t n_images, const rt_image
         const int32_t chunk = 64;
         e = rt::launch_trace(c, o, queue + i, chunk, grid, stream);
         if (e != hipSuccess) {
-            (void)hipFreeAsync(queue, stream);
+            (void)hipFreeAsync(scratch, stream);
             return hip_fail(e, "trace kernel launch");
         }
     }
     if (g_timing_stop) (void)hipEventRecord(g_timing_stop, stream);
     for (int i = 0; i < n_images; ++i) {
         if (emission && out[i].reduce) {
-            e = rt::launch_reduce(consts[i], out[i].intensity, out[i].reduce, stream);
+            e = rt::launch_reduce(consts[i], out[i].intensity, partials, out[i].reduce, stream);
             if (e != hipSuccess) {
-                (void)hipFreeAsync(queue, stream);
+                (void)hipFreeAsync(scratch, stream);
                 return hip_fail(e, "reduce kernel launch");
             }
         }
     }
-    e = hipFreeAsync(queue, stream);
+    e = hipFreeAsync(scratch, stream);
     if (e != hipSuccess) return hip_fail(e, "hipFreeAsync");
     return RT_OK;
 }

@@ -38,8 +38,10 @@ hipError_t launch_trace(const ImageConst& c, const OutPtrs& o, unsigned long lon
 int max_blocks_per_cu(int metric);
 
 // Flux and intensity-weighted centroid of an image (Sec. 6.2): out[0..2] =
-// {F, X_c, Y_c}.  One workgroup; deterministic order.
-hipError_t launch_reduce(const ImageConst& c, const double* intensity, double* out,
-                         hipStream_t stream);
+// {F, X_c, Y_c}.  `partials` is device scratch of 3 * kReduceBlocks doubles.
+// Deterministic summation order.
+constexpr int kReduceBlocks = 256;
+hipError_t launch_reduce(const ImageConst& c, const double* intensity, double* partials,
+                         double* out, hipStream_t stream);
 
 }  // namespace rt

@@ -37,6 +37,22 @@ constexpr double kLn2Hi = 0.6931471805599453;
 constexpr double kLn2Lo = 2.3190468138462996e-17;
 constexpr double kInvLn2 = 1.4426950408889634;
 
+// 1/x for finite, non-zero, normal x: a first estimate refined by two
+// Newton-Raphson steps r <- r (2 - x r), each of which squares the relative
+// error; within about one ulp.  On the device the estimate is the hardware
+// reciprocal; on the host (tests) it is the division itself.
+__host__ __device__ inline double recip(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    double r = __builtin_amdgcn_rcp(x);
+#else
+    double r = 1.0 / x;
+#endif
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+
 // sin and cos of x, |x| < 1.6e6.
 __host__ __device__ inline void sincos(double x, double* s_out, double* c_out) {
     const double k = rint(x * kTwoOverPi);
@@ -111,14 +127,14 @@ __host__ __device__ inline double expm1(double x) {
 __host__ __device__ inline double log1p(double u) {
     const double v = 1.0 + u;
     // rounding error of 1 + u, carried as a first-order correction
-    const double corr = (u - (v - 1.0)) / v;
+    const double corr = (u - (v - 1.0)) * recip(v);
     int e;
     double m = frexp(v, &e);          // v = m 2^e, m in [1/2, 1)
     if (m < 0.70710678118654752) {
         m *= 2.0;
         e -= 1;
     }
-    const double t = (m - 1.0) / (m + 1.0);
+    const double t = (m - 1.0) * recip(m + 1.0);
     const double z = t * t;
     // log m = 2 (t + t^3/3 + ... + t^23/23)
     double p = 1.0 / 23.0;

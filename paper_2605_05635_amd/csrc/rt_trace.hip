@@ -21,16 +21,7 @@ namespace {
 
 constexpr double kHalfPi = 1.5707963267948966;
 
-// Reciprocal: the hardware estimate refined by two Newton-Raphson steps (each
-// squares the relative error), about one ulp for the finite, non-zero normal
-// arguments that occur here; cheaper than the IEEE division sequence.
-__device__ __forceinline__ double rcp(double x) {
-    double r = __builtin_amdgcn_rcp(x);
-    double e = fma(-x, r, 1.0);
-    r = fma(r, e, r);
-    e = fma(-x, r, 1.0);
-    return fma(r, e, r);
-}
+__device__ __forceinline__ double rcp(double x) { return dm::recip(x); }
 
 // ---------------------------------------------------------------- the RHS
 // Hamilton's equations for H = g^{ab} p_a p_b / 2 with p_T = -E, p_phi = l.
@@ -255,7 +246,7 @@ __device__ __forceinline__ int32_t attempt(const ImageConst& c, const OutPtrs& o
         ae[i] += e7 * kk[i];
         ad[i] += d7 * kk[i];
         const double sc = c.atol + c.rtol * fmax(fabs(r.y[i]), fabs(yn[i]));
-        const double q = h * ae[i] / sc;
+        const double q = h * ae[i] * rcp(sc);
         acc += q * q;
     }
     // err^2 = mean of the squared scaled errors; the step is accepted when
