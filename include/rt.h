@@ -116,8 +116,11 @@ typedef struct rt_image_out {
  * integrated with Hamilton's equations and the adaptive Dormand-Prince 5(4)
  * controller; equatorial crossings are located on the continuous extension
  * of each step; the thin-disc intensity uses the Keplerian emitter of
- * eqs. (89)-(91).  Returns RT_ERR_NO_HORIZON if any image has no outer
- * horizon, RT_ERR_ARG for invalid parameters or n_images < 1. */
+ * eqs. (89)-(91).  One image runs the single-image kernel; several images
+ * run in one persistent launch per 128 images, rays of all images drawn from
+ * one work queue, with results bit-identical to tracing each image alone.
+ * Returns RT_ERR_NO_HORIZON if any image has no outer horizon, RT_ERR_ARG for
+ * invalid parameters or n_images < 1; in either case nothing is launched. */
 int rt_trace_image(const rt_image_params *params, int32_t n_images, const rt_image_out *out,
                    void *hip_stream);
 
@@ -139,6 +142,25 @@ int rt_image_setup(const rt_image_params *params, double *setup);
  * The events stay owned by the caller.  Returns RT_ERR_ARG if exactly one is
  * NULL. */
 int rt_set_kernel_timing(void *start_event, void *stop_event);
+
+/* How the persistent trace kernels hand out work (thread-local setting,
+ * applies to later calls on this thread).  Pixels are handed to wavefronts in
+ * chunks of `chunk` consecutive ordinals of a screen enumeration in tiles of
+ * tile_w x tile_h pixels (row by row, clipped at the screen edges); tile_w =
+ * tile_h = 0 means plain row-major order; `blocks_per_cu` caps the resident
+ * workgroups launched per compute unit (0 = as many as fit).  chunk = 0 means
+ * 64.  The results of a trace do not depend on these settings (every ray is
+ * traced the same way); only its speed does. */
+typedef struct rt_launch_config {
+  int32_t chunk;          /* 0..65536                                            */
+  int32_t tile_w, tile_h; /* both 0 or both > 0                                  */
+  int32_t blocks_per_cu;  /* 0..64                                               */
+} rt_launch_config;
+
+/* Set (NULL: restore the defaults) or read the launch configuration.
+ * RT_ERR_ARG for out-of-range fields. */
+int rt_set_launch_config(const rt_launch_config *cfg);
+int rt_get_launch_config(rt_launch_config *cfg);
 
 /* Thread-local description of the last error on this thread ("" if none). */
 const char *rt_last_error(void);

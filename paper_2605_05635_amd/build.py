@@ -27,7 +27,10 @@ DEVICE_FLAGS = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang"
 # the scalar registers and spills them to vector-register lanes (one VALU
 # read per use inside the loop).  Without that pass the constants are
 # rematerialised by scalar moves next to their uses.
-CODEGEN_FLAGS = ["-mllvm", "-disable-machine-licm"]
+# Floating-point contraction only within one expression (the C rule): fused
+# multiply-adds then depend on the source alone, not on the surrounding code,
+# so the single-image and batched kernels round every ray identically.
+CODEGEN_FLAGS = ["-mllvm", "-disable-machine-licm", "-ffp-contract=on"]
 
 
 def build(verbose: bool = False, extra: list[str] | None = None) -> str:

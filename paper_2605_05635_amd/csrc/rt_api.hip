@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -18,6 +19,7 @@ namespace {
 
 thread_local std::string g_last_error;
 thread_local hipEvent_t g_timing_start = nullptr, g_timing_stop = nullptr;
+thread_local rt_launch_config g_launch = {0, 0, 0, 0};
 
 int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
 int fail(int code, const char* fmt, ...) {
@@ -32,6 +34,57 @@ int fail(int code, const char* fmt, ...) {
 
 int hip_fail(hipError_t e, const char* what) {
     return fail(RT_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+// Images per batched launch: their constants must fit in the kernel's LDS
+// table (~270 bytes each); larger batches run as consecutive launches.
+constexpr int kMaxBatch = 128;
+constexpr int kDefaultChunk = 64;
+
+// Pinned host staging for the batched kernel's image tables, reused across
+// calls on this thread; `ready` is recorded after the copy that reads it.
+struct Staging {
+    void* ptr = nullptr;
+    size_t cap = 0;
+    hipEvent_t ready = nullptr;
+};
+thread_local Staging g_staging;
+
+int staging_reserve(size_t bytes, void** out) {
+    Staging& s = g_staging;
+    if (s.ready) {
+        const hipError_t e = hipEventSynchronize(s.ready);   // previous copy has read it
+        if (e != hipSuccess) return fail(RT_ERR_HIP, "staging event: %s", hipGetErrorString(e));
+    } else if (hipEventCreateWithFlags(&s.ready, hipEventDisableTiming) != hipSuccess) {
+        s.ready = nullptr;
+        return fail(RT_ERR_HIP, "hipEventCreate failed");
+    }
+    if (s.cap < bytes) {
+        if (s.ptr) (void)hipHostFree(s.ptr);
+        s.ptr = nullptr;
+        s.cap = 0;
+        if (hipHostMalloc(&s.ptr, bytes, hipHostMallocDefault) != hipSuccess || !s.ptr) {
+            (void)hipGetLastError();
+            s.ptr = nullptr;
+            return fail(RT_ERR_ALLOC, "pinned staging allocation of %zu bytes failed", bytes);
+        }
+        s.cap = bytes;
+    }
+    *out = s.ptr;
+    return RT_OK;
+}
+
+rt::LaunchShape shape_for(int32_t nx, int32_t ny) {
+    rt::LaunchShape sh;
+    sh.chunk = g_launch.chunk > 0 ? g_launch.chunk : kDefaultChunk;
+    if (g_launch.tile_w > 0 && g_launch.tile_h > 0) {
+        sh.tile_w = g_launch.tile_w < nx ? g_launch.tile_w : nx;
+        sh.tile_h = g_launch.tile_h < ny ? g_launch.tile_h : ny;
+    } else {
+        sh.tile_w = nx;
+        sh.tile_h = 1;
+    }
+    return sh;
 }
 
 bool finite_all(std::initializer_list<double> v) {
@@ -194,6 +247,7 @@ int setup_image(const rt_image_params* p, int index, bool emission, rt::ImageCon
 struct DeviceInfo {
     int cus = 0;
     int blocks_per_cu[3] = {0, 0, 0};
+    int batch_blocks_per_cu = 0;   // at the largest batch table
 };
 
 int device_info(DeviceInfo* info) {
@@ -208,6 +262,7 @@ int device_info(DeviceInfo* info) {
         e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
         if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute");
         for (int m = 0; m < 3; ++m) d.blocks_per_cu[m] = rt::max_blocks_per_cu(m);
+        d.batch_blocks_per_cu = rt::max_batch_blocks_per_cu(kMaxBatch);
         d.cus = cus;
     }
     *info = d;
@@ -255,12 +310,33 @@ int trace_common(const rt_image_params* params, int32_t n_images, const rt_image
             return rc;
     }
     hipStream_t stream = static_cast<hipStream_t>(hip_stream);
-    // scratch: one work-queue counter per image, then the reduction partials
+    std::vector<rt::OutPtrs> optrs(n_images);
+    for (int i = 0; i < n_images; ++i)
+        optrs[i] = rt::OutPtrs{out[i].ncross, out[i].status, out[i].r_em, out[i].phi_em,
+                               out[i].t_em, emission ? out[i].g_em : nullptr,
+                               emission ? out[i].intensity : nullptr,
+                               emission ? out[i].intensity_n : nullptr, out[i].attempts};
+    // Batches: images grouped by metric (stable), at most kMaxBatch per launch.
+    std::vector<int> order(n_images);
+    for (int i = 0; i < n_images; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return consts[a].metric < consts[b].metric; });
+    const int n_launch = n_images == 1 ? 1 : (n_images + kMaxBatch - 1) / kMaxBatch;
+
+    // Scratch (stream-ordered): a work-queue counter per launch, the reduction
+    // partials, then per batched launch its image table, output table and
+    // chunk prefix sums.
+    auto up256 = [](size_t b) { return (b + 255) / 256 * 256; };
     bool any_reduce = false;
     for (int i = 0; i < n_images; ++i) any_reduce |= emission && out[i].reduce != nullptr;
-    const size_t queue_bytes = (sizeof(unsigned long long) * n_images + 255) / 256 * 256;
-    const size_t scratch_bytes =
-        queue_bytes + (any_reduce ? sizeof(double) * 3 * rt::kReduceBlocks : 0);
+    const size_t queue_bytes = up256(sizeof(unsigned long long) * n_launch);
+    const size_t part_bytes = any_reduce ? up256(sizeof(double) * 3 * rt::kReduceBlocks) : 0;
+    const size_t table_bytes =
+        n_images == 1 ? 0
+                      : up256(sizeof(rt::ImageConst) * n_images) +
+                            up256(sizeof(rt::OutPtrs) * n_images) +
+                            up256(sizeof(int64_t) * (n_images + n_launch));
+    const size_t scratch_bytes = queue_bytes + part_bytes + table_bytes;
     void* scratch = nullptr;
     hipError_t e = hipMallocAsync(&scratch, scratch_bytes, stream);
     if (e != hipSuccess || !scratch) {
@@ -268,38 +344,83 @@ int trace_common(const rt_image_params* params, int32_t n_images, const rt_image
         return fail(RT_ERR_ALLOC, "stream-ordered allocation of %zu scratch bytes failed",
                     scratch_bytes);
     }
-    unsigned long long* queue = static_cast<unsigned long long*>(scratch);
-    double* partials = reinterpret_cast<double*>(static_cast<char*>(scratch) + queue_bytes);
-    e = rt::launch_zero(queue, n_images, stream);
-    if (e != hipSuccess) {
+    char* base = static_cast<char*>(scratch);
+    unsigned long long* queue = reinterpret_cast<unsigned long long*>(base);
+    double* partials = reinterpret_cast<double*>(base + queue_bytes);
+    char* tables = base + queue_bytes + part_bytes;
+    auto bail = [&](int code) {
         (void)hipFreeAsync(scratch, stream);
-        return hip_fail(e, "queue reset launch");
+        return code;
+    };
+
+    rt::ImageConst* d_table = nullptr;
+    rt::OutPtrs* d_outs = nullptr;
+    int64_t* d_cs = nullptr;
+    if (n_images > 1) {
+        const size_t tb = up256(sizeof(rt::ImageConst) * n_images);
+        const size_t ob = up256(sizeof(rt::OutPtrs) * n_images);
+        d_table = reinterpret_cast<rt::ImageConst*>(tables);
+        d_outs = reinterpret_cast<rt::OutPtrs*>(tables + tb);
+        d_cs = reinterpret_cast<int64_t*>(tables + tb + ob);
+        void* host = nullptr;
+        const int src = staging_reserve(table_bytes, &host);
+        if (src != RT_OK) return bail(src);
+        char* h = static_cast<char*>(host);
+        auto* h_table = reinterpret_cast<rt::ImageConst*>(h);
+        auto* h_outs = reinterpret_cast<rt::OutPtrs*>(h + tb);
+        auto* h_cs = reinterpret_cast<int64_t*>(h + tb + ob);
+        const rt::LaunchShape sh0 = shape_for(1, 1);
+        for (int l = 0, pos = 0; l < n_launch; ++l) {
+            const int lo = l * kMaxBatch, hi = std::min(n_images, lo + kMaxBatch);
+            int64_t acc = 0;
+            for (int j = lo; j < hi; ++j) {
+                h_table[j] = consts[order[j]];
+                h_outs[j] = optrs[order[j]];
+                h_cs[pos++] = acc;
+                acc += (consts[order[j]].n_pix + sh0.chunk - 1) / sh0.chunk;
+            }
+            h_cs[pos++] = acc;
+        }
+        e = hipMemcpyAsync(tables, host, table_bytes, hipMemcpyHostToDevice, stream);
+        if (e == hipSuccess) e = hipEventRecord(g_staging.ready, stream);
+        if (e != hipSuccess) return bail(hip_fail(e, "image table upload"));
     }
+    e = rt::launch_zero(queue, n_launch, stream);
+    if (e != hipSuccess) return bail(hip_fail(e, "queue reset launch"));
     if (g_timing_start) (void)hipEventRecord(g_timing_start, stream);
-    for (int i = 0; i < n_images; ++i) {
-        const rt::ImageConst& c = consts[i];
-        rt::OutPtrs o{out[i].ncross, out[i].status, out[i].r_em, out[i].phi_em, out[i].t_em,
-                      emission ? out[i].g_em : nullptr, emission ? out[i].intensity : nullptr,
-                      emission ? out[i].intensity_n : nullptr, out[i].attempts};
-        const int64_t waves = (c.n_pix + 63) / 64;
-        const int64_t want_blocks = (waves + 3) / 4;
-        const int64_t resident = static_cast<int64_t>(info.cus) * info.blocks_per_cu[c.metric];
+    if (n_images == 1) {
+        const rt::ImageConst& c = consts[0];
+        const int64_t want_blocks = (c.n_pix + 255) / 256;
+        int per_cu = info.blocks_per_cu[c.metric];
+        if (g_launch.blocks_per_cu > 0 && g_launch.blocks_per_cu < per_cu)
+            per_cu = g_launch.blocks_per_cu;
+        const int64_t resident = static_cast<int64_t>(info.cus) * per_cu;
         const int32_t grid = static_cast<int32_t>(want_blocks < resident ? want_blocks : resident);
-        const int32_t chunk = 64;
-        e = rt::launch_trace(c, o, queue + i, chunk, grid, stream);
-        if (e != hipSuccess) {
-            (void)hipFreeAsync(scratch, stream);
-            return hip_fail(e, "trace kernel launch");
+        e = rt::launch_trace(c, optrs[0], queue, shape_for(c.nx, c.ny), grid, stream);
+        if (e != hipSuccess) return bail(hip_fail(e, "trace kernel launch"));
+    } else {
+        for (int l = 0, pos = 0; l < n_launch; ++l) {
+            const int lo = l * kMaxBatch, hi = std::min(n_images, lo + kMaxBatch);
+            int64_t pix = 0;
+            for (int j = lo; j < hi; ++j) pix += consts[order[j]].n_pix;
+            const int64_t want_blocks = (pix + 255) / 256;
+            int per_cu = info.batch_blocks_per_cu;
+            if (g_launch.blocks_per_cu > 0 && g_launch.blocks_per_cu < per_cu)
+                per_cu = g_launch.blocks_per_cu;
+            const int64_t resident = static_cast<int64_t>(info.cus) * per_cu;
+            const int32_t grid =
+                static_cast<int32_t>(want_blocks < resident ? want_blocks : resident);
+            e = rt::launch_trace_batch(d_table + lo, d_outs + lo, d_cs + pos, hi - lo, queue + l,
+                                       shape_for(1, 1), grid, stream);
+            if (e != hipSuccess) return bail(hip_fail(e, "batched trace kernel launch"));
+            pos += hi - lo + 1;
         }
     }
     if (g_timing_stop) (void)hipEventRecord(g_timing_stop, stream);
     for (int i = 0; i < n_images; ++i) {
         if (emission && out[i].reduce) {
             e = rt::launch_reduce(consts[i], out[i].intensity, partials, out[i].reduce, stream);
-            if (e != hipSuccess) {
-                (void)hipFreeAsync(scratch, stream);
-                return hip_fail(e, "reduce kernel launch");
-            }
+            if (e != hipSuccess) return bail(hip_fail(e, "reduce kernel launch"));
         }
     }
     e = hipFreeAsync(scratch, stream);
@@ -341,6 +462,27 @@ int rt_set_kernel_timing(void* start_event, void* stop_event) {
         return fail(RT_ERR_ARG, "timing events must both be set or both be null");
     g_timing_start = static_cast<hipEvent_t>(start_event);
     g_timing_stop = static_cast<hipEvent_t>(stop_event);
+    return RT_OK;
+}
+
+int rt_set_launch_config(const rt_launch_config* cfg) {
+    g_last_error.clear();
+    if (!cfg) {
+        g_launch = rt_launch_config{0, 0, 0, 0};
+        return RT_OK;
+    }
+    if (cfg->chunk < 0 || cfg->chunk > 65536 || cfg->tile_w < 0 || cfg->tile_h < 0 ||
+        (cfg->tile_w > 0) != (cfg->tile_h > 0) || cfg->blocks_per_cu < 0 ||
+        cfg->blocks_per_cu > 64)
+        return fail(RT_ERR_ARG, "launch config out of range");
+    g_launch = *cfg;
+    return RT_OK;
+}
+
+int rt_get_launch_config(rt_launch_config* cfg) {
+    g_last_error.clear();
+    if (!cfg) return fail(RT_ERR_ARG, "null launch config pointer");
+    *cfg = g_launch;
     return RT_OK;
 }
 

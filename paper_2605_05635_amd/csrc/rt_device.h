@@ -51,9 +51,8 @@ struct ImageConst {
 // functions mu_E (from eq. (9)) and mu_cNFW (from eq. (13)) are written in
 // cancellation-free forms: mu_E = 1 - e^{-x}(1 + x + x^2/2) with x = R/lambda_E,
 // mu_cNFW = 1 - (R/2) expm1(Ex) with Ex the exponent of eq. (13).
-template <int METRIC>
-__host__ __device__ inline void mass_function(const ImageConst& c, double R, double& F,
-                                              double& dF) {
+template <int METRIC, class K>
+__host__ __device__ inline void mass_function(const K& c, double R, double& F, double& dF) {
     if constexpr (METRIC == KERR) {
         F = 2.0 * R;
         dF = 2.0;

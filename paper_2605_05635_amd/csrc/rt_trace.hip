@@ -11,7 +11,13 @@
 // from a global counter with one atomic per chunk; a lane whose ray ends takes
 // the next pixel of its wave's chunk at the next refill point, so lanes stay
 // busy while rays of very different lengths are in flight (wavefront-level
-// compaction of terminated rays).
+// compaction of terminated rays).  Two kernels share every line of per-ray
+// code: trace_kernel<metric> for one image (its constants are kernel
+// arguments, held in scalar registers) and trace_batch_kernel for many images
+// of any metrics in one launch (their constants staged in LDS, each lane
+// carrying the few its step loop needs).  Compiled with floating-point
+// contraction limited to single expressions, the two produce bit-identical
+// rays.
 #include "rt_device.h"
 #include "rt_kernels.h"
 #include "rt_math.h"
@@ -22,6 +28,30 @@ namespace {
 constexpr double kHalfPi = 1.5707963267948966;
 
 __device__ __forceinline__ double rcp(double x) { return dm::recip(x); }
+
+// The constants of the step loop: a copy of the ImageConst fields the
+// right-hand side, the controller and the stop tests read.
+struct Hot {
+    double chi, chi2, inv_lam, lam_c, inv_lam_c, eta_lc;
+    double rtol, atol, r_stop, r_esc;
+    int32_t max_attempts;
+};
+
+__device__ __forceinline__ Hot hot_of(const ImageConst& c) {
+    Hot k;
+    k.chi = c.chi;
+    k.chi2 = c.chi2;
+    k.inv_lam = c.inv_lam;
+    k.lam_c = c.lam_c;
+    k.inv_lam_c = c.inv_lam_c;
+    k.eta_lc = c.eta_lc;
+    k.rtol = c.rtol;
+    k.atol = c.atol;
+    k.r_stop = c.r_stop;
+    k.r_esc = c.r_esc;
+    k.max_attempts = c.max_attempts;
+    return k;
+}
 
 // ---------------------------------------------------------------- the RHS
 // Hamilton's equations for H = g^{ab} p_a p_b / 2 with p_T = -E, p_phi = l.
@@ -39,32 +69,32 @@ __device__ __forceinline__ double rcp(double x) { return dm::recip(x); }
 //   dp_th/dl= -dH/dth = cos/Sigma [W (l/sin^2 + chi E) - chi^2 sin N/Sigma]  (62)
 // The N dSigma terms keep the full derivative of H off the constraint shell.
 template <int METRIC>
-__device__ __forceinline__ void rhs(const ImageConst& c, double E, double L, double R, double th,
+__device__ __forceinline__ void rhs(const Hot& k, double E, double L, double R, double th,
                                     double pR, double pth, double d[6]) {
     double s, co;
     dm::sincos(th, &s, &co);
     double F, dF;
-    mass_function<METRIC>(c, R, F, dF);
+    mass_function<METRIC>(k, R, F, dF);
     const double R2 = R * R;
-    const double R2c = R2 + c.chi2;
-    const double Sig = R2 + c.chi2 * co * co;
+    const double R2c = R2 + k.chi2;
+    const double Sig = R2 + k.chi2 * co * co;
     const double Del = R2c - F;
     const double dDel = 2.0 * R - dF;
     const double iS = rcp(Sig);
     const double iD = rcp(Del);
     const double is = rcp(s);
-    const double P = R2c * E - c.chi * L;
+    const double P = R2c * E - k.chi * L;
     const double PiD = P * iD;
     const double Lis2 = L * is * is;
-    const double W = L * is - c.chi * E * s;
+    const double W = L * is - k.chi * E * s;
     const double N = Del * pR * pR + pth * pth - P * PiD + W * W;
     const double dN = dDel * (pR * pR + PiD * PiD) - 4.0 * R * E * PiD;
-    d[0] = (PiD * R2c + c.chi * (L - c.chi * E * s * s)) * iS;
+    d[0] = (PiD * R2c + k.chi * (L - k.chi * E * s * s)) * iS;
     d[1] = Del * pR * iS;
     d[2] = pth * iS;
-    d[3] = (c.chi * PiD + Lis2 - c.chi * E) * iS;
+    d[3] = (k.chi * PiD + Lis2 - k.chi * E) * iS;
     d[4] = (N * R * iS - 0.5 * dN) * iS;
-    d[5] = co * iS * (W * (Lis2 + c.chi * E) - c.chi2 * s * N * iS);
+    d[5] = co * iS * (W * (Lis2 + k.chi * E) - k.chi2 * s * N * iS);
 }
 
 // ------------------------------------------------ Dormand-Prince 5(4) tableau
@@ -95,7 +125,6 @@ struct DenseComp {
     }
 };
 
-
 // ------------------------------------------------------------ emission
 // Keplerian equatorial emitter (eqs. (90)-(91)) and redshift (eq. (89)) for a
 // photon with constants (E, l) and unit observer-frame energy.  At theta =
@@ -104,18 +133,18 @@ struct DenseComp {
 // Omega = (chi G + sqrt(-2 R G)) / (2R + chi^2 G).  g = 0 where no timelike
 // circular orbit exists.
 template <int METRIC>
-__device__ __forceinline__ double redshift(const ImageConst& c, double R, double E, double L) {
+__device__ __forceinline__ double redshift(const Hot& k, double R, double E, double L) {
     double F, dF;
-    mass_function<METRIC>(c, R, F, dF);
+    mass_function<METRIC>(k, R, F, dF);
     const double iR = 1.0 / R;
     const double FoR2 = F * iR * iR;
     const double G = (dF - 2.0 * F * iR) * iR * iR;
     const double disc = -2.0 * R * G;
     if (!(disc >= 0.0)) return 0.0;
-    const double Om = (c.chi * G + sqrt(disc)) / (2.0 * R + c.chi2 * G);
+    const double Om = (k.chi * G + sqrt(disc)) / (2.0 * R + k.chi2 * G);
     const double gTT = -(1.0 - FoR2);
-    const double gTp = -c.chi * FoR2;
-    const double gpp = R * R + c.chi2 + c.chi2 * FoR2;
+    const double gTp = -k.chi * FoR2;
+    const double gpp = R * R + k.chi2 + k.chi2 * FoR2;
     const double A = -(gTT + Om * (2.0 * gTp + Om * gpp));
     if (!(A > 0.0)) return 0.0;
     const double den = E - Om * L;
@@ -144,13 +173,40 @@ struct Ray {
     int64_t pix;
 };
 
+// Pixel index of the p-th pixel of an nx x ny screen in tile order: tiles of
+// tw x th pixels, taken row by row; pixels inside a tile row by row; tiles on
+// the right and bottom edges are clipped to the screen.  tw = nx, th = 1 is
+// plain row-major order.  A bijection of [0, nx ny).
+__device__ __forceinline__ int64_t tile_pixel(int64_t p, int32_t nx, int32_t ny, int32_t tw,
+                                              int32_t th) {
+    const int64_t band = static_cast<int64_t>(th) * nx;   // pixels per full tile row
+    const int64_t r = p / band;                             // tile row
+    const int64_t h = (r + 1) * th <= ny ? th : ny - r * th;
+    const int64_t q = p - r * band;                          // index inside the tile row
+    const int64_t full = nx / tw;                            // unclipped tiles per row
+    const int64_t j = q / (static_cast<int64_t>(tw) * h);
+    int64_t ix, iy;
+    if (j < full) {
+        const int64_t off = q - j * tw * h;
+        iy = r * th + off / tw;
+        ix = j * tw + off % tw;
+    } else {
+        const int64_t w = nx - full * tw;
+        const int64_t off = q - full * tw * h;
+        iy = r * th + off / w;
+        ix = full * tw + off % w;
+    }
+    return iy * nx + ix;
+}
+
 // Screen pixel -> initial state (Sec. 3.2, eqs. (70)-(74) with E_loc = 1):
 // with n = -(R_o, Y, X)/sqrt(R_o^2 + X^2 + Y^2) in the ZAMO triad, lowering
 // p^mu = u_o + n^(a) e_(a) with the observer metric gives
 // E = N_o - g_Tphi n^(phi)/sqrt(g_phiphi), l = sqrt(g_phiphi) n^(phi),
 // p_R = sqrt(g_RR) n^(R), p_theta = sqrt(g_thth) n^(theta).
 template <int METRIC>
-__device__ __forceinline__ void start_ray(const ImageConst& c, int64_t pix, Ray& r) {
+__device__ __forceinline__ void start_ray(const ImageConst& c, const Hot& k, int64_t pix,
+                                          Ray& r) {
     const int64_t iy = pix / c.nx;
     const int64_t ix = pix - iy * c.nx;
     const double X = c.x0 + (static_cast<double>(ix) + 0.5) * c.dx;
@@ -165,10 +221,11 @@ __device__ __forceinline__ void start_ray(const ImageConst& c, int64_t pix, Ray&
     r.y[3] = 0.0;
     r.y[4] = c.obs_sq_gRR * nR;
     r.y[5] = c.obs_sq_gthth * nth;
-    rhs<METRIC>(c, r.E, r.L, r.y[1], r.y[2], r.y[4], r.y[5], r.k1);
+    rhs<METRIC>(k, r.E, r.L, r.y[1], r.y[2], r.y[4], r.y[5], r.k1);
     r.h = c.h0;
     r.lam = 0.0;
     r.last_cross = -INFINITY;
+    r.rc[0] = r.rc[1] = r.rc[2] = 0.0;
     r.attempts = 0;
     r.ncross = 0;
     r.after_reject = 0;
@@ -207,8 +264,9 @@ __device__ __forceinline__ double crossing_root(const DenseComp& d, bool up0) {
 // coefficient r5 are accumulated as the stages are produced, so a stage
 // derivative stays live only while later stage inputs still need it.
 template <int METRIC>
-__device__ __forceinline__ int32_t attempt(const ImageConst& c, const OutPtrs& o, Ray& r) {
-    if (r.attempts >= c.max_attempts) return RAY_STEP_LIMIT;
+__device__ __forceinline__ int32_t attempt(const Hot& k, const OutPtrs& o, int64_t n_pix,
+                                           Ray& r) {
+    if (r.attempts >= k.max_attempts) return RAY_STEP_LIMIT;
     ++r.attempts;
     const double h = r.h;
     double ab[6], ae[6], ad[6];     // sums of b_i k_i, e_i k_i, d_i k_i
@@ -220,7 +278,7 @@ __device__ __forceinline__ int32_t attempt(const ImageConst& c, const OutPtrs& o
     }
 #define RT_STAGE(expr, out)                                                      \
     for (int i = 0; i < 6; ++i) t[i] = r.y[i] + h * (expr);                       \
-    rhs<METRIC>(c, r.E, r.L, t[1], t[2], t[4], t[5], out);
+    rhs<METRIC>(k, r.E, r.L, t[1], t[2], t[4], t[5], out);
 #define RT_ACC(bb, ee, dd, kv)                                                   \
     for (int i = 0; i < 6; ++i) {                                                \
         ab[i] += bb * kv[i];                                                     \
@@ -240,12 +298,12 @@ __device__ __forceinline__ int32_t attempt(const ImageConst& c, const OutPtrs& o
 #undef RT_ACC
     double yn[6];
     for (int i = 0; i < 6; ++i) yn[i] = r.y[i] + h * ab[i];
-    rhs<METRIC>(c, r.E, r.L, yn[1], yn[2], yn[4], yn[5], kk);   // k7 (first-same-as-last)
+    rhs<METRIC>(k, r.E, r.L, yn[1], yn[2], yn[4], yn[5], kk);   // k7 (first-same-as-last)
     double acc = 0.0;
     for (int i = 0; i < 6; ++i) {
         ae[i] += e7 * kk[i];
         ad[i] += d7 * kk[i];
-        const double sc = c.atol + c.rtol * fmax(fabs(r.y[i]), fabs(yn[i]));
+        const double sc = k.atol + k.rtol * fmax(fabs(r.y[i]), fabs(yn[i]));
         const double q = h * ae[i] * rcp(sc);
         acc += q * q;
     }
@@ -286,7 +344,7 @@ __device__ __forceinline__ int32_t attempt(const ImageConst& c, const OutPtrs& o
         if (fabs(pthc) >= 1e-12 * Rc * Rc && (lc - r.last_cross) >= 1e-10) {
             const int n = r.ncross;
             if (n < 3) {
-                const int64_t off = static_cast<int64_t>(n) * c.n_pix + r.pix;
+                const int64_t off = static_cast<int64_t>(n) * n_pix + r.pix;
                 // (selects, not r.rc[n]: a runtime index would put the ray in scratch)
                 r.rc[0] = n == 0 ? Rc : r.rc[0];
                 r.rc[1] = n == 1 ? Rc : r.rc[1];
@@ -306,8 +364,8 @@ __device__ __forceinline__ int32_t attempt(const ImageConst& c, const OutPtrs& o
     }
     r.lam += h;
     r.h = h * factor;
-    if (r.y[1] <= c.r_stop) return RAY_CAPTURED;   // eq. (75)
-    if (r.y[1] >= c.r_esc) return RAY_ESCAPED;
+    if (r.y[1] <= k.r_stop) return RAY_CAPTURED;   // eq. (75)
+    if (r.y[1] >= k.r_esc) return RAY_ESCAPED;
     return 0;
 }
 
@@ -315,19 +373,20 @@ __device__ __forceinline__ int32_t attempt(const ImageConst& c, const OutPtrs& o
 // per ray rather than inside the step loop), then the per-pixel outputs.
 // Records n >= min(N_cross, 3) are NaN.
 template <int METRIC>
-__device__ __forceinline__ void finish_ray(const ImageConst& c, const OutPtrs& o, const Ray& r,
-                                           int32_t status) {
+__device__ __forceinline__ void finish_ray(const ImageConst& c, const Hot& k, const OutPtrs& o,
+                                           const Ray& r, int32_t status) {
     const int64_t p = r.pix;
+    const int64_t n_pix = c.n_pix;
     const int nrec = r.ncross < 3 ? r.ncross : 3;
     const double nan = __builtin_nan("");
     if (c.emission) {
         double intensity = 0.0;
         for (int n = 0; n < 3; ++n) {
-            const int64_t off = static_cast<int64_t>(n) * c.n_pix + p;
+            const int64_t off = static_cast<int64_t>(n) * n_pix + p;
             double g = nan, In = nan;
             if (n < nrec) {
                 const double R = r.rc[n];
-                g = redshift<METRIC>(c, R, r.E, r.L);
+                g = redshift<METRIC>(k, R, r.E, r.L);
                 In = disc_window(c, R) * g * g * g * pow(R, -c.emis_pow);
                 intensity += In;
             }
@@ -340,53 +399,147 @@ __device__ __forceinline__ void finish_ray(const ImageConst& c, const OutPtrs& o
     if (o.status) o.status[p] = static_cast<uint8_t>(status);
     if (o.attempts) o.attempts[p] = r.attempts;
     for (int n = nrec; n < 3; ++n) {
-        const int64_t off = static_cast<int64_t>(n) * c.n_pix + p;
+        const int64_t off = static_cast<int64_t>(n) * n_pix + p;
         if (o.r_em) o.r_em[off] = nan;
         if (o.phi_em) o.phi_em[off] = nan;
         if (o.t_em) o.t_em[off] = nan;
     }
 }
 
-// Persistent trace kernel for one image.
-template <int METRIC>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 8))) void trace_kernel(ImageConst c, OutPtrs o,
-                                                       unsigned long long* queue, int32_t chunk) {
+// Wave-level hand-out of pixels: lanes without a ray take consecutive
+// ordinals from the wave's current chunk; the wave claims a new chunk (one
+// atomic, lane 0) when it runs dry.  Called with all lanes converged.
+// `claim()` returns false when the queue is exhausted and otherwise sets the
+// chunk's ordinal range [next, end) (and whatever image state it tracks);
+// `take(ordinal)` starts a ray on the calling lane.
+template <class Claim, class Take>
+__device__ __forceinline__ void refill(bool& active, bool& exhausted, int64_t& next,
+                                       int64_t& end, Claim claim, Take take) {
     const int lane = __lane_id();
-    Ray r;
-    bool active = false;
-    // Wave-uniform chunk cursor: pixels [next, end) are claimed but not yet started.
-    int64_t next = 0, end = 0;
-    bool exhausted = false;
-    for (;;) {
-        // --- refill point: every lane of the wave is converged here
-        if (!exhausted) {
-            unsigned long long need = __ballot(!active);
-            while (need != 0ull) {
-                if (next >= end) {
-                    unsigned long long base = 0;
-                    if (lane == 0) base = atomicAdd(queue, static_cast<unsigned long long>(chunk));
-                    base = __shfl(base, 0);
-                    if (static_cast<int64_t>(base) >= c.n_pix) { exhausted = true; break; }
-                    next = static_cast<int64_t>(base);
-                    end = next + chunk < c.n_pix ? next + chunk : c.n_pix;
-                }
-                const int64_t avail = end - next;
-                const int nneed = __popcll(need);
-                const int take = avail < nneed ? static_cast<int>(avail) : nneed;
-                const int rank = __popcll(need & ((1ull << lane) - 1ull));
-                if (!active && rank < take) {
-                    start_ray<METRIC>(c, next + rank, r);
-                    active = true;
-                }
-                next += take;
-                need = __ballot(!active);
+    unsigned long long need = __ballot(!active);
+    while (need != 0ull) {
+        if (next >= end) {
+            if (!claim()) {
+                exhausted = true;
+                return;
             }
         }
+        const int64_t avail = end - next;
+        const int nneed = __popcll(need);
+        const int tk = avail < nneed ? static_cast<int>(avail) : nneed;
+        const int rank = __popcll(need & ((1ull << lane) - 1ull));
+        if (!active && rank < tk) {
+            take(next + rank);
+            active = true;
+        }
+        next += tk;
+        need = __ballot(!active);
+    }
+}
+
+// Persistent trace kernel for one image.
+template <int METRIC>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 8))) void trace_kernel(
+    ImageConst c, OutPtrs o, unsigned long long* queue, LaunchShape shape) {
+    const Hot k = hot_of(c);
+    Ray r;
+    bool active = false, exhausted = false;
+    int64_t next = 0, end = 0;   // wave-uniform: claimed ordinals not yet started
+    auto claim = [&]() {
+        unsigned long long base = 0;
+        if (__lane_id() == 0) base = atomicAdd(queue, static_cast<unsigned long long>(shape.chunk));
+        base = __shfl(base, 0);
+        if (static_cast<int64_t>(base) >= c.n_pix) return false;
+        next = static_cast<int64_t>(base);
+        end = next + shape.chunk < c.n_pix ? next + shape.chunk : c.n_pix;
+        return true;
+    };
+    auto take = [&](int64_t ordinal) {
+        start_ray<METRIC>(c, k, tile_pixel(ordinal, c.nx, c.ny, shape.tile_w, shape.tile_h), r);
+    };
+    for (;;) {
+        if (!exhausted) refill(active, exhausted, next, end, claim, take);
         if (__ballot(active) == 0ull) break;
         if (active) {
-            const int32_t st = attempt<METRIC>(c, o, r);
+            const int32_t st = attempt<METRIC>(k, o, c.n_pix, r);
             if (st != 0) {
-                finish_ray<METRIC>(c, o, r, st);
+                finish_ray<METRIC>(c, k, o, r, st);
+                active = false;
+            }
+        }
+    }
+}
+
+// Persistent trace kernel for a batch of images.  The images' constants are
+// copied into LDS once per workgroup; the work queue enumerates chunks of all
+// images (images ordered by metric, so a wavefront's lanes share a metric
+// except at the two metric boundaries).  Each lane keeps its image index and
+// the step-loop constants of that image in registers.
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 8))) void trace_batch_kernel(
+    const ImageConst* __restrict__ table, const OutPtrs* __restrict__ outs,
+    const int64_t* __restrict__ chunk_start, int32_t n_images, unsigned long long* queue,
+    LaunchShape shape) {
+    extern __shared__ unsigned char lds_raw[];
+    ImageConst* lt = reinterpret_cast<ImageConst*>(lds_raw);
+    int64_t* lcs = reinterpret_cast<int64_t*>(lds_raw + sizeof(ImageConst) * n_images);
+    {
+        const int words = static_cast<int>(sizeof(ImageConst) / 8) * n_images;
+        const uint64_t* src = reinterpret_cast<const uint64_t*>(table);
+        uint64_t* dst = reinterpret_cast<uint64_t*>(lt);
+        for (int i = threadIdx.x; i < words; i += blockDim.x) dst[i] = src[i];
+        for (int i = threadIdx.x; i <= n_images; i += blockDim.x) lcs[i] = chunk_start[i];
+    }
+    __syncthreads();
+    const int64_t total_chunks = lcs[n_images];
+
+    Ray r;
+    Hot k{};
+    int32_t img = 0, metric = KERR;
+    bool active = false, exhausted = false;
+    int64_t next = 0, end = 0;
+    int32_t cur = 0;   // wave-uniform image of the current chunk
+    auto claim = [&]() {
+        unsigned long long q = 0;
+        if (__lane_id() == 0) q = atomicAdd(queue, 1ull);
+        q = __shfl(q, 0);
+        if (static_cast<int64_t>(q) >= total_chunks) return false;
+        // image of chunk q: the last i with chunk_start[i] <= q
+        int32_t lo = 0, hi = n_images - 1;
+        while (lo < hi) {
+            const int32_t mid = (lo + hi + 1) >> 1;
+            if (lcs[mid] <= static_cast<int64_t>(q)) lo = mid; else hi = mid - 1;
+        }
+        cur = lo;
+        const int64_t npix = lt[cur].n_pix;
+        next = (static_cast<int64_t>(q) - lcs[cur]) * shape.chunk;
+        end = next + shape.chunk < npix ? next + shape.chunk : npix;
+        return true;
+    };
+    auto take = [&](int64_t ordinal) {
+        img = cur;
+        const ImageConst& c = lt[img];
+        metric = c.metric;
+        k = hot_of(c);
+        const int64_t pix = tile_pixel(ordinal, c.nx, c.ny, shape.tile_w, shape.tile_h);
+        if (metric == CNFW) start_ray<CNFW>(c, k, pix, r);
+        else if (metric == EINASTO) start_ray<EINASTO>(c, k, pix, r);
+        else start_ray<KERR>(c, k, pix, r);
+    };
+    for (;;) {
+        if (!exhausted) refill(active, exhausted, next, end, claim, take);
+        if (__ballot(active) == 0ull) break;
+        if (active) {
+            const OutPtrs& o = outs[img];
+            const int64_t n_pix = lt[img].n_pix;
+            int32_t st;
+            if (metric == CNFW) st = attempt<CNFW>(k, o, n_pix, r);
+            else if (metric == EINASTO) st = attempt<EINASTO>(k, o, n_pix, r);
+            else st = attempt<KERR>(k, o, n_pix, r);
+            if (st != 0) {
+                const ImageConst& c = lt[img];
+                if (metric == CNFW) finish_ray<CNFW>(c, k, o, r, st);
+                else if (metric == EINASTO) finish_ray<EINASTO>(c, k, o, r, st);
+                else finish_ray<KERR>(c, k, o, r, st);
                 active = false;
             }
         }
@@ -406,21 +559,35 @@ hipError_t launch_zero(unsigned long long* queue, int32_t n, hipStream_t stream)
 }
 
 hipError_t launch_trace(const ImageConst& c, const OutPtrs& o, unsigned long long* queue,
-                        int32_t chunk, int32_t grid, hipStream_t stream) {
+                        const LaunchShape& shape, int32_t grid, hipStream_t stream) {
     switch (c.metric) {
         case KERR:
             hipLaunchKernelGGL(trace_kernel<KERR>, dim3(grid), dim3(kBlock), 0, stream, c, o,
-                               queue, chunk);
+                               queue, shape);
             break;
         case EINASTO:
             hipLaunchKernelGGL(trace_kernel<EINASTO>, dim3(grid), dim3(kBlock), 0, stream, c, o,
-                               queue, chunk);
+                               queue, shape);
             break;
         default:
             hipLaunchKernelGGL(trace_kernel<CNFW>, dim3(grid), dim3(kBlock), 0, stream, c, o,
-                               queue, chunk);
+                               queue, shape);
             break;
     }
+    return hipGetLastError();
+}
+
+size_t batch_lds_bytes(int32_t n_images) {
+    return sizeof(ImageConst) * static_cast<size_t>(n_images) +
+           sizeof(int64_t) * static_cast<size_t>(n_images + 1);
+}
+
+hipError_t launch_trace_batch(const ImageConst* table, const OutPtrs* outs,
+                              const int64_t* chunk_start, int32_t n_images,
+                              unsigned long long* queue, const LaunchShape& shape, int32_t grid,
+                              hipStream_t stream) {
+    hipLaunchKernelGGL(trace_batch_kernel, dim3(grid), dim3(kBlock), batch_lds_bytes(n_images),
+                       stream, table, outs, chunk_start, n_images, queue, shape);
     return hipGetLastError();
 }
 
@@ -433,6 +600,13 @@ int max_blocks_per_cu(int metric) {
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, trace_kernel<EINASTO>, kBlock, 0);
     else
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, trace_kernel<CNFW>, kBlock, 0);
+    return (e == hipSuccess && n > 0) ? n : 1;
+}
+
+int max_batch_blocks_per_cu(int32_t n_images) {
+    int n = 0;
+    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &n, trace_batch_kernel, kBlock, batch_lds_bytes(n_images));
     return (e == hipSuccess && n > 0) ? n : 1;
 }
 

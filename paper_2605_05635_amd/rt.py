@@ -49,6 +49,11 @@ class rt_image_out(C.Structure):
     ]
 
 
+class rt_launch_config(C.Structure):
+    _fields_ = [("chunk", C.c_int32), ("tile_w", C.c_int32), ("tile_h", C.c_int32),
+                ("blocks_per_cu", C.c_int32)]
+
+
 class RTError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"rt error {code}: {msg}")
@@ -68,6 +73,10 @@ def _load():
         f.restype = C.c_int
     lib.rt_image_setup.argtypes = [P, C.POINTER(C.c_double)]
     lib.rt_image_setup.restype = C.c_int
+    lib.rt_set_launch_config.argtypes = [C.POINTER(rt_launch_config)]
+    lib.rt_set_launch_config.restype = C.c_int
+    lib.rt_get_launch_config.argtypes = [C.POINTER(rt_launch_config)]
+    lib.rt_get_launch_config.restype = C.c_int
     lib.rt_set_kernel_timing.argtypes = [C.c_void_p, C.c_void_p]
     lib.rt_set_kernel_timing.restype = C.c_int
     lib.rt_last_error.argtypes = []
@@ -159,6 +168,24 @@ def rt_set_kernel_timing(start_event, stop_event) -> None:
     _check(_lib.rt_set_kernel_timing(h(start_event), h(stop_event)))
 
 
+def rt_set_launch_config(chunk: int = 0, tile_w: int = 0, tile_h: int = 0,
+                         blocks_per_cu: int = 0, reset: bool = False) -> None:
+    """Work-distribution settings of later traces on this thread (see rt.h);
+    reset=True restores the library defaults."""
+    if reset:
+        _check(_lib.rt_set_launch_config(None))
+        return
+    cfg = rt_launch_config(chunk, tile_w, tile_h, blocks_per_cu)
+    _check(_lib.rt_set_launch_config(C.byref(cfg)))
+
+
+def rt_get_launch_config() -> dict:
+    cfg = rt_launch_config()
+    _check(_lib.rt_get_launch_config(C.byref(cfg)))
+    return dict(chunk=cfg.chunk, tile_w=cfg.tile_w, tile_h=cfg.tile_h,
+                blocks_per_cu=cfg.blocks_per_cu)
+
+
 def rt_version() -> int:
     return _lib.rt_version()
 
@@ -204,6 +231,7 @@ def trace_many(imgs: list, device="cuda", stream=None) -> list:
 
 
 __all__ = ["rt_trace_image", "rt_transfer_maps", "rt_image_setup", "rt_set_kernel_timing",
+           "rt_set_launch_config", "rt_get_launch_config",
            "rt_version",
            "rt_last_error", "trace", "trace_many", "params_from", "out_from", "alloc_outputs",
            "RTError"]

@@ -129,3 +129,25 @@ def test_image_setup_matches_oracle(rt, orc):
         ref = orc.image_setup(img)
         for k in ("r_plus", "r_stop", "r_esc", "r_in"):
             assert mine[k] == pytest.approx(ref[k], rel=tol, abs=0), (img["metric"], k)
+
+
+def test_launch_config_roundtrip_and_validation(rt):
+    rt.rt_set_launch_config(128, 8, 8, 1)
+    assert rt.rt_get_launch_config() == dict(chunk=128, tile_w=8, tile_h=8, blocks_per_cu=1)
+    for bad in (dict(chunk=-1), dict(tile_w=8), dict(tile_h=4), dict(blocks_per_cu=99),
+                dict(chunk=70000)):
+        with pytest.raises(rt.RTError) as e:
+            rt.rt_set_launch_config(**bad)
+        assert e.value.code == rt.RT_ERR_ARG
+    rt.rt_set_launch_config(reset=True)
+    assert rt.rt_get_launch_config() == dict(chunk=0, tile_w=0, tile_h=0, blocks_per_cu=0)
+
+
+def test_autotune_signature_and_cache(tmp_path, monkeypatch):
+    from paper_2605_05635_amd import autotune
+    monkeypatch.setenv("RT_AUTOTUNE_CACHE", str(tmp_path / "c.json"))
+    a = [W.kerr_small(), W.cnfw_1024()]
+    assert autotune.signature(a) == autotune.signature([dict(x) for x in a])
+    assert autotune.signature(a) != autotune.signature(a[::-1])
+    autotune._store({"k": {"chunk": 64}})
+    assert autotune._load() == {"k": {"chunk": 64}}

@@ -156,3 +156,58 @@ def test_deterministic_and_batched_equals_single(rt):
             x, y, z = (t.cpu().numpy() for t in (a[k], b[k], c[k]))
             assert np.array_equal(x, y, equal_nan=True), k
             assert np.array_equal(x, z, equal_nan=True), k
+
+
+def test_launch_config_does_not_change_results(rt):
+    """Chunk size, tile order and occupancy cap only move rays between lanes."""
+    import torch
+    img = W.image(metric="cnfw", spin=0.9, halo=(0.03, 7.0), incl=1.2, nx=45, ny=38)
+    rt.rt_set_launch_config(reset=True)
+    ref = rt.trace(img)
+    torch.cuda.synchronize()
+    try:
+        for cfg in (dict(chunk=1), dict(chunk=7, tile_w=8, tile_h=8),
+                    dict(chunk=256, tile_w=16, tile_h=4, blocks_per_cu=1),
+                    dict(chunk=33, tile_w=50, tile_h=50)):
+            say(f"[parity] launch config {cfg}")
+            rt.rt_set_launch_config(**cfg)
+            got = rt.trace(img)
+            torch.cuda.synchronize()
+            for k in ref:
+                assert np.array_equal(ref[k].cpu().numpy(), got[k].cpu().numpy(),
+                                      equal_nan=True), (cfg, k)
+    finally:
+        rt.rt_set_launch_config(reset=True)
+
+
+def test_large_mixed_batch_equals_single_images(rt):
+    """130 small images of all metrics: two batched launches (128 + 2 images),
+    each image bit-identical to its own single-image trace."""
+    import torch
+    base = W.batch_64(seed=9, n_images=64)
+    imgs = []
+    for j in range(130):
+        b = dict(base[j % 64])
+        b.update(nx=5 + j % 7, ny=4 + j % 5)
+        imgs.append(b)
+    say("[parity] 130-image batch")
+    many = rt.trace_many(imgs)
+    singles = [rt.trace(i) for i in imgs]
+    torch.cuda.synchronize()
+    for j, (a, b) in enumerate(zip(singles, many)):
+        for k in a:
+            assert np.array_equal(a[k].cpu().numpy(), b[k].cpu().numpy(), equal_nan=True), (j, k)
+
+
+def test_batch_parity_with_oracle(rt, orc):
+    """A batch of three metrics against the oracle, every pixel."""
+    import torch
+    imgs = [W.image(metric="kerr", spin=0.99, incl=1.4, nx=23, ny=19),
+            W.image(metric="einasto", spin=0.7, halo=(0.2, 0.0), incl=0.5, nx=31, ny=17),
+            W.image(metric="cnfw", spin=0.3, halo=(0.05, 5.0), incl=2.7, nx=19, ny=29)]
+    many = rt.trace_many(imgs)
+    torch.cuda.synchronize()
+    for img, outs in zip(imgs, many):
+        g = gpu_to_numpy(outs)
+        o = orc.trace_pixels(img)
+        assert_parity(g, o)
