@@ -67,6 +67,56 @@ def cpu_baseline(img: dict, stride: int) -> dict:
                       f"({idx.size} rays, {dt:.1f} s)"}
 
 
+def batch_measurement(steps: int) -> dict:
+    """64 images of mixed metric and resolution in one persistent launch, plus
+    normalised visibility amplitudes at 2000 seeded (u, v) points per image."""
+    import torch
+
+    from paper_2605_05635_amd import autotune, rt, workloads as W
+    imgs = W.batch_64()
+    rays = sum(i["nx"] * i["ny"] for i in imgs)
+    log(f"batch: 64 images, {rays} rays; autotuning the launch configuration")
+    best = autotune.tune(imgs, log=log)
+    outs = [rt.alloc_outputs(i) for i in imgs]
+    params = [rt.params_from(i) for i in imgs]
+    ouv = [rt.out_from(o) for o in outs]
+    uvs = [torch.tensor(W.uv_points(1000 + j, 2000), device="cuda") for j in range(len(imgs))]
+    amps = [torch.empty(2000, dtype=torch.float64, device="cuda") for _ in imgs]
+    stream = torch.cuda.current_stream()
+
+    def one_batch():
+        rt.rt_trace_image(params, ouv, stream)
+        for img, o, uv, amp in zip(imgs, outs, uvs, amps):
+            rt.rt_visibility_dft(o["intensity"], rt.params_from(img), uv, amp=amp, stream=stream)
+
+    one_batch()
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    t0 = time.perf_counter()
+    ev[0].record(stream)
+    for _ in range(steps):
+        rt.rt_trace_image(params, ouv, stream)
+    ev[1].record(stream)
+    for _ in range(steps):
+        for img, o, uv, amp in zip(imgs, outs, uvs, amps):
+            rt.rt_visibility_dft(o["intensity"], rt.params_from(img), uv, amp=amp, stream=stream)
+    ev[2].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    trace_ms = ev[0].elapsed_time(ev[1]) / steps
+    dft_ms = ev[1].elapsed_time(ev[2]) / steps
+    rt.rt_set_launch_config(reset=True)
+    attempts = sum(o["attempts"].double().sum().item() for o in outs)
+    log(f"batch: trace {trace_ms:.2f} ms, visibilities {dft_ms:.2f} ms per batch")
+    return {"workload": "64 images, res in {128..768}^2, mixed metrics, one launch; "
+                        "2000 (u,v) visibility amplitudes per image",
+            "rays": rays, "steps": steps, "trace_ms": trace_ms, "visibility_ms": dft_ms,
+            "ms_per_batch": wall * 1e3 / steps, "rays_per_s": rays / (trace_ms * 1e-3),
+            "attempts_per_ray": attempts / rays,
+            "launch_config": {k: best[k] for k in ("chunk", "tile_w", "tile_h", "blocks_per_cu")},
+            "visibility_finite": bool(all(torch.isfinite(a).all().item() for a in amps))}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -74,6 +124,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-stride", type=int, default=1)
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the 64-image batched trace + visibility measurement")
     ap.add_argument("--calibration-copy-mib", type=int, default=0,
                     help="after the timed steps, run one plain device-to-device copy of this "
                          "many MiB (the reference kernel for HBM byte counters) and report it")
@@ -147,6 +199,8 @@ def main() -> int:
         "attempts_per_ray": attempts / n_rays,
         "roofline": roofline,
     }
+    if not args.no_batch:
+        line["batch_64"] = batch_measurement(max(2, args.steps // 4))
     if args.calibration_copy_mib > 0:
         nbytes = args.calibration_copy_mib << 20
         src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")

@@ -143,6 +143,20 @@ int rt_image_setup(const rt_image_params *params, double *setup);
  * NULL. */
 int rt_set_kernel_timing(void *start_event, void *stop_event);
 
+/* Normalised visibility amplitudes of a traced image (Sec. 6.4, eqs. (108)-
+ * (109)): V(u,v) = sum over pixel centres of I exp(-2 pi i (u X + v Y)) dX dY
+ * and amp = |V(u,v)| / |V(0,0)|, at K points (u, v) in cycles per M.
+ *   intensity  device [ny][nx] image on the screen of `params` (only nx, ny and
+ *              the extent are read)
+ *   uv         device [K][2] (u, v) pairs
+ *   amp        device [K] normalised amplitudes, or NULL
+ *   vis        device [K][2] (Re V, Im V), or NULL (not both NULL)
+ * Internally one FP64 GEMM (rocBLAS) of the phase table with the image plus a
+ * fixed-order reduction; deterministic.  Scratch (about 16 K (nx + ny) bytes)
+ * is stream-ordered.  RT_ERR_ARG for a bad screen, K < 1 or K > 2^22. */
+int rt_visibility_dft(const double *intensity, const rt_image_params *params, const double *uv,
+                      int32_t K, double *amp, double *vis, void *hip_stream);
+
 /* How the persistent trace kernels hand out work (thread-local setting,
  * applies to later calls on this thread).  Pixels are handed to wavefronts in
  * chunks of `chunk` consecutive ordinals of a screen enumeration in tiles of

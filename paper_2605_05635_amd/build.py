@@ -37,7 +37,8 @@ def build(verbose: bool = False, extra: list[str] | None = None) -> str:
     srcs = sorted(glob.glob(os.path.join(PKG, "csrc", "*.hip")))
     cmd = [HIPCC, *DEVICE_FLAGS, *CODEGEN_FLAGS, "-O3", "-std=c++17", "-fPIC", "-shared", "-Wall",
            "-I", os.path.join(ROOT, "include"), "-I", os.path.join(PKG, "csrc"),
-           *(extra or []), "-o", LIB + ".tmp", *srcs]
+           *(extra or []), "-o", LIB + ".tmp", *srcs,
+           "-L/opt/rocm/lib", "-Wl,-rpath,/opt/rocm/lib", "-lrocblas"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -465,6 +465,59 @@ int rt_set_kernel_timing(void* start_event, void* stop_event) {
     return RT_OK;
 }
 
+int rt_visibility_dft(const double* intensity, const rt_image_params* params, const double* uv,
+                      int32_t K, double* amp, double* vis, void* hip_stream) {
+    g_last_error.clear();
+    if (!intensity || !params || !uv || (!amp && !vis))
+        return fail(RT_ERR_ARG, "null intensity, params, uv or both outputs");
+    if (K < 1 || K > (1 << 22)) return fail(RT_ERR_ARG, "K must lie in [1, 2^22]");
+    const rt_image_params* p = params;
+    if (p->nx < 1 || p->ny < 1 || static_cast<int64_t>(p->nx) * p->ny >= (int64_t(1) << 31))
+        return fail(RT_ERR_ARG, "bad screen size %d x %d", p->nx, p->ny);
+    if (!finite_all({p->x_min, p->x_max, p->y_min, p->y_max}) || !(p->x_min < p->x_max) ||
+        !(p->y_min < p->y_max))
+        return fail(RT_ERR_ARG, "bad screen extent");
+    rt::ImageConst c;
+    std::memset(&c, 0, sizeof c);
+    c.nx = p->nx;
+    c.ny = p->ny;
+    c.n_pix = static_cast<int64_t>(p->nx) * p->ny;
+    c.x0 = p->x_min;
+    c.dx = (p->x_max - p->x_min) / p->nx;
+    c.y0 = p->y_min;
+    c.dy = (p->y_max - p->y_min) / p->ny;
+    int rc;
+    if ((rc = check_device_ptr(intensity, "intensity", 0)) || (rc = check_device_ptr(uv, "uv", 0)) ||
+        (rc = check_device_ptr(amp, "amp", 0)) || (rc = check_device_ptr(vis, "vis", 0)))
+        return rc;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    static thread_local void* handles[64] = {};
+    if (dev < 0 || dev >= 64) return fail(RT_ERR_HIP, "device index %d out of range", dev);
+    if (!handles[dev] && !(handles[dev] = rt::blas_create()))
+        return fail(RT_ERR_HIP, "rocblas_create_handle failed");
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    const size_t vis_bytes = rt::visibility_scratch_bytes(K, p->nx, p->ny);
+    const size_t bytes = vis_bytes + sizeof(double) * (4 + 3 * rt::kReduceBlocks);
+    void* scratch = nullptr;
+    e = hipMallocAsync(&scratch, bytes, stream);
+    if (e != hipSuccess || !scratch) {
+        (void)hipGetLastError();
+        return fail(RT_ERR_ALLOC, "stream-ordered allocation of %zu scratch bytes failed", bytes);
+    }
+    double* base = static_cast<double*>(scratch);
+    double* flux = base + vis_bytes / sizeof(double);
+    double* partials = flux + 4;
+    const char* what = "";
+    e = rt::launch_visibility(handles[dev], c, intensity, uv, K, flux, amp, vis, base, partials,
+                              stream, &what);
+    const hipError_t f = hipFreeAsync(scratch, stream);
+    if (e != hipSuccess) return hip_fail(e, what);
+    if (f != hipSuccess) return hip_fail(f, "hipFreeAsync");
+    return RT_OK;
+}
+
 int rt_set_launch_config(const rt_launch_config* cfg) {
     g_last_error.clear();
     if (!cfg) {

@@ -65,4 +65,18 @@ constexpr int kReduceBlocks = 256;
 hipError_t launch_reduce(const ImageConst& c, const double* intensity, double* partials,
                          double* out, hipStream_t stream);
 
+// Normalised visibility amplitudes (Sec. 6.4) of the image `intensity` on
+// the screen of c at K points uv[K][2]: amp[k] = |V_k| / |V(0,0)|, and the
+// unnormalised V_k into vis[K][2] when vis is not null.  `blas` is a rocBLAS
+// handle (blas_create), `scratch` holds visibility_scratch_bytes(K, nx, ny),
+// `flux` one double (receives F, with x_c, y_c after it: 3 doubles), and
+// reduce_partials 3 kReduceBlocks doubles.  On failure returns an error and
+// names the failing step in *what.
+size_t visibility_scratch_bytes(int32_t K, int32_t nx, int32_t ny);
+hipError_t launch_visibility(void* blas, const ImageConst& c, const double* intensity,
+                             const double* uv, int32_t K, double* flux, double* amp, double* vis,
+                             double* scratch, double* reduce_partials, hipStream_t stream,
+                             const char** what);
+void* blas_create();
+
 }  // namespace rt

@@ -73,6 +73,9 @@ def _load():
         f.restype = C.c_int
     lib.rt_image_setup.argtypes = [P, C.POINTER(C.c_double)]
     lib.rt_image_setup.restype = C.c_int
+    lib.rt_visibility_dft.argtypes = [C.c_void_p, C.POINTER(rt_image_params), C.c_void_p,
+                                      C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]
+    lib.rt_visibility_dft.restype = C.c_int
     lib.rt_set_launch_config.argtypes = [C.POINTER(rt_launch_config)]
     lib.rt_set_launch_config.restype = C.c_int
     lib.rt_get_launch_config.argtypes = [C.POINTER(rt_launch_config)]
@@ -168,6 +171,28 @@ def rt_set_kernel_timing(start_event, stop_event) -> None:
     _check(_lib.rt_set_kernel_timing(h(start_event), h(stop_event)))
 
 
+def rt_visibility_dft(intensity, params: rt_image_params, uv, amp=None, vis=None,
+                      stream=None) -> None:
+    """Calls rt_visibility_dft on device tensors: intensity [ny][nx] f64,
+    uv [K][2] f64, amp [K] f64 and/or vis [K][2] f64 (outputs)."""
+    K = int(uv.shape[0])
+    _check(_lib.rt_visibility_dft(C.c_void_p(intensity.data_ptr()), C.byref(params),
+                                  C.c_void_p(uv.data_ptr()), K,
+                                  None if amp is None else C.c_void_p(amp.data_ptr()),
+                                  None if vis is None else C.c_void_p(vis.data_ptr()),
+                                  _stream_handle(stream)))
+
+
+def visibility(img: dict, intensity, uv, stream=None):
+    """Normalised amplitudes |V|/|V(0,0)| of a traced image at the (u, v) points
+    uv (a numpy array or tensor [K][2]); returns a device tensor [K]."""
+    import torch
+    uv_t = torch.as_tensor(uv, dtype=torch.float64, device=intensity.device).contiguous()
+    amp = torch.empty(uv_t.shape[0], dtype=torch.float64, device=intensity.device)
+    rt_visibility_dft(intensity.contiguous(), params_from(img), uv_t, amp=amp, stream=stream)
+    return amp
+
+
 def rt_set_launch_config(chunk: int = 0, tile_w: int = 0, tile_h: int = 0,
                          blocks_per_cu: int = 0, reset: bool = False) -> None:
     """Work-distribution settings of later traces on this thread (see rt.h);
@@ -231,7 +256,7 @@ def trace_many(imgs: list, device="cuda", stream=None) -> list:
 
 
 __all__ = ["rt_trace_image", "rt_transfer_maps", "rt_image_setup", "rt_set_kernel_timing",
-           "rt_set_launch_config", "rt_get_launch_config",
+           "rt_set_launch_config", "rt_get_launch_config", "rt_visibility_dft", "visibility",
            "rt_version",
            "rt_last_error", "trace", "trace_many", "params_from", "out_from", "alloc_outputs",
            "RTError"]

@@ -151,3 +151,14 @@ def test_autotune_signature_and_cache(tmp_path, monkeypatch):
     assert autotune.signature(a) != autotune.signature(a[::-1])
     autotune._store({"k": {"chunk": 64}})
     assert autotune._load() == {"k": {"chunk": 64}}
+
+
+def test_visibility_argument_errors(rt):
+    lib = rt.lib()
+    p = rt.params_from(W.kerr_small())
+    assert lib.rt_visibility_dft(None, C.byref(p), None, 10, None, None, None) == rt.RT_ERR_ARG
+    assert lib.rt_visibility_dft(C.c_void_p(8), C.byref(p), C.c_void_p(8), 0, C.c_void_p(8),
+                                 None, None) == rt.RT_ERR_ARG
+    bad = rt.params_from(W.image(nx=0))
+    assert lib.rt_visibility_dft(C.c_void_p(8), C.byref(bad), C.c_void_p(8), 5, C.c_void_p(8),
+                                 None, None) == rt.RT_ERR_ARG

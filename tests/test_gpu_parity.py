@@ -211,3 +211,34 @@ def test_batch_parity_with_oracle(rt, orc):
         g = gpu_to_numpy(outs)
         o = orc.trace_pixels(img)
         assert_parity(g, o)
+
+
+def test_visibility_gaussian_closed_form(rt):
+    """|V|/|V(0,0)| of a Gaussian image is exp(-2 pi^2 s^2 q^2) (Sec. 6.4)."""
+    import torch
+    img = W.image(nx=181, ny=157, x_min=-12, x_max=12, y_min=-12, y_max=12)
+    X = img["x_min"] + (np.arange(img["nx"]) + 0.5) * 24 / img["nx"]
+    Y = img["y_min"] + (np.arange(img["ny"]) + 0.5) * 24 / img["ny"]
+    s = 1.4
+    I = np.exp(-((X[None, :] - 0.6) ** 2 + (Y[:, None] + 0.3) ** 2) / (2 * s * s))
+    uv = W.uv_points(5, 2000)
+    amp = rt.visibility(img, torch.tensor(I, device="cuda"), uv).cpu().numpy()
+    q2 = (uv ** 2).sum(1)
+    assert np.allclose(amp, np.exp(-2 * np.pi ** 2 * s * s * q2), rtol=0, atol=1e-10)
+
+
+def test_visibility_of_traced_image_matches_oracle(rt, orc):
+    import torch
+    img = W.image(metric="einasto", spin=0.9, halo=(0.14, 0.0), incl=math.radians(60),
+                  nx=96, ny=80, x_min=-10, x_max=10, y_min=-10, y_max=10)
+    outs = rt.trace(img)
+    uv = W.uv_points(6, 300)
+    amp = rt.visibility(img, outs["intensity"], uv).cpu().numpy()
+    torch.cuda.synchronize()
+    I = outs["intensity"].cpu().numpy()
+    want = orc.visibility_amplitude(img, I, uv)
+    assert np.allclose(amp, want, rtol=1e-11, atol=1e-13)
+    # and against the oracle's own traced image, to the trace parity bar
+    o = orc.trace_image(img)
+    want2 = orc.visibility_amplitude(img, o["intensity"], uv)
+    assert np.allclose(amp, want2, rtol=1e-6, atol=1e-9)
