@@ -80,6 +80,8 @@ def lib():
                                     C.POINTER(C.c_int)]
         L.orc_trace_pixels.argtypes = [P, I64, C.c_int64, I32, I32, I32, D, D, D, D, D, D]
         L.orc_image_setup.argtypes = [P, D]
+        L.orc_trace_grad_pixels.argtypes = [P, I64, C.c_int64, D, D]
+        L.orc_replay_pixels.argtypes = [P, P, I64, C.c_int64, D]
         assert L.orc_sizeof_params() == C.sizeof(OrcParams)
         assert L.orc_sizeof_ray() == C.sizeof(OrcRay)
         _lib = L
@@ -239,6 +241,81 @@ def trace_pixels(img: dict, idx=None, threads: int | None = None, chunk: int = 6
         with ThreadPoolExecutor(max_workers=threads) as ex:
             list(ex.map(work, starts))
     return out
+
+
+def _parallel(n: int, chunk: int, threads: int | None, fn) -> None:
+    starts = list(range(0, n, chunk))
+    threads = threads or os.cpu_count() or 1
+    if threads == 1 or len(starts) == 1:
+        for s0 in starts:
+            fn(s0, min(s0 + chunk, n))
+    else:
+        with ThreadPoolExecutor(max_workers=threads) as ex:
+            list(ex.map(lambda s0: fn(s0, min(s0 + chunk, n)), starts))
+
+
+def trace_grad_pixels(img: dict, idx, threads: int | None = None, chunk: int = 16):
+    """Intensity I and dI/dq for q = (chi, theta_o, halo0, halo1) of the frozen
+    discrete map (dual numbers), for the listed pixels: returns (I [n], G [n, 4])."""
+    idx = np.ascontiguousarray(idx, dtype=np.int64)
+    n = idx.size
+    I = np.zeros(n)
+    G = np.zeros((n, 4))
+    p = params(img)
+    L = lib()
+
+    def work(lo, hi):
+        sub = np.ascontiguousarray(idx[lo:hi])
+        i_loc = np.zeros(hi - lo)
+        g_loc = np.zeros((hi - lo, 4))
+        rc = L.orc_trace_grad_pixels(C.byref(p), sub.ctypes.data_as(C.POINTER(C.c_int64)),
+                                     hi - lo, _dp(i_loc), _dp(g_loc))
+        if rc != 0:
+            raise ValueError("no horizon for these parameters")
+        I[lo:hi] = i_loc
+        G[lo:hi] = g_loc
+
+    _parallel(n, chunk, threads, work)
+    return I, G
+
+
+def replay_pixels(base: dict, pert: dict, idx, threads: int | None = None, chunk: int = 16):
+    """Intensity of the frozen discrete map: each ray's attempts recorded at
+    `base`, replayed at the parameters `pert`."""
+    idx = np.ascontiguousarray(idx, dtype=np.int64)
+    n = idx.size
+    I = np.zeros(n)
+    pb, pp = params(base), params(pert)
+    L = lib()
+
+    def work(lo, hi):
+        sub = np.ascontiguousarray(idx[lo:hi])
+        i_loc = np.zeros(hi - lo)
+        rc = L.orc_replay_pixels(C.byref(pb), C.byref(pp),
+                                 sub.ctypes.data_as(C.POINTER(C.c_int64)), hi - lo, _dp(i_loc))
+        if rc != 0:
+            raise ValueError("no horizon for these parameters")
+        I[lo:hi] = i_loc
+
+    _parallel(n, chunk, threads, work)
+    return I
+
+
+GRAD_KEYS = ("spin", "incl", "halo0", "halo1")
+
+
+def perturbed(img: dict, j: int, delta: float) -> dict:
+    """img with parameter q_j (chi, theta_o, halo0, halo1) shifted by delta."""
+    d = dict(img)
+    if j == 0:
+        d["spin"] = img["spin"] + delta
+    elif j == 1:
+        d["incl"] = img["incl"] + delta
+    else:
+        h = list(img["halo"])
+        h[j - 2] += delta
+        d["halo"] = tuple(h)
+    return d
 
 
 def trace_image(img: dict, threads: int | None = None) -> dict:
