@@ -10,6 +10,7 @@
 #include <cmath>
 #include <cstdint>
 
+#include "rt_dual.h"
 #include "rt_math.h"
 
 namespace rt {
@@ -50,26 +51,28 @@ struct ImageConst {
 // F(R) = 2 R mu(R) (eq. (24)) and dF/dR for the chosen seed.  The mass
 // functions mu_E (from eq. (9)) and mu_cNFW (from eq. (13)) are written in
 // cancellation-free forms: mu_E = 1 - e^{-x}(1 + x + x^2/2) with x = R/lambda_E,
-// mu_cNFW = 1 - (R/2) expm1(Ex) with Ex the exponent of eq. (13).
-template <int METRIC, class K>
-__host__ __device__ inline void mass_function(const K& c, double R, double& F, double& dF) {
+// mu_cNFW = 1 - (R/2) expm1(Ex) with Ex the exponent of eq. (13).  K is any
+// struct with the fields inv_lam, lam_c, inv_lam_c, eta_lc; S is double or a
+// dual number (then K's fields may be dual too).
+template <int METRIC, class K, class S>
+__host__ __device__ inline void mass_function(const K& c, const S& R, S& F, S& dF) {
     if constexpr (METRIC == KERR) {
         F = 2.0 * R;
-        dF = 2.0;
+        dF = S(2.0);
     } else if constexpr (METRIC == EINASTO) {
-        const double x = R * c.inv_lam;
-        const double e = dm::exp(-x);
-        const double mu = 1.0 - e * (1.0 + x * (1.0 + 0.5 * x));
-        const double dmu = 0.5 * e * x * x * c.inv_lam;
+        const S x = R * c.inv_lam;
+        const S e = dm::exp(-x);
+        const S mu = 1.0 - e * (1.0 + x * (1.0 + 0.5 * x));
+        const S dmu = 0.5 * e * x * x * c.inv_lam;
         F = 2.0 * R * mu;
         dF = 2.0 * (mu + R * dmu);
     } else {
-        const double iR = 1.0 / R;
-        const double iRl = 1.0 / (R + c.lam_c);
-        const double lg = dm::log1p(R * c.inv_lam_c);
-        const double ex = c.eta_lc * (iRl - 2.0 * iR * lg);
-        const double dex = c.eta_lc * (2.0 * iR * (iR * lg - iRl) - iRl * iRl);
-        const double em1 = dm::expm1(ex);
+        const S iR = 1.0 / R;
+        const S iRl = 1.0 / (R + c.lam_c);
+        const S lg = dm::log1p(R * c.inv_lam_c);
+        const S ex = c.eta_lc * (iRl - 2.0 * iR * lg);
+        const S dex = c.eta_lc * (2.0 * iR * (iR * lg - iRl) - iRl * iRl);
+        const S em1 = dm::expm1(ex);
         F = R * (2.0 - R * em1);
         dF = 2.0 - R * (2.0 * em1 + R * (em1 + 1.0) * dex);
     }

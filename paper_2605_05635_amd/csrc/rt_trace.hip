@@ -18,424 +18,12 @@
 // carrying the few its step loop needs).  Compiled with floating-point
 // contraction limited to single expressions, the two produce bit-identical
 // rays.
-#include "rt_device.h"
-#include "rt_kernels.h"
-#include "rt_math.h"
+#include "rt_ray.h"
 
 namespace rt {
 namespace {
 
-constexpr double kHalfPi = 1.5707963267948966;
-
-__device__ __forceinline__ double rcp(double x) { return dm::recip(x); }
-
-// The constants of the step loop: a copy of the ImageConst fields the
-// right-hand side, the controller and the stop tests read.
-struct Hot {
-    double chi, chi2, inv_lam, lam_c, inv_lam_c, eta_lc;
-    double rtol, atol, r_stop, r_esc;
-    int32_t max_attempts;
-};
-
-__device__ __forceinline__ Hot hot_of(const ImageConst& c) {
-    Hot k;
-    k.chi = c.chi;
-    k.chi2 = c.chi2;
-    k.inv_lam = c.inv_lam;
-    k.lam_c = c.lam_c;
-    k.inv_lam_c = c.inv_lam_c;
-    k.eta_lc = c.eta_lc;
-    k.rtol = c.rtol;
-    k.atol = c.atol;
-    k.r_stop = c.r_stop;
-    k.r_esc = c.r_esc;
-    k.max_attempts = c.max_attempts;
-    return k;
-}
-
-// ---------------------------------------------------------------- the RHS
-// Hamilton's equations for H = g^{ab} p_a p_b / 2 with p_T = -E, p_phi = l.
-// The inverse metric of eqs. (49)-(53) is used through the algebraically
-// identical separated form of Sec. 3.1 (the Hamilton-Jacobi equation
-// multiplied by Sigma):
-//   2 Sigma H = N = Delta p_R^2 + p_theta^2 - P^2/Delta + W^2,
-//   P = (R^2 + chi^2) E - chi l,   W = l/sin(theta) - chi E sin(theta),
-// so that, with Sigma = R^2 + chi^2 cos^2(theta) (eq. (23)),
-//   dT/dl   = [P (R^2+chi^2)/Delta + chi (l - chi E sin^2)] / Sigma     (57)
-//   dR/dl   = Delta p_R / Sigma                                         (59)
-//   dth/dl  = p_theta / Sigma                                           (60)
-//   dphi/dl = [chi P/Delta + l/sin^2 - chi E] / Sigma                   (58)
-//   dp_R/dl = -dH/dR = (N R/Sigma - dN/dR / 2) / Sigma                  (61)
-//   dp_th/dl= -dH/dth = cos/Sigma [W (l/sin^2 + chi E) - chi^2 sin N/Sigma]  (62)
-// The N dSigma terms keep the full derivative of H off the constraint shell.
-template <int METRIC>
-__device__ __forceinline__ void rhs(const Hot& k, double E, double L, double R, double th,
-                                    double pR, double pth, double d[6]) {
-    double s, co;
-    dm::sincos(th, &s, &co);
-    double F, dF;
-    mass_function<METRIC>(k, R, F, dF);
-    const double R2 = R * R;
-    const double R2c = R2 + k.chi2;
-    const double Sig = R2 + k.chi2 * co * co;
-    const double Del = R2c - F;
-    const double dDel = 2.0 * R - dF;
-    const double iS = rcp(Sig);
-    const double iD = rcp(Del);
-    const double is = rcp(s);
-    const double P = R2c * E - k.chi * L;
-    const double PiD = P * iD;
-    const double Lis2 = L * is * is;
-    const double W = L * is - k.chi * E * s;
-    const double N = Del * pR * pR + pth * pth - P * PiD + W * W;
-    const double dN = dDel * (pR * pR + PiD * PiD) - 4.0 * R * E * PiD;
-    d[0] = (PiD * R2c + k.chi * (L - k.chi * E * s * s)) * iS;
-    d[1] = Del * pR * iS;
-    d[2] = pth * iS;
-    d[3] = (k.chi * PiD + Lis2 - k.chi * E) * iS;
-    d[4] = (N * R * iS - 0.5 * dN) * iS;
-    d[5] = co * iS * (W * (Lis2 + k.chi * E) - k.chi2 * s * N * iS);
-}
-
-// ------------------------------------------------ Dormand-Prince 5(4) tableau
-// Dormand & Prince (1980), first-same-as-last.
-constexpr double a21 = 0.2;
-constexpr double a31 = 3.0 / 40.0, a32 = 9.0 / 40.0;
-constexpr double a41 = 44.0 / 45.0, a42 = -56.0 / 15.0, a43 = 32.0 / 9.0;
-constexpr double a51 = 19372.0 / 6561.0, a52 = -25360.0 / 2187.0, a53 = 64448.0 / 6561.0,
-                 a54 = -212.0 / 729.0;
-constexpr double a61 = 9017.0 / 3168.0, a62 = -355.0 / 33.0, a63 = 46732.0 / 5247.0,
-                 a64 = 49.0 / 176.0, a65 = -5103.0 / 18656.0;
-constexpr double b1 = 35.0 / 384.0, b3 = 500.0 / 1113.0, b4 = 125.0 / 192.0,
-                 b5 = -2187.0 / 6784.0, b6 = 11.0 / 84.0;
-// Error weights: 5th-order minus embedded 4th-order weights.
-constexpr double e1 = 71.0 / 57600.0, e3 = -71.0 / 16695.0, e4 = 71.0 / 1920.0,
-                 e5 = -17253.0 / 339200.0, e6 = 22.0 / 525.0, e7 = -1.0 / 40.0;
-// Continuous extension in Hairer's form (Solving ODEs I, II.6):
-//   y(s) = y0 + s (r2 + (1-s)(r3 + s (r4 + (1-s) r5))),
-//   r2 = y1 - y0, r3 = h k1 - r2, r4 = r2 - h k7 - r3, r5 = h sum_i d_i k_i.
-constexpr double d1 = -12715105075.0 / 11282082432.0, d3 = 87487479700.0 / 32700410799.0,
-                 d4 = -10690763975.0 / 1880347072.0, d5 = 701980252875.0 / 199316789632.0,
-                 d6 = -1453857185.0 / 822651844.0, d7 = 69997945.0 / 29380423.0;
-
-struct DenseComp {
-    double y0, r2, r3, r4, r5;
-    __device__ __forceinline__ double at(double s) const {
-        return y0 + s * (r2 + (1.0 - s) * (r3 + s * (r4 + (1.0 - s) * r5)));
-    }
-};
-
-// ------------------------------------------------------------ emission
-// Keplerian equatorial emitter (eqs. (90)-(91)) and redshift (eq. (89)) for a
-// photon with constants (E, l) and unit observer-frame energy.  At theta =
-// pi/2, Sigma = R^2 and with G = d(F/R^2)/dR the metric derivatives are
-// dg_TT = G, dg_Tphi = -chi G, dg_phiphi = 2R + chi^2 G, so eq. (91) reads
-// Omega = (chi G + sqrt(-2 R G)) / (2R + chi^2 G).  g = 0 where no timelike
-// circular orbit exists.
-template <int METRIC>
-__device__ __forceinline__ double redshift(const Hot& k, double R, double E, double L) {
-    double F, dF;
-    mass_function<METRIC>(k, R, F, dF);
-    const double iR = 1.0 / R;
-    const double FoR2 = F * iR * iR;
-    const double G = (dF - 2.0 * F * iR) * iR * iR;
-    const double disc = -2.0 * R * G;
-    if (!(disc >= 0.0)) return 0.0;
-    const double Om = (k.chi * G + sqrt(disc)) / (2.0 * R + k.chi2 * G);
-    const double gTT = -(1.0 - FoR2);
-    const double gTp = -k.chi * FoR2;
-    const double gpp = R * R + k.chi2 + k.chi2 * FoR2;
-    const double A = -(gTT + Om * (2.0 * gTp + Om * gpp));
-    if (!(A > 0.0)) return 0.0;
-    const double den = E - Om * L;
-    if (!(den > 0.0)) return 0.0;
-    return sqrt(A) / den;
-}
-
-__device__ __forceinline__ double disc_window(const ImageConst& c, double R) {
-    if (c.taper) {
-        const double tin = 0.5 * (1.0 + tanh((R - c.r_in) / c.sigma_in));
-        const double tout = 0.5 * (1.0 - tanh((R - c.r_out) / c.sigma_out));
-        return tin * tout;
-    }
-    return (R >= c.r_in && R <= c.r_out) ? 1.0 : 0.0;
-}
-
-// ------------------------------------------------------------- ray state
-struct Ray {
-    double y[6];    // T, R, theta, phi, p_R, p_theta
-    double k1[6];   // f(y), first-same-as-last
-    double E, L;
-    double h, lam, last_cross;
-    double rc[3];   // radii of the first three trusted crossings
-    int32_t attempts, ncross;
-    int32_t after_reject;
-    int64_t pix;
-};
-
-// Pixel index of the p-th pixel of an nx x ny screen in tile order: tiles of
-// tw x th pixels, taken row by row; pixels inside a tile row by row; tiles on
-// the right and bottom edges are clipped to the screen.  tw = nx, th = 1 is
-// plain row-major order.  A bijection of [0, nx ny).
-__device__ __forceinline__ int64_t tile_pixel(int64_t p, int32_t nx, int32_t ny, int32_t tw,
-                                              int32_t th) {
-    const int64_t band = static_cast<int64_t>(th) * nx;   // pixels per full tile row
-    const int64_t r = p / band;                             // tile row
-    const int64_t h = (r + 1) * th <= ny ? th : ny - r * th;
-    const int64_t q = p - r * band;                          // index inside the tile row
-    const int64_t full = nx / tw;                            // unclipped tiles per row
-    const int64_t j = q / (static_cast<int64_t>(tw) * h);
-    int64_t ix, iy;
-    if (j < full) {
-        const int64_t off = q - j * tw * h;
-        iy = r * th + off / tw;
-        ix = j * tw + off % tw;
-    } else {
-        const int64_t w = nx - full * tw;
-        const int64_t off = q - full * tw * h;
-        iy = r * th + off / w;
-        ix = full * tw + off % w;
-    }
-    return iy * nx + ix;
-}
-
-// Screen pixel -> initial state (Sec. 3.2, eqs. (70)-(74) with E_loc = 1):
-// with n = -(R_o, Y, X)/sqrt(R_o^2 + X^2 + Y^2) in the ZAMO triad, lowering
-// p^mu = u_o + n^(a) e_(a) with the observer metric gives
-// E = N_o - g_Tphi n^(phi)/sqrt(g_phiphi), l = sqrt(g_phiphi) n^(phi),
-// p_R = sqrt(g_RR) n^(R), p_theta = sqrt(g_thth) n^(theta).
-template <int METRIC>
-__device__ __forceinline__ void start_ray(const ImageConst& c, const Hot& k, int64_t pix,
-                                          Ray& r) {
-    const int64_t iy = pix / c.nx;
-    const int64_t ix = pix - iy * c.nx;
-    const double X = c.x0 + (static_cast<double>(ix) + 0.5) * c.dx;
-    const double Y = c.y0 + (static_cast<double>(iy) + 0.5) * c.dy;
-    const double inv = 1.0 / sqrt(c.r_obs * c.r_obs + X * X + Y * Y);
-    const double nR = -c.r_obs * inv, nth = -Y * inv, nph = -X * inv;
-    r.E = c.obs_N - c.obs_gTph_over_sq_gphph * nph;
-    r.L = c.obs_sq_gphph * nph;
-    r.y[0] = 0.0;
-    r.y[1] = c.r_obs;
-    r.y[2] = c.incl;
-    r.y[3] = 0.0;
-    r.y[4] = c.obs_sq_gRR * nR;
-    r.y[5] = c.obs_sq_gthth * nth;
-    rhs<METRIC>(k, r.E, r.L, r.y[1], r.y[2], r.y[4], r.y[5], r.k1);
-    r.h = c.h0;
-    r.lam = 0.0;
-    r.last_cross = -INFINITY;
-    r.rc[0] = r.rc[1] = r.rc[2] = 0.0;
-    r.attempts = 0;
-    r.ncross = 0;
-    r.after_reject = 0;
-    r.pix = pix;
-}
-
-// Root of theta(s) = pi/2 on the step's continuous extension, s in (0, 1),
-// given theta(0) and theta(1) on opposite sides.  Writing the extension as
-// y0 + s (c1 + s (c2 + s (c3 + s c4))), Newton's method starts from the secant
-// root and is kept inside the shrinking sign bracket (bisection when a Newton
-// step would leave it); it stops when the step falls below 1e-15 or the
-// bracket is exhausted.
-__device__ __forceinline__ double crossing_root(const DenseComp& d, bool up0) {
-    const double c1 = d.r2 + d.r3;
-    const double c2 = d.r4 + d.r5 - d.r3;
-    const double c3 = -d.r4 - 2.0 * d.r5;
-    const double c4 = d.r5;
-    double a = 0.0, b = 1.0;
-    double s = (kHalfPi - d.y0) / d.r2;
-    if (!(s > 0.0 && s < 1.0)) s = 0.5;
-    for (int it = 0; it < 48; ++it) {
-        const double f = d.y0 + s * (c1 + s * (c2 + s * (c3 + s * c4))) - kHalfPi;
-        if ((f >= 0.0) == up0) a = s; else b = s;
-        const double df = c1 + s * (2.0 * c2 + s * (3.0 * c3 + s * 4.0 * c4));
-        double sn = s - f / df;
-        if (!(sn > a && sn < b)) sn = 0.5 * (a + b);
-        const double step = fabs(sn - s);
-        s = sn;
-        if (step <= 1e-15 || b - a <= 1e-15) break;
-    }
-    return s;
-}
-
-// One step attempt.  Returns 0 while the ray runs, else its final status.
-// The 5th-order update, the error estimate and the continuous-extension
-// coefficient r5 are accumulated as the stages are produced, so a stage
-// derivative stays live only while later stage inputs still need it.
-template <int METRIC>
-__device__ __forceinline__ int32_t attempt(const Hot& k, const OutPtrs& o, int64_t n_pix,
-                                           Ray& r) {
-    if (r.attempts >= k.max_attempts) return RAY_STEP_LIMIT;
-    ++r.attempts;
-    const double h = r.h;
-    double ab[6], ae[6], ad[6];     // sums of b_i k_i, e_i k_i, d_i k_i
-    double k2[6], k3[6], k4[6], k5[6], kk[6], t[6];
-    for (int i = 0; i < 6; ++i) {
-        ab[i] = b1 * r.k1[i];
-        ae[i] = e1 * r.k1[i];
-        ad[i] = d1 * r.k1[i];
-    }
-#define RT_STAGE(expr, out)                                                      \
-    for (int i = 0; i < 6; ++i) t[i] = r.y[i] + h * (expr);                       \
-    rhs<METRIC>(k, r.E, r.L, t[1], t[2], t[4], t[5], out);
-#define RT_ACC(bb, ee, dd, kv)                                                   \
-    for (int i = 0; i < 6; ++i) {                                                \
-        ab[i] += bb * kv[i];                                                     \
-        ae[i] += ee * kv[i];                                                     \
-        ad[i] += dd * kv[i];                                                     \
-    }
-    RT_STAGE(a21 * r.k1[i], k2)
-    RT_STAGE(a31 * r.k1[i] + a32 * k2[i], k3)
-    RT_ACC(b3, e3, d3, k3)
-    RT_STAGE(a41 * r.k1[i] + a42 * k2[i] + a43 * k3[i], k4)
-    RT_ACC(b4, e4, d4, k4)
-    RT_STAGE(a51 * r.k1[i] + a52 * k2[i] + a53 * k3[i] + a54 * k4[i], k5)
-    RT_ACC(b5, e5, d5, k5)
-    RT_STAGE(a61 * r.k1[i] + a62 * k2[i] + a63 * k3[i] + a64 * k4[i] + a65 * k5[i], kk)
-    RT_ACC(b6, e6, d6, kk)
-#undef RT_STAGE
-#undef RT_ACC
-    double yn[6];
-    for (int i = 0; i < 6; ++i) yn[i] = r.y[i] + h * ab[i];
-    rhs<METRIC>(k, r.E, r.L, yn[1], yn[2], yn[4], yn[5], kk);   // k7 (first-same-as-last)
-    double acc = 0.0;
-    for (int i = 0; i < 6; ++i) {
-        ae[i] += e7 * kk[i];
-        ad[i] += d7 * kk[i];
-        const double sc = k.atol + k.rtol * fmax(fabs(r.y[i]), fabs(yn[i]));
-        const double q = h * ae[i] * rcp(sc);
-        acc += q * q;
-    }
-    // err^2 = mean of the squared scaled errors; the step is accepted when
-    // err < 1 and the size factor is 0.9 err^(-1/5) = 0.9 (err^2)^(-1/10),
-    // clipped to [0.2, 10] (err = 0 gives the maximum, a non-finite err the
-    // minimum).  Outside err^2 in [1e-12, 1e12] the clip decides the factor.
-    const double err2 = acc * (1.0 / 6.0);
-    const double grow = 0.9 * dm::rpow_tenth(fmin(fmax(err2, 1e-12), 1e12));
-    if (!(err2 < 1.0)) {  // reject; NaN lands here too
-        r.h = h * (isfinite(err2) ? fmax(0.2, grow) : 0.2);
-        r.after_reject = 1;
-        return 0;
-    }
-    double factor = err2 == 0.0 ? 10.0 : fmin(10.0, grow);
-    if (r.after_reject) factor = fmin(1.0, factor);
-    r.after_reject = 0;
-
-    // Equatorial crossing (Sec. 3.3): the sign of theta - pi/2 changes.
-    const bool up0 = (r.y[2] - kHalfPi) >= 0.0;
-    const bool up1 = (yn[2] - kHalfPi) >= 0.0;
-    if (up0 != up1) {
-        auto dense = [&](int i) {
-            DenseComp d;
-            d.y0 = r.y[i];
-            d.r2 = yn[i] - r.y[i];
-            d.r3 = h * r.k1[i] - d.r2;
-            d.r4 = d.r2 - h * kk[i] - d.r3;
-            d.r5 = h * ad[i];
-            return d;
-        };
-        const double s = crossing_root(dense(2), up0);
-        const double Rc = dense(1).at(s);
-        const double pthc = dense(5).at(s);
-        const double lc = r.lam + s * h;
-        // trusted crossing (Sec. 4.2): |dtheta/dlambda| = |p_theta|/R^2 bounded away
-        // from zero and not a repeat within a tiny affine interval
-        if (fabs(pthc) >= 1e-12 * Rc * Rc && (lc - r.last_cross) >= 1e-10) {
-            const int n = r.ncross;
-            if (n < 3) {
-                const int64_t off = static_cast<int64_t>(n) * n_pix + r.pix;
-                // (selects, not r.rc[n]: a runtime index would put the ray in scratch)
-                r.rc[0] = n == 0 ? Rc : r.rc[0];
-                r.rc[1] = n == 1 ? Rc : r.rc[1];
-                r.rc[2] = n == 2 ? Rc : r.rc[2];
-                if (o.r_em) o.r_em[off] = Rc;
-                if (o.phi_em) o.phi_em[off] = dense(3).at(s);
-                if (o.t_em) o.t_em[off] = dense(0).at(s);
-            }
-            if (r.ncross < 255) ++r.ncross;
-            r.last_cross = lc;
-        }
-    }
-
-    for (int i = 0; i < 6; ++i) {
-        r.y[i] = yn[i];
-        r.k1[i] = kk[i];
-    }
-    r.lam += h;
-    r.h = h * factor;
-    if (r.y[1] <= k.r_stop) return RAY_CAPTURED;   // eq. (75)
-    if (r.y[1] >= k.r_esc) return RAY_ESCAPED;
-    return 0;
-}
-
-// Ray epilogue: emission of the recorded crossings (Sec. 5.2, evaluated once
-// per ray rather than inside the step loop), then the per-pixel outputs.
-// Records n >= min(N_cross, 3) are NaN.
-template <int METRIC>
-__device__ __forceinline__ void finish_ray(const ImageConst& c, const Hot& k, const OutPtrs& o,
-                                           const Ray& r, int32_t status) {
-    const int64_t p = r.pix;
-    const int64_t n_pix = c.n_pix;
-    const int nrec = r.ncross < 3 ? r.ncross : 3;
-    const double nan = __builtin_nan("");
-    if (c.emission) {
-        double intensity = 0.0;
-        for (int n = 0; n < 3; ++n) {
-            const int64_t off = static_cast<int64_t>(n) * n_pix + p;
-            double g = nan, In = nan;
-            if (n < nrec) {
-                const double R = r.rc[n];
-                g = redshift<METRIC>(k, R, r.E, r.L);
-                In = disc_window(c, R) * g * g * g * pow(R, -c.emis_pow);
-                intensity += In;
-            }
-            if (o.g_em) o.g_em[off] = g;
-            if (o.intensity_n) o.intensity_n[off] = In;
-        }
-        if (o.intensity) o.intensity[p] = intensity;
-    }
-    if (o.ncross) o.ncross[p] = static_cast<uint8_t>(r.ncross);
-    if (o.status) o.status[p] = static_cast<uint8_t>(status);
-    if (o.attempts) o.attempts[p] = r.attempts;
-    for (int n = nrec; n < 3; ++n) {
-        const int64_t off = static_cast<int64_t>(n) * n_pix + p;
-        if (o.r_em) o.r_em[off] = nan;
-        if (o.phi_em) o.phi_em[off] = nan;
-        if (o.t_em) o.t_em[off] = nan;
-    }
-}
-
-// Wave-level hand-out of pixels: lanes without a ray take consecutive
-// ordinals from the wave's current chunk; the wave claims a new chunk (one
-// atomic, lane 0) when it runs dry.  Called with all lanes converged.
-// `claim()` returns false when the queue is exhausted and otherwise sets the
-// chunk's ordinal range [next, end) (and whatever image state it tracks);
-// `take(ordinal)` starts a ray on the calling lane.
-template <class Claim, class Take>
-__device__ __forceinline__ void refill(bool& active, bool& exhausted, int64_t& next,
-                                       int64_t& end, Claim claim, Take take) {
-    const int lane = __lane_id();
-    unsigned long long need = __ballot(!active);
-    while (need != 0ull) {
-        if (next >= end) {
-            if (!claim()) {
-                exhausted = true;
-                return;
-            }
-        }
-        const int64_t avail = end - next;
-        const int nneed = __popcll(need);
-        const int tk = avail < nneed ? static_cast<int>(avail) : nneed;
-        const int rank = __popcll(need & ((1ull << lane) - 1ull));
-        if (!active && rank < tk) {
-            take(next + rank);
-            active = true;
-        }
-        next += tk;
-        need = __ballot(!active);
-    }
-}
+using namespace ray;
 
 // Persistent trace kernel for one image.
 template <int METRIC>
