@@ -1,8 +1,8 @@
 // rt_ray.h -- the per-ray computation shared by the trace and adjoint
-// kernels: the right-hand side of the geodesic equations and its reverse-mode
-// derivative, one Dormand-Prince 5(4) step attempt with its controller and
-// crossing events, the screen map, the emission and the wave-level work
-// hand-out.  Everything a ray computes is written here once.
+// kernels: the right-hand side of the geodesic equations, one Dormand-Prince
+// 5(4) step attempt with its controller and crossing events, the screen map,
+// the emission and the wave-level work hand-out.  Everything a ray computes
+// is written here once (host and device; the reverse mode is in rt_vjp.h).
 //
 // Paper: M. Fathi, "Adaptive ray tracing, image diagnostics, and photon ring
 // signatures of rotating dark-matter-dressed black holes".  Units M = 1.
@@ -18,7 +18,9 @@ namespace ray {
 
 constexpr double kHalfPi = 1.5707963267948966;
 
-__host__ __device__ inline double rcp(double x) { return dm::recip(x); }
+__host__ __device__ __forceinline__ double rcp(double x) { return dm::recip(x); }
+template <int N>
+__host__ __device__ __forceinline__ Dual<N> rcp(const Dual<N>& x) { return 1.0 / x; }
 
 // The constants of the step loop: a copy of the ImageConst fields the
 // right-hand side, the controller and the stop tests read.
@@ -28,7 +30,14 @@ struct Hot {
     int32_t max_attempts;
 };
 
-__host__ __device__ inline Hot hot_of(const ImageConst& c) {
+// The metric constants with a scalar type of choice (dual numbers when
+// differentiating with respect to them).
+template <class S>
+struct Coeffs {
+    S chi, chi2, inv_lam, lam_c, inv_lam_c, eta_lc;
+};
+
+__host__ __device__ __forceinline__ Hot hot_of(const ImageConst& c) {
     Hot k;
     k.chi = c.chi;
     k.chi2 = c.chi2;
@@ -59,27 +68,27 @@ __host__ __device__ inline Hot hot_of(const ImageConst& c) {
 //   dp_R/dl = -dH/dR = (N R/Sigma - dN/dR / 2) / Sigma                  (61)
 //   dp_th/dl= -dH/dth = cos/Sigma [W (l/sin^2 + chi E) - chi^2 sin N/Sigma]  (62)
 // The N dSigma terms keep the full derivative of H off the constraint shell.
-template <int METRIC>
-__host__ __device__ inline void rhs(const Hot& k, double E, double L, double R, double th,
-                                    double pR, double pth, double d[6]) {
-    double s, co;
+template <int METRIC, class K, class S>
+__host__ __device__ __forceinline__ void rhs(const K& k, const S& E, const S& L, const S& R, const S& th,
+                                    const S& pR, const S& pth, S d[6]) {
+    S s, co;
     dm::sincos(th, &s, &co);
-    double F, dF;
+    S F, dF;
     mass_function<METRIC>(k, R, F, dF);
-    const double R2 = R * R;
-    const double R2c = R2 + k.chi2;
-    const double Sig = R2 + k.chi2 * co * co;
-    const double Del = R2c - F;
-    const double dDel = 2.0 * R - dF;
-    const double iS = rcp(Sig);
-    const double iD = rcp(Del);
-    const double is = rcp(s);
-    const double P = R2c * E - k.chi * L;
-    const double PiD = P * iD;
-    const double Lis2 = L * is * is;
-    const double W = L * is - k.chi * E * s;
-    const double N = Del * pR * pR + pth * pth - P * PiD + W * W;
-    const double dN = dDel * (pR * pR + PiD * PiD) - 4.0 * R * E * PiD;
+    const S R2 = R * R;
+    const S R2c = R2 + k.chi2;
+    const S Sig = R2 + k.chi2 * co * co;
+    const S Del = R2c - F;
+    const S dDel = 2.0 * R - dF;
+    const S iS = rcp(Sig);
+    const S iD = rcp(Del);
+    const S is = rcp(s);
+    const S P = R2c * E - k.chi * L;
+    const S PiD = P * iD;
+    const S Lis2 = L * is * is;
+    const S W = L * is - k.chi * E * s;
+    const S N = Del * pR * pR + pth * pth - P * PiD + W * W;
+    const S dN = dDel * (pR * pR + PiD * PiD) - 4.0 * R * E * PiD;
     d[0] = (PiD * R2c + k.chi * (L - k.chi * E * s * s)) * iS;
     d[1] = Del * pR * iS;
     d[2] = pth * iS;
@@ -124,7 +133,7 @@ struct DenseComp {
 // Omega = (chi G + sqrt(-2 R G)) / (2R + chi^2 G).  g = 0 where no timelike
 // circular orbit exists.
 template <int METRIC, class K, class S>
-__host__ __device__ inline S redshift(const K& k, const S& R, const S& E, const S& L) {
+__host__ __device__ __forceinline__ S redshift(const K& k, const S& R, const S& E, const S& L) {
     S F, dF;
     mass_function<METRIC>(k, R, F, dF);
     const S iR = 1.0 / R;
@@ -146,7 +155,7 @@ __host__ __device__ inline S redshift(const K& k, const S& R, const S& E, const 
 // Disc window at equatorial radius R (eq. (77), or the tanh tapers of
 // eqs. (85)-(86) with rho = R) for an inner edge r_in.
 template <class S>
-__host__ __device__ inline S disc_window(const ImageConst& c, const S& R, const S& r_in) {
+__host__ __device__ __forceinline__ S disc_window(const ImageConst& c, const S& R, const S& r_in) {
     if (c.taper) {
         const S tin = 0.5 * (1.0 + tanh((R - r_in) / c.sigma_in));
         const S tout = 0.5 * (1.0 - tanh((R - c.r_out) / c.sigma_out));
@@ -198,23 +207,30 @@ __device__ __forceinline__ int64_t tile_pixel(int64_t p, int32_t nx, int32_t ny,
 // p^mu = u_o + n^(a) e_(a) with the observer metric gives
 // E = N_o - g_Tphi n^(phi)/sqrt(g_phiphi), l = sqrt(g_phiphi) n^(phi),
 // p_R = sqrt(g_RR) n^(R), p_theta = sqrt(g_thth) n^(theta).
-template <int METRIC>
-__device__ __forceinline__ void start_ray(const ImageConst& c, const Hot& k, int64_t pix,
-                                          Ray& r) {
+struct ScreenDir {
+    double nR, nth, nph;
+};
+
+__host__ __device__ __forceinline__ ScreenDir screen_dir(const ImageConst& c, int64_t pix) {
     const int64_t iy = pix / c.nx;
     const int64_t ix = pix - iy * c.nx;
     const double X = c.x0 + (static_cast<double>(ix) + 0.5) * c.dx;
     const double Y = c.y0 + (static_cast<double>(iy) + 0.5) * c.dy;
     const double inv = 1.0 / sqrt(c.r_obs * c.r_obs + X * X + Y * Y);
-    const double nR = -c.r_obs * inv, nth = -Y * inv, nph = -X * inv;
-    r.E = c.obs_N - c.obs_gTph_over_sq_gphph * nph;
-    r.L = c.obs_sq_gphph * nph;
+    return ScreenDir{-c.r_obs * inv, -Y * inv, -X * inv};
+}
+
+template <int METRIC>
+__host__ __device__ __forceinline__ void start_ray(const ImageConst& c, const Hot& k, int64_t pix, Ray& r) {
+    const ScreenDir n = screen_dir(c, pix);
+    r.E = c.obs_N - c.obs_gTph_over_sq_gphph * n.nph;
+    r.L = c.obs_sq_gphph * n.nph;
     r.y[0] = 0.0;
     r.y[1] = c.r_obs;
     r.y[2] = c.incl;
     r.y[3] = 0.0;
-    r.y[4] = c.obs_sq_gRR * nR;
-    r.y[5] = c.obs_sq_gthth * nth;
+    r.y[4] = c.obs_sq_gRR * n.nR;
+    r.y[5] = c.obs_sq_gthth * n.nth;
     rhs<METRIC>(k, r.E, r.L, r.y[1], r.y[2], r.y[4], r.y[5], r.k1);
     r.h = c.h0;
     r.lam = 0.0;
@@ -232,7 +248,7 @@ __device__ __forceinline__ void start_ray(const ImageConst& c, const Hot& k, int
 // root and is kept inside the shrinking sign bracket (bisection when a Newton
 // step would leave it); it stops when the step falls below 1e-15 or the
 // bracket is exhausted.
-__host__ __device__ inline double crossing_root(const DenseComp& d, bool up0) {
+__host__ __device__ __forceinline__ double crossing_root(const DenseComp& d, bool up0) {
     const double c1 = d.r2 + d.r3;
     const double c2 = d.r4 + d.r5 - d.r3;
     const double c3 = -d.r4 - 2.0 * d.r5;
@@ -258,8 +274,7 @@ __host__ __device__ inline double crossing_root(const DenseComp& d, bool up0) {
 // coefficient r5 are accumulated as the stages are produced, so a stage
 // derivative stays live only while later stage inputs still need it.
 template <int METRIC>
-__device__ __forceinline__ int32_t attempt(const Hot& k, const OutPtrs& o, int64_t n_pix,
-                                           Ray& r) {
+__host__ __device__ __forceinline__ int32_t attempt(const Hot& k, const OutPtrs& o, int64_t n_pix, Ray& r) {
     if (r.attempts >= k.max_attempts) return RAY_STEP_LIMIT;
     ++r.attempts;
     const double h = r.h;
@@ -308,7 +323,7 @@ __device__ __forceinline__ int32_t attempt(const Hot& k, const OutPtrs& o, int64
     const double err2 = acc * (1.0 / 6.0);
     const double grow = 0.9 * dm::rpow_tenth(fmin(fmax(err2, 1e-12), 1e12));
     if (!(err2 < 1.0)) {  // reject; NaN lands here too
-        r.h = h * (isfinite(err2) ? fmax(0.2, grow) : 0.2);
+        r.h = h * (__builtin_isfinite(err2) ? fmax(0.2, grow) : 0.2);
         r.after_reject = 1;
         return 0;
     }
