@@ -13,7 +13,6 @@ strided sample of the same screen.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -25,19 +24,10 @@ if ROOT not in sys.path:
 
 METRIC = "geodesic rays/s at 1024² (FP64 vs mixed); adjoint image-gradient ms"
 FP64_VECTOR_PEAK_TFLOPS = 78.6   # MI355X: 256 CUs x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
-TRACE_SOURCES = ("paper_2605_05635_amd/csrc/rt_trace.hip", "paper_2605_05635_amd/csrc/rt_device.h")
 
 
 def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
-
-
-def trace_source_hash() -> str:
-    h = hashlib.sha256()
-    for p in TRACE_SOURCES:
-        with open(os.path.join(ROOT, p), "rb") as f:
-            h.update(f.read())
-    return h.hexdigest()[:16]
 
 
 def measured_traffic(kernel_hash: str):
@@ -117,6 +107,68 @@ def batch_measurement(steps: int) -> dict:
             "visibility_finite": bool(all(torch.isfinite(a).all().item() for a in amps))}
 
 
+def adjoint_measurement(steps: int, cpu: bool) -> dict:
+    """Image gradient of the cored-NFW 256x256 tapered-disc image (chi = 0.94,
+    theta_o = 60 deg, (eta, lambda_c) = (0.02, 10)) for the loss
+    L = sum (I - I_target)^2, I_target traced at a 1 % change of
+    (chi, theta_o, rho_s, r_s): wall time of rt_image_vjp per call (all its
+    passes and its one host synchronisation), beside the forward trace of the
+    same image."""
+    import math
+
+    import numpy as np
+    import torch
+
+    from paper_2605_05635_amd import rt, workloads as W
+    img = W.cnfw_adjoint_256()
+    eta, lc = img["halo"]
+    q = np.array([img["spin"], img["incl"], eta / (4 * math.pi * lc * lc), lc])
+    qt = q * (1 + 0.01 * W.adjoint_target_signs())
+    tgt = dict(img, spin=float(qt[0]), incl=float(qt[1]),
+               halo=(float(4 * math.pi * qt[2] * qt[3] ** 2), float(qt[3])))
+    stream = torch.cuda.current_stream()
+    outs = rt.alloc_outputs(img)
+    p, o = [rt.params_from(img)], [rt.out_from(outs)]
+    rt.rt_trace_image(p, o, stream)
+    I_t = rt.trace(tgt)["intensity"]
+    dl = 2.0 * (outs["intensity"] - I_t)
+    grad = torch.empty(4, dtype=torch.float64, device="cuda")
+    rt.rt_image_vjp(p[0], dl, grad, None, rt.RT_GRAD_DENSITY, stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        rt.rt_image_vjp(p[0], dl, grad, None, rt.RT_GRAD_DENSITY, stream)
+    torch.cuda.synchronize()
+    adj_ms = (time.perf_counter() - t0) * 1e3 / steps
+    stats = rt.rt_vjp_stats()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(steps):
+        rt.rt_trace_image(p, o, stream)
+    b.record(stream)
+    torch.cuda.synchronize()
+    fwd_ms = a.elapsed_time(b) / steps
+    loss = float(((outs["intensity"] - I_t) ** 2).sum().item())
+    log(f"adjoint: {adj_ms:.2f} ms per gradient, forward {fwd_ms:.2f} ms")
+    res = {"workload": "cored-NFW 256x256, tapered disc, L2 loss vs a 1 % parameter change",
+           "adjoint_ms": adj_ms, "forward_ms": fwd_ms, "ratio": adj_ms / fwd_ms,
+           "steps": steps, "loss": loss, "grad_chi_theta_rho_rs": grad.cpu().tolist(),
+           "taped_rays": stats["rays"], "tape_steps": stats["steps"],
+           "tape_bytes": stats["tape_bytes"]}
+    if cpu:
+        from oracle import oracle as O
+        threads = max(1, min(16, os.cpu_count() or 1))
+        idx = W.subsample_indices(img["nx"], img["ny"], 8)
+        t0 = time.perf_counter()
+        O.trace_grad_pixels(img, idx, threads=threads)
+        dt = time.perf_counter() - t0
+        res["cpu_dual_gradient"] = {
+            "ms_per_image": dt * 1e3 * img["nx"] * img["ny"] / idx.size, "cores": threads,
+            "kind": "oracle", "sample": f"every 8th pixel in x and y ({idx.size} rays, "
+                                        f"{dt:.1f} s), scaled to the image"}
+    return res
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -126,6 +178,8 @@ def main() -> int:
     ap.add_argument("--cpu-stride", type=int, default=1)
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the 64-image batched trace + visibility measurement")
+    ap.add_argument("--no-adjoint", action="store_true",
+                    help="skip the image-gradient measurement")
     ap.add_argument("--calibration-copy-mib", type=int, default=0,
                     help="after the timed steps, run one plain device-to-device copy of this "
                          "many MiB (the reference kernel for HBM byte counters) and report it")
@@ -179,6 +233,7 @@ def main() -> int:
              + n_rays * (20 + census.flops_rhs(img["metric"])))
     k_s = float(np.mean(kernel_ms)) * 1e-3
     achieved = flops / k_s / 1e12
+    from paper_2605_05635_amd.profiling import trace_source_hash
     khash = trace_source_hash()
     roofline = {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
@@ -201,6 +256,8 @@ def main() -> int:
     }
     if not args.no_batch:
         line["batch_64"] = batch_measurement(max(2, args.steps // 4))
+    if not args.no_adjoint:
+        line["adjoint"] = adjoint_measurement(max(2, args.steps // 2), not args.no_cpu_baseline)
     if args.calibration_copy_mib > 0:
         nbytes = args.calibration_copy_mib << 20
         src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")

@@ -157,6 +157,48 @@ int rt_set_kernel_timing(void *start_event, void *stop_event);
 int rt_visibility_dft(const double *intensity, const rt_image_params *params, const double *uv,
                       int32_t K, double *amp, double *vis, void *hip_stream);
 
+/* Bases of the image gradient: the parameters as rt_image_params holds them,
+ * q = (spin, incl, halo[0], halo[1]), or for the cored-NFW halo its density
+ * and scale, q = (spin, incl, rho_s, r_s) with eta = 4 pi rho_s r_s^2 and
+ * lambda_c = r_s (eq. (13) and the halo parametrisation of Sec. 2.1). */
+enum { RT_GRAD_NATIVE = 0, RT_GRAD_DENSITY = 1 };
+
+/* Gradient of a scalar loss L(I) of the thin-disc image with respect to the
+ * four image parameters q (basis above), by reverse mode through the map the
+ * trace computes (Sec. 3.1-3.3 geodesics, Sec. 5.2 eqs. (89)-(91) emission,
+ * Sec. 3.2 eqs. (70)-(74) screen map).  It is the exact derivative of the
+ * discrete map with its decisions frozen: the accepted step sizes, which
+ * attempts were accepted, the step holding each crossing, the termination,
+ * and the indicator parts of the disc window (eq. (77)) and of the emitter's
+ * existence (A > 0 in eq. (89)); the crossing points move with q by the
+ * implicit function theorem on the step's continuous extension, and the inner
+ * disc edge, when it is the outer horizon (r_in <= 0), moves with R_+.
+ *   params    the image (as for rt_trace_image; precision RT_FP64)
+ *   dl_dI     device [ny][nx] cotangent dL/dI of the image
+ *   basis     RT_GRAD_NATIVE or RT_GRAD_DENSITY (cored NFW only)
+ *   grad      device [4]: dL/dq = sum over pixels of dl_dI dI/dq (fixed order,
+ *             deterministic)
+ *   grad_pix  device [ny][nx][4] per-pixel dl_dI dI/dq, or NULL
+ * Pixels with dl_dI = 0 are not traced.  Internally a counting trace, a
+ * trace that tapes every accepted step (48 bytes each) of the rays that can
+ * contribute, longest first, and a reverse sweep over the tapes; tapes beyond
+ * the budget (rt_set_tape_budget) are processed in consecutive slices.
+ * Unlike the trace calls this one synchronises `hip_stream` once (after the
+ * counting pass, to size the tapes) and allocates stream-ordered device
+ * memory of about 4 n_pix (2 + 8) bytes plus the tapes.  Errors as for
+ * rt_trace_image; RT_ERR_ARG for an unknown basis or the density basis on a
+ * metric other than RT_CNFW. */
+int rt_image_vjp(const rt_image_params *params, const double *dl_dI, int32_t basis,
+                 double *grad, double *grad_pix, void *hip_stream);
+
+/* Device memory the gradient may use for tapes at once (thread-local, bytes,
+ * at least 1 MiB; default 16 GiB).  A smaller budget only splits the work. */
+int rt_set_tape_budget(int64_t bytes);
+
+/* Statistics of the last rt_image_vjp call on this thread: out[0..3] = {rays
+ * taped, tape records, slices, bytes of the largest slice's tape}. */
+int rt_vjp_stats(int64_t *out);
+
 /* How the persistent trace kernels hand out work (thread-local setting,
  * applies to later calls on this thread).  Pixels are handed to wavefronts in
  * chunks of `chunk` consecutive ordinals of a screen enumeration in tiles of

@@ -152,6 +152,61 @@ bool outer_horizon(const rt::ImageConst& c, double* r_plus) {
 }
 
 // Validates p and fills the image constants.  Returns RT_OK or an error code.
+rt::Coeffs<double> coeffs_of(const rt::ImageConst& c) {
+    return rt::Coeffs<double>{c.chi, c.chi2, c.inv_lam, c.lam_c, c.inv_lam_c, c.eta_lc};
+}
+
+void sin_cos(double th, double& s, double& co) {
+    s = std::sin(th);
+    co = std::cos(th);
+}
+template <int N>
+void sin_cos(const rt::Dual<N>& th, rt::Dual<N>& s, rt::Dual<N>& co) {
+    const double sv = std::sin(th.v), cv = std::cos(th.v);
+    s = rt::chain(th, sv, cv);
+    co = rt::chain(th, cv, -sv);
+}
+
+template <class S>
+void mass_of(int metric, const rt::Coeffs<S>& k, const S& R, S& F, S& dF) {
+    if (metric == rt::EINASTO)
+        rt::mass_function<rt::EINASTO>(k, R, F, dF);
+    else if (metric == rt::CNFW)
+        rt::mass_function<rt::CNFW>(k, R, F, dF);
+    else
+        rt::mass_function<rt::KERR>(k, R, F, dF);
+}
+
+// The static observer's frame at (R_o, theta_o): the metric of eqs. (27)-(31)
+// and the ZAMO lapse of eqs. (63)-(65).  out = {N_o, g_Tphi/sqrt(g_phiphi),
+// sqrt(g_phiphi), sqrt(g_RR), sqrt(g_thth)}.  S is double, or a dual number
+// for the derivatives of the screen map along the image parameters.
+template <class S>
+bool observer_frame(int metric, const rt::Coeffs<S>& k, const S& th, double R, S out[5]) {
+    S F, dF;
+    mass_of(metric, k, S(R), F, dF);
+    S s, co;
+    sin_cos(th, s, co);
+    const S s2 = s * s;
+    const S Sig = R * R + k.chi2 * co * co;
+    const S Del = R * R - F + k.chi2;
+    const S gTT = -(1.0 - F / Sig);
+    const S gTp = -k.chi * F * s2 / Sig;
+    const S gRR = Sig / Del;
+    const S gthth = Sig;
+    const S gpp = s2 * (R * R + k.chi2 + k.chi2 * F * s2 / Sig);
+    const S N2 = gTp * gTp / gpp - gTT;  // -(g_TT + 2 w g_Tphi + w^2 g_phiphi), w = -g_Tphi/g_phiphi
+    if (!(rt::value_of(Del) > 0.0) || !(rt::value_of(N2) > 0.0) || !(rt::value_of(gpp) > 0.0))
+        return false;
+    using std::sqrt;
+    out[0] = sqrt(N2);
+    out[2] = sqrt(gpp);
+    out[1] = gTp / out[2];
+    out[3] = sqrt(gRR);
+    out[4] = sqrt(gthth);
+    return true;
+}
+
 int setup_image(const rt_image_params* p, int index, bool emission, rt::ImageConst* c,
                 double* r_plus_out) {
     if (!p) return fail(RT_ERR_ARG, "image %d: null parameter pointer", index);
@@ -207,27 +262,16 @@ int setup_image(const rt_image_params* p, int index, bool emission, rt::ImageCon
         return fail(RT_ERR_ARG, "image %d: observer must lie outside the disc and horizon", index);
 
     // Observer metric at (R_o, theta_o), eqs. (27)-(31), and the ZAMO (63)-(65).
-    const double R = p->r_obs, th = p->incl;
-    double F, dF;
-    rt::mass_function_any(*c, R, F, dF);
-    const double s = std::sin(th), co = std::cos(th), s2 = s * s;
-    const double Sig = R * R + c->chi2 * co * co;
-    const double Del = R * R - F + c->chi2;
-    const double gTT = -(1.0 - F / Sig);
-    const double gTp = -c->chi * F * s2 / Sig;
-    const double gRR = Sig / Del;
-    const double gthth = Sig;
-    const double gpp = s2 * (R * R + c->chi2 + c->chi2 * F * s2 / Sig);
-    const double N2 = gTp * gTp / gpp - gTT;  // -(g_TT + 2 w g_Tphi + w^2 g_phiphi), w = -g_Tphi/g_phiphi
-    if (!(Del > 0.0) || !(N2 > 0.0) || !(gpp > 0.0))
+    double frame[5];
+    if (!observer_frame(c->metric, coeffs_of(*c), p->incl, p->r_obs, frame))
         return fail(RT_ERR_ARG, "image %d: no static observer frame at R_o", index);
-    c->r_obs = R;
-    c->incl = th;
-    c->obs_N = std::sqrt(N2);
-    c->obs_sq_gphph = std::sqrt(gpp);
-    c->obs_gTph_over_sq_gphph = gTp / c->obs_sq_gphph;
-    c->obs_sq_gRR = std::sqrt(gRR);
-    c->obs_sq_gthth = std::sqrt(gthth);
+    c->r_obs = p->r_obs;
+    c->incl = p->incl;
+    c->obs_N = frame[0];
+    c->obs_gTph_over_sq_gphph = frame[1];
+    c->obs_sq_gphph = frame[2];
+    c->obs_sq_gRR = frame[3];
+    c->obs_sq_gthth = frame[4];
 
     c->dx = (p->x_max - p->x_min) / p->nx;
     c->dy = (p->y_max - p->y_min) / p->ny;
@@ -428,6 +472,250 @@ int trace_common(const rt_image_params* params, int32_t n_images, const rt_image
     return RT_OK;
 }
 
+
+// ------------------------------------------------------------ image gradient
+thread_local int64_t g_tape_budget = int64_t(16) << 30;
+thread_local int64_t g_vjp_stats[4] = {0, 0, 0, 0};   // rays, tape steps, slices, tape bytes
+
+// jac[m][j]: derivative of per-ray parameter m (the kernel's order: chi, three
+// mass constants, window inner edge, five observer-frame constants,
+// inclination) along q_j = (spin, incl, halo[0], halo[1]), or along
+// (spin, incl, rho_s, r_s) for the density basis of the cored NFW halo, where
+// eta = 4 pi rho_s r_s^2 and lambda_c = r_s.
+int vjp_jacobian(const rt_image_params* p, const rt::ImageConst& c, double r_plus, int32_t basis,
+                 double jac[rt::kVjpPrims][4]) {
+    using D = rt::Dual<4>;
+    rt::Coeffs<D> k{};
+    k.chi = D::var(p->spin, 0);
+    k.chi2 = k.chi * k.chi;
+    const D th = D::var(p->incl, 1);
+    const D h0 = D::var(p->halo[0], 2), h1 = D::var(p->halo[1], 3);
+    if (c.metric == rt::EINASTO) k.inv_lam = 1.0 / h0;
+    if (c.metric == rt::CNFW) {
+        k.lam_c = h1;
+        k.inv_lam_c = 1.0 / h1;
+        k.eta_lc = h0 * h1;
+    }
+    D frame[5];
+    if (!observer_frame(c.metric, k, th, p->r_obs, frame))
+        return fail(RT_ERR_ARG, "no static observer frame at R_o");
+    const D zero(0.0);
+    const D* rows[rt::kVjpPrims] = {&k.chi, &zero, &zero, &zero, &zero,
+                                    &frame[0], &frame[1], &frame[2], &frame[3], &frame[4], &th};
+    if (c.metric == rt::EINASTO) rows[1] = &k.inv_lam;
+    if (c.metric == rt::CNFW) {
+        rows[1] = &k.lam_c;
+        rows[2] = &k.inv_lam_c;
+        rows[3] = &k.eta_lc;
+    }
+    for (int m = 0; m < rt::kVjpPrims; ++m)
+        for (int j = 0; j < 4; ++j) jac[m][j] = rows[m]->d[j];
+    // The window's inner edge is the outer horizon unless given: Delta(R_+) = 0
+    // moves by dR_+ = -(dDelta/dq) / (dDelta/dR) (implicit function theorem).
+    for (int j = 0; j < 4; ++j) jac[4][j] = 0.0;
+    if (!(p->r_in > 0.0)) {
+        D F, dF;
+        mass_of(c.metric, k, D(r_plus), F, dF);
+        const D Del = r_plus * r_plus - F + k.chi2;
+        const double dDel_dR = 2.0 * r_plus - dF.v;
+        for (int j = 0; j < 4; ++j) jac[4][j] = -Del.d[j] / dDel_dR;
+    }
+    if (basis == RT_GRAD_DENSITY) {
+        const double eta = p->halo[0], lc = p->halo[1];
+        for (int m = 0; m < rt::kVjpPrims; ++m) {
+            const double d_eta = jac[m][2], d_lc = jac[m][3];
+            jac[m][2] = d_eta * 4.0 * M_PI * lc * lc;
+            jac[m][3] = d_lc + d_eta * 2.0 * eta / lc;
+        }
+    }
+    return RT_OK;
+}
+
+// Pinned host memory for the counts read back by the gradient, reused.
+thread_local void* g_readback = nullptr;
+thread_local size_t g_readback_cap = 0;
+
+int readback_reserve(size_t bytes, void** out) {
+    if (g_readback_cap < bytes) {
+        if (g_readback) (void)hipHostFree(g_readback);
+        g_readback = nullptr;
+        g_readback_cap = 0;
+        if (hipHostMalloc(&g_readback, bytes, hipHostMallocDefault) != hipSuccess || !g_readback) {
+            (void)hipGetLastError();
+            g_readback = nullptr;
+            return fail(RT_ERR_ALLOC, "pinned read-back allocation of %zu bytes failed", bytes);
+        }
+        g_readback_cap = bytes;
+    }
+    *out = g_readback;
+    return RT_OK;
+}
+
+int image_vjp(const rt_image_params* params, const double* dl_dI, int32_t basis, double* grad,
+              double* grad_pix, void* hip_stream) {
+    g_last_error.clear();
+    for (int64_t& v : g_vjp_stats) v = 0;
+    if (!params || !dl_dI || !grad) return fail(RT_ERR_ARG, "null params, dl_dI or grad");
+    if (basis != RT_GRAD_NATIVE && basis != RT_GRAD_DENSITY)
+        return fail(RT_ERR_ARG, "unknown gradient basis %d", basis);
+    if (basis == RT_GRAD_DENSITY && params->metric != RT_CNFW)
+        return fail(RT_ERR_ARG, "the density basis applies to the cored-NFW metric only");
+    rt::ImageConst c;
+    double r_plus = 0.0;
+    int rc = setup_image(params, 0, true, &c, &r_plus);
+    if (rc != RT_OK) return rc;
+    double jac[rt::kVjpPrims][4];
+    if ((rc = vjp_jacobian(params, c, r_plus, basis, jac)) != RT_OK) return rc;
+    if ((rc = check_device_ptr(dl_dI, "dl_dI", 0)) || (rc = check_device_ptr(grad, "grad", 0)) ||
+        (rc = check_device_ptr(grad_pix, "grad_pix", 0)))
+        return rc;
+    DeviceInfo info;
+    if ((rc = device_info(&info)) != RT_OK) return rc;
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    const int64_t n_pix = c.n_pix;
+    auto up256 = [](size_t b) { return (b + 255) / 256 * 256; };
+
+    // Scratch: queue counters (count pass; tape and reverse passes), counts, gradient partials, per-pixel
+    // gradients (when the caller passes none).
+    const size_t q_bytes = 256;
+    const size_t cnt_bytes = up256(sizeof(int32_t) * n_pix);
+    const size_t part_bytes = up256(sizeof(double) * 4 * rt::kGradBlocks);
+    const size_t gp_bytes = grad_pix ? 0 : up256(sizeof(double) * 4 * n_pix);
+    void* scratch = nullptr;
+    hipError_t e = hipMallocAsync(&scratch, q_bytes + cnt_bytes + part_bytes + gp_bytes, stream);
+    if (e != hipSuccess || !scratch) {
+        (void)hipGetLastError();
+        return fail(RT_ERR_ALLOC, "stream-ordered allocation of gradient scratch failed");
+    }
+    char* base = static_cast<char*>(scratch);
+    unsigned long long* queue = reinterpret_cast<unsigned long long*>(base);
+    int32_t* count = reinterpret_cast<int32_t*>(base + q_bytes);
+    double* partials = reinterpret_cast<double*>(base + q_bytes + cnt_bytes);
+    double* gp = grad_pix ? grad_pix
+                          : reinterpret_cast<double*>(base + q_bytes + cnt_bytes + part_bytes);
+    void* tape_mem = nullptr;
+    auto bail = [&](int code) {
+        if (tape_mem) (void)hipFreeAsync(tape_mem, stream);
+        (void)hipFreeAsync(scratch, stream);
+        return code;
+    };
+    auto grid_of = [&](int pass, int64_t items) {
+        const int64_t want = (items + rt::kBlock - 1) / rt::kBlock;
+        int per_cu = rt::vjp_blocks_per_cu(c.metric, pass);
+        if (g_launch.blocks_per_cu > 0 && g_launch.blocks_per_cu < per_cu)
+            per_cu = g_launch.blocks_per_cu;
+        const int64_t resident = static_cast<int64_t>(info.cus) * per_cu;
+        return static_cast<int32_t>(std::max<int64_t>(1, std::min(want, resident)));
+    };
+
+    // Pass 1: counts.
+    if ((e = rt::launch_zero(queue, 32, stream)) != hipSuccess)
+        return bail(hip_fail(e, "queue reset launch"));
+    if ((e = rt::launch_fill_zero(gp, 4 * n_pix, stream)) != hipSuccess)
+        return bail(hip_fail(e, "gradient fill launch"));
+    if ((e = rt::launch_vjp_count(c, dl_dI, count, queue, shape_for(c.nx, c.ny),
+                                  grid_of(0, n_pix), stream)) != hipSuccess)
+        return bail(hip_fail(e, "count kernel launch"));
+    void* host_cnt = nullptr;
+    if ((rc = readback_reserve(sizeof(int32_t) * n_pix, &host_cnt)) != RT_OK) return bail(rc);
+    if ((e = hipMemcpyAsync(host_cnt, count, sizeof(int32_t) * n_pix, hipMemcpyDeviceToHost,
+                            stream)) != hipSuccess ||
+        (e = hipStreamSynchronize(stream)) != hipSuccess)
+        return bail(hip_fail(e, "count read-back"));
+
+    // Rays with a non-zero count, longest first (counting sort, stable in the
+    // pixel index), and their tape offsets.
+    const int32_t* cnt = static_cast<const int32_t*>(host_cnt);
+    int32_t cmax = 0;
+    int64_t n_list = 0;
+    for (int64_t i = 0; i < n_pix; ++i) {
+        cmax = std::max(cmax, cnt[i]);
+        n_list += cnt[i] > 0;
+    }
+    if (n_list > 0) {
+        std::vector<int64_t> start(static_cast<size_t>(cmax) + 2, 0);
+        for (int64_t i = 0; i < n_pix; ++i)
+            if (cnt[i] > 0) ++start[cmax - cnt[i] + 1];
+        for (size_t b = 1; b < start.size(); ++b) start[b] += start[b - 1];
+        const size_t list_bytes = up256(sizeof(int32_t) * n_list) +
+                                  up256(sizeof(int64_t) * n_list) +
+                                  up256(sizeof(int32_t) * n_list);
+        void* host_list = nullptr;
+        if ((rc = staging_reserve(list_bytes, &host_list)) != RT_OK) return bail(rc);
+        char* hl = static_cast<char*>(host_list);
+        int32_t* h_pix = reinterpret_cast<int32_t*>(hl);
+        int64_t* h_off = reinterpret_cast<int64_t*>(hl + up256(sizeof(int32_t) * n_list));
+        for (int64_t i = 0; i < n_pix; ++i)
+            if (cnt[i] > 0) h_pix[start[cmax - cnt[i]]++] = static_cast<int32_t>(i);
+        int64_t total = 0;
+        for (int64_t e2 = 0; e2 < n_list; ++e2) {
+            h_off[e2] = total;
+            total += cnt[h_pix[e2]];
+        }
+        // Slices of the list whose tapes fit the budget.
+        const int64_t rec_budget = std::max<int64_t>(g_tape_budget / rt::kVjpRecBytes, cmax);
+        std::vector<int64_t> cuts{0};
+        for (int64_t e2 = 0; e2 < n_list; ++e2) {
+            const int64_t used = h_off[e2] + cnt[h_pix[e2]] - h_off[cuts.back()];
+            if (used > rec_budget) cuts.push_back(e2);
+        }
+        cuts.push_back(n_list);
+        int64_t max_slice = 0;
+        for (size_t sl = 0; sl + 1 < cuts.size(); ++sl) {
+            const int64_t hi_rec = cuts[sl + 1] < n_list ? h_off[cuts[sl + 1]] : total;
+            max_slice = std::max(max_slice, hi_rec - h_off[cuts[sl]]);
+        }
+        const size_t tape_bytes = static_cast<size_t>(max_slice) * rt::kVjpRecBytes;
+        e = hipMallocAsync(&tape_mem, list_bytes + tape_bytes, stream);
+        if (e != hipSuccess || !tape_mem) {
+            (void)hipGetLastError();
+            tape_mem = nullptr;
+            return bail(fail(RT_ERR_ALLOC, "tape allocation of %zu bytes failed",
+                             list_bytes + tape_bytes));
+        }
+        char* dl = static_cast<char*>(tape_mem);
+        const int32_t* d_pix = reinterpret_cast<const int32_t*>(dl);
+        const int64_t* d_off = reinterpret_cast<const int64_t*>(dl + up256(sizeof(int32_t) * n_list));
+        int32_t* d_taped = reinterpret_cast<int32_t*>(dl + up256(sizeof(int32_t) * n_list) +
+                                                      up256(sizeof(int64_t) * n_list));
+        double* d_tape = reinterpret_cast<double*>(dl + list_bytes);
+        const size_t up_bytes = up256(sizeof(int32_t) * n_list) + up256(sizeof(int64_t) * n_list);
+        if ((e = hipMemcpyAsync(tape_mem, host_list, up_bytes, hipMemcpyHostToDevice, stream)) !=
+                hipSuccess ||
+            (e = hipEventRecord(g_staging.ready, stream)) != hipSuccess)
+            return bail(hip_fail(e, "ray list upload"));
+        const int32_t chunk = g_launch.chunk > 0 ? g_launch.chunk : 32;
+        const int n_slices = static_cast<int>(cuts.size()) - 1;
+        for (int sl = 0; sl < n_slices; ++sl) {
+            const int64_t lo = cuts[sl], hi = cuts[sl + 1];
+            const int64_t rec_base = h_off[lo];
+            const int qi = 1;
+            if (sl > 0 && (e = rt::launch_zero(queue + 1, 2, stream)) != hipSuccess)
+                return bail(hip_fail(e, "queue reset launch"));
+            if ((e = rt::launch_vjp_tape(c, d_pix + lo, d_off + lo, count, hi - lo, rec_base,
+                                         d_tape, d_taped + lo, queue + qi, chunk,
+                                         grid_of(1, hi - lo), stream)) != hipSuccess)
+                return bail(hip_fail(e, "tape kernel launch"));
+            if ((e = rt::launch_vjp_reverse(c, dl_dI, d_pix + lo, d_off + lo, d_taped + lo,
+                                            hi - lo, rec_base, d_tape, jac, gp, queue + qi + 1,
+                                            chunk, grid_of(2, hi - lo), stream)) != hipSuccess)
+                return bail(hip_fail(e, "reverse kernel launch"));
+        }
+        g_vjp_stats[0] = n_list;
+        g_vjp_stats[1] = total;
+        g_vjp_stats[2] = n_slices;
+        g_vjp_stats[3] = static_cast<int64_t>(tape_bytes);
+    }
+    if ((e = rt::launch_grad_reduce(gp, n_pix, partials, grad, stream)) != hipSuccess)
+        return bail(hip_fail(e, "gradient reduction launch"));
+    if (tape_mem && (e = hipFreeAsync(tape_mem, stream)) != hipSuccess) {
+        (void)hipFreeAsync(scratch, stream);
+        return hip_fail(e, "hipFreeAsync");
+    }
+    if ((e = hipFreeAsync(scratch, stream)) != hipSuccess) return hip_fail(e, "hipFreeAsync");
+    return RT_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -536,6 +824,25 @@ int rt_get_launch_config(rt_launch_config* cfg) {
     g_last_error.clear();
     if (!cfg) return fail(RT_ERR_ARG, "null launch config pointer");
     *cfg = g_launch;
+    return RT_OK;
+}
+
+int rt_image_vjp(const rt_image_params* params, const double* dl_dI, int32_t basis,
+                 double* grad, double* grad_pix, void* hip_stream) {
+    return image_vjp(params, dl_dI, basis, grad, grad_pix, hip_stream);
+}
+
+int rt_set_tape_budget(int64_t bytes) {
+    g_last_error.clear();
+    if (bytes < (int64_t(1) << 20)) return fail(RT_ERR_ARG, "tape budget below 1 MiB");
+    g_tape_budget = bytes;
+    return RT_OK;
+}
+
+int rt_vjp_stats(int64_t* out) {
+    g_last_error.clear();
+    if (!out) return fail(RT_ERR_ARG, "null stats pointer");
+    for (int i = 0; i < 4; ++i) out[i] = g_vjp_stats[i];
     return RT_OK;
 }
 

@@ -78,6 +78,13 @@ __host__ __device__ inline void mass_function(const K& c, const S& R, S& F, S& d
     }
 }
 
+// The metric constants with a scalar type of choice (dual numbers when
+// differentiating with respect to them); a K for mass_function.
+template <class S>
+struct Coeffs {
+    S chi, chi2, inv_lam, lam_c, inv_lam_c, eta_lc;
+};
+
 // Runtime dispatch of mass_function (host setup and the batched kernel).
 __host__ __device__ inline void mass_function_any(const ImageConst& c, double R, double& F,
                                                   double& dF) {

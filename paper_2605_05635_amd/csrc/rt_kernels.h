@@ -79,4 +79,40 @@ hipError_t launch_visibility(void* blas, const ImageConst& c, const double* inte
                              const char** what);
 void* blas_create();
 
+// Image gradient (reverse mode through every ray's discrete map).
+//   count:   for each pixel with dl_dI != 0, the accepted steps up to the last
+//            emitting crossing (0 if none) -> count[pix]; persistent over the
+//            screen in the order of `shape`.
+//   tape:    list entries e < n_list (pixel list_pix[e], first record at
+//            list_off[e] - rec_base of `tape`, kVjpRecBytes per record) are
+//            traced again and taped; taped[e] = records written.
+//   reverse: walks the tapes backwards and writes grad_pix[pix][4] =
+//            dL/dq for the pixels of the list, with jac[m][j] the derivative of
+//            per-ray parameter m along the image parameter q_j.
+// Each persistent pass needs its zeroed queue counter.  `pass` of
+// vjp_blocks_per_cu: 0 count, 1 tape, 2 reverse.
+constexpr int kVjpPrims = 11;
+constexpr int kVjpRecBytes = 48;
+constexpr int kGradBlocks = 256;
+hipError_t launch_vjp_count(const ImageConst& c, const double* dl_dI, int32_t* count,
+                            unsigned long long* queue, const LaunchShape& shape, int32_t grid,
+                            hipStream_t stream);
+hipError_t launch_vjp_tape(const ImageConst& c, const int32_t* list_pix, const int64_t* list_off,
+                           const int32_t* count, int64_t n_list, int64_t rec_base, double* tape,
+                           int32_t* taped, unsigned long long* queue, int32_t chunk,
+                           int32_t grid, hipStream_t stream);
+hipError_t launch_vjp_reverse(const ImageConst& c, const double* dl_dI, const int32_t* list_pix,
+                              const int64_t* list_off, const int32_t* taped, int64_t n_list,
+                              int64_t rec_base, const double* tape,
+                              const double (&jac)[kVjpPrims][4], double* grad_pix,
+                              unsigned long long* queue, int32_t chunk, int32_t grid,
+                              hipStream_t stream);
+int vjp_blocks_per_cu(int metric, int pass);
+// p[0..n) = 0 (a fill kernel).
+hipError_t launch_fill_zero(double* p, int64_t n, hipStream_t stream);
+// grad[0..4) = sum over pixels of grad_pix[pix][0..4), in a fixed order;
+// `partials` holds 4 kGradBlocks doubles.
+hipError_t launch_grad_reduce(const double* grad_pix, int64_t n_pix, double* partials,
+                              double* grad, hipStream_t stream);
+
 }  // namespace rt

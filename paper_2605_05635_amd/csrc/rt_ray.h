@@ -30,13 +30,6 @@ struct Hot {
     int32_t max_attempts;
 };
 
-// The metric constants with a scalar type of choice (dual numbers when
-// differentiating with respect to them).
-template <class S>
-struct Coeffs {
-    S chi, chi2, inv_lam, lam_c, inv_lam_c, eta_lc;
-};
-
 __host__ __device__ __forceinline__ Hot hot_of(const ImageConst& c) {
     Hot k;
     k.chi = c.chi;

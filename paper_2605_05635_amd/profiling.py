@@ -1,0 +1,120 @@
+"""Summaries of rocprofv3 output for the committed profiles.
+
+    python -m paper_2605_05635_amd.profiling stats KERNEL_STATS_CSV --command CMD --out TXT
+    python -m paper_2605_05635_amd.profiling traffic --fetch CSV --write CSV
+        --kernel SUBSTRING --copy-bytes N --command CMD --out JSON
+
+`stats` condenses a `rocprofv3 --kernel-trace --stats --output-format csv`
+kernel_stats table (calls, total and average duration per kernel).
+`traffic` turns two `rocprofv3 --pmc FETCH_SIZE` / `--pmc WRITE_SIZE` runs
+(KiB per dispatch) into HBM bytes per launch of one kernel, each counter
+scaled by what it reads for a plain device-to-device copy of known size run
+in the same process (the largest dispatch whose name contains "copy"), and
+records the hash of the trace kernel's sources it was taken on.
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import hashlib
+import json
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(PKG)
+TRACE_SOURCES = ("rt_trace.hip", "rt_ray.h", "rt_device.h", "rt_math.h", "rt_dual.h",
+                 "rt_kernels.h")
+
+
+def trace_source_hash() -> str:
+    """Hash of the sources the single-image trace kernel is compiled from."""
+    h = hashlib.sha256()
+    for name in TRACE_SOURCES:
+        with open(os.path.join(PKG, "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def _rows(path: str) -> list[dict]:
+    with open(path, newline="") as f:
+        return list(csv.DictReader(f))
+
+
+def kernel_stats(path: str) -> list[dict]:
+    out = []
+    for r in _rows(path):
+        out.append(dict(name=r["Name"], calls=int(r["Calls"]),
+                        total_ms=float(r["TotalDurationNs"]) * 1e-6,
+                        avg_ms=float(r["AverageNs"]) * 1e-6,
+                        min_ms=float(r["MinNs"]) * 1e-6, max_ms=float(r["MaxNs"]) * 1e-6,
+                        pct=float(r["Percentage"])))
+    return sorted(out, key=lambda d: -d["total_ms"])
+
+
+def stats_text(path: str, command: str, top: int = 20) -> str:
+    ks = kernel_stats(path)
+    lines = [f"command: {command}", "",
+             f"{'calls':>6} {'total ms':>10} {'avg ms':>10} {'min ms':>10} {'max ms':>10} "
+             f"{'%':>6}  kernel"]
+    for k in ks[:top]:
+        name = k["name"] if len(k["name"]) <= 110 else k["name"][:107] + "..."
+        lines.append(f"{k['calls']:>6} {k['total_ms']:>10.3f} {k['avg_ms']:>10.4f} "
+                     f"{k['min_ms']:>10.4f} {k['max_ms']:>10.4f} {k['pct']:>6.2f}  {name}")
+    return "\n".join(lines) + "\n"
+
+
+def _counter(path: str, name: str) -> list[tuple[str, float]]:
+    return [(r["Kernel_Name"], float(r["Counter_Value"])) for r in _rows(path)
+            if r["Counter_Name"] == name]
+
+
+def traffic(fetch_csv: str, write_csv: str, kernel: str, copy_bytes: int) -> dict:
+    res = {}
+    for key, path, counter in (("fetch", fetch_csv, "FETCH_SIZE"),
+                               ("write", write_csv, "WRITE_SIZE")):
+        rows = _counter(path, counter)
+        kern = [v for n, v in rows if kernel in n]
+        copies = [v for n, v in rows if "copy" in n.lower()]
+        if not kern or not copies:
+            raise SystemExit(f"{counter}: no dispatch of {kernel!r} or of a copy kernel")
+        kib = sum(kern) / len(kern)
+        copy_kib = max(copies)
+        scale = copy_bytes / (copy_kib * 1024.0)
+        res[key] = dict(counter_kib_per_launch=kib, launches=len(kern),
+                        copy_counter_kib=copy_kib, scale=scale,
+                        bytes_per_launch=kib * 1024.0 * scale)
+    res["hbm_bytes_per_launch"] = res["fetch"]["bytes_per_launch"] + res["write"]["bytes_per_launch"]
+    return res
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__,
+                                 formatter_class=argparse.RawDescriptionHelpFormatter)
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    a = sub.add_parser("stats")
+    a.add_argument("csv")
+    a.add_argument("--command", required=True)
+    a.add_argument("--out", required=True)
+    b = sub.add_parser("traffic")
+    b.add_argument("--fetch", required=True)
+    b.add_argument("--write", required=True)
+    b.add_argument("--kernel", required=True)
+    b.add_argument("--copy-bytes", type=int, required=True)
+    b.add_argument("--command", required=True)
+    b.add_argument("--out", required=True)
+    args = ap.parse_args()
+    if args.cmd == "stats":
+        with open(args.out, "w") as f:
+            f.write(stats_text(args.csv, args.command))
+        return 0
+    t = traffic(args.fetch, args.write, args.kernel, args.copy_bytes)
+    t.update(kernel=args.kernel, command=args.command, kernel_source_hash=trace_source_hash(),
+             copy_bytes=args.copy_bytes)
+    with open(args.out, "w") as f:
+        json.dump(t, f, indent=1)
+        f.write("\n")
+    return 0
+
+
+if __name__ == "__main__":
+    raise SystemExit(main())

@@ -20,6 +20,7 @@ RT_KERR, RT_EINASTO, RT_CNFW = 0, 1, 2
 RT_FP64 = 0
 RT_OK, RT_ERR_ARG, RT_ERR_NO_HORIZON, RT_ERR_HIP, RT_ERR_ALLOC = 0, -1, -2, -3, -4
 RT_RAY_CAPTURED, RT_RAY_ESCAPED, RT_RAY_STEP_LIMIT = 1, 2, 3
+RT_GRAD_NATIVE, RT_GRAD_DENSITY = 0, 1
 METRIC_ID = {"kerr": RT_KERR, "einasto": RT_EINASTO, "cnfw": RT_CNFW}
 PRECISION_ID = {"fp64": RT_FP64}
 
@@ -82,6 +83,12 @@ def _load():
     lib.rt_get_launch_config.restype = C.c_int
     lib.rt_set_kernel_timing.argtypes = [C.c_void_p, C.c_void_p]
     lib.rt_set_kernel_timing.restype = C.c_int
+    lib.rt_image_vjp.argtypes = [P, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]
+    lib.rt_image_vjp.restype = C.c_int
+    lib.rt_set_tape_budget.argtypes = [C.c_int64]
+    lib.rt_set_tape_budget.restype = C.c_int
+    lib.rt_vjp_stats.argtypes = [C.POINTER(C.c_int64)]
+    lib.rt_vjp_stats.restype = C.c_int
     lib.rt_last_error.argtypes = []
     lib.rt_last_error.restype = C.c_char_p
     lib.rt_version.argtypes = []
@@ -211,6 +218,26 @@ def rt_get_launch_config() -> dict:
                 blocks_per_cu=cfg.blocks_per_cu)
 
 
+def rt_image_vjp(params: rt_image_params, dl_dI, grad, grad_pix=None,
+                 basis: int = RT_GRAD_NATIVE, stream=None) -> None:
+    """Calls rt_image_vjp on device tensors: dl_dI [ny][nx] f64 (input),
+    grad [4] f64 and optionally grad_pix [ny][nx][4] f64 (outputs)."""
+    _check(_lib.rt_image_vjp(C.byref(params), C.c_void_p(dl_dI.data_ptr()), basis,
+                             C.c_void_p(grad.data_ptr()),
+                             None if grad_pix is None else C.c_void_p(grad_pix.data_ptr()),
+                             _stream_handle(stream)))
+
+
+def rt_set_tape_budget(nbytes: int) -> None:
+    _check(_lib.rt_set_tape_budget(int(nbytes)))
+
+
+def rt_vjp_stats() -> dict:
+    buf = (C.c_int64 * 4)()
+    _check(_lib.rt_vjp_stats(buf))
+    return dict(rays=buf[0], steps=buf[1], slices=buf[2], tape_bytes=buf[3])
+
+
 def rt_version() -> int:
     return _lib.rt_version()
 
@@ -255,7 +282,22 @@ def trace_many(imgs: list, device="cuda", stream=None) -> list:
     return outs
 
 
-__all__ = ["rt_trace_image", "rt_transfer_maps", "rt_image_setup", "rt_set_kernel_timing",
+def image_vjp(img: dict, dl_dI, basis: str = "native", per_pixel: bool = False, stream=None):
+    """dL/dq for the image of `img` given the device tensor dl_dI [ny][nx]:
+    returns a device tensor [4] (and [ny][nx][4] per-pixel terms if asked).
+    basis "native": q = (spin, incl, halo0, halo1); "density" (cored NFW):
+    q = (spin, incl, rho_s, r_s)."""
+    import torch
+    dev = dl_dI.device
+    grad = torch.empty(4, dtype=torch.float64, device=dev)
+    gp = (torch.empty((int(img["ny"]), int(img["nx"]), 4), dtype=torch.float64, device=dev)
+          if per_pixel else None)
+    rt_image_vjp(params_from(img), dl_dI.contiguous(), grad, gp,
+                 RT_GRAD_DENSITY if basis == "density" else RT_GRAD_NATIVE, stream)
+    return (grad, gp) if per_pixel else grad
+
+
+__all__ = ["rt_image_vjp", "rt_set_tape_budget", "rt_vjp_stats", "image_vjp", "rt_trace_image", "rt_transfer_maps", "rt_image_setup", "rt_set_kernel_timing",
            "rt_set_launch_config", "rt_get_launch_config", "rt_visibility_dft", "visibility",
            "rt_version",
            "rt_last_error", "trace", "trace_many", "params_from", "out_from", "alloc_outputs",

@@ -60,7 +60,7 @@ void rhs_case(const double* a, std::vector<double>& out) {
     for (double v : pb) out.push_back(v);
 
     using D = Dual<10>;
-    ray::Coeffs<D> kd;
+    rt::Coeffs<D> kd;
     kd.chi = D::var(c.chi, 6);
     kd.chi2 = kd.chi * kd.chi;
     kd.inv_lam = D::var(c.inv_lam, 7);

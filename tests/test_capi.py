@@ -162,3 +162,25 @@ def test_visibility_argument_errors(rt):
     bad = rt.params_from(W.image(nx=0))
     assert lib.rt_visibility_dft(C.c_void_p(8), C.byref(bad), C.c_void_p(8), 5, C.c_void_p(8),
                                  None, None) == rt.RT_ERR_ARG
+
+
+def test_vjp_argument_errors(rt):
+    lib = rt.lib()
+    cn = rt.params_from(W.cnfw_adjoint_256())
+    kerr = rt.params_from(W.kerr_small())
+    d = C.c_void_p(8)
+    assert lib.rt_image_vjp(None, d, 0, d, None, None) == rt.RT_ERR_ARG
+    assert lib.rt_image_vjp(C.byref(cn), None, 0, d, None, None) == rt.RT_ERR_ARG
+    assert lib.rt_image_vjp(C.byref(cn), d, 0, None, None, None) == rt.RT_ERR_ARG
+    assert lib.rt_image_vjp(C.byref(cn), d, 7, d, None, None) == rt.RT_ERR_ARG
+    assert lib.rt_image_vjp(C.byref(kerr), d, rt.RT_GRAD_DENSITY, d, None, None) == rt.RT_ERR_ARG
+    assert "cored-NFW" in rt.rt_last_error()
+    bad = rt.params_from(W.image(nx=0))
+    assert lib.rt_image_vjp(C.byref(bad), d, 0, d, None, None) == rt.RT_ERR_ARG
+    nohz = rt.params_from(W.image(metric="kerr", spin=1.01))
+    assert lib.rt_image_vjp(C.byref(nohz), d, 0, d, None, None) == rt.RT_ERR_NO_HORIZON
+    assert lib.rt_set_tape_budget(1000) == rt.RT_ERR_ARG
+    assert lib.rt_set_tape_budget(16 << 30) == rt.RT_OK
+    assert lib.rt_vjp_stats(None) == rt.RT_ERR_ARG
+    buf = (C.c_int64 * 4)()
+    assert lib.rt_vjp_stats(buf) == rt.RT_OK

@@ -1,0 +1,221 @@
+"""The image gradient (rt_image_vjp, the discrete adjoint) on the GPU against
+the oracle's forward-mode dual-number gradient of the same frozen discrete
+map, plus its internal consistency: the total is the fixed-order sum of the
+per-pixel terms, slicing the tapes changes nothing, repeated calls are
+bit-identical, the density basis is the chain rule of the native one, and
+the autograd binding returns what the C ABI returns.
+
+Tolerance.  Both sides differentiate the discrete map with its decisions
+frozen, but each freezes the decisions of its own primal run.  Where the two
+runs take the same decisions (same attempt count and crossing count) the two
+derivatives are derivatives of one map evaluated in different rounding, and
+agree to GRAD_SAME (relative to the pixel's largest component).  A ray whose
+primal differs from the oracle's by a rounding-level change of one controller
+decision has a different (equally valid) frozen map; those pixels are only
+held to GRAD_ANY.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2605_05635_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+GRAD_SAME = 1e-7
+GRAD_ANY = 5e-2
+
+
+@pytest.fixture(scope="module")
+def rt():
+    import torch
+    assert torch.cuda.is_available(), "GPU test run without a GPU"
+    from paper_2605_05635_amd import rt as mod
+    return mod
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def gpu_pixel_grads(rt, img):
+    import torch
+    n = img["nx"] * img["ny"]
+    ones = torch.ones((img["ny"], img["nx"]), dtype=torch.float64, device="cuda")
+    grad, gp = rt.image_vjp(img, ones, per_pixel=True)
+    outs = rt.trace(img)
+    torch.cuda.synchronize()
+    return (grad.cpu().numpy(), gp.cpu().numpy().reshape(n, 4),
+            outs["attempts"].cpu().numpy().reshape(n), outs["ncross"].cpu().numpy().reshape(n),
+            outs["intensity"].cpu().numpy().reshape(n))
+
+
+def compare_grads(rt, orc, img, label):
+    say(f"[vjp] {label}: {img['metric']} {img['nx']}x{img['ny']} chi={img['spin']}")
+    grad, gp, att, nc, I = gpu_pixel_grads(rt, img)
+    idx = np.arange(img["nx"] * img["ny"])
+    Io, Go = orc.trace_grad_pixels(img, idx)
+    o = orc.trace_pixels(img, idx)
+    same = (o["attempts"] == att) & (o["ncross"] == nc)
+    scale = np.maximum(np.abs(Go).max(axis=1), np.abs(gp).max(axis=1))
+    err = np.abs(gp - Go).max(axis=1)
+    rel = np.where(scale > 0, err / np.where(scale > 0, scale, 1.0), 0.0)
+    say(f"[vjp] {label}: {same.sum()}/{same.size} pixels with the oracle's decisions; "
+        f"rel err (same) max {rel[same].max():.2e} p99 {np.quantile(rel[same], 0.99):.2e}; "
+        f"(other) max {rel[~same].max() if (~same).any() else 0:.2e}")
+    assert same.mean() > 0.95
+    assert rel[same].max() <= GRAD_SAME, np.argsort(-rel * same)[:5]
+    assert rel.max() <= GRAD_ANY
+    # zero intensity and zero gradient coincide (no crossing inside the window)
+    assert np.all(gp[I == 0.0] == 0.0)
+    # the total is the sum of the per-pixel terms
+    np.testing.assert_allclose(grad, gp.sum(axis=0), rtol=1e-12, atol=1e-300)
+    return grad, gp
+
+
+@pytest.mark.parametrize("img,label", [
+    (W.image(metric="cnfw", spin=0.94, halo=(0.02, 10.0), incl=math.radians(60), nx=48, ny=40,
+             sigma_in=0.5, sigma_out=0.5), "cnfw-taper"),
+    (W.image(metric="einasto", spin=0.9, halo=(0.14, 0.0), incl=math.radians(60), nx=45, ny=37,
+             sigma_in=0.5, sigma_out=0.5), "einasto-taper"),
+    (W.image(metric="kerr", spin=0.5, incl=math.radians(17), nx=41, ny=43, sigma_in=0.3,
+             sigma_out=0.3), "kerr-taper"),
+    (W.image(metric="cnfw", spin=0.7, halo=(0.04, 8.0), incl=math.radians(110), nx=39, ny=33),
+     "cnfw-hard-window"),
+], ids=["cnfw-taper", "einasto-taper", "kerr-taper", "cnfw-hard-window"])
+def test_pixel_gradients_match_oracle(rt, orc, img, label):
+    compare_grads(rt, orc, img, label)
+
+
+def test_adjoint_workload_sampled(rt, orc):
+    """The image-gradient workload at full size (cored NFW, 256x256, tapered
+    window), loss L = sum (I - I_target)^2 with the target at a 1 % change of
+    (chi, theta_o, rho_s, r_s): per-pixel terms on a seeded sample of pixels
+    against the oracle, and the total against the oracle's sum over that
+    sample weighted like the loss."""
+    import torch
+    img = W.cnfw_adjoint_256()
+    say("[vjp] adjoint workload 256x256")
+    signs = W.adjoint_target_signs()
+    eta, lc = img["halo"]
+    rho = eta / (4 * math.pi * lc * lc)
+    q = np.array([img["spin"], img["incl"], rho, lc])
+    qt = q * (1 + 0.01 * signs)
+    tgt = dict(img, spin=qt[0], incl=qt[1], halo=(4 * math.pi * qt[2] * qt[3] ** 2, qt[3]))
+    I = rt.trace(img)["intensity"]
+    It = rt.trace(tgt)["intensity"]
+    dl = 2.0 * (I - It)
+    grad, gp = rt.image_vjp(img, dl, basis="density", per_pixel=True)
+    torch.cuda.synchronize()
+    gp = gp.cpu().numpy().reshape(-1, 4)
+    dln = dl.cpu().numpy().reshape(-1)
+    stats = rt.rt_vjp_stats()
+    say(f"[vjp] taped rays {stats['rays']}, steps {stats['steps']}")
+    live = np.nonzero(dln)[0]
+    idx = np.sort(np.random.default_rng(7).choice(live, size=min(96, live.size), replace=False))
+    Io, Go = orc.trace_grad_pixels(img, idx)
+    # native -> density basis
+    Gd = Go.copy()
+    Gd[:, 2] = Go[:, 2] * 4 * math.pi * lc * lc
+    Gd[:, 3] = Go[:, 3] + Go[:, 2] * 2 * eta / lc
+    want = Gd * dln[idx, None]
+    got = gp[idx]
+    scale = np.maximum(np.abs(want).max(axis=1), 1e-300)
+    rel = np.abs(got - want).max(axis=1) / scale
+    nz = np.abs(want).max(axis=1) > 0
+    say(f"[vjp] sampled rel err max {rel[nz].max() if nz.any() else 0:.2e} "
+        f"median {np.median(rel[nz]) if nz.any() else 0:.2e}")
+    assert np.quantile(rel[nz], 0.9) <= GRAD_SAME
+    assert rel[nz].max() <= GRAD_ANY
+    np.testing.assert_allclose(grad.cpu().numpy(), gp.sum(axis=0), rtol=1e-12)
+
+
+def test_repeat_and_slices_bitwise(rt):
+    import torch
+    img = W.image(metric="cnfw", spin=0.94, halo=(0.02, 10.0), incl=math.radians(60), nx=64,
+                  ny=48, sigma_in=0.5, sigma_out=0.5)
+    say("[vjp] repeat and tape slices")
+    rng = np.random.default_rng(3)
+    dl = torch.tensor(rng.normal(size=(48, 64)), dtype=torch.float64, device="cuda")
+    g1, p1 = rt.image_vjp(img, dl, per_pixel=True)
+    g2, p2 = rt.image_vjp(img, dl, per_pixel=True)
+    one = rt.rt_vjp_stats()
+    rt.rt_set_tape_budget(1 << 20)
+    try:
+        g3, p3 = rt.image_vjp(img, dl, per_pixel=True)
+        sliced = rt.rt_vjp_stats()
+    finally:
+        rt.rt_set_tape_budget(16 << 30)
+    torch.cuda.synchronize()
+    say(f"[vjp] slices {one['slices']} -> {sliced['slices']}, steps {one['steps']}")
+    assert one["slices"] == 1 and sliced["slices"] > 1
+    assert sliced["steps"] == one["steps"] and sliced["rays"] == one["rays"]
+    assert torch.equal(g1, g2) and torch.equal(p1, p2)
+    assert torch.equal(g1, g3) and torch.equal(p1, p3)
+
+
+def test_cotangent_weights_and_zero(rt):
+    """dL/dq is linear in dL/dI: a random cotangent gives the weighted sum of
+    the unit-cotangent per-pixel terms; a zero cotangent traces nothing."""
+    import torch
+    img = W.image(metric="einasto", spin=0.6, halo=(0.2, 0.0), incl=math.radians(40), nx=40,
+                  ny=30, sigma_in=0.5, sigma_out=0.5)
+    say("[vjp] linearity in the cotangent")
+    ones = torch.ones((30, 40), dtype=torch.float64, device="cuda")
+    _, unit = rt.image_vjp(img, ones, per_pixel=True)
+    rng = np.random.default_rng(11)
+    w = rng.normal(size=(30, 40))
+    w[rng.random(size=w.shape) < 0.3] = 0.0
+    wt = torch.tensor(w, dtype=torch.float64, device="cuda")
+    g, gp = rt.image_vjp(img, wt, per_pixel=True)
+    unit = unit.cpu().numpy().reshape(-1, 4)
+    gp = gp.cpu().numpy().reshape(-1, 4)
+    want = unit * w.reshape(-1, 1)
+    np.testing.assert_allclose(gp, want, rtol=1e-12, atol=1e-12 * np.abs(want).max())
+    assert np.all(gp[w.reshape(-1) == 0.0] == 0.0)
+    zero = torch.zeros_like(ones)
+    gz = rt.image_vjp(img, zero)
+    torch.cuda.synchronize()
+    assert np.all(gz.cpu().numpy() == 0.0) and rt.rt_vjp_stats()["rays"] == 0
+
+
+def test_density_basis_is_chain_rule(rt):
+    import torch
+    img = W.image(metric="cnfw", spin=0.8, halo=(0.03, 7.0), incl=math.radians(50), nx=32,
+                  ny=28, sigma_in=0.5, sigma_out=0.5)
+    say("[vjp] density basis")
+    ones = torch.ones((28, 32), dtype=torch.float64, device="cuda")
+    gn = rt.image_vjp(img, ones).cpu().numpy()
+    gd = rt.image_vjp(img, ones, basis="density").cpu().numpy()
+    eta, lc = img["halo"]
+    want = gn.copy()
+    want[2] = gn[2] * 4 * math.pi * lc * lc
+    want[3] = gn[3] + gn[2] * 2 * eta / lc
+    np.testing.assert_allclose(gd, want, rtol=1e-12)
+    with pytest.raises(rt.RTError):
+        rt.image_vjp(W.kerr_small(), torch.ones((64, 64), dtype=torch.float64, device="cuda"),
+                     basis="density")
+
+
+def test_autograd_binding(rt):
+    import torch
+    from paper_2605_05635_amd.autograd import image_params, traced_image
+    img = W.image(metric="cnfw", spin=0.9, halo=(0.02, 10.0), incl=math.radians(70), nx=36,
+                  ny=30, sigma_in=0.5, sigma_out=0.5)
+    say("[vjp] autograd binding")
+    eta, lc = img["halo"]
+    q = torch.tensor([img["spin"], img["incl"], eta / (4 * math.pi * lc * lc), lc],
+                     dtype=torch.float64, requires_grad=True)
+    target = torch.zeros((30, 36), dtype=torch.float64, device="cuda")
+    I = traced_image(q, img, basis="density")
+    loss = ((I - target) ** 2).sum()
+    loss.backward()
+    # the image at q's parameters (eta = 4 pi rho_s r_s^2 rounds differently)
+    at_q = image_params(q, img, "density")
+    assert torch.equal(I.detach(), rt.trace(at_q)["intensity"])
+    dl = 2.0 * (I.detach() - target)
+    want = rt.image_vjp(at_q, dl, basis="density").cpu()
+    assert torch.equal(q.grad, want)
