@@ -107,6 +107,92 @@ def batch_measurement(steps: int) -> dict:
             "visibility_finite": bool(all(torch.isfinite(a).all().item() for a in amps))}
 
 
+def image_error(outs: dict, ref: dict) -> dict:
+    """Per-pixel difference of a traced image from a reference trace of the same
+    screen: |dI|/max I over pixels with equal crossing count and status (50th,
+    99th percentile, max), |dR_em| over their recorded crossings, and the
+    numbers of pixels whose crossing count or status differ."""
+    import torch
+    nc, ncr = outs["ncross"].flatten().long(), ref["ncross"].flatten().long()
+    st, str_ = outs["status"].flatten().long(), ref["status"].flatten().long()
+    same = (nc == ncr) & (st == str_)
+    I, Ir = outs["intensity"].flatten(), ref["intensity"].flatten()
+    dI = ((I - Ir).abs() / Ir.abs().max())[same]
+    r, rr = outs["r_em"].reshape(3, -1), ref["r_em"].reshape(3, -1)
+    have = (torch.arange(3, device=r.device)[:, None] < ncr.clamp(max=3)[None, :]) & same[None, :]
+    dR = (r - rr).abs()[have]
+    q = lambda t, p: float(torch.quantile(t, p).item()) if t.numel() else 0.0  # noqa: E731
+    return {"dI_rel_p50": q(dI, 0.5), "dI_rel_p99": q(dI, 0.99),
+            "dI_rel_max": float(dI.max().item()) if dI.numel() else 0.0,
+            "dR_em_p99": q(dR, 0.99), "dR_em_max": float(dR.max().item()) if dR.numel() else 0.0,
+            "ncross_mismatch": int((nc != ncr).sum().item()),
+            "status_mismatch": int((st != str_).sum().item())}
+
+
+def timed_trace(img: dict, steps: int):
+    """Trace `img` `steps` times (after one warm-up); returns (outputs, kernel ms)."""
+    import numpy as np
+    import torch
+
+    from paper_2605_05635_amd import rt
+    outs = rt.alloc_outputs(img)
+    p, o = [rt.params_from(img)], [rt.out_from(outs)]
+    stream = torch.cuda.current_stream()
+    rt.rt_trace_image(p, o, stream)
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    stops = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    for ev in starts + stops:
+        ev.record(stream)
+    torch.cuda.synchronize()
+    for k in range(steps):
+        rt.rt_set_kernel_timing(starts[k], stops[k])
+        rt.rt_trace_image(p, o, stream)
+    rt.rt_set_kernel_timing(None, None)
+    torch.cuda.synchronize()
+    return outs, float(np.mean([a.elapsed_time(b) for a, b in zip(starts, stops)]))
+
+
+def mixed_measurement(steps: int, ref64: dict) -> dict:
+    """The same 1024x1024 cored-NFW screen in mixed precision (binary32 bulk at
+    1e-6, binary64 from 1.5 R_+ inward, rays with two crossings traced again in
+    binary64): rays/s, its difference from the FP64 run at 1e-8, and the
+    accuracy-matched comparison -- the error of the mixed image and of FP64
+    images at tolerances 1e-6 ... 1e-9 against an FP64 reference at 1e-11,
+    with each one's rays/s."""
+    from paper_2605_05635_amd import rt, workloads as W
+    img = W.cnfw_1024("mixed")
+    n = img["nx"] * img["ny"]
+    outs, ms = timed_trace(img, steps)
+    stats = rt.rt_mixed_stats()
+    log(f"mixed: kernel {ms:.3f} ms, {stats['binary64']} rays finished in FP64 "
+        f"({stats['rerun']} traced again)")
+    res = {"rays_per_s": n / (ms * 1e-3), "kernel_ms": ms, "fp64_finished": stats["binary64"],
+           "fp64_reruns": stats["rerun"],
+           "attempts_per_ray": float(outs["attempts"].double().mean().item()),
+           "error_vs_fp64_1e-8": image_error(outs, ref64)}
+    tight = dict(W.cnfw_1024(), rtol=1e-11, atol=1e-11)
+    ref, ref_ms = timed_trace(tight, 1)
+    log(f"fp64 reference at 1e-11: {ref_ms:.1f} ms")
+    res["error_vs_fp64_1e-11"] = image_error(outs, ref)
+    sweep = []
+    for tol in (1e-6, 1e-7, 1e-8, 1e-9):
+        o, t_ms = timed_trace(dict(W.cnfw_1024(), rtol=tol, atol=tol), max(2, steps // 2))
+        e = image_error(o, ref)
+        sweep.append({"tol": tol, "rays_per_s": n / (t_ms * 1e-3), "kernel_ms": t_ms,
+                      "dI_rel_p99": e["dI_rel_p99"], "dR_em_p99": e["dR_em_p99"],
+                      "ncross_mismatch": e["ncross_mismatch"]})
+        log(f"fp64 tol {tol:g}: {t_ms:.2f} ms, p99 dI/max I {e['dI_rel_p99']:.2e}")
+    res["fp64_sweep_vs_1e-11"] = sweep
+    p99 = res["error_vs_fp64_1e-11"]["dI_rel_p99"]
+    ok = [s_ for s_ in sweep if s_["dI_rel_p99"] <= p99]
+    match = max(ok, key=lambda s_: s_["rays_per_s"]) if ok else None
+    res["fp64_at_matched_accuracy"] = match
+    res["speedup_vs_fp64_1e-8"] = res["rays_per_s"] / next(
+        s_["rays_per_s"] for s_ in sweep if s_["tol"] == 1e-8)
+    res["speedup_vs_fp64_matched"] = res["rays_per_s"] / match["rays_per_s"] if match else None
+    return res
+
+
 def adjoint_measurement(steps: int, cpu: bool) -> dict:
     """Image gradient of the cored-NFW 256x256 tapered-disc image (chi = 0.94,
     theta_o = 60 deg, (eta, lambda_c) = (0.02, 10)) for the loss
@@ -178,6 +264,8 @@ def main() -> int:
     ap.add_argument("--cpu-stride", type=int, default=1)
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the 64-image batched trace + visibility measurement")
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="skip the mixed-precision measurement")
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the image-gradient measurement")
     ap.add_argument("--calibration-copy-mib", type=int, default=0,
@@ -254,6 +342,9 @@ def main() -> int:
         "attempts_per_ray": attempts / n_rays,
         "roofline": roofline,
     }
+    if not args.no_mixed:
+        line["mixed"] = mixed_measurement(max(2, args.steps // 2), outs)
+        line["mixed_rays_per_s"] = line["mixed"]["rays_per_s"]
     if not args.no_batch:
         line["batch_64"] = batch_measurement(max(2, args.steps // 4))
     if not args.no_adjoint:

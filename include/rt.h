@@ -49,8 +49,19 @@ extern "C" {
 /* Spacetime (Sec. 2.1, eqs. (4), (9), (13)). */
 enum { RT_KERR = 0, RT_EINASTO = 1, RT_CNFW = 2 };
 
-/* Arithmetic of the trace. */
-enum { RT_FP64 = 0 };
+/* Arithmetic of the trace.
+ *   RT_FP64   every ray in binary64 at rtol/atol.
+ *   RT_MIXED  rays start in binary32 (right-hand side, stages and step
+ *             controller in single precision at max(rtol, 1e-6) and
+ *             max(atol, 1e-6); the state carried as a compensated float pair).
+ *             A ray continues in binary64 at rtol/atol from the first step
+ *             that would end within 1.5 R_+ of the horizon, and a ray with two
+ *             crossings or more than 1024 accepted binary32 steps is traced
+ *             again entirely in binary64 (its outputs are then those of
+ *             RT_FP64).  Crossings are located, and all outputs written, in
+ *             binary64.  Images of a batch with this precision run after the
+ *             binary64 ones, one launch pair each. */
+enum { RT_FP64 = 0, RT_MIXED = 1 };
 
 /* Return codes. */
 enum {
@@ -71,7 +82,7 @@ enum {
 /* Parameters of one image (host memory). */
 typedef struct rt_image_params {
   int32_t metric;        /* RT_KERR, RT_EINASTO or RT_CNFW                            */
-  int32_t precision;     /* RT_FP64                                                   */
+  int32_t precision;     /* RT_FP64 or RT_MIXED                                       */
   double spin;           /* chi = a/M (eq. (1)); the spacetime must have a horizon    */
   double halo[2];        /* RT_EINASTO: {lambda_E > 0 (eq. (10)), ignored};
                             RT_CNFW: {eta >= 0 (eq. (14)), lambda_c > 0 (eq. (12))};
@@ -173,7 +184,7 @@ enum { RT_GRAD_NATIVE = 0, RT_GRAD_DENSITY = 1 };
  * existence (A > 0 in eq. (89)); the crossing points move with q by the
  * implicit function theorem on the step's continuous extension, and the inner
  * disc edge, when it is the outer horizon (r_in <= 0), moves with R_+.
- *   params    the image (as for rt_trace_image; precision RT_FP64)
+ *   params    the image (as for rt_trace_image; precision must be RT_FP64)
  *   dl_dI     device [ny][nx] cotangent dL/dI of the image
  *   basis     RT_GRAD_NATIVE or RT_GRAD_DENSITY (cored NFW only)
  *   grad      device [4]: dL/dq = sum over pixels of dl_dI dI/dq (fixed order,
@@ -190,6 +201,13 @@ enum { RT_GRAD_NATIVE = 0, RT_GRAD_DENSITY = 1 };
  * metric other than RT_CNFW. */
 int rt_image_vjp(const rt_image_params *params, const double *dl_dI, int32_t basis,
                  double *grad, double *grad_pix, void *hip_stream);
+
+/* Counters of the last mixed-precision image traced on this thread and the
+ * current device: out[0] = rays finished in binary64 (continued from the
+ * horizon zone or traced again), out[1] = of those, rays traced again from the
+ * screen.  Synchronous (waits for that call's work).  Both 0 before any such
+ * call. */
+int rt_mixed_stats(int64_t *out);
 
 /* Device memory the gradient may use for tapes at once (thread-local, bytes,
  * at least 1 MiB; default 16 GiB).  A smaller budget only splits the work. */

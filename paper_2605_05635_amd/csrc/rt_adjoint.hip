@@ -32,18 +32,6 @@ struct ListShape {
     int32_t chunk;
 };
 
-// Claim of the next chunk of ordinals [next, end) below `total` (one atomic per wave).
-__device__ __forceinline__ bool claim_chunk(unsigned long long* queue, int32_t chunk,
-                                            int64_t total, int64_t& next, int64_t& end) {
-    unsigned long long base = 0;
-    if (__lane_id() == 0) base = atomicAdd(queue, static_cast<unsigned long long>(chunk));
-    base = __shfl(base, 0);
-    if (static_cast<int64_t>(base) >= total) return false;
-    next = static_cast<int64_t>(base);
-    end = next + chunk < total ? next + chunk : total;
-    return true;
-}
-
 template <int METRIC>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 8))) void vjp_count_kernel(
     ImageConst c, const double* __restrict__ dl_dI, int32_t* __restrict__ count,

@@ -40,6 +40,11 @@ int hip_fail(hipError_t e, const char* what) {
 // table (~270 bytes each); larger batches run as consecutive launches.
 constexpr int kMaxBatch = 128;
 constexpr int kDefaultChunk = 64;
+// Mixed precision: the binary32 bulk integrates at tolerances no tighter than
+// kTol32Floor (binary32 stage values carry ~6e-8 relative rounding), and a ray
+// continues in binary64 below kZoneFactor R_+.
+constexpr double kTol32Floor = 1e-6;
+constexpr double kZoneFactor = 1.5;
 
 // Pinned host staging for the batched kernel's image tables, reused across
 // calls on this thread; `ready` is recorded after the copy that reads it.
@@ -212,7 +217,7 @@ int setup_image(const rt_image_params* p, int index, bool emission, rt::ImageCon
     if (!p) return fail(RT_ERR_ARG, "image %d: null parameter pointer", index);
     if (p->metric < RT_KERR || p->metric > RT_CNFW)
         return fail(RT_ERR_ARG, "image %d: unknown metric %d", index, p->metric);
-    if (p->precision != RT_FP64)
+    if (p->precision != RT_FP64 && p->precision != RT_MIXED)
         return fail(RT_ERR_ARG, "image %d: unsupported precision %d", index, p->precision);
     if (p->reserved != 0) return fail(RT_ERR_ARG, "image %d: reserved field must be 0", index);
     if (!finite_all({p->spin, p->halo[0], p->halo[1], p->incl, p->r_obs, p->x_min, p->x_max,
@@ -255,6 +260,9 @@ int setup_image(const rt_image_params* p, int index, bool emission, rt::ImageCon
     if (r_plus_out) *r_plus_out = r_plus;
     c->r_stop = p->r_stop_fac * r_plus;
     c->r_esc = p->r_esc_fac * p->r_obs;
+    c->r_zone = kZoneFactor * r_plus;
+    c->rtol32 = std::max(p->rtol, kTol32Floor);
+    c->atol32 = std::max(p->atol, kTol32Floor);
     c->r_in = p->r_in > 0.0 ? p->r_in : r_plus;
     c->r_out = p->r_out;
     if (!(c->r_out > c->r_in)) return fail(RT_ERR_ARG, "image %d: need r_out > r_in", index);
@@ -327,6 +335,31 @@ int check_device_ptr(const T* ptr, const char* name, int index) {
     return RT_OK;
 }
 
+// Per-thread, per-device copy of the last mixed-precision call's counters
+// (rays finished in binary64, of which traced again from the screen),
+// written by the device at the end of each call.
+thread_local long long* g_mixed_stats[64] = {};
+
+int mixed_stats_buffer(long long** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= 64) return fail(RT_ERR_HIP, "device index %d out of range", dev);
+    if (!g_mixed_stats[dev]) {
+        void* p = nullptr;
+        if ((e = hipMalloc(&p, 2 * sizeof(long long))) != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return fail(RT_ERR_ALLOC, "mixed-precision statistics buffer allocation failed");
+        }
+        const long long zeros[2] = {0, 0};
+        if ((e = hipMemcpy(p, zeros, sizeof zeros, hipMemcpyHostToDevice)) != hipSuccess)
+            return hip_fail(e, "statistics buffer initialisation");
+        g_mixed_stats[dev] = static_cast<long long*>(p);
+    }
+    *out = g_mixed_stats[dev];
+    return RT_OK;
+}
+
 int trace_common(const rt_image_params* params, int32_t n_images, const rt_image_out* out,
                  void* hip_stream, bool emission) {
     g_last_error.clear();
@@ -360,27 +393,35 @@ int trace_common(const rt_image_params* params, int32_t n_images, const rt_image
                                out[i].t_em, emission ? out[i].g_em : nullptr,
                                emission ? out[i].intensity : nullptr,
                                emission ? out[i].intensity_n : nullptr, out[i].attempts};
-    // Batches: images grouped by metric (stable), at most kMaxBatch per launch.
-    std::vector<int> order(n_images);
-    for (int i = 0; i < n_images; ++i) order[i] = i;
+    // Binary64 images: one launch for a single image, else batches grouped by
+    // metric (stable), at most kMaxBatch per launch.  Mixed-precision images
+    // run one by one after them.
+    std::vector<int> order, mixed;
+    for (int i = 0; i < n_images; ++i)
+        (params[i].precision == RT_MIXED ? mixed : order).push_back(i);
     std::stable_sort(order.begin(), order.end(),
                      [&](int a, int b) { return consts[a].metric < consts[b].metric; });
-    const int n_launch = n_images == 1 ? 1 : (n_images + kMaxBatch - 1) / kMaxBatch;
+    const int nf = static_cast<int>(order.size());
+    const int n_launch = nf <= 1 ? nf : (nf + kMaxBatch - 1) / kMaxBatch;
 
-    // Scratch (stream-ordered): a work-queue counter per launch, the reduction
-    // partials, then per batched launch its image table, output table and
-    // chunk prefix sums.
+    // Scratch (stream-ordered): work-queue counters (one per binary64 launch,
+    // then two per mixed image), the reduction partials, per batched launch its
+    // image table, output table and chunk prefix sums, then per mixed image its
+    // counters and the hand-off records.
     auto up256 = [](size_t b) { return (b + 255) / 256 * 256; };
     bool any_reduce = false;
     for (int i = 0; i < n_images; ++i) any_reduce |= emission && out[i].reduce != nullptr;
-    const size_t queue_bytes = up256(sizeof(unsigned long long) * n_launch);
+    const int n_queue = n_launch + 2 * static_cast<int>(mixed.size());
+    const size_t queue_bytes = up256(sizeof(unsigned long long) * std::max(n_queue, 1));
     const size_t part_bytes = any_reduce ? up256(sizeof(double) * 3 * rt::kReduceBlocks) : 0;
     const size_t table_bytes =
-        n_images == 1 ? 0
-                      : up256(sizeof(rt::ImageConst) * n_images) +
-                            up256(sizeof(rt::OutPtrs) * n_images) +
-                            up256(sizeof(int64_t) * (n_images + n_launch));
-    const size_t scratch_bytes = queue_bytes + part_bytes + table_bytes;
+        nf <= 1 ? 0
+                : up256(sizeof(rt::ImageConst) * nf) + up256(sizeof(rt::OutPtrs) * nf) +
+                      up256(sizeof(int64_t) * (nf + n_launch));
+    size_t mixed_bytes = 0;
+    for (int i : mixed)
+        mixed_bytes += 256 + up256(rt::mixed_record_bytes() * static_cast<size_t>(consts[i].n_pix));
+    const size_t scratch_bytes = queue_bytes + part_bytes + table_bytes + mixed_bytes;
     void* scratch = nullptr;
     hipError_t e = hipMallocAsync(&scratch, scratch_bytes, stream);
     if (e != hipSuccess || !scratch) {
@@ -392,6 +433,7 @@ int trace_common(const rt_image_params* params, int32_t n_images, const rt_image
     unsigned long long* queue = reinterpret_cast<unsigned long long*>(base);
     double* partials = reinterpret_cast<double*>(base + queue_bytes);
     char* tables = base + queue_bytes + part_bytes;
+    char* mixed_area = tables + table_bytes;
     auto bail = [&](int code) {
         (void)hipFreeAsync(scratch, stream);
         return code;
@@ -400,9 +442,9 @@ int trace_common(const rt_image_params* params, int32_t n_images, const rt_image
     rt::ImageConst* d_table = nullptr;
     rt::OutPtrs* d_outs = nullptr;
     int64_t* d_cs = nullptr;
-    if (n_images > 1) {
-        const size_t tb = up256(sizeof(rt::ImageConst) * n_images);
-        const size_t ob = up256(sizeof(rt::OutPtrs) * n_images);
+    if (nf > 1) {
+        const size_t tb = up256(sizeof(rt::ImageConst) * nf);
+        const size_t ob = up256(sizeof(rt::OutPtrs) * nf);
         d_table = reinterpret_cast<rt::ImageConst*>(tables);
         d_outs = reinterpret_cast<rt::OutPtrs*>(tables + tb);
         d_cs = reinterpret_cast<int64_t*>(tables + tb + ob);
@@ -415,7 +457,7 @@ int trace_common(const rt_image_params* params, int32_t n_images, const rt_image
         auto* h_cs = reinterpret_cast<int64_t*>(h + tb + ob);
         const rt::LaunchShape sh0 = shape_for(1, 1);
         for (int l = 0, pos = 0; l < n_launch; ++l) {
-            const int lo = l * kMaxBatch, hi = std::min(n_images, lo + kMaxBatch);
+            const int lo = l * kMaxBatch, hi = std::min(nf, lo + kMaxBatch);
             int64_t acc = 0;
             for (int j = lo; j < hi; ++j) {
                 h_table[j] = consts[order[j]];
@@ -429,36 +471,52 @@ int trace_common(const rt_image_params* params, int32_t n_images, const rt_image
         if (e == hipSuccess) e = hipEventRecord(g_staging.ready, stream);
         if (e != hipSuccess) return bail(hip_fail(e, "image table upload"));
     }
-    e = rt::launch_zero(queue, n_launch, stream);
+    e = rt::launch_zero(queue, std::max(n_queue, 1), stream);
     if (e != hipSuccess) return bail(hip_fail(e, "queue reset launch"));
     if (g_timing_start) (void)hipEventRecord(g_timing_start, stream);
-    if (n_images == 1) {
-        const rt::ImageConst& c = consts[0];
-        const int64_t want_blocks = (c.n_pix + 255) / 256;
-        int per_cu = info.blocks_per_cu[c.metric];
+    auto grid_for = [&](int64_t pix, int per_cu) {
+        const int64_t want_blocks = (pix + 255) / 256;
         if (g_launch.blocks_per_cu > 0 && g_launch.blocks_per_cu < per_cu)
             per_cu = g_launch.blocks_per_cu;
         const int64_t resident = static_cast<int64_t>(info.cus) * per_cu;
-        const int32_t grid = static_cast<int32_t>(want_blocks < resident ? want_blocks : resident);
-        e = rt::launch_trace(c, optrs[0], queue, shape_for(c.nx, c.ny), grid, stream);
+        return static_cast<int32_t>(std::max<int64_t>(1, std::min(want_blocks, resident)));
+    };
+    if (nf == 1) {
+        const rt::ImageConst& c = consts[order[0]];
+        e = rt::launch_trace(c, optrs[order[0]], queue, shape_for(c.nx, c.ny),
+                             grid_for(c.n_pix, info.blocks_per_cu[c.metric]), stream);
         if (e != hipSuccess) return bail(hip_fail(e, "trace kernel launch"));
     } else {
         for (int l = 0, pos = 0; l < n_launch; ++l) {
-            const int lo = l * kMaxBatch, hi = std::min(n_images, lo + kMaxBatch);
+            const int lo = l * kMaxBatch, hi = std::min(nf, lo + kMaxBatch);
             int64_t pix = 0;
             for (int j = lo; j < hi; ++j) pix += consts[order[j]].n_pix;
-            const int64_t want_blocks = (pix + 255) / 256;
-            int per_cu = info.batch_blocks_per_cu;
-            if (g_launch.blocks_per_cu > 0 && g_launch.blocks_per_cu < per_cu)
-                per_cu = g_launch.blocks_per_cu;
-            const int64_t resident = static_cast<int64_t>(info.cus) * per_cu;
-            const int32_t grid =
-                static_cast<int32_t>(want_blocks < resident ? want_blocks : resident);
             e = rt::launch_trace_batch(d_table + lo, d_outs + lo, d_cs + pos, hi - lo, queue + l,
-                                       shape_for(1, 1), grid, stream);
+                                       shape_for(1, 1), grid_for(pix, info.batch_blocks_per_cu),
+                                       stream);
             if (e != hipSuccess) return bail(hip_fail(e, "batched trace kernel launch"));
             pos += hi - lo + 1;
         }
+    }
+    long long* stats = nullptr;
+    if (!mixed.empty() && (rc = mixed_stats_buffer(&stats)) != RT_OK) return bail(rc);
+    for (size_t m = 0; m < mixed.size(); ++m) {
+        const int i = mixed[m];
+        const rt::ImageConst& c = consts[i];
+        unsigned long long* q = queue + n_launch + 2 * m;
+        unsigned int* counters = reinterpret_cast<unsigned int*>(mixed_area);
+        double* records = reinterpret_cast<double*>(mixed_area + 256);
+        mixed_area += 256 + up256(rt::mixed_record_bytes() * static_cast<size_t>(c.n_pix));
+        if ((e = rt::launch_zero(reinterpret_cast<unsigned long long*>(counters), 32, stream)) !=
+                hipSuccess ||
+            (e = rt::launch_trace32(c, optrs[i], q, shape_for(c.nx, c.ny),
+                                    grid_for(c.n_pix, rt::mixed_blocks_per_cu(c.metric, 0)),
+                                    records, counters, stream)) != hipSuccess ||
+            (e = rt::launch_resume(c, optrs[i], records, counters, q + 1, 16,
+                                   grid_for(c.n_pix, rt::mixed_blocks_per_cu(c.metric, 1)),
+                                   stream)) != hipSuccess ||
+            (e = rt::launch_copy_counters(counters, stats, stream)) != hipSuccess)
+            return bail(hip_fail(e, "mixed-precision kernel launch"));
     }
     if (g_timing_stop) (void)hipEventRecord(g_timing_stop, stream);
     for (int i = 0; i < n_images; ++i) {
@@ -560,6 +618,8 @@ int image_vjp(const rt_image_params* params, const double* dl_dI, int32_t basis,
         return fail(RT_ERR_ARG, "unknown gradient basis %d", basis);
     if (basis == RT_GRAD_DENSITY && params->metric != RT_CNFW)
         return fail(RT_ERR_ARG, "the density basis applies to the cored-NFW metric only");
+    if (params->precision != RT_FP64)
+        return fail(RT_ERR_ARG, "the gradient is taken of the binary64 trace (precision RT_FP64)");
     rt::ImageConst c;
     double r_plus = 0.0;
     int rc = setup_image(params, 0, true, &c, &r_plus);
@@ -830,6 +890,20 @@ int rt_get_launch_config(rt_launch_config* cfg) {
 int rt_image_vjp(const rt_image_params* params, const double* dl_dI, int32_t basis,
                  double* grad, double* grad_pix, void* hip_stream) {
     return image_vjp(params, dl_dI, basis, grad, grad_pix, hip_stream);
+}
+
+int rt_mixed_stats(int64_t* out) {
+    g_last_error.clear();
+    if (!out) return fail(RT_ERR_ARG, "null stats pointer");
+    long long* d = nullptr;
+    int rc = mixed_stats_buffer(&d);
+    if (rc != RT_OK) return rc;
+    long long h[2] = {0, 0};
+    const hipError_t e = hipMemcpy(h, d, sizeof h, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "statistics read-back");
+    out[0] = h[0];
+    out[1] = h[1];
+    return RT_OK;
 }
 
 int rt_set_tape_budget(int64_t bytes) {

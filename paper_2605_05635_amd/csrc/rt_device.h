@@ -42,6 +42,9 @@ struct ImageConst {
     // integrator and events
     double rtol, atol, h0;
     double r_stop, r_esc;
+    // mixed precision: binary32 bulk tolerances and the radius (1.5 R_+) below
+    // which a ray continues in binary64
+    double rtol32, atol32, r_zone;
     // emission
     double r_in, r_out, emis_pow, sigma_in, sigma_out;
     int32_t taper;       // 1: tanh tapers of eqs. (85)-(86); 0: hard window, eq. (77)
@@ -52,29 +55,30 @@ struct ImageConst {
 // functions mu_E (from eq. (9)) and mu_cNFW (from eq. (13)) are written in
 // cancellation-free forms: mu_E = 1 - e^{-x}(1 + x + x^2/2) with x = R/lambda_E,
 // mu_cNFW = 1 - (R/2) expm1(Ex) with Ex the exponent of eq. (13).  K is any
-// struct with the fields inv_lam, lam_c, inv_lam_c, eta_lc; S is double or a
-// dual number (then K's fields may be dual too).
+// struct with the fields inv_lam, lam_c, inv_lam_c, eta_lc; S is double,
+// float or a dual number (then K's fields may be dual too).
 template <int METRIC, class K, class S>
 __host__ __device__ inline void mass_function(const K& c, const S& R, S& F, S& dF) {
+    const S one(1.0), two(2.0), half(0.5);
     if constexpr (METRIC == KERR) {
-        F = 2.0 * R;
-        dF = S(2.0);
+        F = two * R;
+        dF = two;
     } else if constexpr (METRIC == EINASTO) {
         const S x = R * c.inv_lam;
         const S e = dm::exp(-x);
-        const S mu = 1.0 - e * (1.0 + x * (1.0 + 0.5 * x));
-        const S dmu = 0.5 * e * x * x * c.inv_lam;
-        F = 2.0 * R * mu;
-        dF = 2.0 * (mu + R * dmu);
+        const S mu = one - e * (one + x * (one + half * x));
+        const S dmu = half * e * x * x * c.inv_lam;
+        F = two * R * mu;
+        dF = two * (mu + R * dmu);
     } else {
-        const S iR = 1.0 / R;
-        const S iRl = 1.0 / (R + c.lam_c);
+        const S iR = one / R;
+        const S iRl = one / (R + c.lam_c);
         const S lg = dm::log1p(R * c.inv_lam_c);
-        const S ex = c.eta_lc * (iRl - 2.0 * iR * lg);
-        const S dex = c.eta_lc * (2.0 * iR * (iR * lg - iRl) - iRl * iRl);
+        const S ex = c.eta_lc * (iRl - two * iR * lg);
+        const S dex = c.eta_lc * (two * iR * (iR * lg - iRl) - iRl * iRl);
         const S em1 = dm::expm1(ex);
-        F = R * (2.0 - R * em1);
-        dF = 2.0 - R * (2.0 * em1 + R * (em1 + 1.0) * dex);
+        F = R * (two - R * em1);
+        dF = two - R * (two * em1 + R * (em1 + one) * dex);
     }
 }
 

@@ -79,6 +79,25 @@ hipError_t launch_visibility(void* blas, const ImageConst& c, const double* inte
                              const char** what);
 void* blas_create();
 
+// Mixed precision.  trace32: the binary32 pass over the screen (order of
+// `shape`); rays leaving binary32 append a record of mixed_record_bytes() to
+// `records` (room for n_pix) and bump counters[0] (records) and counters[1]
+// (of which traced again from the screen); counters and *queue start at 0.
+// resume: the binary64 pass over the counters[0] records (count read on the
+// device); a continued ray reaching two crossings is traced again from the
+// screen and counted in counters[1].  copy_counters: stats[0..2) = counters[0..2).  `pass` of
+// mixed_blocks_per_cu: 0 trace32, 1 resume.
+size_t mixed_record_bytes();
+hipError_t launch_trace32(const ImageConst& c, const OutPtrs& o, unsigned long long* queue,
+                          const LaunchShape& shape, int32_t grid, double* records,
+                          unsigned int* counters, hipStream_t stream);
+hipError_t launch_resume(const ImageConst& c, const OutPtrs& o, const double* records,
+                         unsigned int* counters, unsigned long long* queue, int32_t chunk,
+                         int32_t grid, hipStream_t stream);
+hipError_t launch_copy_counters(const unsigned int* counters, long long* stats,
+                                hipStream_t stream);
+int mixed_blocks_per_cu(int metric, int pass);
+
 // Image gradient (reverse mode through every ray's discrete map).
 //   count:   for each pixel with dl_dI != 0, the accepted steps up to the last
 //            emitting crossing (0 if none) -> count[pix]; persistent over the

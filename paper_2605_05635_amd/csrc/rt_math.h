@@ -168,5 +168,22 @@ __host__ __device__ inline double rpow_tenth(double x) {
     return y;
 }
 
+// Binary32 versions for the single-precision bulk trace: the device math
+// library's functions and the hardware reciprocal (about one binary32 ulp).
+__host__ __device__ inline float recip(float x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_rcpf(x);
+#else
+    return 1.0f / x;
+#endif
+}
+__host__ __device__ inline void sincos(float x, float* s_out, float* c_out) {
+    ::sincosf(x, s_out, c_out);
+}
+__host__ __device__ inline float exp(float x) { return ::expf(x); }
+__host__ __device__ inline float expm1(float x) { return ::expm1f(x); }
+__host__ __device__ inline float log1p(float u) { return ::log1pf(u); }
+__host__ __device__ inline float rpow_tenth(float x) { return ::powf(x, -0.1f); }
+
 }  // namespace dm
 }  // namespace rt

@@ -64,6 +64,7 @@ __host__ __device__ __forceinline__ Hot hot_of(const ImageConst& c) {
 template <int METRIC, class K, class S>
 __host__ __device__ __forceinline__ void rhs(const K& k, const S& E, const S& L, const S& R, const S& th,
                                     const S& pR, const S& pth, S d[6]) {
+    const S half(0.5), two(2.0), four(4.0);
     S s, co;
     dm::sincos(th, &s, &co);
     S F, dF;
@@ -72,7 +73,7 @@ __host__ __device__ __forceinline__ void rhs(const K& k, const S& E, const S& L,
     const S R2c = R2 + k.chi2;
     const S Sig = R2 + k.chi2 * co * co;
     const S Del = R2c - F;
-    const S dDel = 2.0 * R - dF;
+    const S dDel = two * R - dF;
     const S iS = rcp(Sig);
     const S iD = rcp(Del);
     const S is = rcp(s);
@@ -81,12 +82,12 @@ __host__ __device__ __forceinline__ void rhs(const K& k, const S& E, const S& L,
     const S Lis2 = L * is * is;
     const S W = L * is - k.chi * E * s;
     const S N = Del * pR * pR + pth * pth - P * PiD + W * W;
-    const S dN = dDel * (pR * pR + PiD * PiD) - 4.0 * R * E * PiD;
+    const S dN = dDel * (pR * pR + PiD * PiD) - four * R * E * PiD;
     d[0] = (PiD * R2c + k.chi * (L - k.chi * E * s * s)) * iS;
     d[1] = Del * pR * iS;
     d[2] = pth * iS;
     d[3] = (k.chi * PiD + Lis2 - k.chi * E) * iS;
-    d[4] = (N * R * iS - 0.5 * dN) * iS;
+    d[4] = (N * R * iS - half * dN) * iS;
     d[5] = co * iS * (W * (Lis2 + k.chi * E) - k.chi2 * s * N * iS);
 }
 
@@ -439,6 +440,18 @@ __device__ __forceinline__ void refill(bool& active, bool& exhausted, int64_t& n
     }
 }
 
+// Claim of the next chunk of ordinals [next, end) below `total` by the whole
+// wave (one atomic, lane 0).  Called with all lanes converged.
+__device__ __forceinline__ bool claim_chunk(unsigned long long* queue, int32_t chunk,
+                                            int64_t total, int64_t& next, int64_t& end) {
+    unsigned long long base = 0;
+    if (__lane_id() == 0) base = atomicAdd(queue, static_cast<unsigned long long>(chunk));
+    base = __shfl(base, 0);
+    if (static_cast<int64_t>(base) >= total) return false;
+    next = static_cast<int64_t>(base);
+    end = next + chunk < total ? next + chunk : total;
+    return true;
+}
 
 }  // namespace ray
 }  // namespace rt

@@ -17,12 +17,12 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libgeodesic_rt.so")
 
 RT_KERR, RT_EINASTO, RT_CNFW = 0, 1, 2
-RT_FP64 = 0
+RT_FP64, RT_MIXED = 0, 1
 RT_OK, RT_ERR_ARG, RT_ERR_NO_HORIZON, RT_ERR_HIP, RT_ERR_ALLOC = 0, -1, -2, -3, -4
 RT_RAY_CAPTURED, RT_RAY_ESCAPED, RT_RAY_STEP_LIMIT = 1, 2, 3
 RT_GRAD_NATIVE, RT_GRAD_DENSITY = 0, 1
 METRIC_ID = {"kerr": RT_KERR, "einasto": RT_EINASTO, "cnfw": RT_CNFW}
-PRECISION_ID = {"fp64": RT_FP64}
+PRECISION_ID = {"fp64": RT_FP64, "mixed": RT_MIXED}
 
 
 class rt_image_params(C.Structure):
@@ -85,6 +85,8 @@ def _load():
     lib.rt_set_kernel_timing.restype = C.c_int
     lib.rt_image_vjp.argtypes = [P, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]
     lib.rt_image_vjp.restype = C.c_int
+    lib.rt_mixed_stats.argtypes = [C.POINTER(C.c_int64)]
+    lib.rt_mixed_stats.restype = C.c_int
     lib.rt_set_tape_budget.argtypes = [C.c_int64]
     lib.rt_set_tape_budget.restype = C.c_int
     lib.rt_vjp_stats.argtypes = [C.POINTER(C.c_int64)]
@@ -228,6 +230,13 @@ def rt_image_vjp(params: rt_image_params, dl_dI, grad, grad_pix=None,
                              _stream_handle(stream)))
 
 
+def rt_mixed_stats() -> dict:
+    """Counters of the last mixed-precision image traced on this thread."""
+    buf = (C.c_int64 * 2)()
+    _check(_lib.rt_mixed_stats(buf))
+    return dict(binary64=buf[0], rerun=buf[1], handed_off=buf[0] - buf[1])
+
+
 def rt_set_tape_budget(nbytes: int) -> None:
     _check(_lib.rt_set_tape_budget(int(nbytes)))
 
@@ -297,7 +306,7 @@ def image_vjp(img: dict, dl_dI, basis: str = "native", per_pixel: bool = False, 
     return (grad, gp) if per_pixel else grad
 
 
-__all__ = ["rt_image_vjp", "rt_set_tape_budget", "rt_vjp_stats", "image_vjp", "rt_trace_image", "rt_transfer_maps", "rt_image_setup", "rt_set_kernel_timing",
+__all__ = ["rt_mixed_stats", "rt_image_vjp", "rt_set_tape_budget", "rt_vjp_stats", "image_vjp", "rt_trace_image", "rt_transfer_maps", "rt_image_setup", "rt_set_kernel_timing",
            "rt_set_launch_config", "rt_get_launch_config", "rt_visibility_dft", "visibility",
            "rt_version",
            "rt_last_error", "trace", "trace_many", "params_from", "out_from", "alloc_outputs",
