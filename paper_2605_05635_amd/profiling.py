@@ -1,6 +1,8 @@
 """Summaries of rocprofv3 output for the committed profiles.
 
     python -m paper_2605_05635_amd.profiling stats KERNEL_STATS_CSV --command CMD --out TXT
+    python -m paper_2605_05635_amd.profiling counters COUNTER_CSV --kernel SUBSTRING
+        --command CMD --out TXT
     python -m paper_2605_05635_amd.profiling traffic --fetch CSV --write CSV
         --kernel SUBSTRING --copy-bytes N --command CMD --out JSON
 
@@ -87,6 +89,24 @@ def traffic(fetch_csv: str, write_csv: str, kernel: str, copy_bytes: int) -> dic
     return res
 
 
+def counters_text(path: str, kernel: str, command: str) -> str:
+    """Average of every counter over the dispatches of `kernel` (a substring
+    of the kernel name) in a `rocprofv3 --pmc` counter_collection table."""
+    acc: dict[str, list[float]] = {}
+    name = None
+    for r in _rows(path):
+        if kernel in r["Kernel_Name"]:
+            name = r["Kernel_Name"]
+            acc.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    if not acc:
+        raise SystemExit(f"no dispatch of {kernel!r}")
+    lines = [f"command: {command}", f"kernel: {name}", ""]
+    for k in sorted(acc):
+        v = acc[k]
+        lines.append(f"{k:32s} {sum(v) / len(v):>22.1f}   (mean of {len(v)} dispatches)")
+    return "\n".join(lines) + "\n"
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__,
                                  formatter_class=argparse.RawDescriptionHelpFormatter)
@@ -95,6 +115,11 @@ def main() -> int:
     a.add_argument("csv")
     a.add_argument("--command", required=True)
     a.add_argument("--out", required=True)
+    c = sub.add_parser("counters")
+    c.add_argument("csv")
+    c.add_argument("--kernel", required=True)
+    c.add_argument("--command", required=True)
+    c.add_argument("--out", required=True)
     b = sub.add_parser("traffic")
     b.add_argument("--fetch", required=True)
     b.add_argument("--write", required=True)
@@ -106,6 +131,10 @@ def main() -> int:
     if args.cmd == "stats":
         with open(args.out, "w") as f:
             f.write(stats_text(args.csv, args.command))
+        return 0
+    if args.cmd == "counters":
+        with open(args.out, "w") as f:
+            f.write(counters_text(args.csv, args.kernel, args.command))
         return 0
     t = traffic(args.fetch, args.write, args.kernel, args.copy_bytes)
     t.update(kernel=args.kernel, command=args.command, kernel_source_hash=trace_source_hash(),
