@@ -190,15 +190,18 @@ enum { RT_GRAD_NATIVE = 0, RT_GRAD_DENSITY = 1 };
  *   grad      device [4]: dL/dq = sum over pixels of dl_dI dI/dq (fixed order,
  *             deterministic)
  *   grad_pix  device [ny][nx][4] per-pixel dl_dI dI/dq, or NULL
- * Pixels with dl_dI = 0 are not traced.  Internally a counting trace, a
- * trace that tapes every accepted step (48 bytes each) of the rays that can
- * contribute, longest first, and a reverse sweep over the tapes; tapes beyond
- * the budget (rt_set_tape_budget) are processed in consecutive slices.
- * Unlike the trace calls this one synchronises `hip_stream` once (after the
- * counting pass, to size the tapes) and allocates stream-ordered device
- * memory of about 4 n_pix (2 + 8) bytes plus the tapes.  Errors as for
- * rt_trace_image; RT_ERR_ARG for an unknown basis or the density basis on a
- * metric other than RT_CNFW. */
+ * Pixels with dl_dI = 0 are not traced.  Internally a trace that tapes every
+ * accepted step (48 bytes) of each contributing ray into a tape region of its
+ * own pixel (up to 1024 steps, fewer if the tape budget requires), then a
+ * reverse sweep over the tapes; the rare rays needing longer tapes are counted
+ * exactly and taped packed, longest first, in slices within the budget.  The
+ * dense tape memory is kept by the library per thread and device between
+ * calls (grown on demand; n_pix x steps x 48 bytes, at most the tape budget).
+ * Unlike the trace calls this one synchronises `hip_stream` once (twice when
+ * long rays occur) to read pass counters, and allocates stream-ordered device
+ * memory of about 4 n_pix (2 + 8) bytes.  Errors as for rt_trace_image;
+ * RT_ERR_ARG for an unknown basis or the density basis on a metric other than
+ * RT_CNFW. */
 int rt_image_vjp(const rt_image_params *params, const double *dl_dI, int32_t basis,
                  double *grad, double *grad_pix, void *hip_stream);
 
@@ -209,12 +212,14 @@ int rt_image_vjp(const rt_image_params *params, const double *dl_dI, int32_t bas
  * call. */
 int rt_mixed_stats(int64_t *out);
 
-/* Device memory the gradient may use for tapes at once (thread-local, bytes,
- * at least 1 MiB; default 16 GiB).  A smaller budget only splits the work. */
+/* Device memory the gradient may use for tapes (thread-local, bytes, at least
+ * 1 MiB; default 16 GiB).  A smaller budget only moves rays to the packed
+ * tapes and splits those into more slices; results are unchanged. */
 int rt_set_tape_budget(int64_t bytes);
 
 /* Statistics of the last rt_image_vjp call on this thread: out[0..3] = {rays
- * taped, tape records, slices, bytes of the largest slice's tape}. */
+ * reversed, tape records reversed, slices of packed tapes (0 if no ray needed
+ * them), bytes of the largest tape area}. */
 int rt_vjp_stats(int64_t *out);
 
 /* How the persistent trace kernels hand out work (thread-local setting,

@@ -533,7 +533,7 @@ int trace_common(const rt_image_params* params, int32_t n_images, const rt_image
 
 // ------------------------------------------------------------ image gradient
 thread_local int64_t g_tape_budget = int64_t(16) << 30;
-thread_local int64_t g_vjp_stats[4] = {0, 0, 0, 0};   // rays, tape steps, slices, tape bytes
+thread_local int64_t g_vjp_stats[4] = {0, 0, 0, 0};   // rays, tape steps, list slices, tape bytes
 
 // jac[m][j]: derivative of per-ray parameter m (the kernel's order: chi, three
 // mass constants, window inner edge, five observer-frame constants,
@@ -609,6 +609,42 @@ int readback_reserve(size_t bytes, void** out) {
     return RT_OK;
 }
 
+// Device memory for the dense tapes, kept per thread and device and grown on
+// demand: a gradient is usually taken many times on one screen.
+struct TapeWorkspace {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+};
+thread_local TapeWorkspace g_tape_ws[64];
+
+int tape_workspace(size_t bytes, void** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= 64) return fail(RT_ERR_HIP, "device index %d out of range", dev);
+    TapeWorkspace& w = g_tape_ws[dev];
+    if (w.bytes < bytes) {
+        if (w.ptr) {
+            // earlier calls' kernels may still read the old tapes
+            if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+            (void)hipFree(w.ptr);
+            w.ptr = nullptr;
+            w.bytes = 0;
+        }
+        if ((e = hipMalloc(&w.ptr, bytes)) != hipSuccess || !w.ptr) {
+            (void)hipGetLastError();
+            w.ptr = nullptr;
+            return fail(RT_ERR_ALLOC, "tape workspace allocation of %zu bytes failed", bytes);
+        }
+        w.bytes = bytes;
+    }
+    *out = w.ptr;
+    return RT_OK;
+}
+
+constexpr int64_t kTapeCapMax = 1024;   // steps per pixel of the dense tape
+constexpr int64_t kTapeCapMin = 16;
+
 int image_vjp(const rt_image_params* params, const double* dl_dI, int32_t basis, double* grad,
               double* grad_pix, void* hip_stream) {
     g_last_error.clear();
@@ -635,9 +671,20 @@ int image_vjp(const rt_image_params* params, const double* dl_dI, int32_t basis,
     const int64_t n_pix = c.n_pix;
     auto up256 = [](size_t b) { return (b + 255) / 256 * 256; };
 
-    // Scratch: queue counters (count pass; tape and reverse passes), counts, gradient partials, per-pixel
+    // Dense tape: cap steps per pixel within the budget (none below kTapeCapMin:
+    // then the dense pass only marks the rays and all go through the list).
+    int64_t cap = std::min<int64_t>(kTapeCapMax, g_tape_budget / (n_pix * rt::kVjpRecBytes));
+    if (cap < kTapeCapMin) cap = 0;
+    void* dense_tape = nullptr;
+    if (cap > 0 &&
+        (rc = tape_workspace(static_cast<size_t>(n_pix * cap * rt::kVjpRecBytes), &dense_tape)) !=
+            RT_OK)
+        return rc;
+
+    // Scratch: queue counters (dense tape, dense reverse, count, then tape and
+    // reverse of the list), pass counters, counts, gradient partials, per-pixel
     // gradients (when the caller passes none).
-    const size_t q_bytes = 256;
+    const size_t q_bytes = 512;
     const size_t cnt_bytes = up256(sizeof(int32_t) * n_pix);
     const size_t part_bytes = up256(sizeof(double) * 4 * rt::kGradBlocks);
     const size_t gp_bytes = grad_pix ? 0 : up256(sizeof(double) * 4 * n_pix);
@@ -649,6 +696,7 @@ int image_vjp(const rt_image_params* params, const double* dl_dI, int32_t basis,
     }
     char* base = static_cast<char*>(scratch);
     unsigned long long* queue = reinterpret_cast<unsigned long long*>(base);
+    unsigned int* counters = reinterpret_cast<unsigned int*>(base + 256);
     int32_t* count = reinterpret_cast<int32_t*>(base + q_bytes);
     double* partials = reinterpret_cast<double*>(base + q_bytes + cnt_bytes);
     double* gp = grad_pix ? grad_pix
@@ -667,104 +715,128 @@ int image_vjp(const rt_image_params* params, const double* dl_dI, int32_t basis,
         const int64_t resident = static_cast<int64_t>(info.cus) * per_cu;
         return static_cast<int32_t>(std::max<int64_t>(1, std::min(want, resident)));
     };
+    const rt::LaunchShape shape = shape_for(c.nx, c.ny);
 
-    // Pass 1: counts.
-    if ((e = rt::launch_zero(queue, 32, stream)) != hipSuccess)
+    // Common path: dense tape, then its reverse sweep.
+    if ((e = rt::launch_zero(queue, 64, stream)) != hipSuccess)
         return bail(hip_fail(e, "queue reset launch"));
     if ((e = rt::launch_fill_zero(gp, 4 * n_pix, stream)) != hipSuccess)
         return bail(hip_fail(e, "gradient fill launch"));
-    if ((e = rt::launch_vjp_count(c, dl_dI, count, queue, shape_for(c.nx, c.ny),
-                                  grid_of(0, n_pix), stream)) != hipSuccess)
-        return bail(hip_fail(e, "count kernel launch"));
-    void* host_cnt = nullptr;
-    if ((rc = readback_reserve(sizeof(int32_t) * n_pix, &host_cnt)) != RT_OK) return bail(rc);
-    if ((e = hipMemcpyAsync(host_cnt, count, sizeof(int32_t) * n_pix, hipMemcpyDeviceToHost,
+    if ((e = rt::launch_vjp_tape_dense(c, dl_dI, static_cast<int32_t>(cap),
+                                       static_cast<double*>(dense_tape), count, counters, queue,
+                                       shape, grid_of(3, n_pix), stream)) != hipSuccess)
+        return bail(hip_fail(e, "tape kernel launch"));
+    if (cap > 0 &&
+        (e = rt::launch_vjp_reverse_dense(c, dl_dI, count, static_cast<int32_t>(cap),
+                                          static_cast<const double*>(dense_tape), jac, gp,
+                                          queue + 1, shape, grid_of(2, n_pix), stream)) !=
+            hipSuccess)
+        return bail(hip_fail(e, "reverse kernel launch"));
+    void* host = nullptr;
+    if ((rc = readback_reserve(std::max<size_t>(16, sizeof(int32_t) * n_pix), &host)) != RT_OK)
+        return bail(rc);
+    if ((e = hipMemcpyAsync(host, counters, 3 * sizeof(unsigned int), hipMemcpyDeviceToHost,
                             stream)) != hipSuccess ||
         (e = hipStreamSynchronize(stream)) != hipSuccess)
-        return bail(hip_fail(e, "count read-back"));
+        return bail(hip_fail(e, "counter read-back"));
+    const unsigned int* hc = static_cast<const unsigned int*>(host);
+    const int64_t marked = hc[0];
+    g_vjp_stats[0] = hc[1];
+    g_vjp_stats[1] = hc[2];
+    g_vjp_stats[3] = n_pix * cap * rt::kVjpRecBytes;
 
-    // Rays with a non-zero count, longest first (counting sort, stable in the
-    // pixel index), and their tape offsets.
-    const int32_t* cnt = static_cast<const int32_t*>(host_cnt);
-    int32_t cmax = 0;
-    int64_t n_list = 0;
-    for (int64_t i = 0; i < n_pix; ++i) {
-        cmax = std::max(cmax, cnt[i]);
-        n_list += cnt[i] > 0;
-    }
-    if (n_list > 0) {
-        std::vector<int64_t> start(static_cast<size_t>(cmax) + 2, 0);
-        for (int64_t i = 0; i < n_pix; ++i)
-            if (cnt[i] > 0) ++start[cmax - cnt[i] + 1];
-        for (size_t b = 1; b < start.size(); ++b) start[b] += start[b - 1];
-        const size_t list_bytes = up256(sizeof(int32_t) * n_list) +
-                                  up256(sizeof(int64_t) * n_list) +
-                                  up256(sizeof(int32_t) * n_list);
-        void* host_list = nullptr;
-        if ((rc = staging_reserve(list_bytes, &host_list)) != RT_OK) return bail(rc);
-        char* hl = static_cast<char*>(host_list);
-        int32_t* h_pix = reinterpret_cast<int32_t*>(hl);
-        int64_t* h_off = reinterpret_cast<int64_t*>(hl + up256(sizeof(int32_t) * n_list));
-        for (int64_t i = 0; i < n_pix; ++i)
-            if (cnt[i] > 0) h_pix[start[cmax - cnt[i]]++] = static_cast<int32_t>(i);
-        int64_t total = 0;
-        for (int64_t e2 = 0; e2 < n_list; ++e2) {
-            h_off[e2] = total;
-            total += cnt[h_pix[e2]];
+    // The marked rays: exact counts, tapes packed longest first (counting
+    // sort, stable in the pixel index), in slices that fit the budget.
+    if (marked > 0) {
+        if ((e = rt::launch_vjp_count(c, dl_dI, count, queue + 2, shape, grid_of(0, n_pix),
+                                      stream)) != hipSuccess)
+            return bail(hip_fail(e, "count kernel launch"));
+        if ((e = hipMemcpyAsync(host, count, sizeof(int32_t) * n_pix, hipMemcpyDeviceToHost,
+                                stream)) != hipSuccess ||
+            (e = hipStreamSynchronize(stream)) != hipSuccess)
+            return bail(hip_fail(e, "count read-back"));
+        const int32_t* cnt = static_cast<const int32_t*>(host);
+        int32_t cmax = 0;
+        int64_t n_list = 0;
+        for (int64_t i = 0; i < n_pix; ++i) {
+            cmax = std::max(cmax, cnt[i]);
+            n_list += cnt[i] > 0;
         }
-        // Slices of the list whose tapes fit the budget.
-        const int64_t rec_budget = std::max<int64_t>(g_tape_budget / rt::kVjpRecBytes, cmax);
-        std::vector<int64_t> cuts{0};
-        for (int64_t e2 = 0; e2 < n_list; ++e2) {
-            const int64_t used = h_off[e2] + cnt[h_pix[e2]] - h_off[cuts.back()];
-            if (used > rec_budget) cuts.push_back(e2);
+        if (n_list > 0) {
+            std::vector<int64_t> start(static_cast<size_t>(cmax) + 2, 0);
+            for (int64_t i = 0; i < n_pix; ++i)
+                if (cnt[i] > 0) ++start[cmax - cnt[i] + 1];
+            for (size_t b = 1; b < start.size(); ++b) start[b] += start[b - 1];
+            const size_t list_bytes = up256(sizeof(int32_t) * n_list) +
+                                      up256(sizeof(int64_t) * n_list) +
+                                      up256(sizeof(int32_t) * n_list);
+            void* host_list = nullptr;
+            if ((rc = staging_reserve(list_bytes, &host_list)) != RT_OK) return bail(rc);
+            char* hl = static_cast<char*>(host_list);
+            int32_t* h_pix = reinterpret_cast<int32_t*>(hl);
+            int64_t* h_off = reinterpret_cast<int64_t*>(hl + up256(sizeof(int32_t) * n_list));
+            for (int64_t i = 0; i < n_pix; ++i)
+                if (cnt[i] > 0) h_pix[start[cmax - cnt[i]]++] = static_cast<int32_t>(i);
+            int64_t total = 0;
+            for (int64_t e2 = 0; e2 < n_list; ++e2) {
+                h_off[e2] = total;
+                total += cnt[h_pix[e2]];
+            }
+            const int64_t rec_budget = std::max<int64_t>(g_tape_budget / rt::kVjpRecBytes, cmax);
+            std::vector<int64_t> cuts{0};
+            for (int64_t e2 = 0; e2 < n_list; ++e2) {
+                const int64_t used = h_off[e2] + cnt[h_pix[e2]] - h_off[cuts.back()];
+                if (used > rec_budget) cuts.push_back(e2);
+            }
+            cuts.push_back(n_list);
+            int64_t max_slice = 0;
+            for (size_t sl = 0; sl + 1 < cuts.size(); ++sl) {
+                const int64_t hi_rec = cuts[sl + 1] < n_list ? h_off[cuts[sl + 1]] : total;
+                max_slice = std::max(max_slice, hi_rec - h_off[cuts[sl]]);
+            }
+            const size_t tape_bytes = static_cast<size_t>(max_slice) * rt::kVjpRecBytes;
+            e = hipMallocAsync(&tape_mem, list_bytes + tape_bytes, stream);
+            if (e != hipSuccess || !tape_mem) {
+                (void)hipGetLastError();
+                tape_mem = nullptr;
+                return bail(fail(RT_ERR_ALLOC, "tape allocation of %zu bytes failed",
+                                 list_bytes + tape_bytes));
+            }
+            char* dl = static_cast<char*>(tape_mem);
+            const int32_t* d_pix = reinterpret_cast<const int32_t*>(dl);
+            const int64_t* d_off =
+                reinterpret_cast<const int64_t*>(dl + up256(sizeof(int32_t) * n_list));
+            int32_t* d_taped = reinterpret_cast<int32_t*>(dl + up256(sizeof(int32_t) * n_list) +
+                                                          up256(sizeof(int64_t) * n_list));
+            double* d_tape = reinterpret_cast<double*>(dl + list_bytes);
+            const size_t up_bytes =
+                up256(sizeof(int32_t) * n_list) + up256(sizeof(int64_t) * n_list);
+            if ((e = hipMemcpyAsync(tape_mem, host_list, up_bytes, hipMemcpyHostToDevice,
+                                    stream)) != hipSuccess ||
+                (e = hipEventRecord(g_staging.ready, stream)) != hipSuccess)
+                return bail(hip_fail(e, "ray list upload"));
+            const int32_t chunk = g_launch.chunk > 0 ? g_launch.chunk : 32;
+            const int n_slices = static_cast<int>(cuts.size()) - 1;
+            for (int sl = 0; sl < n_slices; ++sl) {
+                const int64_t lo = cuts[sl], hi = cuts[sl + 1];
+                const int64_t rec_base = h_off[lo];
+                if (sl > 0 && (e = rt::launch_zero(queue + 3, 2, stream)) != hipSuccess)
+                    return bail(hip_fail(e, "queue reset launch"));
+                if ((e = rt::launch_vjp_tape(c, d_pix + lo, d_off + lo, count, hi - lo, rec_base,
+                                             d_tape, d_taped + lo, queue + 3, chunk,
+                                             grid_of(1, hi - lo), stream)) != hipSuccess)
+                    return bail(hip_fail(e, "tape kernel launch"));
+                if ((e = rt::launch_vjp_reverse(c, dl_dI, d_pix + lo, d_off + lo, d_taped + lo,
+                                                hi - lo, rec_base, d_tape, jac, gp, queue + 4,
+                                                chunk, grid_of(2, hi - lo), stream)) !=
+                    hipSuccess)
+                    return bail(hip_fail(e, "reverse kernel launch"));
+            }
+            g_vjp_stats[0] += n_list;
+            g_vjp_stats[1] += total;
+            g_vjp_stats[2] = n_slices;
+            g_vjp_stats[3] = std::max<int64_t>(g_vjp_stats[3], static_cast<int64_t>(tape_bytes));
         }
-        cuts.push_back(n_list);
-        int64_t max_slice = 0;
-        for (size_t sl = 0; sl + 1 < cuts.size(); ++sl) {
-            const int64_t hi_rec = cuts[sl + 1] < n_list ? h_off[cuts[sl + 1]] : total;
-            max_slice = std::max(max_slice, hi_rec - h_off[cuts[sl]]);
-        }
-        const size_t tape_bytes = static_cast<size_t>(max_slice) * rt::kVjpRecBytes;
-        e = hipMallocAsync(&tape_mem, list_bytes + tape_bytes, stream);
-        if (e != hipSuccess || !tape_mem) {
-            (void)hipGetLastError();
-            tape_mem = nullptr;
-            return bail(fail(RT_ERR_ALLOC, "tape allocation of %zu bytes failed",
-                             list_bytes + tape_bytes));
-        }
-        char* dl = static_cast<char*>(tape_mem);
-        const int32_t* d_pix = reinterpret_cast<const int32_t*>(dl);
-        const int64_t* d_off = reinterpret_cast<const int64_t*>(dl + up256(sizeof(int32_t) * n_list));
-        int32_t* d_taped = reinterpret_cast<int32_t*>(dl + up256(sizeof(int32_t) * n_list) +
-                                                      up256(sizeof(int64_t) * n_list));
-        double* d_tape = reinterpret_cast<double*>(dl + list_bytes);
-        const size_t up_bytes = up256(sizeof(int32_t) * n_list) + up256(sizeof(int64_t) * n_list);
-        if ((e = hipMemcpyAsync(tape_mem, host_list, up_bytes, hipMemcpyHostToDevice, stream)) !=
-                hipSuccess ||
-            (e = hipEventRecord(g_staging.ready, stream)) != hipSuccess)
-            return bail(hip_fail(e, "ray list upload"));
-        const int32_t chunk = g_launch.chunk > 0 ? g_launch.chunk : 32;
-        const int n_slices = static_cast<int>(cuts.size()) - 1;
-        for (int sl = 0; sl < n_slices; ++sl) {
-            const int64_t lo = cuts[sl], hi = cuts[sl + 1];
-            const int64_t rec_base = h_off[lo];
-            const int qi = 1;
-            if (sl > 0 && (e = rt::launch_zero(queue + 1, 2, stream)) != hipSuccess)
-                return bail(hip_fail(e, "queue reset launch"));
-            if ((e = rt::launch_vjp_tape(c, d_pix + lo, d_off + lo, count, hi - lo, rec_base,
-                                         d_tape, d_taped + lo, queue + qi, chunk,
-                                         grid_of(1, hi - lo), stream)) != hipSuccess)
-                return bail(hip_fail(e, "tape kernel launch"));
-            if ((e = rt::launch_vjp_reverse(c, dl_dI, d_pix + lo, d_off + lo, d_taped + lo,
-                                            hi - lo, rec_base, d_tape, jac, gp, queue + qi + 1,
-                                            chunk, grid_of(2, hi - lo), stream)) != hipSuccess)
-                return bail(hip_fail(e, "reverse kernel launch"));
-        }
-        g_vjp_stats[0] = n_list;
-        g_vjp_stats[1] = total;
-        g_vjp_stats[2] = n_slices;
-        g_vjp_stats[3] = static_cast<int64_t>(tape_bytes);
     }
     if ((e = rt::launch_grad_reduce(gp, n_pix, partials, grad, stream)) != hipSuccess)
         return bail(hip_fail(e, "gradient reduction launch"));

@@ -99,20 +99,37 @@ hipError_t launch_copy_counters(const unsigned int* counters, long long* stats,
 int mixed_blocks_per_cu(int metric, int pass);
 
 // Image gradient (reverse mode through every ray's discrete map).
-//   count:   for each pixel with dl_dI != 0, the accepted steps up to the last
-//            emitting crossing (0 if none) -> count[pix]; persistent over the
-//            screen in the order of `shape`.
+// Common path:
+//   tape_dense: for each pixel with dl_dI != 0 (screen order of `shape`), the
+//            ray's accepted steps taped at tape + pix * cap records
+//            (kVjpRecBytes each), count[pix] = steps up to the last emitting
+//            crossing (0 if none), or -1 if that exceeds cap; counters[0] +=
+//            such rays, counters[1] += rays with count > 0, counters[2] += the
+//            sum of their counts.
+//   reverse_dense: walks those tapes backwards and writes grad_pix[pix][4] =
+//            dL/dq for the pixels with count > 0, with jac[m][j] the derivative
+//            of per-ray parameter m along the image parameter q_j.
+// Path for the rays marked -1:
+//   count:   traces the pixels whose count is -1 on entry and sets their count
+//            (every other count becomes 0);
 //   tape:    list entries e < n_list (pixel list_pix[e], first record at
-//            list_off[e] - rec_base of `tape`, kVjpRecBytes per record) are
-//            traced again and taped; taped[e] = records written.
-//   reverse: walks the tapes backwards and writes grad_pix[pix][4] =
-//            dL/dq for the pixels of the list, with jac[m][j] the derivative of
-//            per-ray parameter m along the image parameter q_j.
+//            list_off[e] - rec_base of `tape`) traced again and taped;
+//            taped[e] = records written;
+//   reverse: as reverse_dense over the list.
 // Each persistent pass needs its zeroed queue counter.  `pass` of
-// vjp_blocks_per_cu: 0 count, 1 tape, 2 reverse.
+// vjp_blocks_per_cu: 0 count, 1 tape, 2 reverse, 3 tape_dense.
 constexpr int kVjpPrims = 11;
 constexpr int kVjpRecBytes = 48;
 constexpr int kGradBlocks = 256;
+hipError_t launch_vjp_tape_dense(const ImageConst& c, const double* dl_dI, int32_t cap,
+                                 double* tape, int32_t* count, unsigned int* counters,
+                                 unsigned long long* queue, const LaunchShape& shape,
+                                 int32_t grid, hipStream_t stream);
+hipError_t launch_vjp_reverse_dense(const ImageConst& c, const double* dl_dI,
+                                    const int32_t* count, int32_t cap, const double* tape,
+                                    const double (&jac)[kVjpPrims][4], double* grad_pix,
+                                    unsigned long long* queue, const LaunchShape& shape,
+                                    int32_t grid, hipStream_t stream);
 hipError_t launch_vjp_count(const ImageConst& c, const double* dl_dI, int32_t* count,
                             unsigned long long* queue, const LaunchShape& shape, int32_t grid,
                             hipStream_t stream);

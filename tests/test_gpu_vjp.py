@@ -147,13 +147,22 @@ def test_repeat_and_slices_bitwise(rt):
     try:
         g3, p3 = rt.image_vjp(img, dl, per_pixel=True)
         sliced = rt.rt_vjp_stats()
+        # 24 steps per pixel in place: short rays stay, the others are packed
+        rt.rt_set_tape_budget(64 * 48 * 24 * 48)
+        g4, p4 = rt.image_vjp(img, dl, per_pixel=True)
+        split = rt.rt_vjp_stats()
     finally:
         rt.rt_set_tape_budget(16 << 30)
     torch.cuda.synchronize()
-    say(f"[vjp] slices {one['slices']} -> {sliced['slices']}, steps {one['steps']}")
-    assert one["slices"] == 1 and sliced["slices"] > 1
+    say(f"[vjp] slices {one['slices']} -> {sliced['slices']} / {split['slices']}, "
+        f"steps {one['steps']}")
+    # the default budget holds every ray's tape in place; 1 MiB sends all of
+    # them to packed tapes in several slices
+    assert one["slices"] == 0 and sliced["slices"] > 1 and split["slices"] >= 1
     assert sliced["steps"] == one["steps"] and sliced["rays"] == one["rays"]
+    assert split["steps"] == one["steps"] and split["rays"] == one["rays"]
     assert torch.equal(g1, g2) and torch.equal(p1, p2)
+    assert torch.equal(g1, g4) and torch.equal(p1, p4)
     assert torch.equal(g1, g3) and torch.equal(p1, p3)
 
 
