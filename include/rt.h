@@ -44,7 +44,7 @@
 extern "C" {
 #endif
 
-#define RT_VERSION 1
+#define RT_VERSION 2
 
 /* Spacetime (Sec. 2.1, eqs. (4), (9), (13)). */
 enum { RT_KERR = 0, RT_EINASTO = 1, RT_CNFW = 2 };
@@ -223,17 +223,27 @@ int rt_set_tape_budget(int64_t bytes);
 int rt_vjp_stats(int64_t *out);
 
 /* How the persistent trace kernels hand out work (thread-local setting,
- * applies to later calls on this thread).  Pixels are handed to wavefronts in
- * chunks of `chunk` consecutive ordinals of a screen enumeration in tiles of
- * tile_w x tile_h pixels (row by row, clipped at the screen edges); tile_w =
- * tile_h = 0 means plain row-major order; `blocks_per_cu` caps the resident
- * workgroups launched per compute unit (0 = as many as fit).  chunk = 0 means
- * 64.  The results of a trace do not depend on these settings (every ray is
- * traced the same way); only its speed does. */
+ * applies to later calls on this thread).
+ *   order = RT_ORDER_CENTRE (default): a single image's pixels go to
+ *     wavefronts in tiles of tile_w x tile_h pixels (0 x 0: 8 x 8), one tile
+ *     per claim, tiles ordered by the distance of their centre from the screen
+ *     origin (the direction of the hole), so that the long rays near the
+ *     photon ring are traced early and the short distant ones fill the end.
+ *   order = RT_ORDER_SCREEN: pixels go out in chunks of `chunk` consecutive
+ *     ordinals (0: 64) of the screen enumerated in tiles of tile_w x tile_h
+ *     pixels (row by row, clipped at the screen edges; 0 x 0: row-major).
+ * Batched launches (n_images > 1) always use the screen order within each
+ * image, with chunk and tile sizes as set.  `blocks_per_cu` caps the resident
+ * workgroups launched per compute unit (0 = as many as fit).  The results of a
+ * trace do not depend on these settings (every ray is traced the same way);
+ * only its speed does.  The centre-out tables (4 bytes per tile) are built on
+ * the host the first time a screen shape is traced and kept per thread. */
+enum { RT_ORDER_CENTRE = 0, RT_ORDER_SCREEN = 1 };
 typedef struct rt_launch_config {
   int32_t chunk;          /* 0..65536                                            */
   int32_t tile_w, tile_h; /* both 0 or both > 0                                  */
   int32_t blocks_per_cu;  /* 0..64                                               */
+  int32_t order;          /* RT_ORDER_CENTRE or RT_ORDER_SCREEN                   */
 } rt_launch_config;
 
 /* Set (NULL: restore the defaults) or read the launch configuration.

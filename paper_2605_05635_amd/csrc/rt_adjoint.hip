@@ -45,9 +45,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 8))) 
     bool live = false;
     bool active = false, exhausted = false;
     int64_t next = 0, end = 0;
-    auto claim = [&]() { return claim_chunk(queue, shape.chunk, c.n_pix, next, end); };
+    TileClaim tc{0, 0, 1};
+    auto claim = [&]() { return claim_screen(shape, c.nx, c.ny, queue, next, end, tc); };
     auto take = [&](int64_t ordinal) {
-        const int64_t pix = tile_pixel(ordinal, c.nx, c.ny, shape.tile_w, shape.tile_h);
+        const int64_t pix = claimed_pixel(shape, c.nx, c.ny, tc, ordinal);
         start_ray<METRIC>(c, k, pix, r);
         acc = 0;
         last = -1;
@@ -137,9 +138,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 8))) 
     bool live = false;
     bool active = false, exhausted = false;
     int64_t next = 0, end = 0;
-    auto claim = [&]() { return claim_chunk(queue, shape.chunk, c.n_pix, next, end); };
+    TileClaim tc{0, 0, 1};
+    auto claim = [&]() { return claim_screen(shape, c.nx, c.ny, queue, next, end, tc); };
     auto take = [&](int64_t ordinal) {
-        const int64_t pix = tile_pixel(ordinal, c.nx, c.ny, shape.tile_w, shape.tile_h);
+        const int64_t pix = claimed_pixel(shape, c.nx, c.ny, tc, ordinal);
         start_ray<METRIC>(c, k, pix, r);
         acc = 0;
         last = -1;
@@ -225,10 +227,14 @@ __global__ __launch_bounds__(kBlock) void vjp_reverse_kernel(
     double xb[4], Eb, Lb, pb[4], rinb;
     bool active = false, exhausted = false;
     int64_t next = 0, end = 0;
-    auto claim = [&]() { return claim_chunk(queue, shape.chunk, n_items, next, end); };
+    TileClaim tc{0, 0, 1};
+    auto claim = [&]() {
+        if constexpr (DENSE) return claim_screen(shape, c.nx, c.ny, queue, next, end, tc);
+        return claim_chunk(queue, shape.chunk, n_items, next, end);
+    };
     auto take = [&](int64_t e) {
         if constexpr (DENSE) {
-            pix = tile_pixel(e, c.nx, c.ny, shape.tile_w, shape.tile_h);
+            pix = claimed_pixel(shape, c.nx, c.ny, tc, e);
             rec = pix * static_cast<int64_t>(cap);
             step = steps[pix] - 1;
         } else {

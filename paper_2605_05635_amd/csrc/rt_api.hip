@@ -19,7 +19,7 @@ namespace {
 
 thread_local std::string g_last_error;
 thread_local hipEvent_t g_timing_start = nullptr, g_timing_stop = nullptr;
-thread_local rt_launch_config g_launch = {0, 0, 0, 0};
+thread_local rt_launch_config g_launch = {0, 0, 0, 0, 0};
 
 int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
 int fail(int code, const char* fmt, ...) {
@@ -40,6 +40,7 @@ int hip_fail(hipError_t e, const char* what) {
 // table (~270 bytes each); larger batches run as consecutive launches.
 constexpr int kMaxBatch = 128;
 constexpr int kDefaultChunk = 64;
+constexpr int32_t kDefaultTile = 8;   // centre-out hand-out: 8 x 8 pixel tiles
 // Mixed precision: the binary32 bulk integrates at tolerances no tighter than
 // kTol32Floor (binary32 stage values carry ~6e-8 relative rounding), and a ray
 // continues in binary64 below kZoneFactor R_+.
@@ -90,6 +91,76 @@ rt::LaunchShape shape_for(int32_t nx, int32_t ny) {
         sh.tile_h = 1;
     }
     return sh;
+}
+
+// Tiles of a screen in centre-out order: by the distance of the tile's centre
+// from the screen origin (the direction of the hole), ties by tile index.
+// Rays near the photon ring, the longest, are then handed out early and the
+// short rays far from the hole fill the end of the launch.  One device table
+// per screen and tile shape, built on first use and kept (per thread).
+struct TileOrder {
+    int dev;
+    int32_t nx, ny, tw, th;
+    double x0, dx, y0, dy;
+    int32_t* table;
+};
+thread_local std::vector<TileOrder> g_tile_orders;
+constexpr size_t kMaxTileOrders = 64;
+
+int tile_order(const rt::ImageConst& c, int32_t tw, int32_t th, const int32_t** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    for (const TileOrder& t : g_tile_orders)
+        if (t.dev == dev && t.nx == c.nx && t.ny == c.ny && t.tw == tw && t.th == th &&
+            t.x0 == c.x0 && t.dx == c.dx && t.y0 == c.y0 && t.dy == c.dy) {
+            *out = t.table;
+            return RT_OK;
+        }
+    if (g_tile_orders.size() >= kMaxTileOrders) {
+        // earlier launches may still read the tables
+        if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+        for (TileOrder& t : g_tile_orders) (void)hipFree(t.table);
+        g_tile_orders.clear();
+    }
+    const int32_t tiles_x = (c.nx + tw - 1) / tw, tiles_y = (c.ny + th - 1) / th;
+    const int32_t n = tiles_x * tiles_y;
+    std::vector<int32_t> idx(n);
+    std::vector<double> d2(n);
+    for (int32_t i = 0; i < n; ++i) {
+        idx[i] = i;
+        const int32_t ty = i / tiles_x, tx = i - ty * tiles_x;
+        const double w = std::min(tw, c.nx - tx * tw), h = std::min(th, c.ny - ty * th);
+        const double X = c.x0 + (tx * tw + 0.5 * w) * c.dx;
+        const double Y = c.y0 + (ty * th + 0.5 * h) * c.dy;
+        d2[i] = X * X + Y * Y;
+    }
+    std::stable_sort(idx.begin(), idx.end(), [&](int32_t a, int32_t b) { return d2[a] < d2[b]; });
+    void* d = nullptr;
+    if ((e = hipMalloc(&d, sizeof(int32_t) * n)) != hipSuccess || !d) {
+        (void)hipGetLastError();
+        return fail(RT_ERR_ALLOC, "tile order allocation failed");
+    }
+    if ((e = hipMemcpy(d, idx.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice)) != hipSuccess) {
+        (void)hipFree(d);
+        return hip_fail(e, "tile order upload");
+    }
+    g_tile_orders.push_back(TileOrder{dev, c.nx, c.ny, tw, th, c.x0, c.dx, c.y0, c.dy,
+                                      static_cast<int32_t*>(d)});
+    *out = static_cast<int32_t*>(d);
+    return RT_OK;
+}
+
+// The hand-out of one image's pixels under the current launch configuration.
+int image_shape(const rt::ImageConst& c, rt::LaunchShape* sh) {
+    if (g_launch.order == RT_ORDER_SCREEN) {
+        *sh = shape_for(c.nx, c.ny);
+        return RT_OK;
+    }
+    sh->chunk = g_launch.chunk > 0 ? g_launch.chunk : kDefaultChunk;
+    sh->tile_w = std::min(g_launch.tile_w > 0 ? g_launch.tile_w : kDefaultTile, c.nx);
+    sh->tile_h = std::min(g_launch.tile_h > 0 ? g_launch.tile_h : kDefaultTile, c.ny);
+    return tile_order(c, sh->tile_w, sh->tile_h, &sh->order);
 }
 
 bool finite_all(std::initializer_list<double> v) {
@@ -483,7 +554,9 @@ int trace_common(const rt_image_params* params, int32_t n_images, const rt_image
     };
     if (nf == 1) {
         const rt::ImageConst& c = consts[order[0]];
-        e = rt::launch_trace(c, optrs[order[0]], queue, shape_for(c.nx, c.ny),
+        rt::LaunchShape sh;
+        if ((rc = image_shape(c, &sh)) != RT_OK) return bail(rc);
+        e = rt::launch_trace(c, optrs[order[0]], queue, sh,
                              grid_for(c.n_pix, info.blocks_per_cu[c.metric]), stream);
         if (e != hipSuccess) return bail(hip_fail(e, "trace kernel launch"));
     } else {
@@ -504,12 +577,14 @@ int trace_common(const rt_image_params* params, int32_t n_images, const rt_image
         const int i = mixed[m];
         const rt::ImageConst& c = consts[i];
         unsigned long long* q = queue + n_launch + 2 * m;
+        rt::LaunchShape sh;
+        if ((rc = image_shape(c, &sh)) != RT_OK) return bail(rc);
         unsigned int* counters = reinterpret_cast<unsigned int*>(mixed_area);
         double* records = reinterpret_cast<double*>(mixed_area + 256);
         mixed_area += 256 + up256(rt::mixed_record_bytes() * static_cast<size_t>(c.n_pix));
         if ((e = rt::launch_zero(reinterpret_cast<unsigned long long*>(counters), 32, stream)) !=
                 hipSuccess ||
-            (e = rt::launch_trace32(c, optrs[i], q, shape_for(c.nx, c.ny),
+            (e = rt::launch_trace32(c, optrs[i], q, sh,
                                     grid_for(c.n_pix, rt::mixed_blocks_per_cu(c.metric, 0)),
                                     records, counters, stream)) != hipSuccess ||
             (e = rt::launch_resume(c, optrs[i], records, counters, q + 1, 16,
@@ -715,7 +790,8 @@ int image_vjp(const rt_image_params* params, const double* dl_dI, int32_t basis,
         const int64_t resident = static_cast<int64_t>(info.cus) * per_cu;
         return static_cast<int32_t>(std::max<int64_t>(1, std::min(want, resident)));
     };
-    const rt::LaunchShape shape = shape_for(c.nx, c.ny);
+    rt::LaunchShape shape;
+    if ((rc = image_shape(c, &shape)) != RT_OK) return bail(rc);
 
     // Common path: dense tape, then its reverse sweep.
     if ((e = rt::launch_zero(queue, 64, stream)) != hipSuccess)
@@ -941,12 +1017,12 @@ int rt_visibility_dft(const double* intensity, const rt_image_params* params, co
 int rt_set_launch_config(const rt_launch_config* cfg) {
     g_last_error.clear();
     if (!cfg) {
-        g_launch = rt_launch_config{0, 0, 0, 0};
+        g_launch = rt_launch_config{0, 0, 0, 0, 0};
         return RT_OK;
     }
     if (cfg->chunk < 0 || cfg->chunk > 65536 || cfg->tile_w < 0 || cfg->tile_h < 0 ||
         (cfg->tile_w > 0) != (cfg->tile_h > 0) || cfg->blocks_per_cu < 0 ||
-        cfg->blocks_per_cu > 64)
+        cfg->blocks_per_cu > 64 || (cfg->order != RT_ORDER_CENTRE && cfg->order != RT_ORDER_SCREEN))
         return fail(RT_ERR_ARG, "launch config out of range");
     g_launch = *cfg;
     return RT_OK;

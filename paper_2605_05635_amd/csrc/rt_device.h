@@ -71,8 +71,11 @@ __host__ __device__ inline void mass_function(const K& c, const S& R, S& F, S& d
         F = two * R * mu;
         dF = two * (mu + R * dmu);
     } else {
-        const S iR = one / R;
-        const S iRl = one / (R + c.lam_c);
+        // 1/R and 1/(R + lambda_c) from one reciprocal of their product
+        const S Rl = R + c.lam_c;
+        const S inv = dm::recip(R * Rl);
+        const S iR = Rl * inv;
+        const S iRl = R * inv;
         const S lg = dm::log1p(R * c.inv_lam_c);
         const S ex = c.eta_lc * (iRl - two * iR * lg);
         const S dex = c.eta_lc * (two * iR * (iR * lg - iRl) - iRl * iRl);

@@ -116,6 +116,10 @@ __host__ __device__ inline double value_of(const Dual<N>& x) { return x.v; }
 
 namespace dm {
 template <int N>
+__host__ __device__ inline Dual<N> recip(const Dual<N>& a) {
+    return 1.0 / a;
+}
+template <int N>
 __host__ __device__ inline Dual<N> exp(const Dual<N>& a) {
     const double e = dm::exp(a.v);
     return chain(a, e, e);

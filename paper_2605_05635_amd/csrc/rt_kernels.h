@@ -28,13 +28,16 @@ struct OutPtrs {
 // be captured into a graph and replayed.
 hipError_t launch_zero(unsigned long long* queue, int32_t n, hipStream_t stream);
 
-// Work distribution of the persistent trace kernels: pixels are handed out in
-// chunks of `chunk` consecutive ordinals, ordinals enumerate the screen in
-// tiles of tile_w x tile_h pixels (tile_w = nx, tile_h = 1 is row-major).
+// Work distribution of the persistent trace kernels.  With `order` null,
+// pixels are handed out in chunks of `chunk` consecutive ordinals, ordinals
+// enumerating the screen in tiles of tile_w x tile_h pixels (tile_w = nx,
+// tile_h = 1 is row-major).  With `order` set (n_tiles tile indices, row-major
+// tile numbering), a claim takes one whole tile, tiles in that order.
 struct LaunchShape {
     int32_t chunk;
     int32_t tile_w;
     int32_t tile_h;
+    const int32_t* order = nullptr;
 };
 
 // Launches the persistent single-image trace kernel of c.metric on `grid`

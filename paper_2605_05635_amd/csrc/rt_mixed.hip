@@ -21,9 +21,10 @@ __global__ __launch_bounds__(kBlock) void trace32_kernel(ImageConst c, OutPtrs o
     Ray32 r;
     bool active = false, exhausted = false;
     int64_t next = 0, end = 0;
-    auto claim = [&]() { return claim_chunk(queue, shape.chunk, c.n_pix, next, end); };
+    TileClaim tc{0, 0, 1};
+    auto claim = [&]() { return claim_screen(shape, c.nx, c.ny, queue, next, end, tc); };
     auto take = [&](int64_t ordinal) {
-        start_ray32<METRIC>(c, k, tile_pixel(ordinal, c.nx, c.ny, shape.tile_w, shape.tile_h), r);
+        start_ray32<METRIC>(c, k, claimed_pixel(shape, c.nx, c.ny, tc, ordinal), r);
     };
     const int lane = __lane_id();
     for (;;) {

@@ -453,5 +453,45 @@ __device__ __forceinline__ bool claim_chunk(unsigned long long* queue, int32_t c
     return true;
 }
 
+
+// A wave's current claim in tile-order hand-out (wave-uniform).
+struct TileClaim {
+    int32_t x0, y0, w;
+};
+
+// Next claim of a screen's pixels by the whole wave: a chunk of ordinals of
+// the tile enumeration, or the next tile of shape.order (one atomic either
+// way).  Sets the claimed range [next, end) of ordinals within the claim.
+__device__ __forceinline__ bool claim_screen(const LaunchShape& shape, int32_t nx, int32_t ny,
+                                             unsigned long long* queue, int64_t& next,
+                                             int64_t& end, TileClaim& t) {
+    if (!shape.order)
+        return claim_chunk(queue, shape.chunk, static_cast<int64_t>(nx) * ny, next, end);
+    const int32_t tiles_x = (nx + shape.tile_w - 1) / shape.tile_w;
+    const int32_t n_tiles = tiles_x * ((ny + shape.tile_h - 1) / shape.tile_h);
+    unsigned long long q = 0;
+    if (__lane_id() == 0) q = atomicAdd(queue, 1ull);
+    q = __shfl(q, 0);
+    if (static_cast<int64_t>(q) >= n_tiles) return false;
+    const int32_t id = shape.order[q];
+    const int32_t ty = id / tiles_x;
+    t.x0 = (id - ty * tiles_x) * shape.tile_w;
+    t.y0 = ty * shape.tile_h;
+    t.w = nx - t.x0 < shape.tile_w ? nx - t.x0 : shape.tile_w;
+    const int32_t h = ny - t.y0 < shape.tile_h ? ny - t.y0 : shape.tile_h;
+    next = 0;
+    end = static_cast<int64_t>(t.w) * h;
+    return true;
+}
+
+// Pixel index of ordinal p of the current claim.
+__device__ __forceinline__ int64_t claimed_pixel(const LaunchShape& shape, int32_t nx, int32_t ny,
+                                                 const TileClaim& t, int64_t p) {
+    if (!shape.order) return tile_pixel(p, nx, ny, shape.tile_w, shape.tile_h);
+    const int32_t o = static_cast<int32_t>(p);
+    const int32_t iy = o / t.w;
+    return static_cast<int64_t>(t.y0 + iy) * nx + t.x0 + (o - iy * t.w);
+}
+
 }  // namespace ray
 }  // namespace rt

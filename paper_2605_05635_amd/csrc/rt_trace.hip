@@ -25,7 +25,7 @@ namespace {
 
 using namespace ray;
 
-// Persistent trace kernel for one image.
+// Persistent trace kernel for one image (pixels handed out as shape says).
 template <int METRIC>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 8))) void trace_kernel(
     ImageConst c, OutPtrs o, unsigned long long* queue, LaunchShape shape) {
@@ -33,17 +33,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 8))) 
     Ray r;
     bool active = false, exhausted = false;
     int64_t next = 0, end = 0;   // wave-uniform: claimed ordinals not yet started
-    auto claim = [&]() {
-        unsigned long long base = 0;
-        if (__lane_id() == 0) base = atomicAdd(queue, static_cast<unsigned long long>(shape.chunk));
-        base = __shfl(base, 0);
-        if (static_cast<int64_t>(base) >= c.n_pix) return false;
-        next = static_cast<int64_t>(base);
-        end = next + shape.chunk < c.n_pix ? next + shape.chunk : c.n_pix;
-        return true;
-    };
+    TileClaim tc{0, 0, 1};
+    auto claim = [&]() { return claim_screen(shape, c.nx, c.ny, queue, next, end, tc); };
     auto take = [&](int64_t ordinal) {
-        start_ray<METRIC>(c, k, tile_pixel(ordinal, c.nx, c.ny, shape.tile_w, shape.tile_h), r);
+        start_ray<METRIC>(c, k, claimed_pixel(shape, c.nx, c.ny, tc, ordinal), r);
     };
     for (;;) {
         if (!exhausted) refill(active, exhausted, next, end, claim, take);

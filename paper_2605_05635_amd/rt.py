@@ -21,6 +21,7 @@ RT_FP64, RT_MIXED = 0, 1
 RT_OK, RT_ERR_ARG, RT_ERR_NO_HORIZON, RT_ERR_HIP, RT_ERR_ALLOC = 0, -1, -2, -3, -4
 RT_RAY_CAPTURED, RT_RAY_ESCAPED, RT_RAY_STEP_LIMIT = 1, 2, 3
 RT_GRAD_NATIVE, RT_GRAD_DENSITY = 0, 1
+RT_ORDER_CENTRE, RT_ORDER_SCREEN = 0, 1
 METRIC_ID = {"kerr": RT_KERR, "einasto": RT_EINASTO, "cnfw": RT_CNFW}
 PRECISION_ID = {"fp64": RT_FP64, "mixed": RT_MIXED}
 
@@ -52,7 +53,7 @@ class rt_image_out(C.Structure):
 
 class rt_launch_config(C.Structure):
     _fields_ = [("chunk", C.c_int32), ("tile_w", C.c_int32), ("tile_h", C.c_int32),
-                ("blocks_per_cu", C.c_int32)]
+                ("blocks_per_cu", C.c_int32), ("order", C.c_int32)]
 
 
 class RTError(RuntimeError):
@@ -203,13 +204,14 @@ def visibility(img: dict, intensity, uv, stream=None):
 
 
 def rt_set_launch_config(chunk: int = 0, tile_w: int = 0, tile_h: int = 0,
-                         blocks_per_cu: int = 0, reset: bool = False) -> None:
+                         blocks_per_cu: int = 0, order: int = RT_ORDER_CENTRE,
+                         reset: bool = False) -> None:
     """Work-distribution settings of later traces on this thread (see rt.h);
     reset=True restores the library defaults."""
     if reset:
         _check(_lib.rt_set_launch_config(None))
         return
-    cfg = rt_launch_config(chunk, tile_w, tile_h, blocks_per_cu)
+    cfg = rt_launch_config(chunk, tile_w, tile_h, blocks_per_cu, order)
     _check(_lib.rt_set_launch_config(C.byref(cfg)))
 
 
@@ -217,7 +219,7 @@ def rt_get_launch_config() -> dict:
     cfg = rt_launch_config()
     _check(_lib.rt_get_launch_config(C.byref(cfg)))
     return dict(chunk=cfg.chunk, tile_w=cfg.tile_w, tile_h=cfg.tile_h,
-                blocks_per_cu=cfg.blocks_per_cu)
+                blocks_per_cu=cfg.blocks_per_cu, order=cfg.order)
 
 
 def rt_image_vjp(params: rt_image_params, dl_dI, grad, grad_pix=None,

@@ -132,15 +132,17 @@ def test_image_setup_matches_oracle(rt, orc):
 
 
 def test_launch_config_roundtrip_and_validation(rt):
-    rt.rt_set_launch_config(128, 8, 8, 1)
-    assert rt.rt_get_launch_config() == dict(chunk=128, tile_w=8, tile_h=8, blocks_per_cu=1)
+    rt.rt_set_launch_config(128, 8, 8, 1, rt.RT_ORDER_SCREEN)
+    assert rt.rt_get_launch_config() == dict(chunk=128, tile_w=8, tile_h=8, blocks_per_cu=1,
+                                             order=rt.RT_ORDER_SCREEN)
     for bad in (dict(chunk=-1), dict(tile_w=8), dict(tile_h=4), dict(blocks_per_cu=99),
-                dict(chunk=70000)):
+                dict(chunk=70000), dict(order=2), dict(order=-1)):
         with pytest.raises(rt.RTError) as e:
             rt.rt_set_launch_config(**bad)
         assert e.value.code == rt.RT_ERR_ARG
     rt.rt_set_launch_config(reset=True)
-    assert rt.rt_get_launch_config() == dict(chunk=0, tile_w=0, tile_h=0, blocks_per_cu=0)
+    assert rt.rt_get_launch_config() == dict(chunk=0, tile_w=0, tile_h=0, blocks_per_cu=0,
+                                             order=rt.RT_ORDER_CENTRE)
 
 
 def test_autotune_signature_and_cache(tmp_path, monkeypatch):

@@ -159,16 +159,20 @@ def test_deterministic_and_batched_equals_single(rt):
 
 
 def test_launch_config_does_not_change_results(rt):
-    """Chunk size, tile order and occupancy cap only move rays between lanes."""
+    """Chunk size, tile shape and order (screen or centre-out) and occupancy cap
+    only move rays between lanes."""
     import torch
     img = W.image(metric="cnfw", spin=0.9, halo=(0.03, 7.0), incl=1.2, nx=45, ny=38)
     rt.rt_set_launch_config(reset=True)
     ref = rt.trace(img)
     torch.cuda.synchronize()
     try:
-        for cfg in (dict(chunk=1), dict(chunk=7, tile_w=8, tile_h=8),
-                    dict(chunk=256, tile_w=16, tile_h=4, blocks_per_cu=1),
-                    dict(chunk=33, tile_w=50, tile_h=50)):
+        screen = rt.RT_ORDER_SCREEN
+        for cfg in (dict(chunk=1, order=screen), dict(chunk=7, tile_w=8, tile_h=8, order=screen),
+                    dict(chunk=256, tile_w=16, tile_h=4, blocks_per_cu=1, order=screen),
+                    dict(chunk=33, tile_w=50, tile_h=50, order=screen),
+                    dict(tile_w=3, tile_h=5), dict(tile_w=64, tile_h=1, blocks_per_cu=1),
+                    dict(tile_w=50, tile_h=50)):
             say(f"[parity] launch config {cfg}")
             rt.rt_set_launch_config(**cfg)
             got = rt.trace(img)

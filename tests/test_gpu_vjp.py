@@ -151,8 +151,12 @@ def test_repeat_and_slices_bitwise(rt):
         rt.rt_set_tape_budget(64 * 48 * 24 * 48)
         g4, p4 = rt.image_vjp(img, dl, per_pixel=True)
         split = rt.rt_vjp_stats()
+        rt.rt_set_tape_budget(16 << 30)
+        rt.rt_set_launch_config(chunk=5, order=rt.RT_ORDER_SCREEN)
+        g5, p5 = rt.image_vjp(img, dl, per_pixel=True)
     finally:
         rt.rt_set_tape_budget(16 << 30)
+        rt.rt_set_launch_config(reset=True)
     torch.cuda.synchronize()
     say(f"[vjp] slices {one['slices']} -> {sliced['slices']} / {split['slices']}, "
         f"steps {one['steps']}")
@@ -163,6 +167,7 @@ def test_repeat_and_slices_bitwise(rt):
     assert split["steps"] == one["steps"] and split["rays"] == one["rays"]
     assert torch.equal(g1, g2) and torch.equal(p1, p2)
     assert torch.equal(g1, g4) and torch.equal(p1, p4)
+    assert torch.equal(g1, g5) and torch.equal(p1, p5)
     assert torch.equal(g1, g3) and torch.equal(p1, p3)
 
 
