@@ -123,3 +123,25 @@ def test_mixed_in_batch(rt):
         for k in a:
             assert torch.equal(torch.nan_to_num(a[k].double(), nan=-7.0),
                                torch.nan_to_num(b[k].double(), nan=-7.0)), k
+
+
+@pytest.mark.parametrize("img,label", [
+    (W.image(metric="einasto", spin=0.3, halo=(0.3, 0.0), incl=math.radians(30), nx=1, ny=1),
+     "one-pixel"),
+    (W.image(metric="kerr", spin=0.7, incl=math.radians(40), nx=23, ny=17, x_min=-2, x_max=2,
+             y_min=-2, y_max=2), "inside-shadow"),
+    (W.image(metric="cnfw", spin=-0.6, halo=(0.05, 5.0), incl=math.radians(120), nx=77, ny=1),
+     "one-row-retrograde"),
+], ids=["one-pixel", "inside-shadow", "one-row-retrograde"])
+def test_mixed_edge_screens(rt, img, label):
+    """Degenerate screens run through both passes and agree with binary64 on
+    crossing counts and status."""
+    import torch
+    say(f"[mixed] edge screen {label}")
+    g64 = np_outs(rt.trace(img))
+    gm = np_outs(rt.trace(dict(img, precision="mixed")))
+    torch.cuda.synchronize()
+    assert np.array_equal(gm["ncross"], g64["ncross"])
+    assert np.array_equal(gm["status"], g64["status"])
+    rep, same = report(g64, gm)
+    assert rep["dR_max"] <= 1e-3

@@ -271,3 +271,18 @@ def test_loss_gradient_against_central_differences(rt):
     say(f"[vjp] L = {L0:.6e}; adjoint {grad.tolist()}; differences {fd.tolist()}; "
         f"rel {rel.tolist()}")
     assert np.all(rel <= 1e-3)
+
+
+@pytest.mark.parametrize("img,label", [
+    (W.image(metric="cnfw", spin=0.5, halo=(0.02, 10.0), incl=math.radians(75), nx=1, ny=1,
+             x_min=4.0, x_max=4.5, y_min=-0.2, y_max=0.3, sigma_in=0.5, sigma_out=0.5),
+     "one-pixel"),
+    (W.image(metric="kerr", spin=0.7, incl=math.radians(40), nx=23, ny=17, x_min=-2, x_max=2,
+             y_min=-2, y_max=2, sigma_in=0.4, sigma_out=0.4), "inside-shadow"),
+    (W.image(metric="einasto", spin=0.8, halo=(0.12, 0.0), incl=math.radians(70), nx=31, ny=29,
+             r_in=3.0, sigma_in=0.5, sigma_out=0.5), "given-inner-edge"),
+    (W.image(metric="cnfw", spin=0.94, halo=(0.02, 10.0), incl=math.radians(163), nx=40, ny=1,
+             y_min=-0.05, y_max=0.05, sigma_in=0.5, sigma_out=0.5), "one-row"),
+], ids=["one-pixel", "inside-shadow", "given-inner-edge", "one-row"])
+def test_gradient_edge_screens(rt, orc, img, label):
+    compare_grads(rt, orc, img, label)
