@@ -73,7 +73,7 @@ __host__ __device__ inline void mass_function(const K& c, const S& R, S& F, S& d
     } else {
         // 1/R and 1/(R + lambda_c) from one reciprocal of their product
         const S Rl = R + c.lam_c;
-        const S inv = dm::recip(R * Rl);
+        const S inv = dm::recip1(R * Rl);
         const S iR = Rl * inv;
         const S iRl = R * inv;
         const S lg = dm::log1p(R * c.inv_lam_c);

@@ -120,6 +120,10 @@ __host__ __device__ inline Dual<N> recip(const Dual<N>& a) {
     return 1.0 / a;
 }
 template <int N>
+__host__ __device__ inline Dual<N> recip1(const Dual<N>& a) {
+    return 1.0 / a;
+}
+template <int N>
 __host__ __device__ inline Dual<N> exp(const Dual<N>& a) {
     const double e = dm::exp(a.v);
     return chain(a, e, e);

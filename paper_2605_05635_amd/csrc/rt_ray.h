@@ -18,7 +18,8 @@ namespace ray {
 
 constexpr double kHalfPi = 1.5707963267948966;
 
-__host__ __device__ __forceinline__ double rcp(double x) { return dm::recip(x); }
+__host__ __device__ __forceinline__ double rcp(double x) { return dm::recip1(x); }
+__host__ __device__ __forceinline__ float rcp(float x) { return dm::recip(x); }
 template <int N>
 __host__ __device__ __forceinline__ Dual<N> rcp(const Dual<N>& x) { return 1.0 / x; }
 
