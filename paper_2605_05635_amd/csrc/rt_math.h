@@ -14,9 +14,10 @@
 //     truncated where the first omitted term is below 2^-60 relative;
 //   * log(m) = 2 atanh((m-1)/(m+1)) for m in [sqrt(1/2), sqrt(2)), whose odd
 //     series converges like 0.1716^(2n+1);
-//   * x^(-1/10) by two Newton steps on x y^10 = 1 from a binary32 estimate.
+//   * x^(-1/10) by a Newton step on x y^10 = 1 from a binary32 estimate.
 // Each is accurate to a few units in the last place on its stated domain
-// (tests/test_devmath.py measures this against the host libm).  All are
+// (x^(-1/10): 1e-13 relative; tests/test_devmath.py measures this against
+// mpmath).  All are
 // __host__ __device__ so the same source is tested on the CPU.
 #pragma once
 
@@ -169,7 +170,7 @@ __host__ __device__ inline double log1p(double u) {
 
 // x^(-1/10) for x in [1e-12, 1e12]: a binary32 estimate (~1e-7) refined by
 // one Newton step y <- y (1 + (1 - x y^10)/10), which squares the relative
-// error (~1e-14: the step-size factor needs far less).
+// error (below 1e-13: the step-size factor needs far less).
 __host__ __device__ inline double rpow_tenth(double x) {
     double y = static_cast<double>(powf(static_cast<float>(x), -0.1f));
     for (int it = 0; it < 1; ++it) {
