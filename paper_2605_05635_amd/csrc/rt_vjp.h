@@ -43,28 +43,112 @@ enum Prim {
 // start, its size, and the index (0, 1, 2) of the crossing it recorded, or -1.
 constexpr int kRecDoubles = 6;
 
+// F(R), dF/dR (mass_function) and the reverse mode of both: mass_eval gives
+// the values and keeps what the reverse pass needs; mass_vjp adds the
+// cotangents (Fb, dFb) times the derivatives along R to Rb and along the
+// metric's mass constants to mb[0..2] (Einasto: 1/lambda_E; cored NFW:
+// lambda_c, 1/lambda_c, eta lambda_c).  Written out line by line against the
+// forward formulas of mass_function.
 template <int METRIC>
-struct MassDirs {
-    static constexpr int N = METRIC == KERR ? 1 : (METRIC == EINASTO ? 2 : 4);
+struct MassTape {
+    double F, dF;
+    double a[8];   // forward intermediates (metric-specific)
 };
 
-// F and dF/dR as dual numbers along R (direction 0) and the metric's mass
-// constants (directions 1..): Einasto 1/lambda_E; cored NFW lambda_c,
-// 1/lambda_c, eta lambda_c.
 template <int METRIC>
-__host__ __device__ __forceinline__ void mass_jet(const Hot& k, double R,
-                                                  Dual<MassDirs<METRIC>::N>& F,
-                                                  Dual<MassDirs<METRIC>::N>& dF) {
-    using D = Dual<MassDirs<METRIC>::N>;
-    Coeffs<D> kd;
-    if constexpr (METRIC == EINASTO) {
-        kd.inv_lam = D::var(k.inv_lam, 1);
-    } else if constexpr (METRIC == CNFW) {
-        kd.lam_c = D::var(k.lam_c, 1);
-        kd.inv_lam_c = D::var(k.inv_lam_c, 2);
-        kd.eta_lc = D::var(k.eta_lc, 3);
+__host__ __device__ __forceinline__ void mass_eval(const Hot& k, double R, MassTape<METRIC>& t) {
+    if constexpr (METRIC == KERR) {
+        t.F = 2.0 * R;
+        t.dF = 2.0;
+    } else if constexpr (METRIC == EINASTO) {
+        const double x = R * k.inv_lam;
+        const double e = dm::exp(-x);
+        const double mu = 1.0 - e * (1.0 + x * (1.0 + 0.5 * x));
+        const double dmu = 0.5 * e * x * x * k.inv_lam;
+        t.F = 2.0 * R * mu;
+        t.dF = 2.0 * (mu + R * dmu);
+        t.a[0] = x;
+        t.a[1] = e;
+        t.a[2] = mu;
+        t.a[3] = dmu;
+    } else {
+        const double Rl = R + k.lam_c;
+        const double inv = dm::recip1(R * Rl);
+        const double iR = Rl * inv;
+        const double iRl = R * inv;
+        const double u = R * k.inv_lam_c;
+        const double lg = dm::log1p(u);
+        const double P = iRl - 2.0 * iR * lg;
+        const double Q = 2.0 * iR * (iR * lg - iRl) - iRl * iRl;
+        const double ex = k.eta_lc * P;
+        const double dex = k.eta_lc * Q;
+        const double em1 = dm::expm1(ex);
+        t.F = R * (2.0 - R * em1);
+        t.dF = 2.0 - R * (2.0 * em1 + R * (em1 + 1.0) * dex);
+        t.a[0] = iR;
+        t.a[1] = iRl;
+        t.a[2] = u;
+        t.a[3] = lg;
+        t.a[4] = P;
+        t.a[5] = Q;
+        t.a[6] = em1;
+        t.a[7] = dex;
     }
-    mass_function<METRIC>(kd, D::var(R, 0), F, dF);
+}
+
+template <int METRIC>
+__host__ __device__ __forceinline__ void mass_vjp(const Hot& k, double R,
+                                                  const MassTape<METRIC>& t, double Fb,
+                                                  double dFb, double& Rb, double mb[3]) {
+    if constexpr (METRIC == KERR) {
+        Rb += 2.0 * Fb;
+    } else if constexpr (METRIC == EINASTO) {
+        const double x = t.a[0], e = t.a[1], mu = t.a[2], dmu = t.a[3];
+        // F = 2 R mu, dF = 2 (mu + R dmu)
+        const double b_mu = 2.0 * R * Fb + 2.0 * dFb;
+        const double b_dmu = 2.0 * R * dFb;
+        Rb += 2.0 * mu * Fb + 2.0 * dmu * dFb;
+        // dmu = e x^2 inv_lam / 2
+        double b_e = 0.5 * b_dmu * x * x * k.inv_lam;
+        double b_x = b_dmu * e * x * k.inv_lam;
+        double b_inv = 0.5 * b_dmu * e * x * x;
+        // mu = 1 - e (1 + x + x^2/2)
+        b_e -= b_mu * (1.0 + x * (1.0 + 0.5 * x));
+        b_x -= b_mu * e * (1.0 + x);
+        // e = exp(-x), x = R inv_lam
+        b_x -= b_e * e;
+        Rb += b_x * k.inv_lam;
+        b_inv += b_x * R;
+        mb[0] += b_inv;
+    } else {
+        const double iR = t.a[0], iRl = t.a[1], u = t.a[2], lg = t.a[3], P = t.a[4],
+                     Q = t.a[5], em1 = t.a[6], dex = t.a[7];
+        // F = 2R - R^2 em1;  dF = 2 - 2R em1 - R^2 (em1 + 1) dex
+        Rb += Fb * (2.0 - 2.0 * R * em1) + dFb * (-2.0 * em1 - 2.0 * R * (em1 + 1.0) * dex);
+        const double b_em1 = -Fb * R * R + dFb * (-2.0 * R - R * R * dex);
+        const double b_dex = -dFb * R * R * (em1 + 1.0);
+        // em1 = expm1(ex)
+        const double b_ex = b_em1 * (em1 + 1.0);
+        // dex = eta_lc Q, ex = eta_lc P
+        double b_eta = b_dex * Q + b_ex * P;
+        const double b_Q = b_dex * k.eta_lc;
+        const double b_P = b_ex * k.eta_lc;
+        // Q = 2 iR^2 lg - 2 iR iRl - iRl^2;  P = iRl - 2 iR lg
+        const double b_iR = b_Q * (4.0 * iR * lg - 2.0 * iRl) - 2.0 * b_P * lg;
+        const double b_lg = b_Q * 2.0 * iR * iR - 2.0 * b_P * iR;
+        const double b_iRl = b_Q * (-2.0 * iR - 2.0 * iRl) + b_P;
+        // lg = log1p(u), u = R inv_lam_c
+        const double b_u = b_lg * dm::recip1(1.0 + u);
+        Rb += b_u * k.inv_lam_c;
+        const double b_ilc = b_u * R;
+        // iR = 1/R, iRl = 1/(R + lam_c)
+        Rb += -b_iR * iR * iR;
+        const double b_Rl = -b_iRl * iRl * iRl;
+        Rb += b_Rl;
+        mb[0] += b_Rl;     // lambda_c
+        mb[1] += b_ilc;    // 1/lambda_c
+        mb[2] += b_eta;    // eta lambda_c
+    }
 }
 
 // Reverse mode of the R, theta, p_R, p_theta rows of rhs (d[1], d[2], d[4],
@@ -80,9 +164,9 @@ __host__ __device__ __forceinline__ void rhs_vjp(const Hot& k, double E, double 
     const double R = x[0], th = x[1], pR = x[2], pth = x[3];
     double s, co;
     dm::sincos(th, &s, &co);
-    Dual<MassDirs<METRIC>::N> Fj, dFj;
-    mass_jet<METRIC>(k, R, Fj, dFj);
-    const double F = Fj.v, dF = dFj.v;
+    MassTape<METRIC> mt;
+    mass_eval<METRIC>(k, R, mt);
+    const double F = mt.F, dF = mt.dF;
     const double R2 = R * R;
     const double R2c = R2 + k.chi2;
     const double cc = co * co;
@@ -181,8 +265,7 @@ __host__ __device__ __forceinline__ void rhs_vjp(const Hot& k, double E, double 
     // (s, co) = (sin th, cos th)
     const double b_th = b_s * co - b_co * s;
     // mass function
-    b_R += b_F * Fj.d[0] + b_dF * dFj.d[0];
-    for (int j = 1; j < MassDirs<METRIC>::N; ++j) pb[j] += b_F * Fj.d[j] + b_dF * dFj.d[j];
+    mass_vjp<METRIC>(k, R, mt, b_F, b_dF, b_R, pb + 1);
     // chi2 = chi^2
     b_chi += 2.0 * k.chi * b_chi2;
 
