@@ -132,10 +132,18 @@ __host__ __device__ inline double exp(double x) {
     return ldexp(1.0 + expm1_reduced(r), static_cast<int>(k));
 }
 
-// e^x - 1 without cancellation for small |x|.
+// e^x - 1 without cancellation for small |x|, branch-free: with x = k ln 2 + r,
+// e^x - 1 = 2^k (e^r - 1) + (2^k - 1), one fused multiply-add of exact
+// operands (2^k - 1 is exact for the k that matter; k = 0 for |x| <= ln(2)/2,
+// where the result is the reduced series itself).  -1 below -745; x is
+// clamped at 709, below the overflow of e^x.
 __host__ __device__ inline double expm1(double x) {
-    if (fabs(x) <= 0.34657359027997264) return expm1_reduced(x);
-    return exp(x) - 1.0;
+    const double xc = fmin(fmax(x, -745.0), 709.0);
+    const double k = rint(xc * kInvLn2);
+    double r = fma(-k, kLn2Hi, xc);
+    r = fma(-k, kLn2Lo, r);
+    const double tk = ldexp(1.0, static_cast<int>(k));
+    return fma(tk, expm1_reduced(r), tk - 1.0);
 }
 
 // log(1 + u) for u > -1 (finite).

@@ -25,9 +25,16 @@ namespace {
 
 using namespace ray;
 
+// Waves per SIMD the register allocation aims at: three for Kerr and Einasto
+// (168 VGPRs with three binary64 values of the step spilled to scratch;
+// measured 4-7 % faster than two), two for the cored NFW, whose right-hand
+// side needs ~180 VGPRs (three measured no faster).
+template <int METRIC>
+constexpr int kTraceWaves = METRIC == CNFW ? 2 : 3;
+
 // Persistent trace kernel for one image (pixels handed out as shape says).
 template <int METRIC>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 8))) void trace_kernel(
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kTraceWaves<METRIC>, 8))) void trace_kernel(
     ImageConst c, OutPtrs o, unsigned long long* queue, LaunchShape shape) {
     const Hot k = hot_of(c);
     Ray r;

@@ -70,12 +70,17 @@ def test_exp(driver):
 def test_expm1(driver):
     rng = np.random.default_rng(2)
     x = np.concatenate([rng.uniform(-0.6, 0.2, 3000), 10.0 ** rng.uniform(-20, -1, 500),
-                        -(10.0 ** rng.uniform(-20, -1, 500)), [0.0, 0.3465, -0.3466, 2.0]])
+                        -(10.0 ** rng.uniform(-20, -1, 500)), -(10.0 ** rng.uniform(-1, 2.8, 500)),
+                        10.0 ** rng.uniform(-1, 2.8, 500),
+                        [0.0, 0.3465, -0.3466, 0.34657359027997264, -0.34657359027997264,
+                         0.3465735902799727, 2.0, -700.0, 700.0]])
     out = run(driver, "expm1", x)
     ex = [mp.expm1(mp.mpf(v)) for v in x]
     nz = x != 0
     assert ulp_err(out[nz], [e for e, n in zip(ex, nz) if n]).max() < 4
     assert out[x == 0][0] == 0.0
+    # the limit -1 far below zero
+    assert np.all(run(driver, "expm1", np.array([-745.0, -800.0, -1e10])) == -1.0)
 
 
 def test_log1p(driver):
