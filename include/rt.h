@@ -127,9 +127,12 @@ typedef struct rt_image_out {
  * integrated with Hamilton's equations and the adaptive Dormand-Prince 5(4)
  * controller; equatorial crossings are located on the continuous extension
  * of each step; the thin-disc intensity uses the Keplerian emitter of
- * eqs. (89)-(91).  One image runs the single-image kernel; several images
- * run in one persistent launch per 128 images, rays of all images drawn from
- * one work queue, with results bit-identical to tracing each image alone.
+ * eqs. (89)-(91), computed by a per-pixel pass after the trace from the
+ * crossing counts and radii (an image whose out has no ncross or r_em gets
+ * them in stream-ordered scratch memory).  One image runs the single-image
+ * kernel; several images run in one persistent launch per 128 images, rays of
+ * all images drawn from one work queue, with results bit-identical to tracing
+ * each image alone.
  * Returns RT_ERR_NO_HORIZON if any image has no outer horizon, RT_ERR_ARG for
  * invalid parameters or n_images < 1; in either case nothing is launched. */
 int rt_trace_image(const rt_image_params *params, int32_t n_images, const rt_image_out *out,
@@ -148,8 +151,8 @@ int rt_image_setup(const rt_image_params *params, double *setup);
 /* Profiling hook.  When both are non-NULL hipEvent_t handles, every later
  * rt_trace_image / rt_transfer_maps call made on this thread records
  * `start_event` on its stream just before the first trace kernel and
- * `stop_event` just after the last one (the work-queue reset before and the
- * reductions after are outside the bracket).  NULL, NULL switches it off.
+ * `stop_event` just after the last one (the work-queue reset before, the
+ * emission pass and the reductions after are outside the bracket).  NULL, NULL switches it off.
  * The events stay owned by the caller.  Returns RT_ERR_ARG if exactly one is
  * NULL. */
 int rt_set_kernel_timing(void *start_event, void *stop_event);

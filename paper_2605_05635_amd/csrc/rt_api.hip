@@ -492,7 +492,15 @@ int trace_common(const rt_image_params* params, int32_t n_images, const rt_image
     size_t mixed_bytes = 0;
     for (int i : mixed)
         mixed_bytes += 256 + up256(rt::mixed_record_bytes() * static_cast<size_t>(consts[i].n_pix));
-    const size_t scratch_bytes = queue_bytes + part_bytes + table_bytes + mixed_bytes;
+    // The emission pass reads ncross and r_em: images that do not return them
+    // get scratch ones.
+    size_t emit_bytes = 0;
+    if (emission)
+        for (int i = 0; i < n_images; ++i) {
+            if (!out[i].ncross) emit_bytes += up256(static_cast<size_t>(consts[i].n_pix));
+            if (!out[i].r_em) emit_bytes += up256(sizeof(double) * 3 * static_cast<size_t>(consts[i].n_pix));
+        }
+    const size_t scratch_bytes = queue_bytes + part_bytes + table_bytes + mixed_bytes + emit_bytes;
     void* scratch = nullptr;
     hipError_t e = hipMallocAsync(&scratch, scratch_bytes, stream);
     if (e != hipSuccess || !scratch) {
@@ -505,10 +513,22 @@ int trace_common(const rt_image_params* params, int32_t n_images, const rt_image
     double* partials = reinterpret_cast<double*>(base + queue_bytes);
     char* tables = base + queue_bytes + part_bytes;
     char* mixed_area = tables + table_bytes;
+    char* emit_area = mixed_area + mixed_bytes;
     auto bail = [&](int code) {
         (void)hipFreeAsync(scratch, stream);
         return code;
     };
+    if (emission)
+        for (int i = 0; i < n_images; ++i) {
+            if (!optrs[i].ncross) {
+                optrs[i].ncross = reinterpret_cast<uint8_t*>(emit_area);
+                emit_area += up256(static_cast<size_t>(consts[i].n_pix));
+            }
+            if (!optrs[i].r_em) {
+                optrs[i].r_em = reinterpret_cast<double*>(emit_area);
+                emit_area += up256(sizeof(double) * 3 * static_cast<size_t>(consts[i].n_pix));
+            }
+        }
 
     rt::ImageConst* d_table = nullptr;
     rt::OutPtrs* d_outs = nullptr;
@@ -594,6 +614,22 @@ int trace_common(const rt_image_params* params, int32_t n_images, const rt_image
             return bail(hip_fail(e, "mixed-precision kernel launch"));
     }
     if (g_timing_stop) (void)hipEventRecord(g_timing_stop, stream);
+    if (emission) {
+        if (nf == 1) {
+            e = rt::launch_emission(consts[order[0]], optrs[order[0]], stream);
+        } else {
+            e = hipSuccess;
+            for (int l = 0; l < n_launch && e == hipSuccess; ++l) {
+                const int lo = l * kMaxBatch, hi = std::min(nf, lo + kMaxBatch);
+                int64_t max_pix = 0;
+                for (int j = lo; j < hi; ++j) max_pix = std::max(max_pix, consts[order[j]].n_pix);
+                e = rt::launch_emission_batch(d_table + lo, d_outs + lo, hi - lo, max_pix, stream);
+            }
+        }
+        for (size_t m = 0; m < mixed.size() && e == hipSuccess; ++m)
+            e = rt::launch_emission(consts[mixed[m]], optrs[mixed[m]], stream);
+        if (e != hipSuccess) return bail(hip_fail(e, "emission kernel launch"));
+    }
     for (int i = 0; i < n_images; ++i) {
         if (emission && out[i].reduce) {
             e = rt::launch_reduce(consts[i], out[i].intensity, partials, out[i].reduce, stream);

@@ -53,6 +53,16 @@ hipError_t launch_trace_batch(const ImageConst* table, const OutPtrs* outs,
                               unsigned long long* queue, const LaunchShape& shape, int32_t grid,
                               hipStream_t stream);
 
+// Launches the emission pass of an image after its trace (any kernel that
+// traced it, in stream order): g_em, intensity_n and intensity from the
+// ncross and r_em outputs, which must both be set.
+hipError_t launch_emission(const ImageConst& c, const OutPtrs& o, hipStream_t stream);
+
+// The emission pass of n_images images of a batch (device tables as for
+// launch_trace_batch; max_pix the largest image).
+hipError_t launch_emission_batch(const ImageConst* table, const OutPtrs* outs, int32_t n_images,
+                                 int64_t max_pix, hipStream_t stream);
+
 // LDS bytes of the batched kernel for n_images images.
 size_t batch_lds_bytes(int32_t n_images);
 

@@ -215,11 +215,17 @@ __host__ __device__ __forceinline__ ScreenDir screen_dir(const ImageConst& c, in
     return ScreenDir{-c.r_obs * inv, -Y * inv, -X * inv};
 }
 
+// The photon's conserved E and l of pixel pix.
+__host__ __device__ __forceinline__ void photon_constants(const ImageConst& c, const ScreenDir& n,
+                                                          double& E, double& L) {
+    E = c.obs_N - c.obs_gTph_over_sq_gphph * n.nph;
+    L = c.obs_sq_gphph * n.nph;
+}
+
 template <int METRIC>
 __host__ __device__ __forceinline__ void start_ray(const ImageConst& c, const Hot& k, int64_t pix, Ray& r) {
     const ScreenDir n = screen_dir(c, pix);
-    r.E = c.obs_N - c.obs_gTph_over_sq_gphph * n.nph;
-    r.L = c.obs_sq_gphph * n.nph;
+    photon_constants(c, n, r.E, r.L);
     r.y[0] = 0.0;
     r.y[1] = c.r_obs;
     r.y[2] = c.incl;
@@ -373,9 +379,8 @@ __host__ __device__ __forceinline__ int32_t attempt(const Hot& k, const OutPtrs&
     return 0;
 }
 
-// Ray epilogue: emission of the recorded crossings (Sec. 5.2, evaluated once
-// per ray rather than inside the step loop), then the per-pixel outputs.
-// Records n >= min(N_cross, 3) are NaN.
+// Ray epilogue: the per-pixel transfer-map outputs.  Records n >=
+// min(N_cross, 3) are NaN.  The emission is a separate pass (emit_pixel).
 template <int METRIC>
 __device__ __forceinline__ void finish_ray(const ImageConst& c, const Hot& k, const OutPtrs& o,
                                            const Ray& r, int32_t status) {
@@ -383,22 +388,6 @@ __device__ __forceinline__ void finish_ray(const ImageConst& c, const Hot& k, co
     const int64_t n_pix = c.n_pix;
     const int nrec = r.ncross < 3 ? r.ncross : 3;
     const double nan = __builtin_nan("");
-    if (c.emission) {
-        double intensity = 0.0;
-        for (int n = 0; n < 3; ++n) {
-            const int64_t off = static_cast<int64_t>(n) * n_pix + p;
-            double g = nan, In = nan;
-            if (n < nrec) {
-                const double R = r.rc[n];
-                g = redshift<METRIC>(k, R, r.E, r.L);
-                In = disc_window(c, R, c.r_in) * g * g * g * pow(R, -c.emis_pow);
-                intensity += In;
-            }
-            if (o.g_em) o.g_em[off] = g;
-            if (o.intensity_n) o.intensity_n[off] = In;
-        }
-        if (o.intensity) o.intensity[p] = intensity;
-    }
     if (o.ncross) o.ncross[p] = static_cast<uint8_t>(r.ncross);
     if (o.status) o.status[p] = static_cast<uint8_t>(status);
     if (o.attempts) o.attempts[p] = r.attempts;
@@ -408,6 +397,38 @@ __device__ __forceinline__ void finish_ray(const ImageConst& c, const Hot& k, co
         if (o.phi_em) o.phi_em[off] = nan;
         if (o.t_em) o.t_em[off] = nan;
     }
+}
+
+// Emission of pixel p (Sec. 5.2) from its recorded crossings: the redshift
+// (eq. (89)) and disc intensity of each of the first min(N_cross, 3) crossing
+// radii, their sum, NaN for the records beyond.  Reads o.ncross and o.r_em as
+// the trace wrote them and recomputes the photon's E and l from the screen
+// map, so it gives what the ray's own epilogue would.  One thread per pixel
+// after the trace: the trace's wavefronts then do not carry the emission code
+// through their divergent epilogue, where it cost most of the lanes' time.
+template <int METRIC>
+__device__ __forceinline__ void emit_pixel(const ImageConst& c, const Hot& k, const OutPtrs& o,
+                                           int64_t p) {
+    const int64_t n_pix = c.n_pix;
+    const int ncr = o.ncross[p];
+    const int nrec = ncr < 3 ? ncr : 3;
+    const double nan = __builtin_nan("");
+    double E, L;
+    photon_constants(c, screen_dir(c, p), E, L);
+    double intensity = 0.0;
+    for (int n = 0; n < 3; ++n) {
+        const int64_t off = static_cast<int64_t>(n) * n_pix + p;
+        double g = nan, In = nan;
+        if (n < nrec) {
+            const double R = o.r_em[off];
+            g = redshift<METRIC>(k, R, E, L);
+            In = disc_window(c, R, c.r_in) * g * g * g * pow(R, -c.emis_pow);
+            intensity += In;
+        }
+        if (o.g_em) o.g_em[off] = g;
+        if (o.intensity_n) o.intensity_n[off] = In;
+    }
+    if (o.intensity) o.intensity[p] = intensity;
 }
 
 // Wave-level hand-out of pixels: lanes without a ray take consecutive

@@ -3,9 +3,10 @@
 // One wavefront lane integrates one ray (one screen pixel) from the observer
 // toward the hole with Hamilton's equations (Sec. 3.1, eqs. (46)-(47) and
 // (57)-(62)) and an adaptive Dormand-Prince 5(4) step controller, detects
-// equatorial crossings on the step's continuous extension (Sec. 3.3, 4.2),
-// records the transfer maps of the first three crossings (Sec. 4.3, eq. (82))
-// and the redshifted thin-disc intensity (Sec. 5.2, eqs. (89)-(91)).
+// equatorial crossings on the step's continuous extension (Sec. 3.3, 4.2) and
+// records the transfer maps of the first three crossings (Sec. 4.3, eq. (82)).
+// A second, one-thread-per-pixel pass computes the redshifted thin-disc
+// intensity of the recorded crossings (Sec. 5.2, eqs. (89)-(91)).
 //
 // Launch shape: a persistent grid.  Each wavefront claims chunks of pixels
 // from a global counter with one atomic per chunk; a lane whose ray ends takes
@@ -25,12 +26,10 @@ namespace {
 
 using namespace ray;
 
-// Waves per SIMD the register allocation aims at: three for Kerr and Einasto
-// (168 VGPRs with three binary64 values of the step spilled to scratch;
-// measured 4-7 % faster than two), two for the cored NFW, whose right-hand
-// side needs ~180 VGPRs (three measured no faster).
+// The register allocation aims at three waves per SIMD (168 VGPRs; the cored
+// NFW spills two): measured 5-10 % faster than two.
 template <int METRIC>
-constexpr int kTraceWaves = METRIC == CNFW ? 2 : 3;
+constexpr int kTraceWaves = 3;
 
 // Persistent trace kernel for one image (pixels handed out as shape says).
 template <int METRIC>
@@ -134,6 +133,29 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 8))) 
     }
 }
 
+// Emission pass of one image, one thread per pixel, after its trace.
+template <int METRIC>
+__global__ __launch_bounds__(kBlock) void emission_kernel(ImageConst c, OutPtrs o) {
+    const int64_t p = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    if (p < c.n_pix) emit_pixel<METRIC>(c, hot_of(c), o, p);
+}
+
+// Emission pass of a batch of images: image blockIdx.y, pixels by blockIdx.x.
+__global__ __launch_bounds__(kBlock) void emission_batch_kernel(
+    const ImageConst* __restrict__ table, const OutPtrs* __restrict__ outs) {
+    const ImageConst c = table[blockIdx.y];
+    const int64_t p = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    if (p >= c.n_pix) return;
+    const OutPtrs o = outs[blockIdx.y];
+    const Hot k = hot_of(c);
+    if (c.metric == CNFW)
+        emit_pixel<CNFW>(c, k, o, p);
+    else if (c.metric == EINASTO)
+        emit_pixel<EINASTO>(c, k, o, p);
+    else
+        emit_pixel<KERR>(c, k, o, p);
+}
+
 __global__ void zero_counters(unsigned long long* q, int32_t n) {
     const int32_t i = static_cast<int32_t>(blockIdx.x * blockDim.x + threadIdx.x);
     if (i < n) q[i] = 0ull;
@@ -162,6 +184,30 @@ hipError_t launch_trace(const ImageConst& c, const OutPtrs& o, unsigned long lon
                                queue, shape);
             break;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_emission(const ImageConst& c, const OutPtrs& o, hipStream_t stream) {
+    const dim3 grid(static_cast<unsigned>((c.n_pix + kBlock - 1) / kBlock));
+    switch (c.metric) {
+        case KERR:
+            hipLaunchKernelGGL(emission_kernel<KERR>, grid, dim3(kBlock), 0, stream, c, o);
+            break;
+        case EINASTO:
+            hipLaunchKernelGGL(emission_kernel<EINASTO>, grid, dim3(kBlock), 0, stream, c, o);
+            break;
+        default:
+            hipLaunchKernelGGL(emission_kernel<CNFW>, grid, dim3(kBlock), 0, stream, c, o);
+            break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_emission_batch(const ImageConst* table, const OutPtrs* outs, int32_t n_images,
+                                 int64_t max_pix, hipStream_t stream) {
+    const dim3 grid(static_cast<unsigned>((max_pix + kBlock - 1) / kBlock),
+                    static_cast<unsigned>(n_images));
+    hipLaunchKernelGGL(emission_batch_kernel, grid, dim3(kBlock), 0, stream, table, outs);
     return hipGetLastError();
 }
 

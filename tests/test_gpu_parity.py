@@ -158,6 +158,35 @@ def test_deterministic_and_batched_equals_single(rt):
             assert np.array_equal(x, z, equal_nan=True), k
 
 
+def test_intensity_without_crossing_outputs(rt):
+    """The emission pass reads the crossing counts and radii: a call that asks
+    for the intensities only (no ncross, no r_em) gets them from scratch
+    buffers and returns the same intensities, for a single image, a batch with
+    one such image and a mixed-precision image."""
+    import torch
+    imgs = [W.image(metric="cnfw", spin=0.9, halo=(0.03, 7.0), incl=1.2, nx=45, ny=38),
+            W.image(metric="kerr", spin=0.4, incl=0.7, nx=33, ny=29),
+            W.image(metric="einasto", spin=0.6, halo=(0.2, 0.0), incl=2.2, nx=26, ny=40,
+                    precision="mixed")]
+    ref = [rt.trace(i) for i in imgs]
+
+    def lean(img):
+        outs = rt.alloc_outputs(img)
+        return {k: v for k, v in outs.items() if k not in ("ncross", "r_em")}
+
+    say("[parity] intensities without ncross and r_em")
+    single = lean(imgs[0])
+    rt.rt_trace_image([rt.params_from(imgs[0])], [rt.out_from(single)])
+    batch = [lean(imgs[0]), rt.alloc_outputs(imgs[1])]
+    rt.rt_trace_image([rt.params_from(i) for i in imgs[:2]], [rt.out_from(o) for o in batch])
+    mixed = lean(imgs[2])
+    rt.rt_trace_image([rt.params_from(imgs[2])], [rt.out_from(mixed)])
+    torch.cuda.synchronize()
+    for got, want in ((single, ref[0]), (batch[0], ref[0]), (batch[1], ref[1]), (mixed, ref[2])):
+        for k in got:
+            assert np.array_equal(got[k].cpu().numpy(), want[k].cpu().numpy(), equal_nan=True), k
+
+
 def test_launch_config_does_not_change_results(rt):
     """Chunk size, tile shape and order (screen or centre-out) and occupancy cap
     only move rays between lanes."""
