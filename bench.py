@@ -317,7 +317,7 @@ def main() -> int:
     attempts = outs["attempts"].double().sum().item()
     crossings = outs["ncross"].double().sum().item()
     flops = (attempts * (6 * census.flops_rhs(img["metric"]) + census.flops_step_overhead())
-             + crossings * census.flops_crossing(img["metric"])
+             + crossings * census.flops_crossing()
              + n_rays * (20 + census.flops_rhs(img["metric"])))
     k_s = float(np.mean(kernel_ms)) * 1e-3
     achieved = flops / k_s / 1e12

@@ -1,8 +1,9 @@
 """Algorithmic operation census of the trace (for roofline accounting).
 
 Counts the floating-point operations one right-hand-side evaluation, one
-Dormand-Prince step attempt and one recorded crossing must perform, by
-executing the kernel's formulas (rt_trace.hip) once with a counting scalar.
+Dormand-Prince step attempt, the location of one crossing (trace kernel) and
+the emission of one recorded crossing (emission pass) must perform, by
+executing the kernels' formulas once with a counting scalar.
 Convention: every +, -, *, / , sqrt, fabs/fmax/fmin and every special-function
 value (sin, cos, exp, expm1, log1p, pow, tanh) counts as one flop; common
 subexpressions are counted once, as the kernel computes them; comparisons and
@@ -121,14 +122,22 @@ def flops_step_overhead() -> int:
     return n
 
 
-def flops_crossing(metric: str, bisections: int = 60) -> int:
-    """Locating and recording one crossing: dense coefficients for theta, R,
-    p_theta, phi and T; the bisection on theta(s); the evaluations at the root;
-    the Keplerian redshift and the disc emission."""
+def flops_crossing(newton: int = 6) -> int:
+    """Locating one crossing (trace kernel): dense coefficients for theta, R,
+    p_theta, phi and T; the safeguarded Newton iteration on theta(s) (a nominal
+    `newton` iterations: from the secant start it reaches a 1e-15 step in a
+    handful); the evaluations at the root and the trusted-crossing test."""
     dense_coeffs = 5 * (3 + 12 + 1)      # r2, r3, r4 and r5 = h sum d_i k_i
+    start = 5 + 2                         # quartic coefficients, secant root
+    per_iter = 9 + 9 + 2 + 2              # theta(s) - pi/2, derivative, update, bracket
     per_eval = 9                          # y0 + s (r2 + (1-s)(r3 + s (r4 + (1-s) r5)))
-    bis = bisections * (per_eval + 3)     # midpoint, evaluation, compare offset
-    at_root = 4 * per_eval + 4            # R, p_theta, phi, T; affine position
+    at_root = 4 * per_eval + 2 + 4        # R, p_theta, phi, T; affine position; filter
+    return dense_coeffs + start + newton * per_iter + at_root
+
+
+def flops_emission(metric: str) -> int:
+    """The emission of one recorded crossing (emission pass): the Keplerian
+    redshift, the disc window and g^3 R^-p, added to the pixel's sum."""
     Num.ops = 0
     c = _consts(metric)
     R = Num(7.0)
@@ -144,17 +153,19 @@ def flops_crossing(metric: str, bisections: int = 60) -> int:
     g = f("sqrt", A) / (1.0 - Om * 2.0)
     In = g * g * g * f("pow", R, -3.0)
     _ = In + 1.0
-    return dense_coeffs + bis + at_root + Num.ops
+    return Num.ops
 
 
-def flops_per_ray(metric: str, attempts: float, crossings: float) -> float:
-    """Algorithmic flops of a ray with the given step attempts and recorded
-    crossings (plus its start: screen map and one right-hand side)."""
+def flops_trace_ray(metric: str, attempts: float, crossings: float) -> float:
+    """Algorithmic flops of the trace kernel for a ray with the given step
+    attempts and trusted crossings (plus its start: screen map and one
+    right-hand side)."""
     return (attempts * (6 * flops_rhs(metric) + flops_step_overhead())
-            + crossings * flops_crossing(metric) + 20 + flops_rhs(metric))
+            + crossings * flops_crossing() + 20 + flops_rhs(metric))
 
 
 if __name__ == "__main__":
     for m in ("kerr", "einasto", "cnfw"):
         print(m, "rhs", flops_rhs(m), "step", flops_step_overhead(), "crossing",
-              flops_crossing(m), "attempt", 6 * flops_rhs(m) + flops_step_overhead())
+              flops_crossing(), "emission", flops_emission(m), "attempt",
+              6 * flops_rhs(m) + flops_step_overhead())

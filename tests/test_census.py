@@ -30,3 +30,6 @@ def test_census_counts_are_positive_and_ordered():
     k, e, c = (census.flops_rhs(m) for m in ("kerr", "einasto", "cnfw"))
     assert 50 < k < e < c < 200
     assert 250 < census.flops_step_overhead() < 450
+    assert 150 < census.flops_crossing() < 400
+    ke, ee, ce = (census.flops_emission(m) for m in ("kerr", "einasto", "cnfw"))
+    assert 20 < ke < ee < ce < 120
