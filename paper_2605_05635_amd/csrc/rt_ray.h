@@ -248,20 +248,21 @@ __host__ __device__ __forceinline__ void start_ray(const ImageConst& c, const Ho
 // y0 + s (c1 + s (c2 + s (c3 + s c4))), Newton's method starts from the secant
 // root and is kept inside the shrinking sign bracket (bisection when a Newton
 // step would leave it); it stops when the step falls below 1e-15 or the
-// bracket is exhausted.
+// bracket is exhausted.  The quotients use the one-Newton-step reciprocal
+// (2e-15): an error of that size in a Newton step is corrected by the next.
 __host__ __device__ __forceinline__ double crossing_root(const DenseComp& d, bool up0) {
     const double c1 = d.r2 + d.r3;
     const double c2 = d.r4 + d.r5 - d.r3;
     const double c3 = -d.r4 - 2.0 * d.r5;
     const double c4 = d.r5;
     double a = 0.0, b = 1.0;
-    double s = (kHalfPi - d.y0) / d.r2;
+    double s = (kHalfPi - d.y0) * rcp(d.r2);
     if (!(s > 0.0 && s < 1.0)) s = 0.5;
     for (int it = 0; it < 48; ++it) {
         const double f = d.y0 + s * (c1 + s * (c2 + s * (c3 + s * c4))) - kHalfPi;
         if ((f >= 0.0) == up0) a = s; else b = s;
         const double df = c1 + s * (2.0 * c2 + s * (3.0 * c3 + s * 4.0 * c4));
-        double sn = s - f / df;
+        double sn = s - f * rcp(df);
         if (!(sn > a && sn < b)) sn = 0.5 * (a + b);
         const double step = fabs(sn - s);
         s = sn;
