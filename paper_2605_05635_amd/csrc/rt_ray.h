@@ -175,26 +175,28 @@ struct Ray {
 // tw x th pixels, taken row by row; pixels inside a tile row by row; tiles on
 // the right and bottom edges are clipped to the screen.  tw = nx, th = 1 is
 // plain row-major order.  A bijection of [0, nx ny).
-__device__ __forceinline__ int64_t tile_pixel(int64_t p, int32_t nx, int32_t ny, int32_t tw,
+__device__ __forceinline__ int64_t tile_pixel(int64_t p64, int32_t nx, int32_t ny, int32_t tw,
                                               int32_t th) {
-    const int64_t band = static_cast<int64_t>(th) * nx;   // pixels per full tile row
-    const int64_t r = p / band;                             // tile row
-    const int64_t h = (r + 1) * th <= ny ? th : ny - r * th;
-    const int64_t q = p - r * band;                          // index inside the tile row
-    const int64_t full = nx / tw;                            // unclipped tiles per row
-    const int64_t j = q / (static_cast<int64_t>(tw) * h);
-    int64_t ix, iy;
+    // 32-bit index arithmetic: screens hold fewer than 2^31 pixels
+    const int32_t p = static_cast<int32_t>(p64);
+    const int32_t band = th * nx;                  // pixels per full tile row
+    const int32_t r = p / band;                    // tile row
+    const int32_t h = (r + 1) * th <= ny ? th : ny - r * th;
+    const int32_t q = p - r * band;                // index inside the tile row
+    const int32_t full = nx / tw;                  // unclipped tiles per row
+    const int32_t j = q / (tw * h);
+    int32_t ix, iy;
     if (j < full) {
-        const int64_t off = q - j * tw * h;
+        const int32_t off = q - j * tw * h;
         iy = r * th + off / tw;
         ix = j * tw + off % tw;
     } else {
-        const int64_t w = nx - full * tw;
-        const int64_t off = q - full * tw * h;
+        const int32_t w = nx - full * tw;
+        const int32_t off = q - full * tw * h;
         iy = r * th + off / w;
         ix = full * tw + off % w;
     }
-    return iy * nx + ix;
+    return static_cast<int64_t>(iy) * nx + ix;
 }
 
 // Screen pixel -> initial state (Sec. 3.2, eqs. (70)-(74) with E_loc = 1):
@@ -207,8 +209,10 @@ struct ScreenDir {
 };
 
 __host__ __device__ __forceinline__ ScreenDir screen_dir(const ImageConst& c, int64_t pix) {
-    const int64_t iy = pix / c.nx;
-    const int64_t ix = pix - iy * c.nx;
+    // 32-bit index arithmetic: screens hold fewer than 2^31 pixels
+    const int32_t p = static_cast<int32_t>(pix);
+    const int32_t iy = p / c.nx;
+    const int32_t ix = p - iy * c.nx;
     const double X = c.x0 + (static_cast<double>(ix) + 0.5) * c.dx;
     const double Y = c.y0 + (static_cast<double>(iy) + 0.5) * c.dy;
     const double inv = 1.0 / sqrt(c.r_obs * c.r_obs + X * X + Y * Y);
@@ -247,7 +251,8 @@ __host__ __device__ __forceinline__ void start_ray(const ImageConst& c, const Ho
 // given theta(0) and theta(1) on opposite sides.  Writing the extension as
 // y0 + s (c1 + s (c2 + s (c3 + s c4))), Newton's method starts from the secant
 // root and is kept inside the shrinking sign bracket (bisection when a Newton
-// step would leave it); it stops when the step falls below 1e-15 or the
+// step would leave it); it stops after a step below 1e-10 (Newton's quadratic
+// convergence leaves the new iterate ~1e-20 c2/c1 from the root) or when the
 // bracket is exhausted.  The quotients use the one-Newton-step reciprocal
 // (2e-15): an error of that size in a Newton step is corrected by the next.
 __host__ __device__ __forceinline__ double crossing_root(const DenseComp& d, bool up0) {
@@ -266,7 +271,7 @@ __host__ __device__ __forceinline__ double crossing_root(const DenseComp& d, boo
         if (!(sn > a && sn < b)) sn = 0.5 * (a + b);
         const double step = fabs(sn - s);
         s = sn;
-        if (step <= 1e-15 || b - a <= 1e-15) break;
+        if (step <= 1e-10 || b - a <= 1e-15) break;
     }
     return s;
 }
