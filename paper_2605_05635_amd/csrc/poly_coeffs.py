@@ -1,0 +1,77 @@
+"""Coefficients of the polynomial kernels of rt_math.h.
+
+Each kernel approximates a smooth auxiliary function on the reduced interval
+its caller guarantees, by Chebyshev interpolation (mpmath.chebyfit, within a
+small factor of the best uniform approximation of that degree) in 60-digit
+arithmetic, the coefficients then rounded to binary64.  The printed bound is
+the largest relative error of the resulting function value (before the
+rounding of its binary64 evaluation), measured on a 4000-point grid:
+
+    sin r = r + r z S(z),            z = r^2 in [0, (pi/4)^2]
+    cos r = 1 + z C(z)
+    e^r - 1 = r + r^2 E(r),          |r| <= ln(2)/2 (+1e-9)
+    log m = 2 (t + t z L(z)),        t = (m-1)/(m+1), m in [sqrt(1/2), sqrt(2)), z = t^2
+
+Run `python poly_coeffs.py` to print the tables in the order rt_math.h
+evaluates them (highest degree first).
+"""
+import mpmath as mp
+
+mp.mp.dps = 60
+PIO4_2 = (mp.pi / 4) ** 2 * (1 + mp.mpf("1e-12"))
+LN2_2 = mp.log(2) / 2 + mp.mpf("1e-9")
+T_MAX = (mp.sqrt(2) - 1) / (mp.sqrt(2) + 1)
+Z_LOG = T_MAX ** 2 * (1 + mp.mpf("1e-12"))
+
+
+def _S(z):
+    r = mp.sqrt(z)
+    return (mp.sin(r) - r) / (r * z)
+
+
+def _C(z):
+    return (mp.cos(mp.sqrt(z)) - 1) / z
+
+
+def _E(r):
+    return mp.mpf(0.5) if r == 0 else (mp.expm1(r) - r) / (r * r)
+
+
+def _L(z):
+    t = mp.sqrt(z)
+    return (mp.atanh(t) / t - 1) / z
+
+
+KERNELS = {   # name: (auxiliary function, interval, degree, value of the kernel's function)
+    "S": (_S, (0, PIO4_2), 6, lambda x, p: (mp.sqrt(x) * (1 + x * p), mp.sin(mp.sqrt(x)))),
+    "C": (_C, (0, PIO4_2), 6, lambda x, p: (1 + x * p, mp.cos(mp.sqrt(x)))),
+    "E": (_E, (-LN2_2, LN2_2), 10, lambda x, p: (x + x * x * p, mp.expm1(x))),
+    "L": (_L, (0, Z_LOG), 6, lambda x, p: (2 * mp.sqrt(x) * (1 + x * p), 2 * mp.atanh(mp.sqrt(x)))),
+}
+
+
+def coefficients(name):
+    f, (a, b), deg, _ = KERNELS[name]
+    return [float(c) for c in mp.chebyfit(f, [a, b], deg + 1)]
+
+
+def max_rel_error(name, cs, n=4000):
+    f, (a, b), _, value = KERNELS[name]
+    worst = mp.mpf(0)
+    for i in range(1, n):
+        x = a + (b - a) * mp.mpf(i) / n
+        if x == 0:
+            continue
+        p = mp.mpf(cs[0])
+        for c in cs[1:]:
+            p = p * x + mp.mpf(c)
+        got, exact = value(x, p)
+        worst = max(worst, abs((got - exact) / exact))
+    return float(worst)
+
+
+if __name__ == "__main__":
+    for name in KERNELS:
+        cs = coefficients(name)
+        print(f"// {name}: degree {len(cs) - 1}, max rel err {max_rel_error(name, cs):.2e}")
+        print("    " + ",\n    ".join(repr(c) for c in cs))

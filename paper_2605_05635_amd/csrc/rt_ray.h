@@ -75,9 +75,12 @@ __host__ __device__ __forceinline__ void rhs(const K& k, const S& E, const S& L,
     const S Sig = R2 + k.chi2 * co * co;
     const S Del = R2c - F;
     const S dDel = two * R - dF;
-    const S iS = rcp(Sig);
-    const S iD = rcp(Del);
-    const S is = rcp(s);
+    // 1/Sigma, 1/Delta and 1/sin(theta) from one reciprocal of their product
+    const S SD = Sig * Del;
+    const S inv = rcp(SD * s);
+    const S iS = Del * s * inv;
+    const S iD = Sig * s * inv;
+    const S is = SD * inv;
     const S P = R2c * E - k.chi * L;
     const S PiD = P * iD;
     const S Lis2 = L * is * is;
