@@ -350,6 +350,9 @@ hipError_t launch_vjp_count(const ImageConst& c, const double* dl_dI, int32_t* c
     else if (c.metric == EINASTO)
         hipLaunchKernelGGL(vjp_count_kernel<EINASTO>, dim3(grid), dim3(kBlock), 0, stream, c,
                            dl_dI, count, queue, shape);
+    else if (c.ex_near)
+        hipLaunchKernelGGL(vjp_count_kernel<CNFW_NEAR>, dim3(grid), dim3(kBlock), 0, stream, c, dl_dI,
+                           count, queue, shape);
     else
         hipLaunchKernelGGL(vjp_count_kernel<CNFW>, dim3(grid), dim3(kBlock), 0, stream, c, dl_dI,
                            count, queue, shape);
@@ -367,6 +370,9 @@ hipError_t launch_vjp_tape(const ImageConst& c, const int32_t* list_pix, const i
     else if (c.metric == EINASTO)
         hipLaunchKernelGGL(vjp_tape_kernel<EINASTO>, dim3(grid), dim3(kBlock), 0, stream, c,
                            list_pix, list_off, count, n_list, rec_base, tape, taped, queue, sh);
+    else if (c.ex_near)
+        hipLaunchKernelGGL(vjp_tape_kernel<CNFW_NEAR>, dim3(grid), dim3(kBlock), 0, stream, c,
+                           list_pix, list_off, count, n_list, rec_base, tape, taped, queue, sh);
     else
         hipLaunchKernelGGL(vjp_tape_kernel<CNFW>, dim3(grid), dim3(kBlock), 0, stream, c,
                            list_pix, list_off, count, n_list, rec_base, tape, taped, queue, sh);
@@ -382,6 +388,9 @@ hipError_t launch_vjp_tape_dense(const ImageConst& c, const double* dl_dI, int32
                            dl_dI, cap, tape, count, counters, queue, shape);
     else if (c.metric == EINASTO)
         hipLaunchKernelGGL(vjp_tape_dense_kernel<EINASTO>, dim3(grid), dim3(kBlock), 0, stream, c,
+                           dl_dI, cap, tape, count, counters, queue, shape);
+    else if (c.ex_near)
+        hipLaunchKernelGGL(vjp_tape_dense_kernel<CNFW_NEAR>, dim3(grid), dim3(kBlock), 0, stream, c,
                            dl_dI, cap, tape, count, counters, queue, shape);
     else
         hipLaunchKernelGGL(vjp_tape_dense_kernel<CNFW>, dim3(grid), dim3(kBlock), 0, stream, c,
@@ -406,6 +415,10 @@ hipError_t reverse_launch(const ImageConst& c, const double* dl_dI, const int32_
                            rec_base, cap, tape, J, grad_pix, queue, shape);
     else if (c.metric == EINASTO)
         hipLaunchKernelGGL((vjp_reverse_kernel<EINASTO, DENSE>), dim3(grid), dim3(kBlock),
+                           0, stream, c, dl_dI, list_pix, list_off, steps, n_items,
+                           rec_base, cap, tape, J, grad_pix, queue, shape);
+    else if (c.ex_near)
+        hipLaunchKernelGGL((vjp_reverse_kernel<CNFW_NEAR, DENSE>), dim3(grid), dim3(kBlock),
                            0, stream, c, dl_dI, list_pix, list_off, steps, n_items,
                            rec_base, cap, tape, J, grad_pix, queue, shape);
     else

@@ -16,6 +16,10 @@
 namespace rt {
 
 enum : int32_t { KERR = 0, EINASTO = 1, CNFW = 2 };
+// Kernel variant of CNFW (a template argument only, never an image's metric)
+// for images whose halo has |eta| <= dm::kExpm1Near (ImageConst::ex_near).
+constexpr int32_t CNFW_NEAR = 3;
+__host__ __device__ constexpr bool is_cnfw(int32_t m) { return m == CNFW || m == CNFW_NEAR; }
 enum : int32_t { RAY_CAPTURED = 1, RAY_ESCAPED = 2, RAY_STEP_LIMIT = 3 };
 
 // Everything a kernel needs to know about one image.  Passed by value as a
@@ -49,7 +53,20 @@ struct ImageConst {
     double r_in, r_out, emis_pow, sigma_in, sigma_out;
     int32_t taper;       // 1: tanh tapers of eqs. (85)-(86); 0: hard window, eq. (77)
     int32_t emission;    // 0: transfer maps only
+    // cored NFW with 0 <= eta <= kExpm1Near: the exponent of eq. (13), which
+    // lies in [-eta, 0), never needs expm1's argument reduction, and the
+    // kernels run their CNFW_NEAR variant
+    int32_t ex_near;
 };
+
+// e^x - 1 of the cored-NFW exponent: in binary64 without the argument
+// reduction when `near` (the same result for |x| <= kExpm1Near); other scalar
+// types (binary32, dual numbers) use the general function.
+__host__ __device__ inline double expm1_ex(double x, bool near) { return dm::expm1(x, near); }
+template <class S>
+__host__ __device__ inline S expm1_ex(const S& x, bool) {
+    return dm::expm1(x);
+}
 
 // F(R) = 2 R mu(R) (eq. (24)) and dF/dR for the chosen seed.  The mass
 // functions mu_E (from eq. (9)) and mu_cNFW (from eq. (13)) are written in
@@ -79,7 +96,7 @@ __host__ __device__ inline void mass_function(const K& c, const S& R, S& F, S& d
         const S lg = dm::log1p(R * c.inv_lam_c);
         const S ex = c.eta_lc * (iRl - two * iR * lg);
         const S dex = c.eta_lc * (two * iR * (iR * lg - iRl) - iRl * iRl);
-        const S em1 = dm::expm1(ex);
+        const S em1 = expm1_ex(ex, METRIC == CNFW_NEAR);
         F = R * (two - R * em1);
         dF = two - R * (two * em1 + R * (em1 + one) * dex);
     }

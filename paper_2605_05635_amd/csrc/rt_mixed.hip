@@ -145,6 +145,9 @@ hipError_t launch_resume(const ImageConst& c, const OutPtrs& o, const double* re
     else if (c.metric == EINASTO)
         hipLaunchKernelGGL(resume_kernel<EINASTO>, dim3(grid), dim3(kBlock), 0, stream, c, o,
                            records, counters, queue, chunk);
+    else if (c.ex_near)
+        hipLaunchKernelGGL(resume_kernel<CNFW_NEAR>, dim3(grid), dim3(kBlock), 0, stream, c, o,
+                           records, counters, queue, chunk);
     else
         hipLaunchKernelGGL(resume_kernel<CNFW>, dim3(grid), dim3(kBlock), 0, stream, c, o, records,
                            counters, queue, chunk);

@@ -106,10 +106,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
     auto take = [&](int64_t ordinal) {
         img = cur;
         const ImageConst& c = lt[img];
-        metric = c.metric;
+        metric = (c.metric == CNFW && c.ex_near) ? CNFW_NEAR : c.metric;
         k = hot_of(c);
         const int64_t pix = tile_pixel(ordinal, c.nx, c.ny, shape.tile_w, shape.tile_h);
-        if (metric == CNFW) start_ray<CNFW>(c, k, pix, r);
+        if (metric == CNFW_NEAR) start_ray<CNFW_NEAR>(c, k, pix, r);
+        else if (metric == CNFW) start_ray<CNFW>(c, k, pix, r);
         else if (metric == EINASTO) start_ray<EINASTO>(c, k, pix, r);
         else start_ray<KERR>(c, k, pix, r);
     };
@@ -120,12 +121,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
             const OutPtrs& o = outs[img];
             const int64_t n_pix = lt[img].n_pix;
             int32_t st;
-            if (metric == CNFW) st = attempt<CNFW>(k, o, n_pix, r);
+            if (metric == CNFW_NEAR) st = attempt<CNFW_NEAR>(k, o, n_pix, r);
+            else if (metric == CNFW) st = attempt<CNFW>(k, o, n_pix, r);
             else if (metric == EINASTO) st = attempt<EINASTO>(k, o, n_pix, r);
             else st = attempt<KERR>(k, o, n_pix, r);
             if (st != 0) {
                 const ImageConst& c = lt[img];
-                if (metric == CNFW) finish_ray<CNFW>(c, k, o, r, st);
+                if (is_cnfw(metric)) finish_ray<CNFW>(c, k, o, r, st);
                 else if (metric == EINASTO) finish_ray<EINASTO>(c, k, o, r, st);
                 else finish_ray<KERR>(c, k, o, r, st);
                 active = false;
@@ -181,8 +183,12 @@ hipError_t launch_trace(const ImageConst& c, const OutPtrs& o, unsigned long lon
                                queue, shape);
             break;
         default:
-            hipLaunchKernelGGL(trace_kernel<CNFW>, dim3(grid), dim3(kBlock), 0, stream, c, o,
-                               queue, shape);
+            if (c.ex_near)
+                hipLaunchKernelGGL(trace_kernel<CNFW_NEAR>, dim3(grid), dim3(kBlock), 0, stream, c,
+                                   o, queue, shape);
+            else
+                hipLaunchKernelGGL(trace_kernel<CNFW>, dim3(grid), dim3(kBlock), 0, stream, c, o,
+                                   queue, shape);
             break;
     }
     return hipGetLastError();

@@ -82,7 +82,7 @@ __host__ __device__ __forceinline__ void mass_eval(const Hot& k, double R, MassT
         const double Q = 2.0 * iR * (iR * lg - iRl) - iRl * iRl;
         const double ex = k.eta_lc * P;
         const double dex = k.eta_lc * Q;
-        const double em1 = dm::expm1(ex);
+        const double em1 = dm::expm1(ex, METRIC == CNFW_NEAR);
         t.F = R * (2.0 - R * em1);
         t.dF = 2.0 - R * (2.0 * em1 + R * (em1 + 1.0) * dex);
         t.a[0] = iR;
@@ -294,7 +294,7 @@ __host__ __device__ __forceinline__ double emission_vjp(const ImageConst& c, dou
     kd.chi2 = kd.chi * kd.chi;
     if constexpr (METRIC == EINASTO) {
         kd.inv_lam = D::var(c.inv_lam, 4);
-    } else if constexpr (METRIC == CNFW) {
+    } else if constexpr (is_cnfw(METRIC)) {
         kd.lam_c = D::var(c.lam_c, 4);
         kd.inv_lam_c = D::var(c.inv_lam_c, 5);
         kd.eta_lc = D::var(c.eta_lc, 6);

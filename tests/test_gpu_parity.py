@@ -63,8 +63,10 @@ def test_kerr_small_full_screen(rt, orc):
     W.image(metric="einasto", spin=0.3, halo=(0.3, 0.0), incl=math.radians(30), nx=1, ny=1),
     W.image(metric="kerr", spin=0.0, incl=math.radians(45), nx=129, ny=1, y_min=-0.1, y_max=0.1),
     W.image(metric="cnfw", spin=-0.6, halo=(0.05, 5.0), incl=math.radians(120), nx=1, ny=77),
+    W.image(metric="cnfw", spin=0.5, halo=(0.6, 4.0), incl=math.radians(70), nx=41, ny=37,
+            x_min=-14, x_max=14, y_min=-14, y_max=14),
 ], ids=["einasto-ragged", "cnfw-163-ragged", "cnfw-taper", "kerr-0.99-edge-on", "one-pixel",
-        "one-row", "one-column-retrograde"])
+        "one-row", "one-column-retrograde", "cnfw-dense-halo"])
 def test_ragged_screens(rt, orc, img):
     g, o = run_full(rt, orc, img)
     assert_parity(g, o)
@@ -146,7 +148,8 @@ def test_deterministic_and_batched_equals_single(rt):
     import torch
     imgs = [W.image(metric="kerr", spin=0.3, nx=48, ny=40),
             W.image(metric="cnfw", spin=0.8, halo=(0.02, 8.0), incl=1.0, nx=31, ny=50),
-            W.image(metric="einasto", spin=0.5, halo=(0.2, 0.0), incl=2.0, nx=64, ny=64)]
+            W.image(metric="einasto", spin=0.5, halo=(0.2, 0.0), incl=2.0, nx=64, ny=64),
+            W.image(metric="cnfw", spin=0.5, halo=(0.6, 4.0), incl=1.2, nx=29, ny=33)]
     singles = [rt.trace(i) for i in imgs]
     again = [rt.trace(i) for i in imgs]
     many = rt.trace_many(imgs)
