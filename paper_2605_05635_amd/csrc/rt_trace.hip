@@ -28,12 +28,11 @@ using namespace ray;
 
 // The register allocation aims at three waves per SIMD (168 VGPRs; the cored
 // NFW spills two): measured 5-10 % faster than two.
-template <int METRIC>
 constexpr int kTraceWaves = 3;
 
 // Persistent trace kernel for one image (pixels handed out as shape says).
 template <int METRIC>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kTraceWaves<METRIC>, 8))) void trace_kernel(
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kTraceWaves, 8))) void trace_kernel(
     ImageConst c, OutPtrs o, unsigned long long* queue, LaunchShape shape) {
     const Hot k = hot_of(c);
     Ray r;
