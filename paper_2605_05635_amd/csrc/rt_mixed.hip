@@ -36,7 +36,7 @@ __global__ __launch_bounds__(kBlock) void trace32_kernel(ImageConst c, OutPtrs o
             if (st > 0) {
                 Ray w;
                 widen(c, r, w);
-                finish_ray<METRIC>(c, hot_of(c), o, w, st);
+                finish_ray(c, o, w, st);
                 active = false;
             } else if (st < 0) {
                 leave = st;
@@ -98,7 +98,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 8))) 
                 fresh = true;
                 atomicAdd(&counters[1], 1u);
             } else if (st != 0) {
-                finish_ray<METRIC>(c, k, o, r, st);
+                finish_ray(c, o, r, st);
                 active = false;
             }
         }

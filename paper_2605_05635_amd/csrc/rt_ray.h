@@ -390,9 +390,8 @@ __host__ __device__ __forceinline__ int32_t attempt(const Hot& k, const OutPtrs&
 
 // Ray epilogue: the per-pixel transfer-map outputs.  Records n >=
 // min(N_cross, 3) are NaN.  The emission is a separate pass (emit_pixel).
-template <int METRIC>
-__device__ __forceinline__ void finish_ray(const ImageConst& c, const Hot& k, const OutPtrs& o,
-                                           const Ray& r, int32_t status) {
+__device__ __forceinline__ void finish_ray(const ImageConst& c, const OutPtrs& o, const Ray& r,
+                                           int32_t status) {
     const int64_t p = r.pix;
     const int64_t n_pix = c.n_pix;
     const int nrec = r.ncross < 3 ? r.ncross : 3;

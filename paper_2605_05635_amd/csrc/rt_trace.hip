@@ -49,7 +49,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kTraceWa
         if (active) {
             const int32_t st = attempt<METRIC>(k, o, c.n_pix, r);
             if (st != 0) {
-                finish_ray<METRIC>(c, k, o, r, st);
+                finish_ray(c, o, r, st);
                 active = false;
             }
         }
@@ -125,10 +125,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
             else if (metric == EINASTO) st = attempt<EINASTO>(k, o, n_pix, r);
             else st = attempt<KERR>(k, o, n_pix, r);
             if (st != 0) {
-                const ImageConst& c = lt[img];
-                if (is_cnfw(metric)) finish_ray<CNFW>(c, k, o, r, st);
-                else if (metric == EINASTO) finish_ray<EINASTO>(c, k, o, r, st);
-                else finish_ray<KERR>(c, k, o, r, st);
+                finish_ray(lt[img], o, r, st);
                 active = false;
             }
         }
