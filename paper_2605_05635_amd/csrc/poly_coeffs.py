@@ -13,7 +13,9 @@ rounding of its binary64 evaluation), measured on a 4000-point grid:
     log m = 2 (t + t z L(z)),        t = (m-1)/(m+1), m in [sqrt(1/2), sqrt(2)), z = t^2
 
 Run `python poly_coeffs.py` to print the tables in the order rt_math.h
-evaluates them (highest degree first).
+evaluates them (highest degree first): the binary64 kernels, then the
+lower-degree binary32 kernels of the single-precision bulk trace (coefficients
+rounded to binary32).
 """
 import mpmath as mp
 
@@ -50,9 +52,20 @@ KERNELS = {   # name: (auxiliary function, interval, degree, value of the kernel
 }
 
 
-def coefficients(name):
+# Degrees of the binary32 kernels (the single-precision bulk trace); their
+# coefficients are rounded to binary32.
+DEGREES32 = {"S": 3, "C": 3, "E": 5, "L": 2}
+
+
+def coefficients(name, binary32=False):
     f, (a, b), deg, _ = KERNELS[name]
-    return [float(c) for c in mp.chebyfit(f, [a, b], deg + 1)]
+    if binary32:
+        deg = DEGREES32[name]
+    cs = mp.chebyfit(f, [a, b], deg + 1)
+    if binary32:
+        import numpy as np
+        return [float(np.float32(c)) for c in cs]
+    return [float(c) for c in cs]
 
 
 def max_rel_error(name, cs, n=4000):
@@ -71,7 +84,10 @@ def max_rel_error(name, cs, n=4000):
 
 
 if __name__ == "__main__":
-    for name in KERNELS:
-        cs = coefficients(name)
-        print(f"// {name}: degree {len(cs) - 1}, max rel err {max_rel_error(name, cs):.2e}")
-        print("    " + ",\n    ".join(repr(c) for c in cs))
+    for binary32 in (False, True):
+        for name in KERNELS:
+            cs = coefficients(name, binary32)
+            kind = "binary32" if binary32 else "binary64"
+            print(f"// {name} ({kind}): degree {len(cs) - 1}, "
+                  f"max rel err {max_rel_error(name, cs):.2e}")
+            print("    " + ",\n    ".join(repr(c) + ("f" if binary32 else "") for c in cs))

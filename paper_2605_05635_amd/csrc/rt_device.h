@@ -59,10 +59,11 @@ struct ImageConst {
     int32_t ex_near;
 };
 
-// e^x - 1 of the cored-NFW exponent: in binary64 without the argument
-// reduction when `near` (the same result for |x| <= kExpm1Near); other scalar
-// types (binary32, dual numbers) use the general function.
+// e^x - 1 of the cored-NFW exponent: in binary64 and binary32 without the
+// argument reduction when `near` (the same result for |x| <= kExpm1Near);
+// dual numbers use the general function.
 __host__ __device__ inline double expm1_ex(double x, bool near) { return dm::expm1(x, near); }
+__host__ __device__ inline float expm1_ex(float x, bool near) { return dm::expm1(x, near); }
 template <class S>
 __host__ __device__ inline S expm1_ex(const S& x, bool) {
     return dm::expm1(x);

@@ -130,6 +130,9 @@ hipError_t launch_trace32(const ImageConst& c, const OutPtrs& o, unsigned long l
     else if (c.metric == EINASTO)
         hipLaunchKernelGGL(trace32_kernel<EINASTO>, dim3(grid), dim3(kBlock), 0, stream, c, o,
                            queue, shape, records, counters);
+    else if (c.ex_near)
+        hipLaunchKernelGGL(trace32_kernel<CNFW_NEAR>, dim3(grid), dim3(kBlock), 0, stream, c, o,
+                           queue, shape, records, counters);
     else
         hipLaunchKernelGGL(trace32_kernel<CNFW>, dim3(grid), dim3(kBlock), 0, stream, c, o, queue,
                            shape, records, counters);

@@ -1,7 +1,9 @@
 // Host driver for tests/test_devmath.py: evaluates the trace kernels' compact
 // elementary functions (paper_2605_05635_amd/csrc/rt_math.h, compiled for the
 // host) on the doubles read from stdin and writes the results to stdout.
-//   usage: devmath_driver <function>   (sincos | exp | expm1 | log1p | rpow_tenth)
+//   usage: devmath_driver <function>   (sincos | exp | expm1 | log1p | rpow_tenth, and the
+//          binary32 versions sincosf | expf | expm1f | log1pf of the arguments rounded
+//          to binary32)
 #include <cstdio>
 #include <cstring>
 #include <vector>
@@ -28,6 +30,17 @@ int main(int argc, char** argv) {
             out.push_back(rt::dm::log1p(a));
         } else if (!std::strcmp(argv[1], "rpow_tenth")) {
             out.push_back(rt::dm::rpow_tenth(a));
+        } else if (!std::strcmp(argv[1], "sincosf")) {
+            float s, c;
+            rt::dm::sincos(static_cast<float>(a), &s, &c);
+            out.push_back(s);
+            out.push_back(c);
+        } else if (!std::strcmp(argv[1], "expf")) {
+            out.push_back(rt::dm::exp(static_cast<float>(a)));
+        } else if (!std::strcmp(argv[1], "expm1f")) {
+            out.push_back(rt::dm::expm1(static_cast<float>(a)));
+        } else if (!std::strcmp(argv[1], "log1pf")) {
+            out.push_back(rt::dm::log1p(static_cast<float>(a)));
         } else {
             return 3;
         }

@@ -100,3 +100,37 @@ def test_rpow_tenth(driver):
     # one Newton step from the binary32 estimate: relative error ~ (2e-7)^2
     rel = np.array([float(abs(mp.mpf(g) - e) / e) for g, e in zip(out, ex)])
     assert rel.max() < 1e-12
+
+
+# ---------------------------------------------------------------- binary32
+def ulp32_err(got, x32, fn):
+    """Error in binary32 ulps of the exact value at the binary32 argument."""
+    ex = np.array([float(fn(mp.mpf(float(v)))) for v in x32])
+    ulp = np.spacing(np.abs(ex).astype(np.float32)).astype(np.float64)
+    return np.abs(got - ex) / ulp
+
+
+def test_binary32_sincos(driver):
+    rng = np.random.default_rng(10)
+    x = np.concatenate([rng.uniform(-2 * np.pi, 3 * np.pi, 3000), [0.0, 1e-30, 1.0, 100.0]])
+    x32 = x.astype(np.float32)
+    out = run(driver, "sincosf", x32.astype(np.float64)).reshape(-1, 2)
+    es = np.array([float(mp.sin(mp.mpf(float(v)))) for v in x32])
+    ec = np.array([float(mp.cos(mp.mpf(float(v)))) for v in x32])
+    # absolute error against the magnitude 1 of sin and cos: below two binary32 ulps of 1
+    assert np.abs(out[:, 0] - es).max() < 2.4e-7 and np.abs(out[:, 1] - ec).max() < 2.4e-7
+    big = np.abs(es) > 1e-2
+    assert ulp32_err(out[big, 0], x32[big], mp.sin).max() < 4
+
+
+def test_binary32_exp_expm1_log1p(driver):
+    rng = np.random.default_rng(11)
+    xe = np.concatenate([rng.uniform(-80, 80, 2000), rng.uniform(-1, 1, 500), [0.0]]).astype(np.float32)
+    assert ulp32_err(run(driver, "expf", xe.astype(np.float64)), xe, mp.exp).max() < 3
+    xm = np.concatenate([rng.uniform(-0.6, 0.2, 2000), -(10.0 ** rng.uniform(-20, 1.5, 500)),
+                         10.0 ** rng.uniform(-20, 1.5, 500)]).astype(np.float32)
+    xm = xm[xm != 0]
+    assert ulp32_err(run(driver, "expm1f", xm.astype(np.float64)), xm, mp.expm1).max() < 4
+    xl = np.concatenate([10.0 ** rng.uniform(-3, 3.5, 2000), rng.uniform(-0.5, 0.5, 500)]).astype(np.float32)
+    xl = xl[xl != 0]
+    assert ulp32_err(run(driver, "log1pf", xl.astype(np.float64)), xl, mp.log1p).max() < 4
