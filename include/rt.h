@@ -24,8 +24,10 @@
  *     memory, read before the call returns.
  *   - Every call is asynchronous on `hip_stream` (a hipStream_t; NULL means the
  *     null stream).  Outputs are valid once that stream has reached the point
- *     of the call.  Scratch memory (a work-queue counter per image) is
- *     allocated stream-ordered and released before the work completes.
+ *     of the call.  Scratch memory (work-queue counters and intermediate
+ *     buffers) is allocated stream-ordered and released before the work
+ *     completes; the image gradient keeps its tape workspace between calls
+ *     (see rt_image_vjp).
  *   - Return value: RT_OK (0) on success, a negative RT_ERR_* code otherwise;
  *     rt_last_error() then describes the failure (thread-local string).  On an
  *     error nothing has been launched.  The library never aborts or prints.
