@@ -65,8 +65,10 @@ def test_kerr_small_full_screen(rt, orc):
     W.image(metric="cnfw", spin=-0.6, halo=(0.05, 5.0), incl=math.radians(120), nx=1, ny=77),
     W.image(metric="cnfw", spin=0.5, halo=(0.6, 4.0), incl=math.radians(70), nx=41, ny=37,
             x_min=-14, x_max=14, y_min=-14, y_max=14),
+    W.image(metric="cnfw", spin=0.7, halo=(0.33, 3.0), incl=math.radians(110), nx=39, ny=35,
+            x_min=-12, x_max=12, y_min=-12, y_max=12),
 ], ids=["einasto-ragged", "cnfw-163-ragged", "cnfw-taper", "kerr-0.99-edge-on", "one-pixel",
-        "one-row", "one-column-retrograde", "cnfw-dense-halo"])
+        "one-row", "one-column-retrograde", "cnfw-dense-halo", "cnfw-eta-0.33"])
 def test_ragged_screens(rt, orc, img):
     g, o = run_full(rt, orc, img)
     assert_parity(g, o)
