@@ -231,9 +231,11 @@ int rt_vjp_stats(int64_t *out);
  * applies to later calls on this thread).
  *   order = RT_ORDER_CENTRE (default): a single image's pixels go to
  *     wavefronts in tiles of tile_w x tile_h pixels (0 x 0: 8 x 8), one tile
- *     per claim, tiles ordered by the distance of their centre from the screen
- *     origin (the direction of the hole), so that the long rays near the
- *     photon ring are traced early and the short distant ones fill the end.
+ *     per claim, tiles ordered by the distance of their centre from the photon
+ *     ring's radius around the screen origin (the direction of the hole; the
+ *     radius is the critical impact parameter of the metric without spin), so
+ *     that the long rays near the ring are traced first and the short ones,
+ *     deep in the shadow and far out, fill the end.
  *   order = RT_ORDER_SCREEN: pixels go out in chunks of `chunk` consecutive
  *     ordinals (0: 64) of the screen enumerated in tiles of tile_w x tile_h
  *     pixels (row by row, clipped at the screen edges; 0 x 0: row-major).
@@ -241,8 +243,9 @@ int rt_vjp_stats(int64_t *out);
  * image, with chunk and tile sizes as set.  `blocks_per_cu` caps the resident
  * workgroups launched per compute unit (0 = as many as fit).  The results of a
  * trace do not depend on these settings (every ray is traced the same way);
- * only its speed does.  The centre-out tables (4 bytes per tile) are built on
- * the host the first time a screen shape is traced and kept per thread. */
+ * only its speed does.  The order tables (4 bytes per tile) are built on the
+ * host the first time a screen shape and halo are traced and kept per
+ * thread. */
 enum { RT_ORDER_CENTRE = 0, RT_ORDER_SCREEN = 1 };
 typedef struct rt_launch_config {
   int32_t chunk;          /* 0..65536                                            */

@@ -40,7 +40,7 @@ int hip_fail(hipError_t e, const char* what) {
 // table (~270 bytes each); larger batches run as consecutive launches.
 constexpr int kMaxBatch = 128;
 constexpr int kDefaultChunk = 64;
-constexpr int32_t kDefaultTile = 8;   // centre-out hand-out: 8 x 8 pixel tiles
+constexpr int32_t kDefaultTile = 8;   // ring-out hand-out: 8 x 8 pixel tiles
 // Mixed precision: the binary32 bulk integrates at tolerances no tighter than
 // kTol32Floor (binary32 stage values carry ~6e-8 relative rounding), and a ray
 // continues in binary64 below kZoneFactor R_+.
@@ -93,15 +93,33 @@ rt::LaunchShape shape_for(int32_t nx, int32_t ny) {
     return sh;
 }
 
-// Tiles of a screen in centre-out order: by the distance of the tile's centre
-// from the screen origin (the direction of the hole), ties by tile index.
-// Rays near the photon ring, the longest, are then handed out early and the
-// short rays far from the hole fill the end of the launch.  One device table
-// per screen and tile shape, built on first use and kept (per thread).
+// Screen radius of the photon ring, for the hand-out order: the critical
+// impact parameter min_r r / sqrt(1 - F(r)/r^2) of the non-rotating metric
+// with the image's halo (sqrt(27) for Kerr), by a coarse scan (the order needs
+// no precision).
+double ring_radius(const rt::ImageConst& c) {
+    double best = 1e300;
+    for (int i = 0; i <= 2900; ++i) {
+        const double r = 1.0 + 0.01 * i;
+        double F, dF;
+        rt::mass_function_any(c, r, F, dF);
+        const double f = 1.0 - F / (r * r);
+        if (f > 0.0) best = std::min(best, r / std::sqrt(f));
+    }
+    return best < 1e300 ? best : 0.0;
+}
+
+// Tiles of a screen in ring-out order: by the distance of the tile's centre
+// from the photon ring's screen radius (ring_radius, centred on the screen
+// origin, the direction of the hole), ties by tile index.  The rays near the
+// ring, the longest, are handed out first; the shortest -- deep inside the
+// shadow and far out -- fill the end of the launch, where the persistent
+// grid drains.  One device table per screen, tile shape and halo, built on
+// first use and kept (per thread).
 struct TileOrder {
     int dev;
-    int32_t nx, ny, tw, th;
-    double x0, dx, y0, dy;
+    int32_t nx, ny, tw, th, metric;
+    double x0, dx, y0, dy, inv_lam, lam_c, eta_lc;
     int32_t* table;
 };
 thread_local std::vector<TileOrder> g_tile_orders;
@@ -113,7 +131,9 @@ int tile_order(const rt::ImageConst& c, int32_t tw, int32_t th, const int32_t** 
     if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
     for (const TileOrder& t : g_tile_orders)
         if (t.dev == dev && t.nx == c.nx && t.ny == c.ny && t.tw == tw && t.th == th &&
-            t.x0 == c.x0 && t.dx == c.dx && t.y0 == c.y0 && t.dy == c.dy) {
+            t.x0 == c.x0 && t.dx == c.dx && t.y0 == c.y0 && t.dy == c.dy &&
+            t.metric == c.metric && t.inv_lam == c.inv_lam && t.lam_c == c.lam_c &&
+            t.eta_lc == c.eta_lc) {
             *out = t.table;
             return RT_OK;
         }
@@ -125,17 +145,19 @@ int tile_order(const rt::ImageConst& c, int32_t tw, int32_t th, const int32_t** 
     }
     const int32_t tiles_x = (c.nx + tw - 1) / tw, tiles_y = (c.ny + th - 1) / th;
     const int32_t n = tiles_x * tiles_y;
+    const double ring = ring_radius(c);
     std::vector<int32_t> idx(n);
-    std::vector<double> d2(n);
+    std::vector<double> dist(n);
     for (int32_t i = 0; i < n; ++i) {
         idx[i] = i;
         const int32_t ty = i / tiles_x, tx = i - ty * tiles_x;
         const double w = std::min(tw, c.nx - tx * tw), h = std::min(th, c.ny - ty * th);
         const double X = c.x0 + (tx * tw + 0.5 * w) * c.dx;
         const double Y = c.y0 + (ty * th + 0.5 * h) * c.dy;
-        d2[i] = X * X + Y * Y;
+        dist[i] = std::fabs(std::sqrt(X * X + Y * Y) - ring);
     }
-    std::stable_sort(idx.begin(), idx.end(), [&](int32_t a, int32_t b) { return d2[a] < d2[b]; });
+    std::stable_sort(idx.begin(), idx.end(),
+                     [&](int32_t a, int32_t b) { return dist[a] < dist[b]; });
     void* d = nullptr;
     if ((e = hipMalloc(&d, sizeof(int32_t) * n)) != hipSuccess || !d) {
         (void)hipGetLastError();
@@ -145,8 +167,8 @@ int tile_order(const rt::ImageConst& c, int32_t tw, int32_t th, const int32_t** 
         (void)hipFree(d);
         return hip_fail(e, "tile order upload");
     }
-    g_tile_orders.push_back(TileOrder{dev, c.nx, c.ny, tw, th, c.x0, c.dx, c.y0, c.dy,
-                                      static_cast<int32_t*>(d)});
+    g_tile_orders.push_back(TileOrder{dev, c.nx, c.ny, tw, th, c.metric, c.x0, c.dx, c.y0, c.dy,
+                                      c.inv_lam, c.lam_c, c.eta_lc, static_cast<int32_t*>(d)});
     *out = static_cast<int32_t*>(d);
     return RT_OK;
 }

@@ -193,7 +193,7 @@ def test_intensity_without_crossing_outputs(rt):
 
 
 def test_launch_config_does_not_change_results(rt):
-    """Chunk size, tile shape and order (screen or centre-out) and occupancy cap
+    """Chunk size, tile shape and order (screen or ring-out) and occupancy cap
     only move rays between lanes."""
     import torch
     img = W.image(metric="cnfw", spin=0.9, halo=(0.03, 7.0), incl=1.2, nx=45, ny=38)
