@@ -196,12 +196,13 @@ enum { RT_GRAD_NATIVE = 0, RT_GRAD_DENSITY = 1 };
  *             deterministic)
  *   grad_pix  device [ny][nx][4] per-pixel dl_dI dI/dq, or NULL
  * Pixels with dl_dI = 0 are not traced.  Internally a trace that tapes every
- * accepted step (48 bytes) of each contributing ray into a tape region of its
- * own pixel (up to 1024 steps, fewer if the tape budget requires), then a
- * reverse sweep over the tapes; the rare rays needing longer tapes are counted
- * exactly and taped packed, longest first, in slices within the budget.  The
- * dense tape memory is kept by the library per thread and device between
- * calls (grown on demand; n_pix x steps x 48 bytes, at most the tape budget).
+ * accepted step (240 bytes: its start state, size, crossing and six stage
+ * derivatives) of each contributing ray into a tape region of its own pixel
+ * (up to 1024 steps, fewer if the tape budget requires), then a reverse sweep
+ * over the tapes; the rare rays needing longer tapes are counted exactly and
+ * taped packed, longest first, in slices within the budget.  The dense tape
+ * memory is kept by the library per thread and device between calls (grown
+ * on demand; n_pix x steps x 240 bytes, at most the tape budget).
  * Unlike the trace calls this one synchronises `hip_stream` once (twice when
  * long rays occur) to read pass counters, and allocates stream-ordered device
  * memory of about 4 n_pix (2 + 8) bytes.  Errors as for rt_trace_image;

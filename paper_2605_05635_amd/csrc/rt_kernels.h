@@ -132,7 +132,7 @@ int mixed_blocks_per_cu(int metric, int pass);
 // Each persistent pass needs its zeroed queue counter.  `pass` of
 // vjp_blocks_per_cu: 0 count, 1 tape, 2 reverse, 3 tape_dense.
 constexpr int kVjpPrims = 11;
-constexpr int kVjpRecBytes = 48;
+constexpr int kVjpRecBytes = 240;
 constexpr int kGradBlocks = 256;
 hipError_t launch_vjp_tape_dense(const ImageConst& c, const double* dl_dI, int32_t cap,
                                  double* tape, int32_t* count, unsigned int* counters,

@@ -283,13 +283,22 @@ __host__ __device__ __forceinline__ double crossing_root(const DenseComp& d, boo
 // The 5th-order update, the error estimate and the continuous-extension
 // coefficient r5 are accumulated as the stages are produced, so a stage
 // derivative stays live only while later stage inputs still need it.
-template <int METRIC>
-__host__ __device__ __forceinline__ int32_t attempt(const Hot& k, const OutPtrs& o, int64_t n_pix, Ray& r) {
+// `sink(j, k_j)` sees each stage derivative k_{j+1} (j = 0..5, six
+// components) as it is produced; the trace kernels pass StageNone, the
+// gradient's tape kernels record them.
+struct StageNone {
+    __host__ __device__ __forceinline__ void operator()(int, const double*) const {}
+};
+
+template <int METRIC, class Sink = StageNone>
+__host__ __device__ __forceinline__ int32_t attempt(const Hot& k, const OutPtrs& o, int64_t n_pix,
+                                                    Ray& r, Sink sink = Sink{}) {
     if (r.attempts >= k.max_attempts) return RAY_STEP_LIMIT;
     ++r.attempts;
     const double h = r.h;
     double ab[6], ae[6], ad[6];     // sums of b_i k_i, e_i k_i, d_i k_i
     double k2[6], k3[6], k4[6], k5[6], kk[6], t[6];
+    sink(0, r.k1);
     for (int i = 0; i < 6; ++i) {
         ab[i] = b1 * r.k1[i];
         ae[i] = e1 * r.k1[i];
@@ -305,13 +314,18 @@ __host__ __device__ __forceinline__ int32_t attempt(const Hot& k, const OutPtrs&
         ad[i] += dd * kv[i];                                                     \
     }
     RT_STAGE(a21 * r.k1[i], k2)
+    sink(1, k2);
     RT_STAGE(a31 * r.k1[i] + a32 * k2[i], k3)
+    sink(2, k3);
     RT_ACC(b3, e3, d3, k3)
     RT_STAGE(a41 * r.k1[i] + a42 * k2[i] + a43 * k3[i], k4)
+    sink(3, k4);
     RT_ACC(b4, e4, d4, k4)
     RT_STAGE(a51 * r.k1[i] + a52 * k2[i] + a53 * k3[i] + a54 * k4[i], k5)
+    sink(4, k5);
     RT_ACC(b5, e5, d5, k5)
     RT_STAGE(a61 * r.k1[i] + a62 * k2[i] + a63 * k3[i] + a64 * k4[i] + a65 * k5[i], kk)
+    sink(5, kk);
     RT_ACC(b6, e6, d6, kk)
 #undef RT_STAGE
 #undef RT_ACC

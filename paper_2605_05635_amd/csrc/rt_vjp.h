@@ -40,8 +40,23 @@ enum Prim {
 };
 
 // One accepted step on the tape: the state (R, theta, p_R, p_theta) at its
-// start, its size, and the index (0, 1, 2) of the crossing it recorded, or -1.
-constexpr int kRecDoubles = 6;
+// start, its size, the index (0, 1, 2) of the crossing it recorded or -1, and
+// its six stage derivatives' (R, theta, p_R, p_theta) rows (record[6 + 4j + i]
+// for k_{j+1}), so that the reverse pass need not recompute them.
+constexpr int kRecDoubles = 30;
+constexpr int kRecStages = 6;   // offset of the stage derivatives
+
+// Attempt sink that writes the stage derivatives into a tape record (nothing
+// when rec is null).
+struct TapeStages {
+    double* rec;
+    __host__ __device__ __forceinline__ void operator()(int j, const double* kj) const {
+        if (!rec) return;
+        double2* q = reinterpret_cast<double2*>(rec + kRecStages + 4 * j);
+        q[0] = double2{kj[1], kj[2]};
+        q[1] = double2{kj[4], kj[5]};
+    }
+};
 
 // F(R), dF/dR (mass_function) and the reverse mode of both: mass_eval gives
 // the values and keeps what the reverse pass needs; mass_vjp adds the
@@ -327,14 +342,16 @@ __host__ __device__ __forceinline__ bool emits(const ImageConst& c, const Hot& k
 //   beta_j = (3s^2 - 2s^3) b_j + [j=1] s(1-s)^2 - [j=7] s^2(1-s) + s^2(1-s)^2 d_j,
 // R_c = R(s*) moves by dR - (R'(s*)/theta'(s*)) dtheta (implicit function
 // theorem), so the R and theta rows receive the cotangents Rb and
-// -Rb R'/theta'.  The stages are recomputed exactly as the forward step
-// computes them, then reversed from the last to the first.
+// -Rb R'/theta'.  The stage derivatives kin[4j + i] are the forward step's
+// (its tape record); the stage inputs are formed from them exactly as the
+// forward step forms them, then the stages are reversed from the last to the
+// first.
 template <int METRIC>
 __host__ __device__ __forceinline__ void reverse_step(const ImageConst& c, const Hot& k, double E,
                                                       double L, const double x0[4], double h,
-                                                      int cross, double Ib, double xb[4],
-                                                      double& Eb, double& Lb, double pb[4],
-                                                      double& rinb) {
+                                                      int cross, const double* kin, double Ib,
+                                                      double xb[4], double& Eb, double& Lb,
+                                                      double pb[4], double& rinb) {
     constexpr double A[6][5] = {{0.0, 0.0, 0.0, 0.0, 0.0},
                                 {a21, 0.0, 0.0, 0.0, 0.0},
                                 {a31, a32, 0.0, 0.0, 0.0},
@@ -351,23 +368,10 @@ __host__ __device__ __forceinline__ void reverse_step(const ImageConst& c, const
         out[2] = d[4];
         out[3] = d[5];
     };
-    // Forward stages, in the forward step's arithmetic.
-    double kv[6][4], t[4], ab[4];
-    f(x0, kv[0]);
-    for (int i = 0; i < 4; ++i) t[i] = x0[i] + h * (a21 * kv[0][i]);
-    f(t, kv[1]);
-    for (int i = 0; i < 4; ++i) t[i] = x0[i] + h * (a31 * kv[0][i] + a32 * kv[1][i]);
-    f(t, kv[2]);
-    for (int i = 0; i < 4; ++i)
-        t[i] = x0[i] + h * (a41 * kv[0][i] + a42 * kv[1][i] + a43 * kv[2][i]);
-    f(t, kv[3]);
-    for (int i = 0; i < 4; ++i)
-        t[i] = x0[i] + h * (a51 * kv[0][i] + a52 * kv[1][i] + a53 * kv[2][i] + a54 * kv[3][i]);
-    f(t, kv[4]);
-    for (int i = 0; i < 4; ++i)
-        t[i] = x0[i] + h * (a61 * kv[0][i] + a62 * kv[1][i] + a63 * kv[2][i] + a64 * kv[3][i] +
-                            a65 * kv[4][i]);
-    f(t, kv[5]);
+    // The forward step's stage derivatives.
+    double kv[6][4], ab[4];
+    for (int j = 0; j < 6; ++j)
+        for (int i = 0; i < 4; ++i) kv[j][i] = kin[4 * j + i];
     double yn[4];
     for (int i = 0; i < 4; ++i) {
         ab[i] = b1 * kv[0][i];

@@ -106,7 +106,8 @@ void step_case(const double* a, std::vector<double>& out) {
     r.h = h;
     r.last_cross = -1e300;
     const OutPtrs none{};
-    ray::attempt<M>(k, none, 1, r);
+    double rec[vjp::kRecDoubles] = {};
+    ray::attempt<M>(k, none, 1, r, vjp::TapeStages{rec});
     const bool accepted = r.after_reject == 0;
     const bool crossed = r.ncross == 1;
     double phi = w[0] * r.y[1] + w[1] * r.y[2] + w[2] * r.y[4] + w[3] * r.y[5];
@@ -120,7 +121,8 @@ void step_case(const double* a, std::vector<double>& out) {
     out.push_back(crossed ? 1.0 : 0.0);
     double xb[4] = {w[0], w[1], w[2], w[3]};
     double Eb = 0, Lb = 0, pb[4] = {0, 0, 0, 0}, rinb = 0;
-    vjp::reverse_step<M>(c, k, E, L, x, h, crossed ? 0 : -1, Ib, xb, Eb, Lb, pb, rinb);
+    vjp::reverse_step<M>(c, k, E, L, x, h, crossed ? 0 : -1, rec + vjp::kRecStages, Ib, xb, Eb,
+                         Lb, pb, rinb);
     for (double v : xb) out.push_back(v);
     out.push_back(Eb);
     out.push_back(Lb);
