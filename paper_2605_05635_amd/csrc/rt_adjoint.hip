@@ -132,8 +132,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 8))) 
 template <int METRIC>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 8))) void vjp_tape_dense_kernel(
     ImageConst c, const double* __restrict__ dl_dI, int32_t cap, double* __restrict__ tape,
-    int32_t* __restrict__ count, unsigned int* counters, unsigned long long* queue,
-    LaunchShape shape) {
+    double* overflow, int32_t* __restrict__ count, unsigned int* counters,
+    unsigned long long* queue, LaunchShape shape) {
     const Hot k = hot_of(c);
     const OutPtrs none{};
     Ray r;
@@ -161,9 +161,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 8))) 
             if (live) {
                 const double x0 = r.y[1], x1 = r.y[2], x2 = r.y[4], x3 = r.y[5], h = r.h;
                 const int32_t n0 = r.ncross;
+                // steps past the pixel's region write their stages to a scratch
+                // record that nothing reads (a branch-free store target)
                 double* const slot =
                     acc < cap ? tape + (r.pix * static_cast<int64_t>(cap) + acc) * kRecDoubles
-                              : nullptr;
+                              : overflow;
                 const int32_t st = attempt<METRIC>(k, none, c.n_pix, r, vjp::TapeStages{slot});
                 if (st != RAY_STEP_LIMIT && r.after_reject == 0) {
                     const bool crossed = r.ncross != n0 && n0 < 3;
@@ -393,21 +395,22 @@ hipError_t launch_vjp_tape(const ImageConst& c, const int32_t* list_pix, const i
 }
 
 hipError_t launch_vjp_tape_dense(const ImageConst& c, const double* dl_dI, int32_t cap,
-                                 double* tape, int32_t* count, unsigned int* counters,
+                                 double* tape, double* overflow, int32_t* count,
+                                 unsigned int* counters,
                                  unsigned long long* queue, const LaunchShape& shape,
                                  int32_t grid, hipStream_t stream) {
     if (c.metric == KERR)
         hipLaunchKernelGGL(vjp_tape_dense_kernel<KERR>, dim3(grid), dim3(kBlock), 0, stream, c,
-                           dl_dI, cap, tape, count, counters, queue, shape);
+                           dl_dI, cap, tape, overflow, count, counters, queue, shape);
     else if (c.metric == EINASTO)
         hipLaunchKernelGGL(vjp_tape_dense_kernel<EINASTO>, dim3(grid), dim3(kBlock), 0, stream, c,
-                           dl_dI, cap, tape, count, counters, queue, shape);
+                           dl_dI, cap, tape, overflow, count, counters, queue, shape);
     else if (c.ex_near)
         hipLaunchKernelGGL(vjp_tape_dense_kernel<CNFW_NEAR>, dim3(grid), dim3(kBlock), 0, stream, c,
-                           dl_dI, cap, tape, count, counters, queue, shape);
+                           dl_dI, cap, tape, overflow, count, counters, queue, shape);
     else
         hipLaunchKernelGGL(vjp_tape_dense_kernel<CNFW>, dim3(grid), dim3(kBlock), 0, stream, c,
-                           dl_dI, cap, tape, count, counters, queue, shape);
+                           dl_dI, cap, tape, overflow, count, counters, queue, shape);
     return hipGetLastError();
 }
 

@@ -818,9 +818,10 @@ int image_vjp(const rt_image_params* params, const double* dl_dI, int32_t basis,
         return rc;
 
     // Scratch: queue counters (dense tape, dense reverse, count, then tape and
-    // reverse of the list), pass counters, counts, gradient partials, per-pixel
-    // gradients (when the caller passes none).
-    const size_t q_bytes = 512;
+    // reverse of the list), pass counters, the dense tape's overflow record,
+    // counts, gradient partials, per-pixel gradients (when the caller passes
+    // none).
+    const size_t q_bytes = 768;
     const size_t cnt_bytes = up256(sizeof(int32_t) * n_pix);
     const size_t part_bytes = up256(sizeof(double) * 4 * rt::kGradBlocks);
     const size_t gp_bytes = grad_pix ? 0 : up256(sizeof(double) * 4 * n_pix);
@@ -833,6 +834,8 @@ int image_vjp(const rt_image_params* params, const double* dl_dI, int32_t basis,
     char* base = static_cast<char*>(scratch);
     unsigned long long* queue = reinterpret_cast<unsigned long long*>(base);
     unsigned int* counters = reinterpret_cast<unsigned int*>(base + 256);
+    static_assert(rt::kVjpRecBytes <= 256, "overflow record fits its scratch slot");
+    double* overflow = reinterpret_cast<double*>(base + 512);
     int32_t* count = reinterpret_cast<int32_t*>(base + q_bytes);
     double* partials = reinterpret_cast<double*>(base + q_bytes + cnt_bytes);
     double* gp = grad_pix ? grad_pix
@@ -860,8 +863,8 @@ int image_vjp(const rt_image_params* params, const double* dl_dI, int32_t basis,
     if ((e = rt::launch_fill_zero(gp, 4 * n_pix, stream)) != hipSuccess)
         return bail(hip_fail(e, "gradient fill launch"));
     if ((e = rt::launch_vjp_tape_dense(c, dl_dI, static_cast<int32_t>(cap),
-                                       static_cast<double*>(dense_tape), count, counters, queue,
-                                       shape, grid_of(3, n_pix), stream)) != hipSuccess)
+                                       static_cast<double*>(dense_tape), overflow, count, counters,
+                                       queue, shape, grid_of(3, n_pix), stream)) != hipSuccess)
         return bail(hip_fail(e, "tape kernel launch"));
     if (cap > 0 &&
         (e = rt::launch_vjp_reverse_dense(c, dl_dI, count, static_cast<int32_t>(cap),

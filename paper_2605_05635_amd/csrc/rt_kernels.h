@@ -134,10 +134,12 @@ int mixed_blocks_per_cu(int metric, int pass);
 constexpr int kVjpPrims = 11;
 constexpr int kVjpRecBytes = 240;
 constexpr int kGradBlocks = 256;
+// `overflow`: one writable tape record (kVjpRecBytes) that takes the stage
+// derivatives of steps past a pixel's region.
 hipError_t launch_vjp_tape_dense(const ImageConst& c, const double* dl_dI, int32_t cap,
-                                 double* tape, int32_t* count, unsigned int* counters,
-                                 unsigned long long* queue, const LaunchShape& shape,
-                                 int32_t grid, hipStream_t stream);
+                                 double* tape, double* overflow, int32_t* count,
+                                 unsigned int* counters, unsigned long long* queue,
+                                 const LaunchShape& shape, int32_t grid, hipStream_t stream);
 hipError_t launch_vjp_reverse_dense(const ImageConst& c, const double* dl_dI,
                                     const int32_t* count, int32_t cap, const double* tape,
                                     const double (&jac)[kVjpPrims][4], double* grad_pix,

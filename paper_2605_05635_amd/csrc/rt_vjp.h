@@ -46,12 +46,12 @@ enum Prim {
 constexpr int kRecDoubles = 30;
 constexpr int kRecStages = 6;   // offset of the stage derivatives
 
-// Attempt sink that writes the stage derivatives into a tape record (nothing
-// when rec is null).
+// Attempt sink that writes the stage derivatives into the tape record `rec`
+// (always a writable record: a branch here would keep registers live across
+// every stage).
 struct TapeStages {
     double* rec;
     __host__ __device__ __forceinline__ void operator()(int j, const double* kj) const {
-        if (!rec) return;
         double2* q = reinterpret_cast<double2*>(rec + kRecStages + 4 * j);
         q[0] = double2{kj[1], kj[2]};
         q[1] = double2{kj[4], kj[5]};
