@@ -94,7 +94,7 @@ __host__ __device__ inline void mass_function(const K& c, const S& R, S& F, S& d
         const S inv = dm::recip1(R * Rl);
         const S iR = Rl * inv;
         const S iRl = R * inv;
-        const S lg = dm::log1p(R * c.inv_lam_c);
+        const S lg = dm::log1p_fast(R * c.inv_lam_c);
         const S ex = c.eta_lc * (iRl - two * iR * lg);
         const S dex = c.eta_lc * (two * iR * (iR * lg - iRl) - iRl * iRl);
         const S em1 = expm1_ex(ex, METRIC == CNFW_NEAR);

@@ -137,6 +137,10 @@ __host__ __device__ inline Dual<N> log1p(const Dual<N>& a) {
     return chain(a, dm::log1p(a.v), 1.0 / (1.0 + a.v));
 }
 template <int N>
+__host__ __device__ inline Dual<N> log1p_fast(const Dual<N>& a) {
+    return chain(a, dm::log1p_fast(a.v), 1.0 / (1.0 + a.v));
+}
+template <int N>
 __host__ __device__ inline void sincos(const Dual<N>& a, Dual<N>* s, Dual<N>* c) {
     double sv, cv;
     dm::sincos(a.v, &sv, &cv);

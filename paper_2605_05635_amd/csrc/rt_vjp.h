@@ -92,7 +92,7 @@ __host__ __device__ __forceinline__ void mass_eval(const Hot& k, double R, MassT
         const double iR = Rl * inv;
         const double iRl = R * inv;
         const double u = R * k.inv_lam_c;
-        const double lg = dm::log1p(u);
+        const double lg = dm::log1p_fast(u);
         const double P = iRl - 2.0 * iR * lg;
         const double Q = 2.0 * iR * (iR * lg - iRl) - iRl * iRl;
         const double ex = k.eta_lc * P;

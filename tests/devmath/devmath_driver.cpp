@@ -1,7 +1,7 @@
 // Host driver for tests/test_devmath.py: evaluates the trace kernels' compact
 // elementary functions (paper_2605_05635_amd/csrc/rt_math.h, compiled for the
 // host) on the doubles read from stdin and writes the results to stdout.
-//   usage: devmath_driver <function>   (sincos | exp | expm1 | log1p | rpow_tenth, and the
+//   usage: devmath_driver <function>   (sincos | exp | expm1 | log1p | log1p_fast | rpow_tenth, and the
 //          binary32 versions sincosf | expf | expm1f | log1pf of the arguments rounded
 //          to binary32)
 #include <cstdio>
@@ -28,6 +28,8 @@ int main(int argc, char** argv) {
             out.push_back(rt::dm::expm1(a));
         } else if (!std::strcmp(argv[1], "log1p")) {
             out.push_back(rt::dm::log1p(a));
+        } else if (!std::strcmp(argv[1], "log1p_fast")) {
+            out.push_back(rt::dm::log1p_fast(a));
         } else if (!std::strcmp(argv[1], "rpow_tenth")) {
             out.push_back(rt::dm::rpow_tenth(a));
         } else if (!std::strcmp(argv[1], "sincosf")) {
