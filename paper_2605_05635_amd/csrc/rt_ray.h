@@ -255,9 +255,12 @@ __host__ __device__ __forceinline__ void start_ray(const ImageConst& c, const Ho
 // y0 + s (c1 + s (c2 + s (c3 + s c4))), Newton's method starts from the secant
 // root and is kept inside the shrinking sign bracket (bisection when a Newton
 // step would leave it); it stops after a step below 1e-10 (Newton's quadratic
-// convergence leaves the new iterate ~1e-20 c2/c1 from the root) or when the
-// bracket is exhausted.  The quotients use the one-Newton-step reciprocal
-// (2e-15): an error of that size in a Newton step is corrected by the next.
+// convergence leaves the new iterate ~1e-20 c2/c1 from the root), when the
+// bracket is exhausted, or at once where the extension evaluates to exactly
+// pi/2 (the zero Newton step from there would not lie strictly inside the
+// bracket and would hand over to bisection).  The quotients use the
+// one-Newton-step reciprocal (2e-15): an error of that size in a Newton step
+// is corrected by the next.
 __host__ __device__ __forceinline__ double crossing_root(const DenseComp& d, bool up0) {
     const double c1 = d.r2 + d.r3;
     const double c2 = d.r4 + d.r5 - d.r3;
@@ -268,6 +271,7 @@ __host__ __device__ __forceinline__ double crossing_root(const DenseComp& d, boo
     if (!(s > 0.0 && s < 1.0)) s = 0.5;
     for (int it = 0; it < 48; ++it) {
         const double f = d.y0 + s * (c1 + s * (c2 + s * (c3 + s * c4))) - kHalfPi;
+        if (f == 0.0) break;   // s is a root of the evaluated extension
         if ((f >= 0.0) == up0) a = s; else b = s;
         const double df = c1 + s * (2.0 * c2 + s * (3.0 * c3 + s * 4.0 * c4));
         double sn = s - f * rcp(df);

@@ -12,6 +12,9 @@
 //     step attempt of size h from x = (R, th, pR, pth) (the kernels' attempt()).
 //     out: Phi, accepted, crossed, then 11 values of reverse_step
 //          (R th pR pth E L chi m0 m1 m2 r_in).
+//   vjp_driver root  row = y0 r2 r3 r4 r5 up0
+//     The crossing root of theta's continuous extension with those
+//     coefficients (ray::crossing_root).  out: s.
 #include <cstdio>
 #include <cstring>
 #include <vector>
@@ -136,8 +139,9 @@ int main(int argc, char** argv) {
     if (argc != 2) return 2;
     const bool rhs_mode = !std::strcmp(argv[1], "rhs");
     const bool step_mode = !std::strcmp(argv[1], "step");
-    if (!rhs_mode && !step_mode) return 2;
-    const size_t width = rhs_mode ? 15 : 22;
+    const bool root_mode = !std::strcmp(argv[1], "root");
+    if (!rhs_mode && !step_mode && !root_mode) return 2;
+    const size_t width = rhs_mode ? 15 : step_mode ? 22 : 6;
     std::vector<double> in;
     double v;
     while (std::fread(&v, sizeof v, 1, stdin) == 1) in.push_back(v);
@@ -146,7 +150,15 @@ int main(int argc, char** argv) {
     for (size_t i = 0; i < in.size(); i += width) {
         const double* a = &in[i];
         const int m = static_cast<int>(a[0]);
-        if (rhs_mode) {
+        if (root_mode) {
+            ray::DenseComp d;
+            d.y0 = a[0];
+            d.r2 = a[1];
+            d.r3 = a[2];
+            d.r4 = a[3];
+            d.r5 = a[4];
+            out.push_back(ray::crossing_root(d, a[5] != 0.0));
+        } else if (rhs_mode) {
             if (m == KERR) rhs_case<KERR>(a, out);
             else if (m == EINASTO) rhs_case<EINASTO>(a, out);
             else rhs_case<CNFW>(a, out);

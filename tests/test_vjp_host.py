@@ -7,7 +7,9 @@ the same source the adjoint kernel uses, against independent derivatives:
 * reverse_step, the adjoint of one accepted Dormand-Prince step with a
   crossing located on its continuous extension (Sec. 3.3) and the emission of
   that crossing (Sec. 5.2, eqs. (89)-(91)), against central differences of the
-  forward step attempt the trace kernels run, with the step size frozen.
+  forward step attempt the trace kernels run, with the step size frozen;
+* crossing_root, the equatorial crossing on a step's continuous extension
+  (Sec. 3.3), against the root of the same quartic in 40-digit arithmetic.
 """
 import os
 import subprocess
@@ -145,3 +147,37 @@ def test_reverse_step_matches_differences(driver, metric, crossing):
         assert np.any(grad[:, 10] != 0.0)
     else:
         assert np.all(grad[:, 10] == 0.0)
+
+
+def test_crossing_root(driver):
+    """The root of theta(s) = pi/2 on the quartic extension, to a few ulp of s
+    (its conditioning here: one ulp of pi/2 over |dtheta/ds| ~ 0.08).  Among the
+    cases are extensions on which the Newton iteration lands on a point where
+    the extension evaluates to exactly pi/2, from which it once fell back to
+    bisection and stopped up to 1e-10 away."""
+    import mpmath as mp
+    mp.mp.dps = 40
+    half_pi = 1.5707963267948966
+    rng = np.random.default_rng(7)
+    rows = []
+    for _ in range(400):
+        d0 = rng.uniform(1e-4, 0.05) * rng.choice([-1.0, 1.0])   # theta(0) - pi/2
+        c1 = -np.sign(d0) * rng.uniform(abs(d0) * 1.05, 0.15)    # crosses inside (0, 1)
+        c2, c3, c4 = rng.normal(0, 1e-4), rng.normal(0, 1e-4), rng.normal(0, 1e-6)
+        # back to the extension's coefficients: c4 = r5, c3 = -r4 - 2 r5,
+        # c2 = r4 + r5 - r3, c1 = r2 + r3
+        r5 = c4
+        r4 = -c3 - 2.0 * r5
+        r3 = r4 + r5 - c2
+        r2 = c1 - r3
+        rows.append([half_pi + d0, r2, r3, r4, r5, 1.0 if d0 >= 0 else 0.0])
+    rows = np.array(rows)
+    s = run(driver, "root", rows, 1)[:, 0]
+    for row, got in zip(rows, s):
+        y0, r2, r3, r4, r5 = row[:5]
+        c1, c2, c3, c4 = r2 + r3, r4 + r5 - r3, -r4 - 2.0 * r5, r5   # as the kernel forms them
+        f = lambda x: (mp.mpf(y0) + x * (mp.mpf(c1) + x * (mp.mpf(c2) + x * (mp.mpf(c3) + x * mp.mpf(c4))))
+                       - mp.mpf(half_pi))
+        exact = mp.findroot(f, (mp.mpf(0), mp.mpf(1)), solver="anderson")
+        assert 0.0 < got < 1.0
+        assert abs(got - float(exact)) < 1e-14, (row, got, float(exact))
