@@ -122,11 +122,12 @@ def flops_step_overhead() -> int:
     return n
 
 
-def flops_crossing(newton: int = 6) -> int:
+def flops_crossing(newton: int = 3) -> int:
     """Locating one crossing (trace kernel): dense coefficients for theta, R,
-    p_theta, phi and T; the safeguarded Newton iteration on theta(s) (a nominal
-    `newton` iterations: from the secant start it reaches a 1e-15 step in a
-    handful); the evaluations at the root and the trusted-crossing test."""
+    p_theta, phi and T; the safeguarded Newton iteration on theta(s) (`newton`
+    iterations: from the secant start it takes three on average, measured on
+    the cored-NFW benchmark screen, at most four); the evaluations at the root
+    and the trusted-crossing test."""
     dense_coeffs = 5 * (3 + 12 + 1)      # r2, r3, r4 and r5 = h sum d_i k_i
     start = 5 + 2                         # quartic coefficients, secant root
     per_iter = 9 + 9 + 2 + 2              # theta(s) - pi/2, derivative, update, bracket
