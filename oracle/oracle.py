@@ -357,3 +357,64 @@ def visibility_amplitude(img: dict, intensity: np.ndarray, uv: np.ndarray) -> np
         ex = np.exp(-2j * math.pi * u * X)[None, :] * np.exp(-2j * math.pi * v * Y)[:, None]
         out[k] = abs((I * ex).sum() * dx * dy) / V0
     return out
+
+
+def shadow_boundary(img: dict, dirs, b_lo: float, b_hi: float, b_tol: float,
+                    samples: int = 64, max_rounds: int = 64, threads: int | None = None):
+    """Shadow boundary (Sec. 4.1, eqs. (78)-(79)): along each screen direction
+    (cos psi, sin psi) of `dirs` ([n, 2]), the impact parameter b at which the
+    rays from X = b cos psi, Y = b sin psi turn from captured to escaping.
+
+    The search is the multisection the GPU path runs (one sample per lane of
+    a 64-lane wavefront): the bracket [lo, hi] starts at [b_lo, b_hi]; each
+    round traces `samples` rays at b_j = lo + j w, w = (hi - lo)/(samples + 1),
+    j = 1..samples, and keeps [b_{j-1}, b_j] around the first sample j whose ray
+    escapes (b_0 = lo), or [b_samples, hi] if none does, while hi - lo > b_tol
+    (at most max_rounds rounds, and no further once a round leaves the bracket
+    unchanged).  A ray escapes when it ends at the escape radius (eq. (75));
+    captured rays and rays ending otherwise count as inside.
+    Returns (lo, hi, ok): ok is False where the ray at b_lo escapes or the one
+    at b_hi does not (lo, hi are then b_lo, b_hi).  The boundary point is
+    b = (lo + hi)/2 times the direction."""
+    dirs = np.ascontiguousarray(dirs, dtype=np.float64).reshape(-1, 2)
+    n = len(dirs)
+    lo_out, hi_out, ok = np.zeros(n), np.zeros(n), np.zeros(n, dtype=bool)
+
+    def escapes(ux, uy, b):
+        ray, _ = trace_ray(img, b * ux, b * uy)
+        return ray.status == STATUS["escaped"]
+
+    def one(i):
+        ux, uy = float(dirs[i, 0]), float(dirs[i, 1])
+        lo, hi = float(b_lo), float(b_hi)
+        lo_out[i], hi_out[i] = lo, hi
+        if escapes(ux, uy, lo) or not escapes(ux, uy, hi):
+            return
+        for _ in range(max_rounds):
+            if not hi - lo > b_tol:
+                break
+            w = (hi - lo) / (samples + 1)
+            first = None
+            for j in range(1, samples + 1):
+                t = j * w
+                if escapes(ux, uy, lo + t):
+                    first = j
+                    break
+            if first is None:
+                nlo, nhi = lo + samples * w, hi
+            else:
+                nhi = lo + first * w
+                nlo = lo if first == 1 else lo + (first - 1) * w
+            if nlo == lo and nhi == hi:
+                break
+            lo, hi = nlo, nhi
+        lo_out[i], hi_out[i], ok[i] = lo, hi, True
+
+    threads = threads or os.cpu_count() or 1
+    if threads == 1 or n == 1:
+        for i in range(n):
+            one(i)
+    else:
+        with ThreadPoolExecutor(max_workers=threads) as ex:
+            list(ex.map(one, range(n)))
+    return lo_out, hi_out, ok
