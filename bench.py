@@ -255,6 +255,55 @@ def adjoint_measurement(steps: int, cpu: bool) -> dict:
     return res
 
 
+def shadow_measurement(steps: int, cpu: bool) -> dict:
+    """Shadow boundary (Sec. 4.1) of the benchmark spacetime and observer along
+    4096 screen directions, b in [2, 9] M to a bracket of 1e-10 M: wall time of
+    rt_shadow_boundary per call (HIP events on the stream)."""
+    import numpy as np
+    import torch
+
+    from paper_2605_05635_amd import rt, workloads as W
+    img = W.cnfw_1024()
+    n, b_lo, b_hi, b_tol = 4096, 2.0, 9.0, 1e-10
+    psi = (np.arange(n) + 0.5) * (2.0 * np.pi / n)
+    dirs = np.stack([np.cos(psi), np.sin(psi)], axis=1)
+    d = torch.tensor(dirs, device="cuda")
+    stream = torch.cuda.current_stream()
+    out = torch.empty(n, 2, dtype=torch.float64, device="cuda")
+    st = torch.empty(n, dtype=torch.int32, device="cuda")
+    p = rt.params_from(img)
+    rt.rt_shadow_boundary(p, d, b_lo, b_hi, b_tol, out, st, stream)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(steps):
+        rt.rt_shadow_boundary(p, d, b_lo, b_hi, b_tol, out, st, stream)
+    b.record(stream)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / steps
+    bc = out.mean(dim=1).cpu().numpy()
+    rounds = int(np.ceil(np.log((b_hi - b_lo) / b_tol) / np.log(65.0)))
+    log(f"shadow boundary: {n} directions in {ms:.2f} ms")
+    res = {"workload": "cored-NFW benchmark spacetime, 4096 directions, b in [2, 9], "
+                       "bracket 1e-10 (64-point multisection)",
+           "ms": ms, "directions_per_s": n / ms * 1e3, "steps": steps,
+           "rounds": rounds, "rays_traced": n * 64 * rounds + 2 * n,
+           "all_found": bool((st == 0).all().item()),
+           "b_mean": float(bc.mean()), "b_min": float(bc.min()), "b_max": float(bc.max())}
+    if cpu:
+        from oracle import oracle as O
+        threads = max(1, min(16, os.cpu_count() or 1))
+        pick = np.arange(0, n, n // 16)
+        t0 = time.perf_counter()
+        O.shadow_boundary(img, dirs[pick], b_lo, b_hi, b_tol, threads=threads)
+        dt = time.perf_counter() - t0
+        res["cpu_oracle"] = {"directions_per_s": len(pick) / dt, "cores": threads,
+                             "kind": "oracle",
+                             "sample": f"every {n // 16}th direction ({len(pick)} directions, "
+                                       f"{dt:.1f} s)"}
+    return res
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -266,6 +315,8 @@ def main() -> int:
                     help="skip the 64-image batched trace + visibility measurement")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the mixed-precision measurement")
+    ap.add_argument("--no-shadow", action="store_true",
+                    help="skip the shadow-boundary measurement")
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the image-gradient measurement")
     ap.add_argument("--calibration-copy-mib", type=int, default=0,
@@ -350,6 +401,8 @@ def main() -> int:
         line["batch_64"] = batch_measurement(max(2, args.steps // 4))
     if not args.no_adjoint:
         line["adjoint"] = adjoint_measurement(max(2, args.steps // 2), not args.no_cpu_baseline)
+    if not args.no_shadow:
+        line["shadow_boundary"] = shadow_measurement(max(2, args.steps // 4), not args.no_cpu_baseline)
     if args.calibration_copy_mib > 0:
         nbytes = args.calibration_copy_mib << 20
         src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")

@@ -150,6 +150,29 @@ int rt_transfer_maps(const rt_image_params *params, int32_t n_images, const rt_i
  * inner disc edge}.  `setup` is host memory.  Synchronous. */
 int rt_image_setup(const rt_image_params *params, double *setup);
 
+/* Shadow boundary (Sec. 4.1, eqs. (78)-(79)): along each screen direction
+ * (cos psi, sin psi), the impact parameter b at which the rays from
+ * X = b cos psi, Y = b sin psi turn from captured to escaping (a ray escapes
+ * when it reaches r_esc_fac R_o; captured rays and rays ending otherwise count
+ * as inside).  Multisection: the bracket [lo, hi] starts at [b_lo, b_hi];
+ * each round traces 64 rays at b_j = lo + j w, w = (hi - lo)/65, j = 1..64,
+ * and keeps [b_{j-1}, b_j] around the first escaping sample (b_0 = lo), or
+ * [b_64, hi] if none escapes, while hi - lo > b_tol (at most 64 rounds, and
+ * none once a round leaves the bracket unchanged).  Rays are traced as by
+ * rt_trace_image in binary64 (params->precision must be RT_FP64; the screen
+ * fields are validated but not used).
+ *   dirs    device [n][2] (cos psi, sin psi); any length, the ray starts from
+ *           b times it
+ *   out     device [n][2] the final bracket (lo, hi); the boundary point of
+ *           eq. (79) is (lo + hi)/2 times the direction
+ *   status  device [n]: 0, or 1 where the ray at b_lo escapes or the one at
+ *           b_hi does not (out is then b_lo, b_hi)
+ * Asynchronous on the stream; no scratch.  RT_ERR_ARG for null pointers,
+ * n outside [1, 2^24], b_lo <= 0, b_lo >= b_hi, b_tol < 1e-13 b_hi or
+ * non-finite values. */
+int rt_shadow_boundary(const rt_image_params *params, const double *dirs, int32_t n, double b_lo,
+                       double b_hi, double b_tol, double *out, int32_t *status, void *hip_stream);
+
 /* Profiling hook.  When both are non-NULL hipEvent_t handles, every later
  * rt_trace_image / rt_transfer_maps call made on this thread records
  * `start_event` on its stream just before the first trace kernel and

@@ -1002,6 +1002,29 @@ int rt_transfer_maps(const rt_image_params* params, int32_t n_images, const rt_i
     return trace_common(params, n_images, out, hip_stream, false);
 }
 
+int rt_shadow_boundary(const rt_image_params* params, const double* dirs, int32_t n, double b_lo,
+                       double b_hi, double b_tol, double* out, int32_t* status, void* hip_stream) {
+    g_last_error.clear();
+    if (!params || !dirs || !out || !status) return fail(RT_ERR_ARG, "null params, dirs, out or status");
+    if (n < 1 || n > (1 << 24)) return fail(RT_ERR_ARG, "n must lie in [1, 2^24]");
+    if (!finite_all({b_lo, b_hi, b_tol}) || !(b_lo > 0.0) || !(b_lo < b_hi))
+        return fail(RT_ERR_ARG, "need finite 0 < b_lo < b_hi");
+    if (!(b_tol >= 1e-13 * b_hi))
+        return fail(RT_ERR_ARG, "b_tol must be at least 1e-13 b_hi");
+    if (params->precision != RT_FP64)
+        return fail(RT_ERR_ARG, "the boundary search traces in binary64 (precision RT_FP64)");
+    rt::ImageConst c;
+    int rc = setup_image(params, 0, false, &c, nullptr);
+    if (rc != RT_OK) return rc;
+    if ((rc = check_device_ptr(dirs, "dirs", 0)) || (rc = check_device_ptr(out, "out", 0)) ||
+        (rc = check_device_ptr(status, "status", 0)))
+        return rc;
+    const hipError_t e = rt::launch_boundary(c, dirs, n, b_lo, b_hi, b_tol, out, status,
+                                             static_cast<hipStream_t>(hip_stream));
+    if (e != hipSuccess) return hip_fail(e, "boundary kernel launch");
+    return RT_OK;
+}
+
 int rt_image_setup(const rt_image_params* params, double* setup) {
     g_last_error.clear();
     if (!setup) return fail(RT_ERR_ARG, "null setup pointer");

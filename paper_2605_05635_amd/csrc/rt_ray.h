@@ -211,6 +211,13 @@ struct ScreenDir {
     double nR, nth, nph;
 };
 
+// The direction of screen point (X, Y).
+__host__ __device__ __forceinline__ ScreenDir screen_dir_xy(const ImageConst& c, double X, double Y) {
+    const double inv = 1.0 / sqrt(c.r_obs * c.r_obs + X * X + Y * Y);
+    return ScreenDir{-c.r_obs * inv, -Y * inv, -X * inv};
+}
+
+// The direction of pixel pix's centre.
 __host__ __device__ __forceinline__ ScreenDir screen_dir(const ImageConst& c, int64_t pix) {
     // 32-bit index arithmetic: screens hold fewer than 2^31 pixels
     const int32_t p = static_cast<int32_t>(pix);
@@ -218,8 +225,7 @@ __host__ __device__ __forceinline__ ScreenDir screen_dir(const ImageConst& c, in
     const int32_t ix = p - iy * c.nx;
     const double X = c.x0 + (static_cast<double>(ix) + 0.5) * c.dx;
     const double Y = c.y0 + (static_cast<double>(iy) + 0.5) * c.dy;
-    const double inv = 1.0 / sqrt(c.r_obs * c.r_obs + X * X + Y * Y);
-    return ScreenDir{-c.r_obs * inv, -Y * inv, -X * inv};
+    return screen_dir_xy(c, X, Y);
 }
 
 // The photon's conserved E and l of pixel pix.
@@ -229,9 +235,10 @@ __host__ __device__ __forceinline__ void photon_constants(const ImageConst& c, c
     L = c.obs_sq_gphph * n.nph;
 }
 
+// A ray from screen direction n, recorded as pixel pix.
 template <int METRIC>
-__host__ __device__ __forceinline__ void start_ray(const ImageConst& c, const Hot& k, int64_t pix, Ray& r) {
-    const ScreenDir n = screen_dir(c, pix);
+__host__ __device__ __forceinline__ void start_ray_dir(const ImageConst& c, const Hot& k,
+                                                       const ScreenDir& n, int64_t pix, Ray& r) {
     photon_constants(c, n, r.E, r.L);
     r.y[0] = 0.0;
     r.y[1] = c.r_obs;
@@ -248,6 +255,11 @@ __host__ __device__ __forceinline__ void start_ray(const ImageConst& c, const Ho
     r.ncross = 0;
     r.after_reject = 0;
     r.pix = pix;
+}
+
+template <int METRIC>
+__host__ __device__ __forceinline__ void start_ray(const ImageConst& c, const Hot& k, int64_t pix, Ray& r) {
+    start_ray_dir<METRIC>(c, k, screen_dir(c, pix), pix, r);
 }
 
 // Root of theta(s) = pi/2 on the step's continuous extension, s in (0, 1),

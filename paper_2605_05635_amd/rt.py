@@ -78,6 +78,9 @@ def _load():
     lib.rt_visibility_dft.argtypes = [C.c_void_p, C.POINTER(rt_image_params), C.c_void_p,
                                       C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]
     lib.rt_visibility_dft.restype = C.c_int
+    lib.rt_shadow_boundary.argtypes = [P, C.c_void_p, C.c_int32, C.c_double, C.c_double,
+                                       C.c_double, C.c_void_p, C.c_void_p, C.c_void_p]
+    lib.rt_shadow_boundary.restype = C.c_int
     lib.rt_set_launch_config.argtypes = [C.POINTER(rt_launch_config)]
     lib.rt_set_launch_config.restype = C.c_int
     lib.rt_get_launch_config.argtypes = [C.POINTER(rt_launch_config)]
@@ -203,6 +206,28 @@ def visibility(img: dict, intensity, uv, stream=None):
     return amp
 
 
+def rt_shadow_boundary(params: rt_image_params, dirs, b_lo: float, b_hi: float, b_tol: float,
+                       out, status, stream=None) -> None:
+    """Calls rt_shadow_boundary on device tensors: dirs [n][2] f64 (cos psi,
+    sin psi), out [n][2] f64 and status [n] int32 (outputs)."""
+    n = int(dirs.shape[0])
+    _check(_lib.rt_shadow_boundary(C.byref(params), C.c_void_p(dirs.data_ptr()), n, b_lo, b_hi,
+                                   b_tol, C.c_void_p(out.data_ptr()),
+                                   C.c_void_p(status.data_ptr()), _stream_handle(stream)))
+
+
+def shadow_boundary(img: dict, dirs, b_lo: float, b_hi: float, b_tol: float, stream=None):
+    """The shadow boundary of img's spacetime and observer along the screen
+    directions dirs ([n][2] (cos psi, sin psi), numpy or tensor): returns device
+    tensors (out [n][2] = the final bracket of b, status [n])."""
+    import torch
+    d = torch.as_tensor(dirs, dtype=torch.float64, device="cuda").reshape(-1, 2).contiguous()
+    out = torch.empty(d.shape[0], 2, dtype=torch.float64, device=d.device)
+    status = torch.empty(d.shape[0], dtype=torch.int32, device=d.device)
+    rt_shadow_boundary(params_from(img), d, b_lo, b_hi, b_tol, out, status, stream)
+    return out, status
+
+
 def rt_set_launch_config(chunk: int = 0, tile_w: int = 0, tile_h: int = 0,
                          blocks_per_cu: int = 0, order: int = RT_ORDER_CENTRE,
                          reset: bool = False) -> None:
@@ -310,6 +335,7 @@ def image_vjp(img: dict, dl_dI, basis: str = "native", per_pixel: bool = False, 
 
 __all__ = ["rt_mixed_stats", "rt_image_vjp", "rt_set_tape_budget", "rt_vjp_stats", "image_vjp", "rt_trace_image", "rt_transfer_maps", "rt_image_setup", "rt_set_kernel_timing",
            "rt_set_launch_config", "rt_get_launch_config", "rt_visibility_dft", "visibility",
+           "rt_shadow_boundary", "shadow_boundary",
            "rt_version",
            "rt_last_error", "trace", "trace_many", "params_from", "out_from", "alloc_outputs",
            "RTError"]

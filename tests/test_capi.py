@@ -186,3 +186,26 @@ def test_vjp_argument_errors(rt):
     assert lib.rt_vjp_stats(None) == rt.RT_ERR_ARG
     buf = (C.c_int64 * 4)()
     assert lib.rt_vjp_stats(buf) == rt.RT_OK
+
+
+def test_shadow_boundary_argument_errors(rt):
+    lib = rt.lib()
+    p = rt.params_from(W.kerr_small())
+    d = C.c_void_p(8)
+    call = lambda params, dirs, n, lo, hi, tol, out, st: lib.rt_shadow_boundary(
+        params, dirs, n, lo, hi, tol, out, st, None)
+    assert call(None, d, 4, 2.0, 9.0, 1e-9, d, d) == rt.RT_ERR_ARG
+    assert call(C.byref(p), None, 4, 2.0, 9.0, 1e-9, d, d) == rt.RT_ERR_ARG
+    assert call(C.byref(p), d, 4, 2.0, 9.0, 1e-9, None, d) == rt.RT_ERR_ARG
+    assert call(C.byref(p), d, 4, 2.0, 9.0, 1e-9, d, None) == rt.RT_ERR_ARG
+    assert call(C.byref(p), d, 0, 2.0, 9.0, 1e-9, d, d) == rt.RT_ERR_ARG
+    assert call(C.byref(p), d, (1 << 24) + 1, 2.0, 9.0, 1e-9, d, d) == rt.RT_ERR_ARG
+    assert call(C.byref(p), d, 4, 0.0, 9.0, 1e-9, d, d) == rt.RT_ERR_ARG
+    assert call(C.byref(p), d, 4, 9.0, 2.0, 1e-9, d, d) == rt.RT_ERR_ARG
+    assert call(C.byref(p), d, 4, 2.0, float("inf"), 1e-9, d, d) == rt.RT_ERR_ARG
+    assert call(C.byref(p), d, 4, 2.0, 9.0, 1e-14, d, d) == rt.RT_ERR_ARG
+    assert "b_tol" in rt.rt_last_error()
+    mixed = rt.params_from(W.image(precision="mixed"))
+    assert call(C.byref(mixed), d, 4, 2.0, 9.0, 1e-9, d, d) == rt.RT_ERR_ARG
+    nohz = rt.params_from(W.image(metric="kerr", spin=1.01))
+    assert call(C.byref(nohz), d, 4, 2.0, 9.0, 1e-9, d, d) == rt.RT_ERR_NO_HORIZON
