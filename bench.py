@@ -271,23 +271,32 @@ def shadow_measurement(steps: int, cpu: bool) -> dict:
     stream = torch.cuda.current_stream()
     out = torch.empty(n, 2, dtype=torch.float64, device="cuda")
     st = torch.empty(n, dtype=torch.int32, device="cuda")
+    att = torch.empty(n, dtype=torch.int64, device="cuda")
     p = rt.params_from(img)
-    rt.rt_shadow_boundary(p, d, b_lo, b_hi, b_tol, out, st, stream)
+    rt.rt_shadow_boundary(p, d, b_lo, b_hi, b_tol, out, st, att, stream)
     torch.cuda.synchronize()
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     a.record(stream)
     for _ in range(steps):
-        rt.rt_shadow_boundary(p, d, b_lo, b_hi, b_tol, out, st, stream)
+        rt.rt_shadow_boundary(p, d, b_lo, b_hi, b_tol, out, st, att, stream)
     b.record(stream)
     torch.cuda.synchronize()
     ms = a.elapsed_time(b) / steps
     bc = out.mean(dim=1).cpu().numpy()
     rounds = int(np.ceil(np.log((b_hi - b_lo) / b_tol) / np.log(65.0)))
-    log(f"shadow boundary: {n} directions in {ms:.2f} ms")
+    rays = n * 64 * rounds + 2 * n
+    attempts = float(att.sum().item())
+    from paper_2605_05635_amd import census
+    # algorithmic flops as for the trace kernel, without the crossings (not counted)
+    flops = (attempts * (6 * census.flops_rhs(img["metric"]) + census.flops_step_overhead())
+             + rays * (20 + census.flops_rhs(img["metric"])))
+    tflops = flops / (ms * 1e-3) / 1e12
+    log(f"shadow boundary: {n} directions in {ms:.2f} ms, {attempts / rays:.0f} attempts per ray")
     res = {"workload": "cored-NFW benchmark spacetime, 4096 directions, b in [2, 9], "
                        "bracket 1e-10 (64-point multisection)",
            "ms": ms, "directions_per_s": n / ms * 1e3, "steps": steps,
-           "rounds": rounds, "rays_traced": n * 64 * rounds + 2 * n,
+           "rounds": rounds, "rays_traced": rays, "attempts_per_ray": attempts / rays,
+           "algorithmic_tflops": tflops, "frac_of_fp64_vector_peak": tflops / FP64_VECTOR_PEAK_TFLOPS,
            "all_found": bool((st == 0).all().item()),
            "b_mean": float(bc.mean()), "b_min": float(bc.min()), "b_max": float(bc.max())}
     if cpu:

@@ -167,11 +167,13 @@ int rt_image_setup(const rt_image_params *params, double *setup);
  *           eq. (79) is (lo + hi)/2 times the direction
  *   status  device [n]: 0, or 1 where the ray at b_lo escapes or the one at
  *           b_hi does not (out is then b_lo, b_hi)
+ *   attempts device [n] step attempts of all the direction's rays, or NULL
  * Asynchronous on the stream; no scratch.  RT_ERR_ARG for null pointers,
  * n outside [1, 2^24], b_lo <= 0, b_lo >= b_hi, b_tol < 1e-13 b_hi or
  * non-finite values. */
 int rt_shadow_boundary(const rt_image_params *params, const double *dirs, int32_t n, double b_lo,
-                       double b_hi, double b_tol, double *out, int32_t *status, void *hip_stream);
+                       double b_hi, double b_tol, double *out, int32_t *status, int64_t *attempts,
+                       void *hip_stream);
 
 /* Profiling hook.  When both are non-NULL hipEvent_t handles, every later
  * rt_trace_image / rt_transfer_maps call made on this thread records

@@ -1003,7 +1003,8 @@ int rt_transfer_maps(const rt_image_params* params, int32_t n_images, const rt_i
 }
 
 int rt_shadow_boundary(const rt_image_params* params, const double* dirs, int32_t n, double b_lo,
-                       double b_hi, double b_tol, double* out, int32_t* status, void* hip_stream) {
+                       double b_hi, double b_tol, double* out, int32_t* status, int64_t* attempts,
+                       void* hip_stream) {
     g_last_error.clear();
     if (!params || !dirs || !out || !status) return fail(RT_ERR_ARG, "null params, dirs, out or status");
     if (n < 1 || n > (1 << 24)) return fail(RT_ERR_ARG, "n must lie in [1, 2^24]");
@@ -1017,9 +1018,10 @@ int rt_shadow_boundary(const rt_image_params* params, const double* dirs, int32_
     int rc = setup_image(params, 0, false, &c, nullptr);
     if (rc != RT_OK) return rc;
     if ((rc = check_device_ptr(dirs, "dirs", 0)) || (rc = check_device_ptr(out, "out", 0)) ||
-        (rc = check_device_ptr(status, "status", 0)))
+        (rc = check_device_ptr(status, "status", 0)) ||
+        (rc = check_device_ptr(attempts, "attempts", 0)))
         return rc;
-    const hipError_t e = rt::launch_boundary(c, dirs, n, b_lo, b_hi, b_tol, out, status,
+    const hipError_t e = rt::launch_boundary(c, dirs, n, b_lo, b_hi, b_tol, out, status, attempts,
                                              static_cast<hipStream_t>(hip_stream));
     if (e != hipSuccess) return hip_fail(e, "boundary kernel launch");
     return RT_OK;

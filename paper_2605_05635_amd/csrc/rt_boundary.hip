@@ -19,7 +19,8 @@ constexpr int kMaxRounds = 64;
 template <int METRIC>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) void boundary_kernel(
     ImageConst c, const double* __restrict__ dirs, int32_t n, double b_lo, double b_hi,
-    double b_tol, double* __restrict__ out, int32_t* __restrict__ status) {
+    double b_tol, double* __restrict__ out, int32_t* __restrict__ status,
+    int64_t* __restrict__ attempts) {
     const int64_t wave = (static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x) / 64;
     if (wave >= n) return;   // whole wavefronts: kBlock is a multiple of 64
     const int lane = __lane_id();
@@ -27,6 +28,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
     const OutPtrs none{};    // no per-pixel outputs
     const double ux = dirs[2 * wave], uy = dirs[2 * wave + 1];
     double lo = b_lo, hi = b_hi;
+    int64_t used = 0;        // this lane's step attempts
     int32_t result = 1;      // bracket without the transition, until checked
     // Round -1 checks the bracket (lane 0 at b_lo must stay inside, lane 1 at
     // b_hi must escape); rounds 0, 1, ... sample b_j = lo + j w, j = lane + 1.
@@ -50,6 +52,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
                 if (st != 0) active = false;
             }
         }
+        if (live) used += r.attempts;
         const unsigned long long esc = __ballot(live && st == RAY_ESCAPED);
         if (round < 0) {
             if ((esc & 1ull) || !(esc & 2ull)) break;
@@ -72,10 +75,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
         }
         if (round + 1 >= kMaxRounds || !(hi - lo > b_tol)) break;
     }
+    for (int off = 32; off > 0; off >>= 1) used += __shfl_xor(used, off);
     if (lane == 0) {
         out[2 * wave] = lo;
         out[2 * wave + 1] = hi;
         status[wave] = result;
+        if (attempts) attempts[wave] = used;
     }
 }
 
@@ -83,20 +88,20 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
 
 hipError_t launch_boundary(const ImageConst& c, const double* dirs, int32_t n, double b_lo,
                            double b_hi, double b_tol, double* out, int32_t* status,
-                           hipStream_t stream) {
+                           int64_t* attempts, hipStream_t stream) {
     const int32_t blocks = (n + kBlock / 64 - 1) / (kBlock / 64);
     if (c.metric == KERR)
         hipLaunchKernelGGL(boundary_kernel<KERR>, dim3(blocks), dim3(kBlock), 0, stream, c, dirs,
-                           n, b_lo, b_hi, b_tol, out, status);
+                           n, b_lo, b_hi, b_tol, out, status, attempts);
     else if (c.metric == EINASTO)
         hipLaunchKernelGGL(boundary_kernel<EINASTO>, dim3(blocks), dim3(kBlock), 0, stream, c,
-                           dirs, n, b_lo, b_hi, b_tol, out, status);
+                           dirs, n, b_lo, b_hi, b_tol, out, status, attempts);
     else if (c.ex_near)
         hipLaunchKernelGGL(boundary_kernel<CNFW_NEAR>, dim3(blocks), dim3(kBlock), 0, stream, c,
-                           dirs, n, b_lo, b_hi, b_tol, out, status);
+                           dirs, n, b_lo, b_hi, b_tol, out, status, attempts);
     else
         hipLaunchKernelGGL(boundary_kernel<CNFW>, dim3(blocks), dim3(kBlock), 0, stream, c, dirs,
-                           n, b_lo, b_hi, b_tol, out, status);
+                           n, b_lo, b_hi, b_tol, out, status, attempts);
     return hipGetLastError();
 }
 

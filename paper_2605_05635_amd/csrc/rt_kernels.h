@@ -66,10 +66,10 @@ hipError_t launch_emission_batch(const ImageConst* table, const OutPtrs* outs, i
 // Shadow-boundary search: one wavefront per direction dirs[2i], dirs[2i+1]
 // (cos psi, sin psi); out[2i], out[2i+1] = the final bracket of b, status[i]
 // = 0, or 1 (bracket left as given) when the ray at b_lo escapes or the one at
-// b_hi does not.
+// b_hi does not; attempts[i] (if non-null) = the direction's step attempts.
 hipError_t launch_boundary(const ImageConst& c, const double* dirs, int32_t n, double b_lo,
                            double b_hi, double b_tol, double* out, int32_t* status,
-                           hipStream_t stream);
+                           int64_t* attempts, hipStream_t stream);
 
 // LDS bytes of the batched kernel for n_images images.
 size_t batch_lds_bytes(int32_t n_images);

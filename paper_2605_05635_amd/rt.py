@@ -79,7 +79,7 @@ def _load():
                                       C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]
     lib.rt_visibility_dft.restype = C.c_int
     lib.rt_shadow_boundary.argtypes = [P, C.c_void_p, C.c_int32, C.c_double, C.c_double,
-                                       C.c_double, C.c_void_p, C.c_void_p, C.c_void_p]
+                                       C.c_double, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
     lib.rt_shadow_boundary.restype = C.c_int
     lib.rt_set_launch_config.argtypes = [C.POINTER(rt_launch_config)]
     lib.rt_set_launch_config.restype = C.c_int
@@ -207,13 +207,16 @@ def visibility(img: dict, intensity, uv, stream=None):
 
 
 def rt_shadow_boundary(params: rt_image_params, dirs, b_lo: float, b_hi: float, b_tol: float,
-                       out, status, stream=None) -> None:
+                       out, status, attempts=None, stream=None) -> None:
     """Calls rt_shadow_boundary on device tensors: dirs [n][2] f64 (cos psi,
-    sin psi), out [n][2] f64 and status [n] int32 (outputs)."""
+    sin psi), out [n][2] f64, status [n] int32 and optionally attempts [n]
+    int64 (outputs)."""
     n = int(dirs.shape[0])
     _check(_lib.rt_shadow_boundary(C.byref(params), C.c_void_p(dirs.data_ptr()), n, b_lo, b_hi,
                                    b_tol, C.c_void_p(out.data_ptr()),
-                                   C.c_void_p(status.data_ptr()), _stream_handle(stream)))
+                                   C.c_void_p(status.data_ptr()),
+                                   None if attempts is None else C.c_void_p(attempts.data_ptr()),
+                                   _stream_handle(stream)))
 
 
 def shadow_boundary(img: dict, dirs, b_lo: float, b_hi: float, b_tol: float, stream=None):
@@ -224,7 +227,7 @@ def shadow_boundary(img: dict, dirs, b_lo: float, b_hi: float, b_tol: float, str
     d = torch.as_tensor(dirs, dtype=torch.float64, device="cuda").reshape(-1, 2).contiguous()
     out = torch.empty(d.shape[0], 2, dtype=torch.float64, device=d.device)
     status = torch.empty(d.shape[0], dtype=torch.int32, device=d.device)
-    rt_shadow_boundary(params_from(img), d, b_lo, b_hi, b_tol, out, status, stream)
+    rt_shadow_boundary(params_from(img), d, b_lo, b_hi, b_tol, out, status, stream=stream)
     return out, status
 
 

@@ -193,7 +193,7 @@ def test_shadow_boundary_argument_errors(rt):
     p = rt.params_from(W.kerr_small())
     d = C.c_void_p(8)
     call = lambda params, dirs, n, lo, hi, tol, out, st: lib.rt_shadow_boundary(
-        params, dirs, n, lo, hi, tol, out, st, None)
+        params, dirs, n, lo, hi, tol, out, st, None, None)
     assert call(None, d, 4, 2.0, 9.0, 1e-9, d, d) == rt.RT_ERR_ARG
     assert call(C.byref(p), None, 4, 2.0, 9.0, 1e-9, d, d) == rt.RT_ERR_ARG
     assert call(C.byref(p), d, 4, 2.0, 9.0, 1e-9, None, d) == rt.RT_ERR_ARG

@@ -126,3 +126,22 @@ def test_many_directions_sampled(rt, orc):
     pick = np.arange(0, n, n // 8) + 17
     lo, hi, ok = orc.shadow_boundary(img, d[pick], 2.0, 9.0, 1e-10)
     assert ok.all() and np.abs(b[pick] - 0.5 * (lo + hi)).max() <= 1.5e-10
+
+
+def test_attempt_counts_do_not_change_results(rt):
+    import torch
+    img = W.image(metric="einasto", halo=(0.3, 0.0), **FIG3)
+    d = torch.tensor(dirs_of(np.linspace(0.1, 6.0, 40)), device="cuda")
+    p = rt.params_from(img)
+    out1 = torch.empty(40, 2, dtype=torch.float64, device="cuda")
+    out2 = torch.empty_like(out1)
+    st1 = torch.empty(40, dtype=torch.int32, device="cuda")
+    st2 = torch.empty_like(st1)
+    att = torch.full((40,), -1, dtype=torch.int64, device="cuda")
+    rt.rt_shadow_boundary(p, d, 2.0, 9.0, TOL_B, out1, st1)
+    rt.rt_shadow_boundary(p, d, 2.0, 9.0, TOL_B, out2, st2, att)
+    torch.cuda.synchronize()
+    assert torch.equal(out1, out2) and torch.equal(st1, st2)
+    rounds = math.ceil(math.log(7.0 / TOL_B) / math.log(65.0))
+    # every traced ray takes at least a few dozen attempts from R_o = 1000
+    assert int(att.min()) >= (64 * rounds + 2) * 20
