@@ -418,3 +418,52 @@ def shadow_boundary(img: dict, dirs, b_lo: float, b_hi: float, b_tol: float,
         with ThreadPoolExecutor(max_workers=threads) as ex:
             list(ex.map(one, range(n)))
     return lo_out, hi_out, ok
+
+
+DIAG_KEYS = ("F", "X_c", "Y_c", "C", "rho_bar", "d_img", "w_img", "w_over_d", "A_LR",
+             "I_max", "I_mean_emitting", "P", "rho_peak", "d_peak")
+
+
+def image_diagnostics(img: dict, intensity: np.ndarray, bin_width: float, n_bins: int) -> dict:
+    """Image-level morphology diagnostics of a raw intensity map (Sec. 6.2 and
+    the bright-peak scale of Sec. 6.3), midpoint rule over pixel centres:
+
+    F = sum I dX dY; X_c, Y_c the intensity-weighted centroid; C = |(X_c, Y_c)|;
+    rho = |(X - X_c, Y - Y_c)|; rho_bar = sum rho I dX dY / F; d_img = 2 rho_bar;
+    w_img = [sum (rho - rho_bar)^2 I dX dY / F]^(1/2); A_LR = (F_R - F_L)/(F_R + F_L)
+    with F_R, F_L the flux of the pixels with X > X_c, X < X_c; P = I_max over
+    the mean intensity of the emitting pixels (I > 0); and, from the
+    origin-centred radial profile (the mean intensity of the pixels whose
+    rho_0 = |(X, Y)| falls in [k bin_width, (k + 1) bin_width), k < n_bins), the
+    centre rho_peak of the first bin of largest mean and d_peak = 2 rho_peak.
+    Also returns the profile (NaN for empty bins)."""
+    X, Y, dx, dy = screen_axes(img)
+    I = np.asarray(intensity, dtype=np.float64).reshape(img["ny"], img["nx"])
+    Xg, Yg = np.meshgrid(X, Y)
+    F = I.sum() * dx * dy
+    Xc = (I * Xg).sum() * dx * dy / F
+    Yc = (I * Yg).sum() * dx * dy / F
+    rho = np.sqrt((Xg - Xc) ** 2 + (Yg - Yc) ** 2)
+    rho_bar = (rho * I).sum() * dx * dy / F
+    w = math.sqrt(((rho - rho_bar) ** 2 * I).sum() * dx * dy / F)
+    FR = I[Xg > Xc].sum() * dx * dy
+    FL = I[Xg < Xc].sum() * dx * dy
+    emitting = I > 0
+    I_max = I.max()
+    I_mean = I[emitting].mean() if emitting.any() else 0.0
+    rho0 = np.sqrt(Xg ** 2 + Yg ** 2)
+    k = np.floor(rho0 / bin_width).astype(np.int64)
+    sums = np.zeros(n_bins)
+    counts = np.zeros(n_bins)
+    inside = k < n_bins
+    np.add.at(sums, k[inside], I[inside])
+    np.add.at(counts, k[inside], 1.0)
+    profile = np.where(counts > 0, sums / np.maximum(counts, 1.0), np.nan)
+    kp = int(np.nanargmax(profile)) if np.isfinite(profile).any() else 0
+    rho_peak = (kp + 0.5) * bin_width
+    vals = (F, Xc, Yc, math.hypot(Xc, Yc), rho_bar, 2 * rho_bar, w, w / (2 * rho_bar),
+            (FR - FL) / (FR + FL), I_max, I_mean, I_max / I_mean if I_mean > 0 else 0.0,
+            rho_peak, 2 * rho_peak)
+    out = dict(zip(DIAG_KEYS, vals))
+    out["profile"] = profile
+    return out
