@@ -150,6 +150,27 @@ int rt_transfer_maps(const rt_image_params *params, int32_t n_images, const rt_i
  * inner disc edge}.  `setup` is host memory.  Synchronous. */
 int rt_image_setup(const rt_image_params *params, double *setup);
 
+/* Image-level morphology diagnostics of a raw intensity map (Sec. 6.2) and
+ * its bright-peak scale (Sec. 6.3), midpoint rule over the pixel centres of
+ * the screen of `params` (only nx, ny and the extent are read):
+ *   out device [RT_DIAG_COUNT] = {F, X_c, Y_c, C = |(X_c, Y_c)|, rho_bar,
+ *       d_img = 2 rho_bar, w_img, w_img / d_img, A_LR, I_max, <I>_img, P,
+ *       rho_peak, d_peak}: rho is the distance from the centroid, rho_bar its
+ *       intensity-weighted mean, w_img = [sum (rho - rho_bar)^2 I dX dY / F]^(1/2),
+ *       A_LR = (F_R - F_L)/(F_R + F_L) with F_R, F_L the flux of the pixels
+ *       with X > X_c and X < X_c, <I>_img the mean intensity of the pixels with
+ *       I > 0, P = I_max / <I>_img; rho_peak the centre of the first bin of
+ *       largest mean of the origin-centred radial profile, d_peak = 2 rho_peak
+ *   profile device [n_bins] or NULL: the mean intensity of the pixels with
+ *       floor(|(X, Y)| / bin_width) = k (NaN for an empty bin); pixels beyond
+ *       the last bin are not binned
+ * Deterministic (fixed summation order).  Scratch (~10 KB + 8 n_bins bytes)
+ * is stream-ordered.  RT_ERR_ARG for null intensity/params/out, a bad screen,
+ * bin_width <= 0 or n_bins outside [1, 2^20]. */
+enum { RT_DIAG_COUNT = 14 };
+int rt_image_diagnostics(const double *intensity, const rt_image_params *params, double bin_width,
+                         int32_t n_bins, double *out, double *profile, void *hip_stream);
+
 /* Shadow boundary (Sec. 4.1, eqs. (78)-(79)): along each screen direction
  * (cos psi, sin psi), the impact parameter b at which the rays from
  * X = b cos psi, Y = b sin psi turn from captured to escaping (a ray escapes

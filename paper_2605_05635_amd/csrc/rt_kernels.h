@@ -63,6 +63,14 @@ hipError_t launch_emission(const ImageConst& c, const OutPtrs& o, hipStream_t st
 hipError_t launch_emission_batch(const ImageConst* table, const OutPtrs* outs, int32_t n_images,
                                  int64_t max_pix, hipStream_t stream);
 
+// Image diagnostics of `intensity` on the screen of c (rt_image_diagnostics):
+// out[0..14); profile[n_bins] (or scratch when null); scratch holds
+// diagnostics_scratch_doubles(n_bins) doubles.  Deterministic.
+size_t diagnostics_scratch_doubles(int32_t n_bins);
+hipError_t launch_diagnostics(const ImageConst& c, const double* intensity, double bw,
+                              int32_t n_bins, double* out, double* profile, double* scratch,
+                              hipStream_t stream);
+
 // Shadow-boundary search: one wavefront per direction dirs[2i], dirs[2i+1]
 // (cos psi, sin psi); out[2i], out[2i+1] = the final bracket of b, status[i]
 // = 0, or 1 (bracket left as given) when the ray at b_lo escapes or the one at

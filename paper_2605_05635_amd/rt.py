@@ -78,6 +78,9 @@ def _load():
     lib.rt_visibility_dft.argtypes = [C.c_void_p, C.POINTER(rt_image_params), C.c_void_p,
                                       C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]
     lib.rt_visibility_dft.restype = C.c_int
+    lib.rt_image_diagnostics.argtypes = [C.c_void_p, P, C.c_double, C.c_int32, C.c_void_p,
+                                         C.c_void_p, C.c_void_p]
+    lib.rt_image_diagnostics.restype = C.c_int
     lib.rt_shadow_boundary.argtypes = [P, C.c_void_p, C.c_int32, C.c_double, C.c_double,
                                        C.c_double, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
     lib.rt_shadow_boundary.restype = C.c_int
@@ -204,6 +207,34 @@ def visibility(img: dict, intensity, uv, stream=None):
     amp = torch.empty(uv_t.shape[0], dtype=torch.float64, device=intensity.device)
     rt_visibility_dft(intensity.contiguous(), params_from(img), uv_t, amp=amp, stream=stream)
     return amp
+
+
+RT_DIAG_COUNT = 14
+DIAG_KEYS = ("F", "X_c", "Y_c", "C", "rho_bar", "d_img", "w_img", "w_over_d", "A_LR",
+             "I_max", "I_mean_emitting", "P", "rho_peak", "d_peak")
+
+
+def rt_image_diagnostics(intensity, params: rt_image_params, bin_width: float, n_bins: int,
+                         out, profile=None, stream=None) -> None:
+    """Calls rt_image_diagnostics on device tensors: intensity [ny][nx] f64,
+    out [RT_DIAG_COUNT] f64 and optionally profile [n_bins] f64 (outputs)."""
+    _check(_lib.rt_image_diagnostics(C.c_void_p(intensity.data_ptr()), C.byref(params),
+                                     bin_width, n_bins, C.c_void_p(out.data_ptr()),
+                                     None if profile is None else C.c_void_p(profile.data_ptr()),
+                                     _stream_handle(stream)))
+
+
+def image_diagnostics(img: dict, intensity, bin_width: float, n_bins: int, stream=None):
+    """The diagnostics of a traced image as a dict of device scalars (DIAG_KEYS)
+    plus the radial profile (device tensor [n_bins])."""
+    import torch
+    out = torch.empty(RT_DIAG_COUNT, dtype=torch.float64, device=intensity.device)
+    prof = torch.empty(n_bins, dtype=torch.float64, device=intensity.device)
+    rt_image_diagnostics(intensity.contiguous(), params_from(img), bin_width, n_bins, out, prof,
+                         stream)
+    d = dict(zip(DIAG_KEYS, out))
+    d["profile"] = prof
+    return d
 
 
 def rt_shadow_boundary(params: rt_image_params, dirs, b_lo: float, b_hi: float, b_tol: float,
@@ -338,7 +369,8 @@ def image_vjp(img: dict, dl_dI, basis: str = "native", per_pixel: bool = False, 
 
 __all__ = ["rt_mixed_stats", "rt_image_vjp", "rt_set_tape_budget", "rt_vjp_stats", "image_vjp", "rt_trace_image", "rt_transfer_maps", "rt_image_setup", "rt_set_kernel_timing",
            "rt_set_launch_config", "rt_get_launch_config", "rt_visibility_dft", "visibility",
-           "rt_shadow_boundary", "shadow_boundary",
+           "rt_shadow_boundary", "shadow_boundary", "rt_image_diagnostics", "image_diagnostics",
+           "RT_DIAG_COUNT", "DIAG_KEYS",
            "rt_version",
            "rt_last_error", "trace", "trace_many", "params_from", "out_from", "alloc_outputs",
            "RTError"]

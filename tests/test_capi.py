@@ -209,3 +209,20 @@ def test_shadow_boundary_argument_errors(rt):
     assert call(C.byref(mixed), d, 4, 2.0, 9.0, 1e-9, d, d) == rt.RT_ERR_ARG
     nohz = rt.params_from(W.image(metric="kerr", spin=1.01))
     assert call(C.byref(nohz), d, 4, 2.0, 9.0, 1e-9, d, d) == rt.RT_ERR_NO_HORIZON
+
+
+def test_image_diagnostics_argument_errors(rt):
+    lib = rt.lib()
+    p = rt.params_from(W.kerr_small())
+    d = C.c_void_p(8)
+    call = lambda I, params, bw, nb, out: lib.rt_image_diagnostics(I, params, bw, nb, out, None, None)
+    assert call(None, C.byref(p), 0.1, 10, d) == rt.RT_ERR_ARG
+    assert call(d, None, 0.1, 10, d) == rt.RT_ERR_ARG
+    assert call(d, C.byref(p), 0.1, 10, None) == rt.RT_ERR_ARG
+    assert call(d, C.byref(p), 0.0, 10, d) == rt.RT_ERR_ARG
+    assert call(d, C.byref(p), float("nan"), 10, d) == rt.RT_ERR_ARG
+    assert call(d, C.byref(p), 0.1, 0, d) == rt.RT_ERR_ARG
+    assert call(d, C.byref(p), 0.1, (1 << 20) + 1, d) == rt.RT_ERR_ARG
+    bad = rt.params_from(W.image(nx=0))
+    assert call(d, C.byref(bad), 0.1, 10, d) == rt.RT_ERR_ARG
+    assert "screen" in rt.rt_last_error()
