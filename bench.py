@@ -255,6 +255,45 @@ def adjoint_measurement(steps: int, cpu: bool) -> dict:
     return res
 
 
+def diagnostics_measurement(steps: int, outs: dict, img: dict, cpu: bool) -> dict:
+    """Image diagnostics (Sec. 6.2-6.3) of the bench's traced 1024x1024 image:
+    wall time of rt_image_diagnostics per call (HIP events on the stream),
+    300 radial bins of 0.05 M."""
+    import torch
+
+    from paper_2605_05635_amd import rt
+    I = outs["intensity"]
+    bw, nb = 0.05, 300
+    out = torch.empty(rt.RT_DIAG_COUNT, dtype=torch.float64, device="cuda")
+    prof = torch.empty(nb, dtype=torch.float64, device="cuda")
+    p = rt.params_from(img)
+    stream = torch.cuda.current_stream()
+    rt.rt_image_diagnostics(I, p, bw, nb, out, prof, stream)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(steps):
+        rt.rt_image_diagnostics(I, p, bw, nb, out, prof, stream)
+    b.record(stream)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / steps
+    vals = dict(zip(rt.DIAG_KEYS, out.cpu().tolist()))
+    # four full reads of the image (flux/centroid, the moments, the width, the
+    # profile's visits: ~1.2 reads measured by the run lengths) as the traffic floor
+    nbytes = 8 * I.numel() * 4
+    log(f"diagnostics: {ms * 1e3:.1f} us per image")
+    res = {"workload": "image diagnostics of the 1024x1024 cored-NFW image, 300 bins of 0.05 M",
+           "us": ms * 1e3, "steps": steps, "values": vals,
+           "image_reads_GBps": nbytes / (ms * 1e-3) / 1e9}
+    if cpu:
+        from oracle import oracle as O
+        In = I.cpu().numpy()
+        t0 = time.perf_counter()
+        O.image_diagnostics(img, In, bw, nb)
+        res["cpu_oracle_ms"] = (time.perf_counter() - t0) * 1e3
+    return res
+
+
 def shadow_measurement(steps: int, cpu: bool) -> dict:
     """Shadow boundary (Sec. 4.1) of the benchmark spacetime and observer along
     4096 screen directions, b in [2, 9] M to a bracket of 1e-10 M: wall time of
@@ -410,6 +449,7 @@ def main() -> int:
         line["batch_64"] = batch_measurement(max(2, args.steps // 4))
     if not args.no_adjoint:
         line["adjoint"] = adjoint_measurement(max(2, args.steps // 2), not args.no_cpu_baseline)
+    line["diagnostics"] = diagnostics_measurement(args.steps, outs, img, not args.no_cpu_baseline)
     if not args.no_shadow:
         line["shadow_boundary"] = shadow_measurement(max(2, args.steps // 4), not args.no_cpu_baseline)
     if args.calibration_copy_mib > 0:

@@ -7,9 +7,9 @@
 // centroid that need only the centroid (sum rho I, the fluxes right and left
 // of X_c, the emitting pixels' sum and count, the peak intensity), one pass
 // for the width about the mean radius, one workgroup per radial bin for the
-// profile (it visits only the rows and columns that can reach its annulus and
-// keeps the pixels whose bin is exactly its own), and one workgroup that picks
-// the first bin of largest mean.
+// profile (its threads take whole rows and visit only the columns that can
+// reach its annulus, keeping the pixels whose bin is exactly its own), and one
+// workgroup that picks the first bin of largest mean.
 #include "rt_kernels.h"
 
 namespace rt {
@@ -146,25 +146,28 @@ __device__ __forceinline__ int64_t radial_bin(double X, double Y, double bw) {
 }
 
 // One workgroup per bin k: the mean intensity of the pixels with
-// floor(rho_0 / bw) == k (NaN if none).  Each row visits the column runs that
-// can reach the annulus [k bw, (k + 1) bw), widened by two pixels on each
-// side, and keeps the pixels of exactly this bin; rows farther than the
-// annulus are skipped.  (dx, dy > 0: the screen extent is validated.)
+// floor(rho_0 / bw) == k (NaN if none).  Each thread takes whole rows (rows
+// t, t + 256, ...): it visits the column runs of its row that can reach the
+// annulus [k bw, (k + 1) bw), widened by two pixels on each side, and keeps
+// the pixels of exactly this bin; rows farther than the annulus are skipped.
+// A thread's rows and pixels go in a fixed order, then a fixed-order tree
+// over the threads.  (dx, dy > 0: the screen extent is validated.)
 __global__ __launch_bounds__(kThreads) void profile_kernel(ImageConst c, const double* __restrict__ I,
                                                            double bw, double* __restrict__ profile) {
     const int64_t k = blockIdx.x;
     const double r_lo = static_cast<double>(k) * bw, r_hi = static_cast<double>(k + 1) * bw;
+    const double inv_dx = 1.0 / c.dx;   // column bounds only: the margins absorb its rounding
     auto first_col = [&](double a) {
-        const double f = floor((a - c.x0) / c.dx - 0.5);
+        const double f = floor((a - c.x0) * inv_dx - 0.5);
         return f < 0.0 ? int64_t(0) : static_cast<int64_t>(fmin(f, static_cast<double>(c.nx)));
     };
     auto last_col = [&](double b) {
-        const double f = ceil((b - c.x0) / c.dx - 0.5);
+        const double f = ceil((b - c.x0) * inv_dx - 0.5);
         return f > static_cast<double>(c.nx - 1) ? static_cast<int64_t>(c.nx - 1)
                                                  : static_cast<int64_t>(fmax(f, -1.0));
     };
     double s = 0.0, n = 0.0;
-    for (int64_t iy = 0; iy < c.ny; ++iy) {
+    for (int64_t iy = threadIdx.x; iy < c.ny; iy += kThreads) {
         const double Y = centre(c.y0, c.dy, iy);
         if (fabs(Y) > r_hi + c.dy) continue;
         const double xo = sqrt(fmax(0.0, r_hi * r_hi - Y * Y)) + 2.0 * c.dx;
@@ -172,13 +175,13 @@ __global__ __launch_bounds__(kThreads) void profile_kernel(ImageConst c, const d
         const int64_t a0 = first_col(-xo), a1 = last_col(-xi);
         const int64_t b0 = first_col(xi), b1 = last_col(xo);
         const bool one = b0 <= a1 + 1;   // the runs touch: visit [a0, b1] once
+        const double* row = I + iy * c.nx;
         for (int run = 0; run < (one ? 1 : 2); ++run) {
             const int64_t lo = run == 0 ? a0 : b0;
             const int64_t hi = one ? b1 : (run == 0 ? a1 : b1);
-            for (int64_t ix = lo + threadIdx.x; ix <= hi; ix += kThreads) {
-                const double X = centre(c.x0, c.dx, ix);
-                if (radial_bin(X, Y, bw) == k) {
-                    s += I[iy * c.nx + ix];
+            for (int64_t ix = lo; ix <= hi; ++ix) {
+                if (radial_bin(centre(c.x0, c.dx, ix), Y, bw) == k) {
+                    s += row[ix];
                     n += 1.0;
                 }
             }
