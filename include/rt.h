@@ -150,6 +150,31 @@ int rt_transfer_maps(const rt_image_params *params, int32_t n_images, const rt_i
  * inner disc edge}.  `setup` is host memory.  Synchronous. */
 int rt_image_setup(const rt_image_params *params, double *setup);
 
+/* Parameter scans of the spacetimes (Sec. 2), one point per entry:
+ *   points device [n] rt_scan_point (metric and halo as in rt_image_params,
+ *          spin chi, theta the polar angle of the ergosurface radius)
+ *   out    device [n][4] = {R_+ (eq. (33): the largest root of Delta =
+ *          R^2 - F(R) + chi^2 in (0.05, 50]), the ergosurface radius at theta
+ *          (the largest root of R^2 - F(R) + chi^2 cos^2 theta, g_TT = 0),
+ *          chi_e (the extremal spin: chi_e^2 = max_R (F(R) - R^2)), r_e (the
+ *          radius of that maximum)}; NaN where a root or maximum does not
+ *          exist (spin beyond extremal) and for an invalid point (unknown
+ *          metric, lambda_E or lambda_c <= 0, eta < 0, reserved != 0,
+ *          non-finite values)
+ * One thread per point: downward scan of spacing 1e-2 for the roots (with
+ * the interior-minimum test near extremality), 1e-3 upward for the maximum,
+ * each refined by bisection to the last representable bracket; the same code
+ * as the image set-up's horizon.  Asynchronous on the stream, no scratch.
+ * RT_ERR_ARG for null pointers or n outside [1, 2^24]. */
+typedef struct rt_scan_point {
+  int32_t metric;        /* RT_KERR, RT_EINASTO or RT_CNFW                            */
+  int32_t reserved;      /* must be 0                                                 */
+  double spin;           /* chi                                                       */
+  double halo[2];        /* as rt_image_params.halo                                   */
+  double theta;          /* polar angle of the ergosurface radius [rad]               */
+} rt_scan_point;
+int rt_parameter_scan(const rt_scan_point *points, int32_t n, double *out, void *hip_stream);
+
 /* Image-level morphology diagnostics of a raw intensity map (Sec. 6.2) and
  * its bright-peak scale (Sec. 6.3), midpoint rule over the pixel centres of
  * the screen of `params` (only nx, ny and the extent are read):

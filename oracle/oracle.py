@@ -467,3 +467,27 @@ def image_diagnostics(img: dict, intensity: np.ndarray, bin_width: float, n_bins
     out = dict(zip(DIAG_KEYS, vals))
     out["profile"] = profile
     return out
+
+
+def parameter_scan(points) -> np.ndarray:
+    """For each parameter point (metric name, spin, halo0, halo1, theta): the
+    outer horizon R_+ (Sec. 2, eq. (33)), the ergosurface radius at theta (the
+    outer horizon of the same metric with chi^2 cos^2 theta in place of chi^2,
+    i.e. where g_TT = 0), the extremal spin chi_e and its radius r_e; NaN
+    where they do not exist.  Returns [n, 4]."""
+    out = np.full((len(points), 4), np.nan)
+    for i, (metric, spin, h0, h1, theta) in enumerate(points):
+        img = dict(metric=metric, spin=spin, halo=(h0, h1), incl=1.0, r_obs=1000.0, nx=1, ny=1,
+                   x_min=-1.0, x_max=1.0, y_min=-1.0, y_max=1.0, rtol=1e-8, atol=1e-8,
+                   r_stop_fac=1.01, r_esc_fac=1.1, r_in=0.0, r_out=20.0, emis_pow=3.0,
+                   sigma_in=0.0, sigma_out=0.0, max_attempts=1, h0=1.0, precision="fp64")
+        r = horizon(img)
+        if r is not None:
+            out[i, 0] = r
+        r = horizon(dict(img, spin=abs(spin * math.cos(theta))))
+        if r is not None:
+            out[i, 1] = r
+        e = extremal_spin(img)
+        if e is not None:
+            out[i, 2], out[i, 3] = e
+    return out

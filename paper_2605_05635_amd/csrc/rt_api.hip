@@ -14,6 +14,7 @@
 #include "rt.h"
 #include "rt_device.h"
 #include "rt_kernels.h"
+#include "rt_scan.h"
 
 namespace {
 
@@ -191,62 +192,10 @@ bool finite_all(std::initializer_list<double> v) {
     return true;
 }
 
-// Delta(R) = R^2 - F(R) + chi^2 (eq. (25)) and its R-derivative.
-void delta(const rt::ImageConst& c, double R, double* D, double* dD) {
-    double F, dF;
-    rt::mass_function_any(c, R, F, dF);
-    *D = R * R - F + c.chi2;
-    *dD = 2.0 * R - dF;
-}
-
-// Outer horizon: the largest root of Delta (eq. (33)) in (0.05, 50].  Delta is
-// sampled downward on a grid of spacing 1e-2; an interval counts when Delta
-// changes sign across it, or when Delta has an interior minimum <= 0 (two
-// close roots, near extremality).  The root is refined by bisection to the
-// last representable bracket.
+// Outer horizon: the largest root of Delta (eq. (33)) in (0.05, 50]
+// (rt_scan.h).
 bool outer_horizon(const rt::ImageConst& c, double* r_plus) {
-    const double top = 50.0, step = 1e-2;
-    double D_hi, dD_hi;
-    delta(c, top, &D_hi, &dD_hi);
-    if (!(D_hi > 0.0)) return false;
-    for (int k = 1; top - k * step >= 0.05 - 1e-12; ++k) {
-        const double hi = top - (k - 1) * step, lo = top - k * step;
-        double D_lo, dD_lo;
-        delta(c, lo, &D_lo, &dD_lo);
-        double a = lo, b = hi;  // want Delta(a) <= 0 < Delta(b)
-        bool bracket = D_lo <= 0.0;
-        if (!bracket && dD_lo < 0.0 && dD_hi > 0.0) {
-            // interior minimum: locate it where dDelta/dR = 0
-            double u = lo, v = hi;
-            for (int it = 0; it < 200; ++it) {
-                const double m = 0.5 * (u + v);
-                if (m <= u || m >= v) break;
-                double Dm, dDm;
-                delta(c, m, &Dm, &dDm);
-                if (dDm < 0.0) u = m; else v = m;
-            }
-            double Dm, dDm;
-            delta(c, 0.5 * (u + v), &Dm, &dDm);
-            if (Dm <= 0.0) {
-                a = 0.5 * (u + v);
-                bracket = true;
-            }
-        }
-        if (bracket) {
-            for (int it = 0; it < 200; ++it) {
-                const double m = 0.5 * (a + b);
-                if (m <= a || m >= b) break;
-                double Dm, dDm;
-                delta(c, m, &Dm, &dDm);
-                if (Dm > 0.0) b = m; else a = m;
-            }
-            *r_plus = 0.5 * (a + b);
-            return true;
-        }
-        D_hi = D_lo;
-        dD_hi = dD_lo;
-    }
-    return false;
+    return rt::scan::largest_root(c, c.chi2, r_plus);
 }
 
 // Validates p and fills the image constants.  Returns RT_OK or an error code.
@@ -1000,6 +949,18 @@ int rt_trace_image(const rt_image_params* params, int32_t n_images, const rt_ima
 int rt_transfer_maps(const rt_image_params* params, int32_t n_images, const rt_image_out* out,
                      void* hip_stream) {
     return trace_common(params, n_images, out, hip_stream, false);
+}
+
+int rt_parameter_scan(const rt_scan_point* points, int32_t n, double* out, void* hip_stream) {
+    g_last_error.clear();
+    if (!points || !out) return fail(RT_ERR_ARG, "null points or out");
+    if (n < 1 || n > (1 << 24)) return fail(RT_ERR_ARG, "n must lie in [1, 2^24]");
+    int rc;
+    if ((rc = check_device_ptr(points, "points", 0)) || (rc = check_device_ptr(out, "out", 0)))
+        return rc;
+    const hipError_t e = rt::launch_scan(points, n, out, static_cast<hipStream_t>(hip_stream));
+    if (e != hipSuccess) return hip_fail(e, "scan kernel launch");
+    return RT_OK;
 }
 
 int rt_image_diagnostics(const double* intensity, const rt_image_params* params, double bin_width,

@@ -7,6 +7,8 @@
 
 #include "rt_device.h"
 
+struct rt_scan_point;   // include/rt.h
+
 namespace rt {
 
 constexpr int kBlock = 256;  // 4 wavefronts of 64 lanes
@@ -62,6 +64,9 @@ hipError_t launch_emission(const ImageConst& c, const OutPtrs& o, hipStream_t st
 // launch_trace_batch; max_pix the largest image).
 hipError_t launch_emission_batch(const ImageConst* table, const OutPtrs* outs, int32_t n_images,
                                  int64_t max_pix, hipStream_t stream);
+
+// Parameter scan (rt_parameter_scan): out[4i..4i+4) for pts[i].
+hipError_t launch_scan(const ::rt_scan_point* pts, int32_t n, double* out, hipStream_t stream);
 
 // Image diagnostics of `intensity` on the screen of c (rt_image_diagnostics):
 // out[0..14); profile[n_bins] (or scratch when null); scratch holds

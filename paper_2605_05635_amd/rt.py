@@ -56,6 +56,11 @@ class rt_launch_config(C.Structure):
                 ("blocks_per_cu", C.c_int32), ("order", C.c_int32)]
 
 
+class rt_scan_point(C.Structure):
+    _fields_ = [("metric", C.c_int32), ("reserved", C.c_int32), ("spin", C.c_double),
+                ("halo", C.c_double * 2), ("theta", C.c_double)]
+
+
 class RTError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"rt error {code}: {msg}")
@@ -78,6 +83,8 @@ def _load():
     lib.rt_visibility_dft.argtypes = [C.c_void_p, C.POINTER(rt_image_params), C.c_void_p,
                                       C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]
     lib.rt_visibility_dft.restype = C.c_int
+    lib.rt_parameter_scan.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]
+    lib.rt_parameter_scan.restype = C.c_int
     lib.rt_image_diagnostics.argtypes = [C.c_void_p, P, C.c_double, C.c_int32, C.c_void_p,
                                          C.c_void_p, C.c_void_p]
     lib.rt_image_diagnostics.restype = C.c_int
@@ -207,6 +214,39 @@ def visibility(img: dict, intensity, uv, stream=None):
     amp = torch.empty(uv_t.shape[0], dtype=torch.float64, device=intensity.device)
     rt_visibility_dft(intensity.contiguous(), params_from(img), uv_t, amp=amp, stream=stream)
     return amp
+
+
+def rt_parameter_scan(points, out, stream=None) -> None:
+    """Calls rt_parameter_scan on device tensors: points a uint8 tensor holding
+    n rt_scan_point structs (packed by parameter_scan), out [n][4] f64."""
+    n = int(out.shape[0])
+    _check(_lib.rt_parameter_scan(C.c_void_p(points.data_ptr()), n, C.c_void_p(out.data_ptr()),
+                                  _stream_handle(stream)))
+
+
+def parameter_scan(metric, spin, halo0, halo1, theta, stream=None):
+    """R_+, the ergosurface radius at theta, chi_e and r_e for each parameter
+    point (array-likes of one length; metric as "kerr"/"einasto"/"cnfw" or the
+    RT_* codes): returns a device tensor [n][4]."""
+    import numpy as np
+    import torch
+    codes = {"kerr": RT_KERR, "einasto": RT_EINASTO, "cnfw": RT_CNFW}
+    seq = list(metric) if isinstance(metric, (list, tuple)) else list(np.atleast_1d(metric))
+    m = [codes[str(x)] if isinstance(x, (str, np.str_)) else int(x) for x in seq]
+    n = len(m)
+    host = (rt_scan_point * n)()
+    cols = [np.broadcast_to(np.asarray(v, dtype=np.float64), (n,)) for v in (spin, halo0, halo1, theta)]
+    for i in range(n):
+        host[i].metric = m[i]
+        host[i].reserved = 0
+        host[i].spin = float(cols[0][i])
+        host[i].halo[0] = float(cols[1][i])
+        host[i].halo[1] = float(cols[2][i])
+        host[i].theta = float(cols[3][i])
+    raw = torch.frombuffer(bytearray(bytes(host)), dtype=torch.uint8).to("cuda")
+    out = torch.empty(n, 4, dtype=torch.float64, device="cuda")
+    rt_parameter_scan(raw, out, stream)
+    return out
 
 
 RT_DIAG_COUNT = 14
@@ -370,6 +410,7 @@ def image_vjp(img: dict, dl_dI, basis: str = "native", per_pixel: bool = False, 
 __all__ = ["rt_mixed_stats", "rt_image_vjp", "rt_set_tape_budget", "rt_vjp_stats", "image_vjp", "rt_trace_image", "rt_transfer_maps", "rt_image_setup", "rt_set_kernel_timing",
            "rt_set_launch_config", "rt_get_launch_config", "rt_visibility_dft", "visibility",
            "rt_shadow_boundary", "shadow_boundary", "rt_image_diagnostics", "image_diagnostics",
+           "rt_parameter_scan", "parameter_scan", "rt_scan_point",
            "RT_DIAG_COUNT", "DIAG_KEYS",
            "rt_version",
            "rt_last_error", "trace", "trace_many", "params_from", "out_from", "alloc_outputs",

@@ -226,3 +226,25 @@ def test_image_diagnostics_argument_errors(rt):
     bad = rt.params_from(W.image(nx=0))
     assert call(d, C.byref(bad), 0.1, 10, d) == rt.RT_ERR_ARG
     assert "screen" in rt.rt_last_error()
+
+
+def test_scan_point_layout_and_argument_errors(rt, tmp_path):
+    fields = [f for f, _ in rt.rt_scan_point._fields_]
+    src = ['#include <stdio.h>', '#include <stddef.h>', '#include "rt.h"', "int main(void){",
+           'printf("%zu\\n", sizeof(rt_scan_point));']
+    src += [f'printf("%zu\\n", offsetof(rt_scan_point, {f}));' for f in fields]
+    src += ["return 0;}"]
+    c = tmp_path / "scan.c"
+    c.write_text("\n".join(src))
+    exe = tmp_path / "scan"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(c), "-o", str(exe)], check=True)
+    vals = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True,
+                                           check=True).stdout.split()]
+    assert vals[0] == C.sizeof(rt.rt_scan_point)
+    assert vals[1:] == [getattr(rt.rt_scan_point, f).offset for f in fields]
+    lib = rt.lib()
+    d = C.c_void_p(8)
+    assert lib.rt_parameter_scan(None, 4, d, None) == rt.RT_ERR_ARG
+    assert lib.rt_parameter_scan(d, 4, None, None) == rt.RT_ERR_ARG
+    assert lib.rt_parameter_scan(d, 0, d, None) == rt.RT_ERR_ARG
+    assert lib.rt_parameter_scan(d, (1 << 24) + 1, d, None) == rt.RT_ERR_ARG

@@ -1,0 +1,70 @@
+"""Parameter scans (rt_parameter_scan, Sec. 2) on the GPU against the
+oracle's horizon and extremal-spin searches.  Both refine every root by
+bisection to the last representable bracket; they differ in the rounding of
+F(R) (the GPU's own elementary functions against libm), which moves a simple
+root by ~1e-15 relative: R_+, the ergosurface radius and chi_e are held to
+1e-11 relative, r_e (the root of 2R - F'(R), one derivative more) to 1e-9.
+Points within 2 % of the extremal spin are left out: there the oracle's
+plain sign-change scan and the GPU's interior-minimum test may resolve a
+double root differently."""
+import math
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rt():
+    import torch
+    assert torch.cuda.is_available(), "GPU test run without a GPU"
+    from paper_2605_05635_amd import rt as mod
+    return mod
+
+
+def points(seed, n):
+    rng = np.random.default_rng(seed)
+    pts = []
+    while len(pts) < n:
+        m = ("kerr", "einasto", "cnfw")[rng.integers(3)]
+        h0 = rng.uniform(0.05, 0.35) if m == "einasto" else rng.uniform(0.0, 0.3) if m == "cnfw" else 0.0
+        h1 = rng.uniform(2.0, 20.0) if m == "cnfw" else 0.0
+        pts.append((m, float(rng.uniform(0.0, 1.1)), h0, h1, float(rng.uniform(0.0, math.pi))))
+    return pts
+
+
+def test_scan_matches_oracle(rt, orc):
+    import torch
+    pts = points(11, 96)
+    o = orc.parameter_scan(pts)
+    keep = [i for i, (p, row) in enumerate(zip(pts, o))
+            if not (math.isfinite(row[2]) and abs(p[1] / row[2] - 1.0) < 0.02)]
+    pts = [pts[i] for i in keep]
+    o = o[keep]
+    g = rt.parameter_scan([p[0] for p in pts], [p[1] for p in pts], [p[2] for p in pts],
+                          [p[3] for p in pts], [p[4] for p in pts])
+    torch.cuda.synchronize()
+    g = g.cpu().numpy()
+    assert np.array_equal(np.isnan(g), np.isnan(o))
+    f = ~np.isnan(o)
+    rel = np.abs(g[f] - o[f]) / np.abs(o[f])
+    cols = np.broadcast_to(np.arange(4), g.shape)[f]
+    assert rel[cols != 3].max() < 1e-11 and rel[cols == 3].max() < 1e-9
+    assert (~np.isnan(o[:, 0])).sum() > 30 and np.isnan(o[:, 0]).sum() > 3   # both kinds present
+
+
+def test_kerr_closed_forms_and_invalid_points(rt):
+    import torch
+    chi = np.array([0.0, 0.5, 0.9, 0.99, 1.05])
+    th = np.array([0.3, 1.0, math.pi / 2, 2.5, 1.2])
+    g = rt.parameter_scan(["kerr"] * 5, chi, 0.0, 0.0, th).cpu().numpy()
+    ok = chi < 1.0
+    assert np.allclose(g[ok, 0], 1 + np.sqrt(1 - chi[ok] ** 2), rtol=1e-12)
+    assert np.isnan(g[~ok, 0]).all()
+    assert np.allclose(g[:, 1], 1 + np.sqrt(1 - (chi * np.cos(th)) ** 2), rtol=1e-12)
+    assert np.allclose(g[:, 2], 1.0, rtol=1e-12) and np.allclose(g[:, 3], 1.0, rtol=1e-6)
+    bad = rt.parameter_scan([7, "einasto", "cnfw"], [0.5, 0.5, 0.5], [0.1, -1.0, 0.02],
+                            [0.0, 0.0, 0.0], [1.0, 1.0, 1.0])
+    torch.cuda.synchronize()
+    assert torch.isnan(bad).all()
