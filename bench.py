@@ -13,6 +13,7 @@ strided sample of the same screen.
 from __future__ import annotations
 
 import argparse
+import math
 import json
 import os
 import sys
@@ -294,6 +295,49 @@ def diagnostics_measurement(steps: int, outs: dict, img: dict, cpu: bool) -> dic
     return res
 
 
+def scan_measurement(steps: int, cpu: bool) -> dict:
+    """Parameter scan (Sec. 2) over a 64 x 64 grid of cored-NFW points, chi in
+    [0, 1.05] x eta in [0, 0.3] at lambda_c = 10, theta = 60 deg: wall time of
+    rt_parameter_scan per call (HIP events on the stream)."""
+    import numpy as np
+    import torch
+
+    from paper_2605_05635_amd import rt
+    chi, eta = np.meshgrid(np.linspace(0.0, 1.05, 64), np.linspace(0.0, 0.3, 64))
+    n = chi.size
+    stream = torch.cuda.current_stream()
+    out = rt.parameter_scan(["cnfw"] * n, chi.ravel(), eta.ravel(), 10.0, math.radians(60.0))
+    host = (rt.rt_scan_point * n)()
+    for i, (c, e) in enumerate(zip(chi.ravel(), eta.ravel())):
+        host[i].metric, host[i].spin, host[i].theta = rt.RT_CNFW, float(c), math.radians(60.0)
+        host[i].halo[0], host[i].halo[1] = float(e), 10.0
+    pts = torch.frombuffer(bytearray(bytes(host)), dtype=torch.uint8).to("cuda")
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(steps):
+        rt.rt_parameter_scan(pts, out, stream)
+    b.record(stream)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / steps
+    o = out.cpu().numpy()
+    log(f"parameter scan: {n} points in {ms:.2f} ms")
+    res = {"workload": "cored-NFW 64 x 64 grid of (chi, eta), lambda_c = 10, ergosurface at 60 deg",
+           "ms": ms, "points_per_s": n / ms * 1e3, "steps": steps,
+           "with_horizon": int(np.isfinite(o[:, 0]).sum()),
+           "chi_e_range": [float(np.nanmin(o[:, 2])), float(np.nanmax(o[:, 2]))]}
+    if cpu:
+        from oracle import oracle as O
+        pick = list(range(0, n, n // 16))
+        t0 = time.perf_counter()
+        O.parameter_scan([("cnfw", float(chi.ravel()[i]), float(eta.ravel()[i]), 10.0,
+                           math.radians(60.0)) for i in pick])
+        dt = time.perf_counter() - t0
+        res["cpu_oracle"] = {"points_per_s": len(pick) / dt, "cores": 1, "kind": "oracle",
+                             "sample": f"every {n // 16}th point ({len(pick)} points, {dt:.1f} s)"}
+    return res
+
+
 def shadow_measurement(steps: int, cpu: bool) -> dict:
     """Shadow boundary (Sec. 4.1) of the benchmark spacetime and observer along
     4096 screen directions, b in [2, 9] M to a bracket of 1e-10 M: wall time of
@@ -450,6 +494,7 @@ def main() -> int:
     if not args.no_adjoint:
         line["adjoint"] = adjoint_measurement(max(2, args.steps // 2), not args.no_cpu_baseline)
     line["diagnostics"] = diagnostics_measurement(args.steps, outs, img, not args.no_cpu_baseline)
+    line["parameter_scan"] = scan_measurement(max(2, args.steps // 2), not args.no_cpu_baseline)
     if not args.no_shadow:
         line["shadow_boundary"] = shadow_measurement(max(2, args.steps // 4), not args.no_cpu_baseline)
     if args.calibration_copy_mib > 0:
