@@ -407,6 +407,10 @@ def main() -> int:
                     help="skip the 64-image batched trace + visibility measurement")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the mixed-precision measurement")
+    ap.add_argument("--no-scan", action="store_true",
+                    help="skip the parameter-scan measurement")
+    ap.add_argument("--no-diagnostics", action="store_true",
+                    help="skip the image-diagnostics measurement")
     ap.add_argument("--no-shadow", action="store_true",
                     help="skip the shadow-boundary measurement")
     ap.add_argument("--no-adjoint", action="store_true",
@@ -493,8 +497,10 @@ def main() -> int:
         line["batch_64"] = batch_measurement(max(2, args.steps // 4))
     if not args.no_adjoint:
         line["adjoint"] = adjoint_measurement(max(2, args.steps // 2), not args.no_cpu_baseline)
-    line["diagnostics"] = diagnostics_measurement(args.steps, outs, img, not args.no_cpu_baseline)
-    line["parameter_scan"] = scan_measurement(max(2, args.steps // 2), not args.no_cpu_baseline)
+    if not args.no_diagnostics:
+        line["diagnostics"] = diagnostics_measurement(args.steps, outs, img, not args.no_cpu_baseline)
+    if not args.no_scan:
+        line["parameter_scan"] = scan_measurement(max(2, args.steps // 2), not args.no_cpu_baseline)
     if not args.no_shadow:
         line["shadow_boundary"] = shadow_measurement(max(2, args.steps // 4), not args.no_cpu_baseline)
     if args.calibration_copy_mib > 0:
