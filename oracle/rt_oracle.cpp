@@ -819,6 +819,136 @@ void trace_ray(const OrcParams& p, const Phys<T>& q, const ImageSetup& S, double
     if (tout) *tout = rt;
 }
 
+// ------------------------------------- Sec. 5.1-5.2: thick-disc emission
+// Parameters of the volumetric emissivity eq. (84) beyond those of the image:
+// the radial scale R_s and the height H(rho) = H_0 + h rho (eq. (85)).
+struct ThickParams {
+    double r_scale, h0, h_slope;
+};
+
+// j(R, theta) of eq. (84) with j_0 = 1: rho = R sin(theta), z = R cos(theta),
+// the tanh tapers of eqs. (85)-(86) (hard edges R_in <= rho <= R_out when a
+// width is not positive).
+double thick_emissivity(const OrcParams& p, const ThickParams& t, double r_in, double R, double th) {
+    const double rho = R * std::sin(th), z = R * std::cos(th);
+    if (!(rho > 0.0)) return 0.0;
+    double w;
+    if (p.sigma_in > 0.0 && p.sigma_out > 0.0)
+        w = 0.5 * (1.0 + std::tanh((rho - r_in) / p.sigma_in)) *
+            (0.5 * (1.0 - std::tanh((rho - p.r_out) / p.sigma_out)));
+    else
+        w = (rho >= r_in && rho <= p.r_out) ? 1.0 : 0.0;
+    if (w == 0.0) return 0.0;
+    const double H = t.h0 + t.h_slope * rho;
+    return std::pow(rho / r_in, -p.emis_pow) * std::exp(-(rho - r_in) / t.r_scale) *
+           std::exp(-z * z / (2.0 * H * H)) * w;
+}
+
+// Redshift of eq. (89) for an emitter at (R, theta) moving with the circular
+// equatorial angular velocity of eq. (91) at the same R, u^T from u.u = -1
+// with the metric at (R, theta); 0 where that has no solution.
+double thick_redshift(const OrcParams& p, const Phys<double>& q, double R, double th, double E,
+                      double L, double obs_energy) {
+    const Radial<double> r = radial(p, q, R);
+    const double chi = q.chi, chi2 = chi * chi;
+    const double dFoR2 = r.dF / (R * R) - 2.0 * r.F / (R * R * R);
+    const double dgTT = dFoR2, dgTph = -chi * dFoR2, dgphph = 2.0 * R + chi2 * dFoR2;
+    const double disc = dgTph * dgTph - dgTT * dgphph;
+    if (!(disc >= 0.0)) return 0.0;
+    const double Om = (-dgTph + std::sqrt(disc)) / dgphph;
+    const Metric<double> m = metric(p, q, R, th);
+    const double A = -(m.g_TT + 2.0 * Om * m.g_Tph + Om * Om * m.g_phph);
+    if (!(A > 0.0)) return 0.0;
+    const double em_energy = (E - Om * L) / std::sqrt(A);
+    if (!(em_energy > 0.0)) return 0.0;
+    return obs_energy / em_energy;
+}
+
+// dI/dlambda = g^3 j at state y (eq. (88)).
+double thick_source(const OrcParams& p, const Phys<double>& q, const ThickParams& t, double r_in,
+                    double E, double L, double obs_energy, const double y[6]) {
+    const double j = thick_emissivity(p, t, r_in, y[1], y[2]);
+    if (j == 0.0) return 0.0;
+    const double g = thick_redshift(p, q, y[1], y[2], E, L, obs_energy);
+    return g * g * g * j;
+}
+
+// One ray of the thick disc: the Dormand-Prince 5(4) integration of the
+// geodesic with the intensity I as a seventh component (dI/dlambda = g^3 j,
+// which does not feed back), the RMS error norm taken over all seven
+// components; otherwise the controller and stops of trace_ray.
+void trace_ray_thick(const OrcParams& p, const ThickParams& t, const ImageSetup& S, double X,
+                     double Y, int32_t* status, int32_t* attempts, double* intensity) {
+    const Phys<double> q = phys_of(p);
+    const Observer<double> obs = observer(p, q);
+    double p_up[4], p_dn[4];
+    initial_momentum(obs, p.r_obs, X, Y, p_up, p_dn);
+    const double E = -p_dn[0], L = p_dn[3];
+    const double obs_energy = -(p_dn[0] * obs.u[0] + p_dn[3] * obs.u[3]);
+    const double r_in = S.r_in;
+    double y[7] = {0.0, p.r_obs, q.incl, 0.0, p_dn[1], p_dn[2], 0.0};
+    auto f = [&](const double* yy, double* d) {
+        rhs(p, q, E, L, yy, d);
+        d[6] = thick_source(p, q, t, r_in, E, L, obs_energy, yy);
+    };
+    double k[7][7];
+    f(y, k[0]);
+    double h = p.h0;
+    bool after_reject = false;
+    int32_t att = 0, st = RUNNING;
+    const double A[6][5] = {{0, 0, 0, 0, 0}, {A21, 0, 0, 0, 0}, {A31, A32, 0, 0, 0},
+                            {A41, A42, A43, 0, 0}, {A51, A52, A53, A54, 0},
+                            {A61, A62, A63, A64, A65}};
+    const double Bw[7] = {B1, 0.0, B3, B4, B5, B6, 0.0};
+    const double Ew[7] = {B1 - BH1, 0.0, B3 - BH3, B4 - BH4, B5 - BH5, B6 - BH6, 0.0 - BH7};
+    for (;;) {
+        if (att >= p.max_attempts) { st = STEP_LIMIT; break; }
+        ++att;
+        double tmp[7], yn[7];
+        for (int j = 1; j < 6; ++j) {
+            for (int i = 0; i < 7; ++i) {
+                double sum = 0.0;
+                for (int l = 0; l < j; ++l) sum += A[j][l] * k[l][i];
+                tmp[i] = y[i] + h * sum;
+            }
+            f(tmp, k[j]);
+        }
+        for (int i = 0; i < 7; ++i) {
+            double sum = 0.0;
+            for (int l = 0; l < 7; ++l) sum += Bw[l] * k[l][i];
+            yn[i] = y[i] + h * sum;
+        }
+        f(yn, k[6]);
+        double acc = 0.0;
+        for (int i = 0; i < 7; ++i) {
+            double e = 0.0;
+            for (int l = 0; l < 7; ++l) e += Ew[l] * k[l][i];
+            const double sc = p.atol + p.rtol * std::fmax(std::fabs(y[i]), std::fabs(yn[i]));
+            const double qq = h * e / sc;
+            acc += qq * qq;
+        }
+        const double err = std::sqrt(acc / 7.0);
+        if (!(err < 1.0)) {
+            h *= std::isfinite(err) ? std::fmax(0.2, 0.9 * std::pow(err, -0.2)) : 0.2;
+            after_reject = true;
+            continue;
+        }
+        double factor = err == 0.0 ? 10.0 : std::fmin(10.0, 0.9 * std::pow(err, -0.2));
+        if (after_reject) factor = std::fmin(1.0, factor);
+        after_reject = false;
+        for (int i = 0; i < 7; ++i) {
+            y[i] = yn[i];
+            k[0][i] = k[6][i];
+        }
+        h *= factor;
+        if (y[1] <= S.r_stop) { st = CAPTURED; break; }
+        if (y[1] >= S.r_esc) { st = ESCAPED; break; }
+    }
+    *status = st;
+    *attempts = att;
+    *intensity = y[6];
+}
+
 void pixel_centre(const OrcParams& p, int64_t idx, double* X, double* Y) {
     const int64_t ix = idx % p.nx, iy = idx / p.nx;
     *X = p.x_min + (static_cast<double>(ix) + 0.5) * ((p.x_max - p.x_min) / p.nx);
@@ -967,6 +1097,26 @@ int orc_replay_pixels(const OrcParams* base, const OrcParams* pert, const int64_
 }
 
 // Image setup summary: out = {R_+, r_stop, r_esc, r_in}.
+// Thick-disc intensity of the pixels idx[0..n) (Sec. 5.1-5.2); thick =
+// {R_s, H_0, h}.  Any output pointer may be null.
+int orc_trace_thick_pixels(const OrcParams* p, const double* thick, const int64_t* idx, int64_t n,
+                           int32_t* status, int32_t* attempts, double* intensity) {
+    ImageSetup S;
+    if (!image_setup(*p, &S)) return -2;
+    const ThickParams t{thick[0], thick[1], thick[2]};
+    for (int64_t k = 0; k < n; ++k) {
+        double X, Y;
+        pixel_centre(*p, idx[k], &X, &Y);
+        int32_t st, att;
+        double I;
+        trace_ray_thick(*p, t, S, X, Y, &st, &att, &I);
+        if (status) status[k] = st;
+        if (attempts) attempts[k] = att;
+        if (intensity) intensity[k] = I;
+    }
+    return 0;
+}
+
 int orc_image_setup(const OrcParams* p, double* out) {
     ImageSetup S;
     if (!image_setup(*p, &S)) return -2;
