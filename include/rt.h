@@ -150,6 +150,32 @@ int rt_transfer_maps(const rt_image_params *params, int32_t n_images, const rt_i
  * inner disc edge}.  `setup` is host memory.  Synchronous. */
 int rt_image_setup(const rt_image_params *params, double *setup);
 
+/* Thick-disc image (Sec. 5.1-5.2, eqs. (84)-(90)): every pixel's ray is
+ * traced as by rt_trace_image (binary64, params->precision RT_FP64) with the
+ * observed intensity I = int g^3 j dlambda integrated along it as a seventh
+ * Dormand-Prince component in the same error norm (so the steps also resolve
+ * the emitting layer).  j(R, theta) = (rho/R_in)^-p exp(-(rho - R_in)/R_s)
+ * exp(-z^2 / (2 H^2)) T(rho) with j_0 = 1, rho = R sin(theta),
+ * z = R cos(theta), H = h0 + h_slope rho, p = params->emis_pow, R_in as
+ * params->r_in (<= 0: R_+), T the tapers of eqs. (85)-(86) with
+ * params->sigma_in/out (hard edges R_in <= rho <= r_out unless both > 0);
+ * the emitter moves with the circular equatorial angular velocity of eq. (91)
+ * at the same R, u^T from u.u = -1 with the metric at (R, theta); no emission
+ * where that has no solution.  Layers much thinner than the steps the
+ * geodesic needs can be stepped over (every stage misses them, the error
+ * estimate is zero): about 0.05 M at rtol = atol = 1e-8.
+ *   out->intensity required; ncross, status, attempts, r_em, phi_em, t_em as
+ *   for rt_transfer_maps, or NULL; g_em, intensity_n and reduce must be NULL.
+ * RT_ERR_ARG for a null/invalid thick (r_scale, h0 > 0, h_slope >= 0, finite),
+ * a missing intensity or a non-null g_em / intensity_n / reduce. */
+typedef struct rt_thick_disc {
+  double r_scale;        /* R_s of eq. (84), > 0                                       */
+  double h0;             /* H_0 of eq. (85), > 0                                       */
+  double h_slope;        /* h of eq. (85), >= 0                                        */
+} rt_thick_disc;
+int rt_trace_thick(const rt_image_params *params, const rt_thick_disc *thick,
+                   const rt_image_out *out, void *hip_stream);
+
 /* Parameter scans of the spacetimes (Sec. 2), one point per entry:
  *   points device [n] rt_scan_point (metric and halo as in rt_image_params,
  *          spin chi, theta the polar angle of the ergosurface radius)

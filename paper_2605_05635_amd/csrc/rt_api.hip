@@ -951,6 +951,55 @@ int rt_transfer_maps(const rt_image_params* params, int32_t n_images, const rt_i
     return trace_common(params, n_images, out, hip_stream, false);
 }
 
+int rt_trace_thick(const rt_image_params* params, const rt_thick_disc* thick,
+                   const rt_image_out* out, void* hip_stream) {
+    g_last_error.clear();
+    if (!params || !thick || !out) return fail(RT_ERR_ARG, "null params, thick or out");
+    if (!finite_all({thick->r_scale, thick->h0, thick->h_slope}) || !(thick->r_scale > 0.0) ||
+        !(thick->h0 > 0.0) || !(thick->h_slope >= 0.0))
+        return fail(RT_ERR_ARG, "thick disc needs finite r_scale > 0, h0 > 0, h_slope >= 0");
+    if (!out->intensity) return fail(RT_ERR_ARG, "the thick disc needs out->intensity");
+    if (out->g_em || out->intensity_n || out->reduce)
+        return fail(RT_ERR_ARG, "g_em, intensity_n and reduce are not produced by the thick disc");
+    if (params->precision != RT_FP64)
+        return fail(RT_ERR_ARG, "the thick disc is traced in binary64 (precision RT_FP64)");
+    rt::ImageConst c;
+    int rc = setup_image(params, 0, true, &c, nullptr);
+    if (rc != RT_OK) return rc;
+    c.thick_rs = thick->r_scale;
+    c.thick_h0 = thick->h0;
+    c.thick_h = thick->h_slope;
+    const rt_image_out& o = *out;
+    if ((rc = check_device_ptr(o.ncross, "ncross", 0)) || (rc = check_device_ptr(o.status, "status", 0)) ||
+        (rc = check_device_ptr(o.r_em, "r_em", 0)) || (rc = check_device_ptr(o.phi_em, "phi_em", 0)) ||
+        (rc = check_device_ptr(o.t_em, "t_em", 0)) || (rc = check_device_ptr(o.intensity, "intensity", 0)) ||
+        (rc = check_device_ptr(o.attempts, "attempts", 0)))
+        return rc;
+    const rt::OutPtrs optrs{o.ncross, o.status, o.r_em, o.phi_em, o.t_em, nullptr, o.intensity,
+                            nullptr, o.attempts};
+    DeviceInfo info;
+    if ((rc = device_info(&info)) != RT_OK) return rc;
+    rt::LaunchShape sh;
+    if ((rc = image_shape(c, &sh)) != RT_OK) return rc;
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    void* q = nullptr;
+    hipError_t e = hipMallocAsync(&q, 256, stream);
+    if (e != hipSuccess || !q) {
+        (void)hipGetLastError();
+        return fail(RT_ERR_ALLOC, "stream-ordered allocation of the work queue failed");
+    }
+    auto* queue = static_cast<unsigned long long*>(q);
+    const int64_t want = (c.n_pix + 255) / 256;
+    const int64_t resident = static_cast<int64_t>(info.cus) * rt::thick_blocks_per_cu(c.metric);
+    const int32_t grid = static_cast<int32_t>(std::max<int64_t>(1, std::min(want, resident)));
+    e = rt::launch_zero(queue, 1, stream);
+    if (e == hipSuccess) e = rt::launch_trace_thick(c, optrs, queue, sh, grid, stream);
+    const hipError_t ef = hipFreeAsync(q, stream);
+    if (e != hipSuccess) return hip_fail(e, "thick-disc kernel launch");
+    if (ef != hipSuccess) return hip_fail(ef, "hipFreeAsync");
+    return RT_OK;
+}
+
 int rt_parameter_scan(const rt_scan_point* points, int32_t n, double* out, void* hip_stream) {
     g_last_error.clear();
     if (!points || !out) return fail(RT_ERR_ARG, "null points or out");

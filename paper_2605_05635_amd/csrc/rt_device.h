@@ -57,6 +57,8 @@ struct ImageConst {
     // lies in [-eta, 0), never needs expm1's argument reduction, and the
     // kernels run their CNFW_NEAR variant
     int32_t ex_near;
+    // thick disc (Sec. 5.1): radial scale R_s and height H = H_0 + h rho of eqs. (84)-(85)
+    double thick_rs, thick_h0, thick_h;
 };
 
 // e^x - 1 of the cored-NFW exponent: in binary64 and binary32 without the

@@ -65,6 +65,12 @@ hipError_t launch_emission(const ImageConst& c, const OutPtrs& o, hipStream_t st
 hipError_t launch_emission_batch(const ImageConst* table, const OutPtrs* outs, int32_t n_images,
                                  int64_t max_pix, hipStream_t stream);
 
+// Thick-disc trace of one image (rt_trace_thick): as launch_trace, with
+// o.intensity the thick disc's intensity; *queue must be zero.
+int thick_blocks_per_cu(int metric);
+hipError_t launch_trace_thick(const ImageConst& c, const OutPtrs& o, unsigned long long* queue,
+                              const LaunchShape& shape, int32_t grid, hipStream_t stream);
+
 // Parameter scan (rt_parameter_scan): out[4i..4i+4) for pts[i].
 hipError_t launch_scan(const ::rt_scan_point* pts, int32_t n, double* out, hipStream_t stream);
 

@@ -29,6 +29,9 @@ struct Hot {
     double chi, chi2, inv_lam, lam_c, inv_lam_c, eta_lc;
     double rtol, atol, r_stop, r_esc;
     int32_t max_attempts;
+    // thick-disc source (read by the THICK attempts only)
+    int32_t taper;
+    double r_in, r_out, emis_pow, sigma_in, sigma_out, thick_rs, thick_h0, thick_h;
 };
 
 __host__ __device__ __forceinline__ Hot hot_of(const ImageConst& c) {
@@ -44,6 +47,15 @@ __host__ __device__ __forceinline__ Hot hot_of(const ImageConst& c) {
     k.r_stop = c.r_stop;
     k.r_esc = c.r_esc;
     k.max_attempts = c.max_attempts;
+    k.taper = c.taper;
+    k.r_in = c.r_in;
+    k.r_out = c.r_out;
+    k.emis_pow = c.emis_pow;
+    k.sigma_in = c.sigma_in;
+    k.sigma_out = c.sigma_out;
+    k.thick_rs = c.thick_rs;
+    k.thick_h0 = c.thick_h0;
+    k.thick_h = c.thick_h;
     return k;
 }
 
@@ -166,6 +178,7 @@ __host__ __device__ __forceinline__ S disc_window(const ImageConst& c, const S& 
 struct Ray {
     double y[6];    // T, R, theta, phi, p_R, p_theta
     double k1[6];   // f(y), first-same-as-last
+    double I, kI;   // thick disc: intensity so far and g^3 j at y (THICK attempts only)
     double E, L;
     double h, lam, last_cross;
     double rc[3];   // radii of the first three trusted crossings
@@ -295,6 +308,57 @@ __host__ __device__ __forceinline__ double crossing_root(const DenseComp& d, boo
     return s;
 }
 
+// dI/dlambda = g^3 j of the thick disc (Sec. 5.1-5.2) at (R, theta) for a
+// photon (E, l) of unit observer-frame energy: the emissivity eq. (84) with
+// j_0 = 1, rho = R sin(theta), z = R cos(theta), H = H_0 + h rho and the
+// window of the image (tapers of eqs. (85)-(86) or hard edges); the emitter
+// moves with the circular equatorial angular velocity of eq. (91) at the same
+// R, its u^T from u.u = -1 with the metric at (R, theta) (eqs. (89)-(90)); no
+// emission where that has no solution.
+template <int METRIC>
+__host__ __device__ inline double thick_source(const Hot& k, double R, double th, double E, double L) {
+    double s, co;
+    dm::sincos(th, &s, &co);
+    const double rho = R * s, z = R * co;
+    if (!(rho > 0.0)) return 0.0;
+    double w;
+    if (k.taper)
+        w = 0.5 * (1.0 + tanh((rho - k.r_in) / k.sigma_in)) *
+            (0.5 * (1.0 - tanh((rho - k.r_out) / k.sigma_out)));
+    else
+        w = (rho >= k.r_in && rho <= k.r_out) ? 1.0 : 0.0;
+    if (w == 0.0) return 0.0;
+    const double H = k.thick_h0 + k.thick_h * rho;
+    const double j = pow(rho / k.r_in, -k.emis_pow) * exp(-(rho - k.r_in) / k.thick_rs) *
+                     exp(-z * z / (2.0 * H * H)) * w;
+    double F, dF;
+    mass_function<METRIC>(k, R, F, dF);
+    const double G = (dF - 2.0 * F / R) / (R * R);   // d(F/R^2)/dR
+    const double disc = -2.0 * R * G;
+    if (!(disc >= 0.0)) return 0.0;
+    const double Om = (k.chi * G + sqrt(disc)) / (2.0 * R + k.chi2 * G);
+    const double Sig = R * R + k.chi2 * co * co;
+    const double s2 = s * s;
+    const double gTT = -(1.0 - F / Sig);
+    const double gTph = -F * k.chi * s2 / Sig;
+    const double gphph = (R * R + k.chi2 + F * k.chi2 * s2 / Sig) * s2;
+    const double A = -(gTT + 2.0 * Om * gTph + Om * Om * gphph);
+    if (!(A > 0.0)) return 0.0;
+    const double den = E - Om * L;
+    if (!(den > 0.0)) return 0.0;
+    const double g = sqrt(A) / den;
+    return g * g * g * j;
+}
+
+// A thick-disc ray: as start_ray, with I = 0 and its source at the start.
+template <int METRIC>
+__host__ __device__ __forceinline__ void start_ray_thick(const ImageConst& c, const Hot& k, int64_t pix,
+                                                         Ray& r) {
+    start_ray<METRIC>(c, k, pix, r);
+    r.I = 0.0;
+    r.kI = thick_source<METRIC>(k, r.y[1], r.y[2], r.E, r.L);
+}
+
 // One step attempt.  Returns 0 while the ray runs, else its final status.
 // The 5th-order update, the error estimate and the continuous-extension
 // coefficient r5 are accumulated as the stages are produced, so a stage
@@ -306,7 +370,9 @@ struct StageNone {
     __host__ __device__ __forceinline__ void operator()(int, const double*) const {}
 };
 
-template <int METRIC, class Sink = StageNone>
+// THICK: the thick disc's intensity as a seventh component (dI/dlambda =
+// thick_source, no feedback), in the error norm with the other six.
+template <int METRIC, class Sink = StageNone, bool THICK = false>
 __host__ __device__ __forceinline__ int32_t attempt(const Hot& k, const OutPtrs& o, int64_t n_pix,
                                                     Ray& r, Sink sink = Sink{}) {
     if (r.attempts >= k.max_attempts) return RAY_STEP_LIMIT;
@@ -319,6 +385,19 @@ __host__ __device__ __forceinline__ int32_t attempt(const Hot& k, const OutPtrs&
         ab[i] = b1 * r.k1[i];
         ae[i] = e1 * r.k1[i];
         ad[i] = d1 * r.k1[i];
+    }
+    double abI = 0.0, aeI = 0.0;   // THICK: sums of b_i kI_i, e_i kI_i
+    if constexpr (THICK) {
+        abI = b1 * r.kI;
+        aeI = e1 * r.kI;
+    }
+// THICK: the source at the current stage input t (b_2 = e_2 = 0: stage 2
+// needs none)
+#define RT_ACC_I(bb, ee)                                                         \
+    if constexpr (THICK) {                                                       \
+        const double kI_ = thick_source<METRIC>(k, t[1], t[2], r.E, r.L);        \
+        abI += bb * kI_;                                                         \
+        aeI += ee * kI_;                                                         \
     }
 #define RT_STAGE(expr, out)                                                      \
     for (int i = 0; i < 6; ++i) t[i] = r.y[i] + h * (expr);                       \
@@ -334,17 +413,22 @@ __host__ __device__ __forceinline__ int32_t attempt(const Hot& k, const OutPtrs&
     RT_STAGE(a31 * r.k1[i] + a32 * k2[i], k3)
     sink(2, k3);
     RT_ACC(b3, e3, d3, k3)
+    RT_ACC_I(b3, e3)
     RT_STAGE(a41 * r.k1[i] + a42 * k2[i] + a43 * k3[i], k4)
     sink(3, k4);
     RT_ACC(b4, e4, d4, k4)
+    RT_ACC_I(b4, e4)
     RT_STAGE(a51 * r.k1[i] + a52 * k2[i] + a53 * k3[i] + a54 * k4[i], k5)
     sink(4, k5);
     RT_ACC(b5, e5, d5, k5)
+    RT_ACC_I(b5, e5)
     RT_STAGE(a61 * r.k1[i] + a62 * k2[i] + a63 * k3[i] + a64 * k4[i] + a65 * k5[i], kk)
     sink(5, kk);
     RT_ACC(b6, e6, d6, kk)
+    RT_ACC_I(b6, e6)
 #undef RT_STAGE
 #undef RT_ACC
+#undef RT_ACC_I
     double yn[6];
     for (int i = 0; i < 6; ++i) yn[i] = r.y[i] + h * ab[i];
     rhs<METRIC>(k, r.E, r.L, yn[1], yn[2], yn[4], yn[5], kk);   // k7 (first-same-as-last)
@@ -356,11 +440,20 @@ __host__ __device__ __forceinline__ int32_t attempt(const Hot& k, const OutPtrs&
         const double q = h * ae[i] * rcp(sc);
         acc += q * q;
     }
+    double ynI = 0.0, kI7 = 0.0;
+    if constexpr (THICK) {
+        kI7 = thick_source<METRIC>(k, yn[1], yn[2], r.E, r.L);
+        aeI += e7 * kI7;
+        ynI = r.I + h * abI;
+        const double sc = k.atol + k.rtol * fmax(fabs(r.I), fabs(ynI));
+        const double q = h * aeI * rcp(sc);
+        acc += q * q;
+    }
     // err^2 = mean of the squared scaled errors; the step is accepted when
     // err < 1 and the size factor is 0.9 err^(-1/5) = 0.9 (err^2)^(-1/10),
     // clipped to [0.2, 10] (err = 0 gives the maximum, a non-finite err the
     // minimum).  Outside err^2 in [1e-12, 1e12] the clip decides the factor.
-    const double err2 = acc * (1.0 / 6.0);
+    const double err2 = acc * (THICK ? 1.0 / 7.0 : 1.0 / 6.0);
     const double grow = 0.9 * dm::rpow_tenth(fmin(fmax(err2, 1e-12), 1e12));
     if (!(err2 < 1.0)) {  // reject; NaN lands here too
         r.h = h * (__builtin_isfinite(err2) ? fmax(0.2, grow) : 0.2);
@@ -410,6 +503,10 @@ __host__ __device__ __forceinline__ int32_t attempt(const Hot& k, const OutPtrs&
     for (int i = 0; i < 6; ++i) {
         r.y[i] = yn[i];
         r.k1[i] = kk[i];
+    }
+    if constexpr (THICK) {
+        r.I = ynI;
+        r.kI = kI7;
     }
     r.lam += h;
     r.h = h * factor;

@@ -56,6 +56,10 @@ class rt_launch_config(C.Structure):
                 ("blocks_per_cu", C.c_int32), ("order", C.c_int32)]
 
 
+class rt_thick_disc(C.Structure):
+    _fields_ = [("r_scale", C.c_double), ("h0", C.c_double), ("h_slope", C.c_double)]
+
+
 class rt_scan_point(C.Structure):
     _fields_ = [("metric", C.c_int32), ("reserved", C.c_int32), ("spin", C.c_double),
                 ("halo", C.c_double * 2), ("theta", C.c_double)]
@@ -83,6 +87,8 @@ def _load():
     lib.rt_visibility_dft.argtypes = [C.c_void_p, C.POINTER(rt_image_params), C.c_void_p,
                                       C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]
     lib.rt_visibility_dft.restype = C.c_int
+    lib.rt_trace_thick.argtypes = [P, C.POINTER(rt_thick_disc), O, C.c_void_p]
+    lib.rt_trace_thick.restype = C.c_int
     lib.rt_parameter_scan.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]
     lib.rt_parameter_scan.restype = C.c_int
     lib.rt_image_diagnostics.argtypes = [C.c_void_p, P, C.c_double, C.c_int32, C.c_void_p,
@@ -214,6 +220,24 @@ def visibility(img: dict, intensity, uv, stream=None):
     amp = torch.empty(uv_t.shape[0], dtype=torch.float64, device=intensity.device)
     rt_visibility_dft(intensity.contiguous(), params_from(img), uv_t, amp=amp, stream=stream)
     return amp
+
+
+def rt_trace_thick(params: rt_image_params, thick: rt_thick_disc, out: rt_image_out,
+                   stream=None) -> None:
+    """Calls rt_trace_thick (one image)."""
+    _check(_lib.rt_trace_thick(C.byref(params), C.byref(thick), C.byref(out),
+                               _stream_handle(stream)))
+
+
+def trace_thick(img: dict, r_scale: float, h0: float, h_slope: float, stream=None) -> dict:
+    """The thick-disc image of img (Sec. 5.1-5.2): device tensors intensity,
+    status, attempts, ncross and the transfer maps."""
+    outs = alloc_outputs(img, reduce=False)
+    for k in ("g_em", "intensity_n", "reduce"):
+        outs.pop(k, None)
+    o = out_from(outs)
+    rt_trace_thick(params_from(img), rt_thick_disc(r_scale, h0, h_slope), o, stream)
+    return outs
 
 
 def rt_parameter_scan(points, out, stream=None) -> None:
@@ -411,6 +435,7 @@ __all__ = ["rt_mixed_stats", "rt_image_vjp", "rt_set_tape_budget", "rt_vjp_stats
            "rt_set_launch_config", "rt_get_launch_config", "rt_visibility_dft", "visibility",
            "rt_shadow_boundary", "shadow_boundary", "rt_image_diagnostics", "image_diagnostics",
            "rt_parameter_scan", "parameter_scan", "rt_scan_point",
+           "rt_trace_thick", "trace_thick", "rt_thick_disc",
            "RT_DIAG_COUNT", "DIAG_KEYS",
            "rt_version",
            "rt_last_error", "trace", "trace_many", "params_from", "out_from", "alloc_outputs",

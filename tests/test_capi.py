@@ -248,3 +248,24 @@ def test_scan_point_layout_and_argument_errors(rt, tmp_path):
     assert lib.rt_parameter_scan(d, 4, None, None) == rt.RT_ERR_ARG
     assert lib.rt_parameter_scan(d, 0, d, None) == rt.RT_ERR_ARG
     assert lib.rt_parameter_scan(d, (1 << 24) + 1, d, None) == rt.RT_ERR_ARG
+
+
+def test_thick_disc_argument_errors(rt):
+    lib = rt.lib()
+    p = rt.params_from(W.kerr_small())
+    d = C.c_void_p(8)
+    good = rt.rt_thick_disc(8.0, 0.2, 0.1)
+    o = rt.rt_image_out()
+    o.intensity = 8
+    assert lib.rt_trace_thick(None, C.byref(good), C.byref(o), None) == rt.RT_ERR_ARG
+    assert lib.rt_trace_thick(C.byref(p), None, C.byref(o), None) == rt.RT_ERR_ARG
+    for bad in (rt.rt_thick_disc(0.0, 0.2, 0.1), rt.rt_thick_disc(8.0, 0.0, 0.1),
+                rt.rt_thick_disc(8.0, 0.2, -0.1), rt.rt_thick_disc(float("nan"), 0.2, 0.1)):
+        assert lib.rt_trace_thick(C.byref(p), C.byref(bad), C.byref(o), None) == rt.RT_ERR_ARG
+    none = rt.rt_image_out()
+    assert lib.rt_trace_thick(C.byref(p), C.byref(good), C.byref(none), None) == rt.RT_ERR_ARG
+    o2 = rt.rt_image_out()
+    o2.intensity, o2.g_em = 8, 8
+    assert lib.rt_trace_thick(C.byref(p), C.byref(good), C.byref(o2), None) == rt.RT_ERR_ARG
+    mixed = rt.params_from(W.image(precision="mixed"))
+    assert lib.rt_trace_thick(C.byref(mixed), C.byref(good), C.byref(o), None) == rt.RT_ERR_ARG
