@@ -295,6 +295,48 @@ def diagnostics_measurement(steps: int, outs: dict, img: dict, cpu: bool) -> dic
     return res
 
 
+def thick_measurement(steps: int, cpu: bool) -> dict:
+    """Thick-disc image (Sec. 5.1-5.2) of the 1024x1024 cored-NFW screen with
+    (R_s, H_0, h) = (8, 0.2, 0.1), p = 2: kernel time per image (HIP events on
+    the stream) against the thin-disc trace of the same screen."""
+    import torch
+
+    from paper_2605_05635_amd import rt, workloads as W
+    img = dict(W.cnfw_1024(), emis_pow=2.0)
+    thick = rt.rt_thick_disc(8.0, 0.2, 0.1)
+    outs = rt.alloc_outputs(img, reduce=False)
+    for k in ("g_em", "intensity_n"):
+        outs.pop(k)
+    o = rt.out_from(outs)
+    p = rt.params_from(img)
+    stream = torch.cuda.current_stream()
+    rt.rt_trace_thick(p, thick, o, stream)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(steps):
+        rt.rt_trace_thick(p, thick, o, stream)
+    b.record(stream)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / steps
+    n = img["nx"] * img["ny"]
+    att = outs["attempts"].double().mean().item()
+    log(f"thick disc: {ms:.2f} ms per image, {att:.1f} attempts per ray")
+    res = {"workload": "cored-NFW 1024x1024 screen, thick disc (R_s, H_0, h) = (8, 0.2, 0.1), p = 2",
+           "ms": ms, "rays_per_s": n / ms * 1e3, "steps": steps, "attempts_per_ray": att,
+           "flux_sum": float(outs["intensity"].sum().item())}
+    if cpu:
+        from oracle import oracle as O
+        idx = W.subsample_indices(img["nx"], img["ny"], 16)
+        threads = max(1, min(16, os.cpu_count() or 1))
+        t0 = time.perf_counter()
+        O.trace_thick_pixels(img, (8.0, 0.2, 0.1), idx, threads=threads)
+        dt = time.perf_counter() - t0
+        res["cpu_oracle"] = {"rays_per_s": len(idx) / dt, "cores": threads, "kind": "oracle",
+                             "sample": f"every 16th pixel in x and y ({len(idx)} rays, {dt:.1f} s)"}
+    return res
+
+
 def scan_measurement(steps: int, cpu: bool) -> dict:
     """Parameter scan (Sec. 2) over a 64 x 64 grid of cored-NFW points, chi in
     [0, 1.05] x eta in [0, 0.3] at lambda_c = 10, theta = 60 deg: wall time of
@@ -407,6 +449,8 @@ def main() -> int:
                     help="skip the 64-image batched trace + visibility measurement")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the mixed-precision measurement")
+    ap.add_argument("--no-thick", action="store_true",
+                    help="skip the thick-disc measurement")
     ap.add_argument("--no-scan", action="store_true",
                     help="skip the parameter-scan measurement")
     ap.add_argument("--no-diagnostics", action="store_true",
@@ -499,6 +543,8 @@ def main() -> int:
         line["adjoint"] = adjoint_measurement(max(2, args.steps // 2), not args.no_cpu_baseline)
     if not args.no_diagnostics:
         line["diagnostics"] = diagnostics_measurement(args.steps, outs, img, not args.no_cpu_baseline)
+    if not args.no_thick:
+        line["thick_disc"] = thick_measurement(max(2, args.steps // 2), not args.no_cpu_baseline)
     if not args.no_scan:
         line["parameter_scan"] = scan_measurement(max(2, args.steps // 2), not args.no_cpu_baseline)
     if not args.no_shadow:
