@@ -322,15 +322,20 @@ __host__ __device__ inline double thick_source(const Hot& k, double R, double th
     const double rho = R * s, z = R * co;
     if (!(rho > 0.0)) return 0.0;
     double w;
-    if (k.taper)
-        w = 0.5 * (1.0 + tanh((rho - k.r_in) / k.sigma_in)) *
-            (0.5 * (1.0 - tanh((rho - k.r_out) / k.sigma_out)));
-    else
+    if (k.taper) {
+        // (1 + tanh u)/2 = 1/(1 + e^{-2u}), (1 - tanh u)/2 = 1/(1 + e^{2u}); a
+        // division, which gives 0 for an infinite e^{...} far outside the edges
+        w = (1.0 / (1.0 + dm::exp(-2.0 * (rho - k.r_in) / k.sigma_in))) *
+            (1.0 / (1.0 + dm::exp(2.0 * (rho - k.r_out) / k.sigma_out)));
+    } else {
         w = (rho >= k.r_in && rho <= k.r_out) ? 1.0 : 0.0;
+    }
     if (w == 0.0) return 0.0;
     const double H = k.thick_h0 + k.thick_h * rho;
-    const double j = pow(rho / k.r_in, -k.emis_pow) * exp(-(rho - k.r_in) / k.thick_rs) *
-                     exp(-z * z / (2.0 * H * H)) * w;
+    // the three factors of eq. (84) as one exponential
+    const double j = dm::exp(-k.emis_pow * dm::log1p(rho / k.r_in - 1.0) - (rho - k.r_in) / k.thick_rs -
+                             z * z / (2.0 * H * H)) *
+                     w;
     double F, dF;
     mass_function<METRIC>(k, R, F, dF);
     const double G = (dF - 2.0 * F / R) / (R * R);   // d(F/R^2)/dR
