@@ -408,8 +408,8 @@ def shadow_measurement(steps: int, cpu: bool) -> dict:
     torch.cuda.synchronize()
     ms = a.elapsed_time(b) / steps
     bc = out.mean(dim=1).cpu().numpy()
-    rounds = int(np.ceil(np.log((b_hi - b_lo) / b_tol) / np.log(65.0)))
-    rays = n * 64 * rounds + 2 * n
+    passes = int(np.ceil(np.log((b_hi - b_lo) / b_tol) / np.log(65.0)))
+    rays = n * 64 * passes + 2 * n
     attempts = float(att.sum().item())
     from paper_2605_05635_amd import census
     # algorithmic flops as for the trace kernel, without the crossings (not counted)
@@ -420,7 +420,7 @@ def shadow_measurement(steps: int, cpu: bool) -> dict:
     res = {"workload": "cored-NFW benchmark spacetime, 4096 directions, b in [2, 9], "
                        "bracket 1e-10 (64-point multisection)",
            "ms": ms, "directions_per_s": n / ms * 1e3, "steps": steps,
-           "rounds": rounds, "rays_traced": rays, "attempts_per_ray": attempts / rays,
+           "passes": passes, "rays_traced": rays, "attempts_per_ray": attempts / rays,
            "algorithmic_tflops": tflops, "frac_of_fp64_vector_peak": tflops / FP64_VECTOR_PEAK_TFLOPS,
            "all_found": bool((st == 0).all().item()),
            "b_mean": float(bc.mean()), "b_min": float(bc.min()), "b_max": float(bc.max())}

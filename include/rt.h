@@ -227,10 +227,10 @@ int rt_image_diagnostics(const double *intensity, const rt_image_params *params,
  * X = b cos psi, Y = b sin psi turn from captured to escaping (a ray escapes
  * when it reaches r_esc_fac R_o; captured rays and rays ending otherwise count
  * as inside).  Multisection: the bracket [lo, hi] starts at [b_lo, b_hi];
- * each round traces 64 rays at b_j = lo + j w, w = (hi - lo)/65, j = 1..64,
+ * each pass traces 64 rays at b_j = lo + j w, w = (hi - lo)/65, j = 1..64,
  * and keeps [b_{j-1}, b_j] around the first escaping sample (b_0 = lo), or
- * [b_64, hi] if none escapes, while hi - lo > b_tol (at most 64 rounds, and
- * none once a round leaves the bracket unchanged).  Rays are traced as by
+ * [b_64, hi] if none escapes, while hi - lo > b_tol (at most 64 passes, and
+ * none once a pass leaves the bracket unchanged).  Rays are traced as by
  * rt_trace_image in binary64 (params->precision must be RT_FP64; the screen
  * fields are validated but not used).
  *   dirs    device [n][2] (cos psi, sin psi); any length, the ray starts from

@@ -360,17 +360,17 @@ def visibility_amplitude(img: dict, intensity: np.ndarray, uv: np.ndarray) -> np
 
 
 def shadow_boundary(img: dict, dirs, b_lo: float, b_hi: float, b_tol: float,
-                    samples: int = 64, max_rounds: int = 64, threads: int | None = None):
+                    samples: int = 64, max_passes: int = 64, threads: int | None = None):
     """Shadow boundary (Sec. 4.1, eqs. (78)-(79)): along each screen direction
     (cos psi, sin psi) of `dirs` ([n, 2]), the impact parameter b at which the
     rays from X = b cos psi, Y = b sin psi turn from captured to escaping.
 
     The search is the multisection the GPU path runs (one sample per lane of
     a 64-lane wavefront): the bracket [lo, hi] starts at [b_lo, b_hi]; each
-    round traces `samples` rays at b_j = lo + j w, w = (hi - lo)/(samples + 1),
+    pass traces `samples` rays at b_j = lo + j w, w = (hi - lo)/(samples + 1),
     j = 1..samples, and keeps [b_{j-1}, b_j] around the first sample j whose ray
     escapes (b_0 = lo), or [b_samples, hi] if none does, while hi - lo > b_tol
-    (at most max_rounds rounds, and no further once a round leaves the bracket
+    (at most max_passes passes, and no further once a pass leaves the bracket
     unchanged).  A ray escapes when it ends at the escape radius (eq. (75));
     captured rays and rays ending otherwise count as inside.
     Returns (lo, hi, ok): ok is False where the ray at b_lo escapes or the one
@@ -390,7 +390,7 @@ def shadow_boundary(img: dict, dirs, b_lo: float, b_hi: float, b_tol: float,
         lo_out[i], hi_out[i] = lo, hi
         if escapes(ux, uy, lo) or not escapes(ux, uy, hi):
             return
-        for _ in range(max_rounds):
+        for _ in range(max_passes):
             if not hi - lo > b_tol:
                 break
             w = (hi - lo) / (samples + 1)

@@ -1,9 +1,9 @@
 // rt_boundary.hip -- gfx950 kernel of the shadow-boundary search (Sec. 4.1,
 // eqs. (78)-(79)): along a screen direction (cos psi, sin psi), the impact
 // parameter b at which the rays from X = b cos psi, Y = b sin psi turn from
-// captured to escaping.  One wavefront per direction; each round traces one
+// captured to escaping.  One wavefront per direction; each pass traces one
 // ray per lane at 64 points inside the bracket and keeps the interval around
-// the first escaping one, so the bracket shrinks 65-fold per round (7 rounds
+// the first escaping one, so the bracket shrinks 65-fold per pass (7 passes
 // from a width of 10 to 1e-12) instead of 2-fold per traced ray.
 #include "rt_ray.h"
 
@@ -12,8 +12,8 @@ namespace {
 
 using namespace ray;
 
-constexpr int kSamples = 64;     // rays per round: one per lane of a wavefront
-constexpr int kMaxRounds = 64;
+constexpr int kSamples = 64;     // rays per pass: one per lane of a wavefront
+constexpr int kMaxPasses = 64;
 
 // Register-allocated like the trace kernel (three waves per SIMD).
 template <int METRIC>
@@ -30,18 +30,18 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
     double lo = b_lo, hi = b_hi;
     int64_t used = 0;        // this lane's step attempts
     int32_t result = 1;      // bracket without the transition, until checked
-    // Round -1 checks the bracket (lane 0 at b_lo must stay inside, lane 1 at
-    // b_hi must escape); rounds 0, 1, ... sample b_j = lo + j w, j = lane + 1.
-    for (int round = -1;; ++round) {
+    // Pass -1 checks the bracket (lane 0 at b_lo must stay inside, lane 1 at
+    // b_hi must escape); passes 0, 1, ... sample b_j = lo + j w, j = lane + 1.
+    for (int pass = -1;; ++pass) {
         const double w = (hi - lo) / (kSamples + 1);
         double b;
-        if (round < 0) {
+        if (pass < 0) {
             b = lane == 0 ? b_lo : b_hi;
         } else {
             const double t = static_cast<double>(lane + 1) * w;   // no contraction
             b = lo + t;
         }
-        const bool live = round >= 0 || lane < 2;
+        const bool live = pass >= 0 || lane < 2;
         Ray r;
         bool active = live;
         int32_t st = 0;
@@ -54,7 +54,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
         }
         if (live) used += r.attempts;
         const unsigned long long esc = __ballot(live && st == RAY_ESCAPED);
-        if (round < 0) {
+        if (pass < 0) {
             if ((esc & 1ull) || !(esc & 2ull)) break;
             result = 0;
         } else {
@@ -73,7 +73,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
             lo = nlo;
             hi = nhi;
         }
-        if (round + 1 >= kMaxRounds || !(hi - lo > b_tol)) break;
+        if (pass + 1 >= kMaxPasses || !(hi - lo > b_tol)) break;
     }
     for (int off = 32; off > 0; off >>= 1) used += __shfl_xor(used, off);
     if (lane == 0) {

@@ -2,7 +2,7 @@
 on the GPU against the oracle's multisection of the same definition, and
 against the exact finite-distance Kerr critical curve.
 
-Tolerance.  Both sides run the same multisection (64 samples per round, the
+Tolerance.  Both sides run the same multisection (64 samples per pass, the
 same sample points) and differ only in the rounding of the traced rays, which
 can change the fate of a ray only within about 1e-14 of the transition.  Both
 final brackets hold the transition and are at most b_tol wide, so their
@@ -142,6 +142,6 @@ def test_attempt_counts_do_not_change_results(rt):
     rt.rt_shadow_boundary(p, d, 2.0, 9.0, TOL_B, out2, st2, att)
     torch.cuda.synchronize()
     assert torch.equal(out1, out2) and torch.equal(st1, st2)
-    rounds = math.ceil(math.log(7.0 / TOL_B) / math.log(65.0))
+    passes = math.ceil(math.log(7.0 / TOL_B) / math.log(65.0))
     # every traced ray takes at least a few dozen attempts from R_o = 1000
-    assert int(att.min()) >= (64 * rounds + 2) * 20
+    assert int(att.min()) >= (64 * passes + 2) * 20
