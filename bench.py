@@ -321,9 +321,18 @@ def thick_measurement(steps: int, cpu: bool) -> dict:
     ms = a.elapsed_time(b) / steps
     n = img["nx"] * img["ny"]
     att = outs["attempts"].double().mean().item()
-    log(f"thick disc: {ms:.2f} ms per image, {att:.1f} attempts per ray")
+    from paper_2605_05635_amd import census
+    # algorithmic flops: the trace's per attempt (crossings not counted) plus
+    # five source evaluations per attempt and one per ray start; seven error terms
+    m = img["metric"]
+    flops = n * (att * (6 * census.flops_rhs(m) + census.flops_step_overhead()
+                        + 5 * census.flops_thick_source(m) + 2 * 7)
+                 + 20 + census.flops_rhs(m) + census.flops_thick_source(m))
+    tflops = flops / (ms * 1e-3) / 1e12
+    log(f"thick disc: {ms:.2f} ms per image, {att:.1f} attempts per ray, {tflops:.1f} TFLOP/s")
     res = {"workload": "cored-NFW 1024x1024 screen, thick disc (R_s, H_0, h) = (8, 0.2, 0.1), p = 2",
            "ms": ms, "rays_per_s": n / ms * 1e3, "steps": steps, "attempts_per_ray": att,
+           "algorithmic_tflops": tflops, "frac_of_fp64_vector_peak": tflops / FP64_VECTOR_PEAK_TFLOPS,
            "flux_sum": float(outs["intensity"].sum().item())}
     if cpu:
         from oracle import oracle as O

@@ -157,6 +157,33 @@ def flops_emission(metric: str) -> int:
     return Num.ops
 
 
+def flops_thick_source(metric: str) -> int:
+    """One evaluation of the thick disc's source g^3 j at (R, theta) (Sec.
+    5.1-5.2): sine and cosine, the emissivity of eq. (84) with tapers, the
+    circular emitter's Omega (eq. (91)) at R and u^T from the metric at
+    (R, theta), g^3 times j."""
+    Num.ops = 0
+    c = _consts(metric)
+    R, th = Num(7.0), Num(1.4)
+    s, co = f("sin", th), f("cos", th)
+    rho, z = R * s, R * co
+    w = (1.0 / (1.0 + f("exp", -2.0 * (rho - 2.0) / 0.5))) * (1.0 / (1.0 + f("exp", 2.0 * (rho - 20.0) / 0.5)))
+    H = 0.2 + 0.1 * rho
+    j = f("exp", -2.0 * f("log1p", rho / 2.0 - 1.0) - (rho - 2.0) / 8.0 - z * z / (2.0 * H * H)) * w
+    F, dF = mass_function(metric, c, R)
+    G = (dF - 2.0 * F / R) / (R * R)
+    Om = (c["chi"] * G + f("sqrt", -2.0 * R * G)) / (2.0 * R + c["chi2"] * G)
+    Sig = R * R + c["chi2"] * co * co
+    s2 = s * s
+    gTT = -(1.0 - F / Sig)
+    gTp = -F * c["chi"] * s2 / Sig
+    gpp = (R * R + c["chi2"] + F * c["chi2"] * s2 / Sig) * s2
+    A = -(gTT + 2.0 * Om * gTp + Om * Om * gpp)
+    g = f("sqrt", A) / (1.0 - Om * 2.0)
+    _ = g * g * g * j
+    return Num.ops
+
+
 def flops_trace_ray(metric: str, attempts: float, crossings: float) -> float:
     """Algorithmic flops of the trace kernel for a ray with the given step
     attempts and trusted crossings (plus its start: screen map and one
@@ -168,5 +195,6 @@ def flops_trace_ray(metric: str, attempts: float, crossings: float) -> float:
 if __name__ == "__main__":
     for m in ("kerr", "einasto", "cnfw"):
         print(m, "rhs", flops_rhs(m), "step", flops_step_overhead(), "crossing",
-              flops_crossing(), "emission", flops_emission(m), "attempt",
+              flops_crossing(), "emission", flops_emission(m), "thick source",
+              flops_thick_source(m), "attempt",
               6 * flops_rhs(m) + flops_step_overhead())

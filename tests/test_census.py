@@ -33,3 +33,11 @@ def test_census_counts_are_positive_and_ordered():
     assert 150 < census.flops_crossing() < 400
     ke, ee, ce = (census.flops_emission(m) for m in ("kerr", "einasto", "cnfw"))
     assert 20 < ke < ee < ce < 120
+
+
+def test_thick_source_count():
+    from paper_2605_05635_amd import census
+    for m in ("kerr", "einasto", "cnfw"):
+        # the source adds the emissivity's exponentials and the local metric to
+        # the Keplerian redshift of the thin disc
+        assert census.flops_emission(m) < census.flops_thick_source(m) < 3 * census.flops_emission(m)
