@@ -68,3 +68,22 @@ def test_kerr_closed_forms_and_invalid_points(rt):
                             [0.0, 0.0, 0.0], [1.0, 1.0, 1.0])
     torch.cuda.synchronize()
     assert torch.isnan(bad).all()
+
+
+def test_wavefront_search_equals_the_image_setup(rt):
+    """The scan kernel splits the searches over the lanes of a wavefront but
+    keeps the serial search's interval: R_+ agrees with the host image
+    set-up's serial search (the host evaluates F(R) with exact divisions
+    where the device uses the refined hardware reciprocal: a few ulp),
+    including next to the extremal spin, where the interval matters."""
+    import torch
+    from paper_2605_05635_amd import workloads as W
+    imgs = [W.image(metric="kerr", spin=0.7), W.image(metric="einasto", spin=0.6, halo=(0.2, 0.0)),
+            W.image(metric="cnfw", spin=0.94, halo=(0.02, 10.0)),
+            W.image(metric="cnfw", spin=0.99, halo=(0.25, 3.0)),
+            W.image(metric="einasto", spin=0.63, halo=(0.3, 0.0))]   # near its extremal 0.640
+    host = [rt.rt_image_setup(rt.params_from(i))["r_plus"] for i in imgs]
+    g = rt.parameter_scan([i["metric"] for i in imgs], [i["spin"] for i in imgs],
+                          [i["halo"][0] for i in imgs], [i["halo"][1] for i in imgs], 1.0)
+    torch.cuda.synchronize()
+    assert np.allclose(g[:, 0].cpu().numpy(), np.array(host), rtol=1e-13, atol=0.0)
