@@ -391,14 +391,15 @@ def scan_measurement(steps: int, cpu: bool) -> dict:
 
 def shadow_measurement(steps: int, cpu: bool) -> dict:
     """Shadow boundary (Sec. 4.1) of the benchmark spacetime and observer along
-    4096 screen directions, b in [2, 9] M to a bracket of 1e-10 M: wall time of
-    rt_shadow_boundary per call (HIP events on the stream)."""
+    4096 screen directions, b in [2, 9] M to a bracket of 1e-10 M, 16 samples
+    per pass (four directions per wavefront): wall time of rt_shadow_boundary
+    per call (HIP events on the stream)."""
     import numpy as np
     import torch
 
     from paper_2605_05635_amd import rt, workloads as W
     img = W.cnfw_1024()
-    n, b_lo, b_hi, b_tol = 4096, 2.0, 9.0, 1e-10
+    n, b_lo, b_hi, b_tol, S = 4096, 2.0, 9.0, 1e-10, 16
     psi = (np.arange(n) + 0.5) * (2.0 * np.pi / n)
     dirs = np.stack([np.cos(psi), np.sin(psi)], axis=1)
     d = torch.tensor(dirs, device="cuda")
@@ -407,18 +408,18 @@ def shadow_measurement(steps: int, cpu: bool) -> dict:
     st = torch.empty(n, dtype=torch.int32, device="cuda")
     att = torch.empty(n, dtype=torch.int64, device="cuda")
     p = rt.params_from(img)
-    rt.rt_shadow_boundary(p, d, b_lo, b_hi, b_tol, out, st, att, stream)
+    rt.rt_shadow_boundary(p, d, b_lo, b_hi, b_tol, out, st, att, stream, samples=S)
     torch.cuda.synchronize()
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     a.record(stream)
     for _ in range(steps):
-        rt.rt_shadow_boundary(p, d, b_lo, b_hi, b_tol, out, st, att, stream)
+        rt.rt_shadow_boundary(p, d, b_lo, b_hi, b_tol, out, st, att, stream, samples=S)
     b.record(stream)
     torch.cuda.synchronize()
     ms = a.elapsed_time(b) / steps
     bc = out.mean(dim=1).cpu().numpy()
-    passes = int(np.ceil(np.log((b_hi - b_lo) / b_tol) / np.log(65.0)))
-    rays = n * 64 * passes + 2 * n
+    passes = int(np.ceil(np.log((b_hi - b_lo) / b_tol) / np.log(S + 1.0)))
+    rays = n * S * passes + 2 * n
     attempts = float(att.sum().item())
     from paper_2605_05635_amd import census
     # algorithmic flops as for the trace kernel, without the crossings (not counted)
@@ -427,7 +428,7 @@ def shadow_measurement(steps: int, cpu: bool) -> dict:
     tflops = flops / (ms * 1e-3) / 1e12
     log(f"shadow boundary: {n} directions in {ms:.2f} ms, {attempts / rays:.0f} attempts per ray")
     res = {"workload": "cored-NFW benchmark spacetime, 4096 directions, b in [2, 9], "
-                       "bracket 1e-10 (64-point multisection)",
+                       "bracket 1e-10 (16-point multisection)", "samples": S,
            "ms": ms, "directions_per_s": n / ms * 1e3, "steps": steps,
            "passes": passes, "rays_traced": rays, "attempts_per_ray": attempts / rays,
            "algorithmic_tflops": tflops, "frac_of_fp64_vector_peak": tflops / FP64_VECTOR_PEAK_TFLOPS,
@@ -438,7 +439,7 @@ def shadow_measurement(steps: int, cpu: bool) -> dict:
         threads = max(1, min(16, os.cpu_count() or 1))
         pick = np.arange(0, n, n // 16)
         t0 = time.perf_counter()
-        O.shadow_boundary(img, dirs[pick], b_lo, b_hi, b_tol, threads=threads)
+        O.shadow_boundary(img, dirs[pick], b_lo, b_hi, b_tol, samples=S, threads=threads)
         dt = time.perf_counter() - t0
         res["cpu_oracle"] = {"directions_per_s": len(pick) / dt, "cores": threads,
                              "kind": "oracle",

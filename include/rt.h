@@ -227,9 +227,9 @@ int rt_image_diagnostics(const double *intensity, const rt_image_params *params,
  * X = b cos psi, Y = b sin psi turn from captured to escaping (a ray escapes
  * when it reaches r_esc_fac R_o; captured rays and rays ending otherwise count
  * as inside).  Multisection: the bracket [lo, hi] starts at [b_lo, b_hi];
- * each pass traces 64 rays at b_j = lo + j w, w = (hi - lo)/65, j = 1..64,
- * and keeps [b_{j-1}, b_j] around the first escaping sample (b_0 = lo), or
- * [b_64, hi] if none escapes, while hi - lo > b_tol (at most 64 passes, and
+ * each pass traces S = samples (64, 32 or 16) rays at b_j = lo + j w,
+ * w = (hi - lo)/(S + 1), j = 1..S, and keeps [b_{j-1}, b_j] around the first
+ * escaping sample (b_0 = lo), or [b_S, hi] if none escapes, while hi - lo > b_tol (at most 64 passes, and
  * none once a pass leaves the bracket unchanged).  Rays are traced as by
  * rt_trace_image in binary64 (params->precision must be RT_FP64; the screen
  * fields are validated but not used).
@@ -241,11 +241,11 @@ int rt_image_diagnostics(const double *intensity, const rt_image_params *params,
  *           b_hi does not (out is then b_lo, b_hi)
  *   attempts device [n] step attempts of all the direction's rays, or NULL
  * Asynchronous on the stream; no scratch.  RT_ERR_ARG for null pointers,
- * n outside [1, 2^24], b_lo <= 0, b_lo >= b_hi, b_tol < 1e-13 b_hi or
+ * n outside [1, 2^24], samples not 16, 32 or 64, b_lo <= 0, b_lo >= b_hi, b_tol < 1e-13 b_hi or
  * non-finite values. */
-int rt_shadow_boundary(const rt_image_params *params, const double *dirs, int32_t n, double b_lo,
-                       double b_hi, double b_tol, double *out, int32_t *status, int64_t *attempts,
-                       void *hip_stream);
+int rt_shadow_boundary(const rt_image_params *params, const double *dirs, int32_t n,
+                       int32_t samples, double b_lo, double b_hi, double b_tol, double *out,
+                       int32_t *status, int64_t *attempts, void *hip_stream);
 
 /* Profiling hook.  When both are non-NULL hipEvent_t handles, every later
  * rt_trace_image / rt_transfer_maps call made on this thread records

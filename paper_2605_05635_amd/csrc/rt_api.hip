@@ -1054,12 +1054,14 @@ int rt_image_diagnostics(const double* intensity, const rt_image_params* params,
     return RT_OK;
 }
 
-int rt_shadow_boundary(const rt_image_params* params, const double* dirs, int32_t n, double b_lo,
-                       double b_hi, double b_tol, double* out, int32_t* status, int64_t* attempts,
-                       void* hip_stream) {
+int rt_shadow_boundary(const rt_image_params* params, const double* dirs, int32_t n,
+                       int32_t samples, double b_lo, double b_hi, double b_tol, double* out,
+                       int32_t* status, int64_t* attempts, void* hip_stream) {
     g_last_error.clear();
     if (!params || !dirs || !out || !status) return fail(RT_ERR_ARG, "null params, dirs, out or status");
     if (n < 1 || n > (1 << 24)) return fail(RT_ERR_ARG, "n must lie in [1, 2^24]");
+    if (samples != 16 && samples != 32 && samples != 64)
+        return fail(RT_ERR_ARG, "samples must be 16, 32 or 64");
     if (!finite_all({b_lo, b_hi, b_tol}) || !(b_lo > 0.0) || !(b_lo < b_hi))
         return fail(RT_ERR_ARG, "need finite 0 < b_lo < b_hi");
     if (!(b_tol >= 1e-13 * b_hi))
@@ -1073,7 +1075,7 @@ int rt_shadow_boundary(const rt_image_params* params, const double* dirs, int32_
         (rc = check_device_ptr(status, "status", 0)) ||
         (rc = check_device_ptr(attempts, "attempts", 0)))
         return rc;
-    const hipError_t e = rt::launch_boundary(c, dirs, n, b_lo, b_hi, b_tol, out, status, attempts,
+    const hipError_t e = rt::launch_boundary(c, dirs, n, samples, b_lo, b_hi, b_tol, out, status, attempts,
                                              static_cast<hipStream_t>(hip_stream));
     if (e != hipSuccess) return hip_fail(e, "boundary kernel launch");
     return RT_OK;

@@ -82,12 +82,12 @@ hipError_t launch_diagnostics(const ImageConst& c, const double* intensity, doub
                               int32_t n_bins, double* out, double* profile, double* scratch,
                               hipStream_t stream);
 
-// Shadow-boundary search: one wavefront per direction dirs[2i], dirs[2i+1]
-// (cos psi, sin psi); out[2i], out[2i+1] = the final bracket of b, status[i]
+// Shadow-boundary search: `samples` (64, 32 or 16) lanes per direction
+// dirs[2i], dirs[2i+1] (cos psi, sin psi); out[2i], out[2i+1] = the final bracket of b, status[i]
 // = 0, or 1 (bracket left as given) when the ray at b_lo escapes or the one at
 // b_hi does not; attempts[i] (if non-null) = the direction's step attempts.
-hipError_t launch_boundary(const ImageConst& c, const double* dirs, int32_t n, double b_lo,
-                           double b_hi, double b_tol, double* out, int32_t* status,
+hipError_t launch_boundary(const ImageConst& c, const double* dirs, int32_t n, int32_t samples,
+                           double b_lo, double b_hi, double b_tol, double* out, int32_t* status,
                            int64_t* attempts, hipStream_t stream);
 
 // LDS bytes of the batched kernel for n_images images.

@@ -94,7 +94,7 @@ def _load():
     lib.rt_image_diagnostics.argtypes = [C.c_void_p, P, C.c_double, C.c_int32, C.c_void_p,
                                          C.c_void_p, C.c_void_p]
     lib.rt_image_diagnostics.restype = C.c_int
-    lib.rt_shadow_boundary.argtypes = [P, C.c_void_p, C.c_int32, C.c_double, C.c_double,
+    lib.rt_shadow_boundary.argtypes = [P, C.c_void_p, C.c_int32, C.c_int32, C.c_double, C.c_double,
                                        C.c_double, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
     lib.rt_shadow_boundary.restype = C.c_int
     lib.rt_set_launch_config.argtypes = [C.POINTER(rt_launch_config)]
@@ -302,19 +302,20 @@ def image_diagnostics(img: dict, intensity, bin_width: float, n_bins: int, strea
 
 
 def rt_shadow_boundary(params: rt_image_params, dirs, b_lo: float, b_hi: float, b_tol: float,
-                       out, status, attempts=None, stream=None) -> None:
+                       out, status, attempts=None, stream=None, samples: int = 64) -> None:
     """Calls rt_shadow_boundary on device tensors: dirs [n][2] f64 (cos psi,
     sin psi), out [n][2] f64, status [n] int32 and optionally attempts [n]
     int64 (outputs)."""
     n = int(dirs.shape[0])
-    _check(_lib.rt_shadow_boundary(C.byref(params), C.c_void_p(dirs.data_ptr()), n, b_lo, b_hi,
+    _check(_lib.rt_shadow_boundary(C.byref(params), C.c_void_p(dirs.data_ptr()), n, samples, b_lo, b_hi,
                                    b_tol, C.c_void_p(out.data_ptr()),
                                    C.c_void_p(status.data_ptr()),
                                    None if attempts is None else C.c_void_p(attempts.data_ptr()),
                                    _stream_handle(stream)))
 
 
-def shadow_boundary(img: dict, dirs, b_lo: float, b_hi: float, b_tol: float, stream=None):
+def shadow_boundary(img: dict, dirs, b_lo: float, b_hi: float, b_tol: float, stream=None,
+                    samples: int = 64):
     """The shadow boundary of img's spacetime and observer along the screen
     directions dirs ([n][2] (cos psi, sin psi), numpy or tensor): returns device
     tensors (out [n][2] = the final bracket of b, status [n])."""
@@ -322,7 +323,8 @@ def shadow_boundary(img: dict, dirs, b_lo: float, b_hi: float, b_tol: float, str
     d = torch.as_tensor(dirs, dtype=torch.float64, device="cuda").reshape(-1, 2).contiguous()
     out = torch.empty(d.shape[0], 2, dtype=torch.float64, device=d.device)
     status = torch.empty(d.shape[0], dtype=torch.int32, device=d.device)
-    rt_shadow_boundary(params_from(img), d, b_lo, b_hi, b_tol, out, status, stream=stream)
+    rt_shadow_boundary(params_from(img), d, b_lo, b_hi, b_tol, out, status, stream=stream,
+                       samples=samples)
     return out, status
 
 

@@ -192,8 +192,8 @@ def test_shadow_boundary_argument_errors(rt):
     lib = rt.lib()
     p = rt.params_from(W.kerr_small())
     d = C.c_void_p(8)
-    call = lambda params, dirs, n, lo, hi, tol, out, st: lib.rt_shadow_boundary(
-        params, dirs, n, lo, hi, tol, out, st, None, None)
+    call = lambda params, dirs, n, lo, hi, tol, out, st, s=64: lib.rt_shadow_boundary(
+        params, dirs, n, s, lo, hi, tol, out, st, None, None)
     assert call(None, d, 4, 2.0, 9.0, 1e-9, d, d) == rt.RT_ERR_ARG
     assert call(C.byref(p), None, 4, 2.0, 9.0, 1e-9, d, d) == rt.RT_ERR_ARG
     assert call(C.byref(p), d, 4, 2.0, 9.0, 1e-9, None, d) == rt.RT_ERR_ARG
@@ -205,6 +205,7 @@ def test_shadow_boundary_argument_errors(rt):
     assert call(C.byref(p), d, 4, 2.0, float("inf"), 1e-9, d, d) == rt.RT_ERR_ARG
     assert call(C.byref(p), d, 4, 2.0, 9.0, 1e-14, d, d) == rt.RT_ERR_ARG
     assert "b_tol" in rt.rt_last_error()
+    assert call(C.byref(p), d, 4, 2.0, 9.0, 1e-9, d, d, 48) == rt.RT_ERR_ARG
     mixed = rt.params_from(W.image(precision="mixed"))
     assert call(C.byref(mixed), d, 4, 2.0, 9.0, 1e-9, d, d) == rt.RT_ERR_ARG
     nohz = rt.params_from(W.image(metric="kerr", spin=1.01))

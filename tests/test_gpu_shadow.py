@@ -145,3 +145,29 @@ def test_attempt_counts_do_not_change_results(rt):
     passes = math.ceil(math.log(7.0 / TOL_B) / math.log(65.0))
     # every traced ray takes at least a few dozen attempts from R_o = 1000
     assert int(att.min()) >= (64 * passes + 2) * 20
+
+
+@pytest.mark.parametrize("samples", [32, 16])
+def test_fewer_samples_per_direction(rt, orc, samples):
+    """Two or four directions per wavefront, 32 or 16 samples each, against the
+    oracle's multisection with the same number of samples (an odd count of
+    directions leaves a partly filled wavefront)."""
+    import torch
+    img = W.cnfw_1024()
+    psi = np.linspace(0.0, 2.0 * np.pi, 13, endpoint=False) + 0.1
+    d = dirs_of(psi)
+    out, st = rt.shadow_boundary(img, d, 2.0, 9.0, TOL_B, samples=samples)
+    torch.cuda.synchronize()
+    out, st = out.cpu().numpy(), st.cpu().numpy()
+    lo, hi, ok = orc.shadow_boundary(img, d, 2.0, 9.0, TOL_B, samples=samples)
+    assert np.all(st == 0) and ok.all()
+    assert np.all(out[:, 1] - out[:, 0] <= TOL_B)
+    assert np.abs(out.mean(axis=1) - 0.5 * (lo + hi)).max() <= 1.5 * TOL_B
+    # the same transition as with 64 samples
+    out64, _ = rt.shadow_boundary(img, d, 2.0, 9.0, TOL_B)
+    assert np.abs(out.mean(axis=1) - out64.cpu().numpy().mean(axis=1)).max() <= 2 * TOL_B
+    # a bracket without the transition in one group only
+    out2, st2 = rt.shadow_boundary(img, np.concatenate([d[:1], 3.0 * d[1:2]]), 2.0, 9.0, TOL_B,
+                                   samples=samples)
+    torch.cuda.synchronize()
+    assert st2.cpu().numpy().tolist() == [0, 1]
