@@ -54,7 +54,8 @@ def cpu_baseline(img: dict, stride: int) -> dict:
     O.trace_pixels(img, idx, threads=threads)
     dt = time.perf_counter() - t0
     return {"value": idx.size / dt, "unit": "rays/s", "cores": threads, "kind": "oracle",
-            "sample": f"every {stride}th pixel in x and y of the same screen "
+            "sample": (f"every {stride}th pixel in x and y of" if stride > 1 else "every pixel of")
+                      + " the same screen "
                       f"({idx.size} rays, {dt:.1f} s)"}
 
 
