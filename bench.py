@@ -392,15 +392,17 @@ def scan_measurement(steps: int, cpu: bool) -> dict:
 
 def shadow_measurement(steps: int, cpu: bool) -> dict:
     """Shadow boundary (Sec. 4.1) of the benchmark spacetime and observer along
-    4096 screen directions, b in [2, 9] M to a bracket of 1e-10 M, 16 samples
-    per pass (four directions per wavefront): wall time of rt_shadow_boundary
-    per call (HIP events on the stream)."""
+    4096 screen directions, b in [2, 9] M to a bracket of 1e-10 M, with the
+    library's sample count for that many directions (16 per pass on 256 compute
+    units: four directions per wavefront): wall time of rt_shadow_boundary per
+    call (HIP events on the stream)."""
     import numpy as np
     import torch
 
     from paper_2605_05635_amd import rt, workloads as W
     img = W.cnfw_1024()
-    n, b_lo, b_hi, b_tol, S = 4096, 2.0, 9.0, 1e-10, 16
+    n, b_lo, b_hi, b_tol = 4096, 2.0, 9.0, 1e-10
+    S = rt.rt_shadow_boundary_samples(n)
     psi = (np.arange(n) + 0.5) * (2.0 * np.pi / n)
     dirs = np.stack([np.cos(psi), np.sin(psi)], axis=1)
     d = torch.tensor(dirs, device="cuda")
@@ -429,7 +431,7 @@ def shadow_measurement(steps: int, cpu: bool) -> dict:
     tflops = flops / (ms * 1e-3) / 1e12
     log(f"shadow boundary: {n} directions in {ms:.2f} ms, {attempts / rays:.0f} attempts per ray")
     res = {"workload": "cored-NFW benchmark spacetime, 4096 directions, b in [2, 9], "
-                       "bracket 1e-10 (16-point multisection)", "samples": S,
+                       f"bracket 1e-10 ({S}-point multisection)", "samples": S,
            "ms": ms, "directions_per_s": n / ms * 1e3, "steps": steps,
            "passes": passes, "rays_traced": rays, "attempts_per_ray": attempts / rays,
            "algorithmic_tflops": tflops, "frac_of_fp64_vector_peak": tflops / FP64_VECTOR_PEAK_TFLOPS,

@@ -247,6 +247,15 @@ int rt_shadow_boundary(const rt_image_params *params, const double *dirs, int32_
                        int32_t samples, double b_lo, double b_hi, double b_tol, double *out,
                        int32_t *status, int64_t *attempts, void *hip_stream);
 
+/* A sample count for rt_shadow_boundary with n directions on the current
+ * device: the largest S of 64, 32 and 16 whose n S rays fit in one wavefront
+ * per SIMD (4 SIMDs of 64 lanes per compute unit), else 16.  A pass lasts as
+ * long as its slowest ray, the one that winds longest near the photon shell:
+ * while the device has idle SIMDs, more samples (fewer passes) finish first;
+ * once it is full, fewer samples waste less of each pass.  Returns 16, 32 or
+ * 64; RT_ERR_ARG for n < 1, RT_ERR_HIP if the device cannot be queried. */
+int rt_shadow_boundary_samples(int32_t n);
+
 /* Profiling hook.  When both are non-NULL hipEvent_t handles, every later
  * rt_trace_image / rt_transfer_maps call made on this thread records
  * `start_event` on its stream just before the first trace kernel and

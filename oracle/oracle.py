@@ -436,7 +436,13 @@ def image_diagnostics(img: dict, intensity: np.ndarray, bin_width: float, n_bins
     origin-centred radial profile (the mean intensity of the pixels whose
     rho_0 = |(X, Y)| falls in [k bin_width, (k + 1) bin_width), k < n_bins), the
     centre rho_peak of the first bin of largest mean and d_peak = 2 rho_peak.
-    Also returns the profile (NaN for empty bins)."""
+    Also returns the profile (NaN for empty bins).  An image without flux gives
+    NaN for the ratios, silently."""
+    with np.errstate(divide="ignore", invalid="ignore"):
+        return _image_diagnostics(img, intensity, bin_width, n_bins)
+
+
+def _image_diagnostics(img: dict, intensity: np.ndarray, bin_width: float, n_bins: int) -> dict:
     X, Y, dx, dy = screen_axes(img)
     I = np.asarray(intensity, dtype=np.float64).reshape(img["ny"], img["nx"])
     Xg, Yg = np.meshgrid(X, Y)

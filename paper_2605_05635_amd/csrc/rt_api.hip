@@ -1081,6 +1081,18 @@ int rt_shadow_boundary(const rt_image_params* params, const double* dirs, int32_
     return RT_OK;
 }
 
+int rt_shadow_boundary_samples(int32_t n) {
+    g_last_error.clear();
+    if (n < 1) return fail(RT_ERR_ARG, "n must be at least 1");
+    DeviceInfo info;
+    const int rc = device_info(&info);
+    if (rc != RT_OK) return rc;
+    const int64_t lanes = static_cast<int64_t>(info.cus) * 4 * 64;
+    for (int s = 64; s > 16; s /= 2)
+        if (static_cast<int64_t>(n) * s <= lanes) return s;
+    return 16;
+}
+
 int rt_image_setup(const rt_image_params* params, double* setup) {
     g_last_error.clear();
     if (!setup) return fail(RT_ERR_ARG, "null setup pointer");

@@ -97,6 +97,8 @@ def _load():
     lib.rt_shadow_boundary.argtypes = [P, C.c_void_p, C.c_int32, C.c_int32, C.c_double, C.c_double,
                                        C.c_double, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
     lib.rt_shadow_boundary.restype = C.c_int
+    lib.rt_shadow_boundary_samples.argtypes = [C.c_int32]
+    lib.rt_shadow_boundary_samples.restype = C.c_int
     lib.rt_set_launch_config.argtypes = [C.POINTER(rt_launch_config)]
     lib.rt_set_launch_config.restype = C.c_int
     lib.rt_get_launch_config.argtypes = [C.POINTER(rt_launch_config)]
@@ -314,6 +316,14 @@ def rt_shadow_boundary(params: rt_image_params, dirs, b_lo: float, b_hi: float, 
                                    _stream_handle(stream)))
 
 
+def rt_shadow_boundary_samples(n: int) -> int:
+    """The library's sample count for n directions on the current device
+    (16, 32 or 64, see rt.h)."""
+    rc = _lib.rt_shadow_boundary_samples(n)
+    _check(min(rc, 0))
+    return rc
+
+
 def shadow_boundary(img: dict, dirs, b_lo: float, b_hi: float, b_tol: float, stream=None,
                     samples: int = 64):
     """The shadow boundary of img's spacetime and observer along the screen
@@ -435,7 +445,7 @@ def image_vjp(img: dict, dl_dI, basis: str = "native", per_pixel: bool = False, 
 
 __all__ = ["rt_mixed_stats", "rt_image_vjp", "rt_set_tape_budget", "rt_vjp_stats", "image_vjp", "rt_trace_image", "rt_transfer_maps", "rt_image_setup", "rt_set_kernel_timing",
            "rt_set_launch_config", "rt_get_launch_config", "rt_visibility_dft", "visibility",
-           "rt_shadow_boundary", "shadow_boundary", "rt_image_diagnostics", "image_diagnostics",
+           "rt_shadow_boundary", "rt_shadow_boundary_samples", "shadow_boundary", "rt_image_diagnostics", "image_diagnostics",
            "rt_parameter_scan", "parameter_scan", "rt_scan_point",
            "rt_trace_thick", "trace_thick", "rt_thick_disc",
            "RT_DIAG_COUNT", "DIAG_KEYS",

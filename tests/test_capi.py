@@ -103,6 +103,9 @@ def test_null_pointers_and_counts(rt):
     assert lib.rt_trace_image(C.byref(p), 0, C.byref(o), None) == rt.RT_ERR_ARG
     assert lib.rt_transfer_maps(C.byref(p), -1, C.byref(o), None) == rt.RT_ERR_ARG
     assert lib.rt_image_setup(C.byref(p), None) == rt.RT_ERR_ARG
+    # argument checks come before any device query
+    assert lib.rt_shadow_boundary_samples(0) == rt.RT_ERR_ARG
+    assert lib.rt_shadow_boundary_samples(-5) == rt.RT_ERR_ARG
 
 
 def test_no_horizon_beyond_extremal_spin(rt):

@@ -171,3 +171,14 @@ def test_fewer_samples_per_direction(rt, orc, samples):
                                    samples=samples)
     torch.cuda.synchronize()
     assert st2.cpu().numpy().tolist() == [0, 1]
+
+
+def test_sample_count_rule(rt):
+    """The library's sample count: the largest of 64, 32, 16 whose n S rays fit
+    one wavefront per SIMD of the device, else 16."""
+    import torch
+    lanes = torch.cuda.get_device_properties(0).multi_processor_count * 4 * 64
+    for n in (1, lanes // 64, lanes // 64 + 1, lanes // 32, lanes // 32 + 1, lanes // 16,
+              lanes, 1 << 24):
+        want = next((s for s in (64, 32) if n * s <= lanes), 16)
+        assert rt.rt_shadow_boundary_samples(n) == want, n
