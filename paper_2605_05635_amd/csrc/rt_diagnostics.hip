@@ -179,10 +179,23 @@ __global__ __launch_bounds__(kThreads) void profile_kernel(ImageConst c, const d
         for (int run = 0; run < (one ? 1 : 2); ++run) {
             const int64_t lo = run == 0 ? a0 : b0;
             const int64_t hi = one ? b1 : (run == 0 ? a1 : b1);
-            for (int64_t ix = lo; ix <= hi; ++ix) {
-                if (radial_bin(centre(c.x0, c.dx, ix), Y, bw) == k) {
-                    s += row[ix];
-                    n += 1.0;
+            // four pixels a round: their loads are issued together, the sums
+            // still taken in column order
+            for (int64_t ix = lo; ix <= hi; ix += 4) {
+                double v[4];
+                bool in[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int64_t j = ix + u;
+                    in[u] = j <= hi && radial_bin(centre(c.x0, c.dx, j), Y, bw) == k;
+                    v[u] = in[u] ? row[j] : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    if (in[u]) {
+                        s += v[u];
+                        n += 1.0;
+                    }
                 }
             }
         }
