@@ -442,7 +442,7 @@ def shadow_measurement(steps: int, cpu: bool) -> dict:
         threads = max(1, min(16, os.cpu_count() or 1))
         pick = np.arange(0, n, n // 16)
         t0 = time.perf_counter()
-        O.shadow_boundary(img, dirs[pick], b_lo, b_hi, b_tol, samples=S, threads=threads)
+        O.shadow_boundary(img, dirs[pick], b_lo, b_hi, b_tol, threads=threads)
         dt = time.perf_counter() - t0
         res["cpu_oracle"] = {"directions_per_s": len(pick) / dt, "cores": threads,
                              "kind": "oracle",

@@ -174,6 +174,15 @@ def image_setup(img: dict) -> dict | None:
     return dict(r_plus=out[0], r_stop=out[1], r_esc=out[2], r_in=out[3])
 
 
+def set_fault(first: int, last: int) -> None:
+    """Fault injection for the failure-handling tests: step attempts first..last
+    (1-based, per ray) of every later ray get a non-finite error estimate, as a
+    stage that produced NaN would give; first > last switches it off."""
+    L = lib()
+    L.orc_set_fault.argtypes = [C.c_int, C.c_int]
+    L.orc_set_fault(int(first), int(last))
+
+
 def trace_ray(img: dict, X: float, Y: float, log_cap: int = 0):
     """Trace one screen point.  Returns (OrcRay, step_log) where step_log is an
     (n, 8) array of accepted steps (lambda, h, y[6]) when log_cap > 0."""
@@ -360,19 +369,18 @@ def visibility_amplitude(img: dict, intensity: np.ndarray, uv: np.ndarray) -> np
 
 
 def shadow_boundary(img: dict, dirs, b_lo: float, b_hi: float, b_tol: float,
-                    samples: int = 64, max_passes: int = 64, threads: int | None = None):
+                    max_halvings: int = 200, threads: int | None = None):
     """Shadow boundary (Sec. 4.1, eqs. (78)-(79)): along each screen direction
     (cos psi, sin psi) of `dirs` ([n, 2]), the impact parameter b at which the
     rays from X = b cos psi, Y = b sin psi turn from captured to escaping.
 
-    The search is the multisection the GPU path runs (one sample per lane of
-    a 64-lane wavefront): the bracket [lo, hi] starts at [b_lo, b_hi]; each
-    pass traces `samples` rays at b_j = lo + j w, w = (hi - lo)/(samples + 1),
-    j = 1..samples, and keeps [b_{j-1}, b_j] around the first sample j whose ray
-    escapes (b_0 = lo), or [b_samples, hi] if none does, while hi - lo > b_tol
-    (at most max_passes passes, and no further once a pass leaves the bracket
-    unchanged).  A ray escapes when it ends at the escape radius (eq. (75));
-    captured rays and rays ending otherwise count as inside.
+    The paper varies b along each direction until the transition is located;
+    here that is plain bisection: the bracket [lo, hi] starts at [b_lo, b_hi]
+    with the ray at lo inside and the one at hi escaping; the ray at the
+    midpoint is traced and replaces the end of the same kind, while
+    hi - lo > b_tol (at most max_halvings times, and no further once the
+    midpoint rounds onto an end).  A ray escapes when it ends at the escape
+    radius (eq. (75)); captured rays and rays ending otherwise count as inside.
     Returns (lo, hi, ok): ok is False where the ray at b_lo escapes or the one
     at b_hi does not (lo, hi are then b_lo, b_hi).  The boundary point is
     b = (lo + hi)/2 times the direction."""
@@ -390,24 +398,16 @@ def shadow_boundary(img: dict, dirs, b_lo: float, b_hi: float, b_tol: float,
         lo_out[i], hi_out[i] = lo, hi
         if escapes(ux, uy, lo) or not escapes(ux, uy, hi):
             return
-        for _ in range(max_passes):
+        for _ in range(max_halvings):
             if not hi - lo > b_tol:
                 break
-            w = (hi - lo) / (samples + 1)
-            first = None
-            for j in range(1, samples + 1):
-                t = j * w
-                if escapes(ux, uy, lo + t):
-                    first = j
-                    break
-            if first is None:
-                nlo, nhi = lo + samples * w, hi
-            else:
-                nhi = lo + first * w
-                nlo = lo if first == 1 else lo + (first - 1) * w
-            if nlo == lo and nhi == hi:
+            mid = 0.5 * (lo + hi)
+            if mid <= lo or mid >= hi:
                 break
-            lo, hi = nlo, nhi
+            if escapes(ux, uy, mid):
+                hi = mid
+            else:
+                lo = mid
         lo_out[i], hi_out[i], ok[i] = lo, hi, True
 
     threads = threads or os.cpu_count() or 1

@@ -27,13 +27,22 @@
 //    components with scale atol + rtol*max(|y|,|y_new|), first step h0.
 //  * capture R <= r_stop_fac * R_+ and escape R >= r_esc_fac * R_o, both tested
 //    at the end of each accepted step (Sec. 3.3, eq. (75)).
-//  * an equatorial crossing is a change of the boolean (theta - pi/2 >= 0)
-//    across an accepted step; its position is the root of the continuous
-//    extension's theta(s) - pi/2 on s in [0,1], found by 60 bisections
-//    (Sec. 3.3, eq. (76)).  A crossing is trusted when |dtheta/dlambda| >=
-//    1e-12 at the root and the affine gap to the previous trusted crossing is
-//    >= 1e-10 (Sec. 4.2).  Crossings of the final step count before the stop
-//    test.
+//  * the equatorial plane is theta = pi/2 (mod pi): Boyer-Lindquist theta is
+//    continued through the poles (a ray with l = 0 passes over the axis and
+//    theta leaves (0, pi); (theta, phi) and (-theta, phi + pi) are the same
+//    point).  The band index k = floor((theta - pi/2)/pi) labels the regions
+//    between equatorial passages; an equatorial crossing is a change of k
+//    across an accepted step (for theta in (0, pi) that is a change of the
+//    boolean theta >= pi/2).  Its position is the root of the continuous
+//    extension's theta(s) - theta_eq on s in [0,1], theta_eq = pi/2 + k pi for
+//    the larger of the two band indices, found by 60 bisections (Sec. 3.3,
+//    eq. (76)); where theta_eq = -pi/2 (mod 2 pi) the point's azimuth is
+//    phi + pi.  A crossing is trusted when |dtheta/dlambda| >= 1e-12 at the
+//    root and the affine gap to the previous trusted crossing is >= 1e-10
+//    (Sec. 4.2).  Crossings of the final step count before the stop test.
+//  * a ray whose error estimate is not finite on kNonfiniteRun consecutive
+//    attempts (its step shrunk by 0.2 each time, to ~1e-14 of where it
+//    started) ends with status NONFINITE.
 //  * thin-disc intensity: I = sum_{n<3} w(R_n) g_n^3 R_n^(-emis_pow), the
 //    equatorial limit of eq. (88) with the emitter of eqs. (89)-(91); g = 0
 //    where no timelike circular orbit exists.
@@ -106,6 +115,17 @@ namespace {
 
 constexpr double kNaN = std::numeric_limits<double>::quiet_NaN();
 constexpr double kHalfPi = 1.57079632679489661923;
+constexpr double kPi = 3.14159265358979323846;
+constexpr int kNonfiniteRun = 20;
+
+// Band index of theta between equatorial passages: theta = pi/2 + k pi is the
+// equator, band k holds [pi/2 + k pi, pi/2 + (k + 1) pi).
+double equator_band(double theta) { return std::floor((theta - kHalfPi) / kPi); }
+
+// Fault injection for the failure-handling tests: attempts numbered
+// [g_fault_from, g_fault_to] (1-based, per ray) get a non-finite error
+// estimate, as a stage that produced NaN would give.  Off by default.
+int g_fault_from = 0, g_fault_to = -1;
 
 // ----------------------------------------------------------- dual numbers
 // Forward-mode dual number: value v and N directional derivatives d.
@@ -713,6 +733,7 @@ void trace_ray(const OrcParams& p, const Phys<T>& q, const ImageSetup& S, double
     r.carter_drift = 0.0;
     double h = p.h0, lambda = 0.0, last_cross = -std::numeric_limits<double>::infinity();
     bool after_reject = false;
+    int nonfinite_run = 0;   // consecutive attempts with a non-finite error estimate
     int nl = 0;
     size_t ri = 0;
     Step<T> st;
@@ -727,6 +748,7 @@ void trace_ray(const OrcParams& p, const Phys<T>& q, const ImageSetup& S, double
         }
         ++r.attempts;
         dp5_attempt(p, q, E, L, y, k1, h, &st);
+        if (r.attempts >= g_fault_from && r.attempts <= g_fault_to) st.err = T(kNaN);
         const double err = val(st.err);
         bool accept = err < 1.0;
         if (replay) accept = replay->accepted[ri] != 0;
@@ -736,30 +758,40 @@ void trace_ray(const OrcParams& p, const Phys<T>& q, const ImageSetup& S, double
         }
         ++ri;
         if (!accept) {  // rejected (also when err is NaN)
-            const double f = std::isfinite(err) ? std::fmax(0.2, 0.9 * std::pow(err, -0.2)) : 0.2;
+            const bool finite = std::isfinite(err);
+            const double f = finite ? std::fmax(0.2, 0.9 * std::pow(err, -0.2)) : 0.2;
             h *= f;
             after_reject = true;
+            nonfinite_run = finite ? 0 : nonfinite_run + 1;
+            if (nonfinite_run >= kNonfiniteRun && !replay) { r.status = NONFINITE; break; }
             continue;
         }
+        nonfinite_run = 0;
         double factor = err == 0.0 ? 10.0 : std::fmin(10.0, 0.9 * std::pow(err, -0.2));
         if (after_reject) factor = std::fmin(1.0, factor);
         after_reject = false;
         ++r.accepted;
 
-        // Equatorial crossing on this accepted step (Sec. 3.3, eq. (76)).
-        const bool above0 = (val(y[2]) - kHalfPi) >= 0.0;
-        const bool above1 = (val(st.y_new[2]) - kHalfPi) >= 0.0;
-        if (above0 != above1) {
-            double a = 0.0, b = 1.0;  // sign(theta(a)-pi/2) == above0
+        // Equatorial crossing on this accepted step (Sec. 3.3, eq. (76)): the
+        // band index of theta changes; the crossed equator is theta_eq.
+        const double band0 = equator_band(val(y[2]));
+        const double band1 = equator_band(val(st.y_new[2]));
+        if (band0 != band1) {
+            const double kk = std::fmax(band0, band1);
+            const double th_eq = kHalfPi + kk * kPi;
+            const bool above0 = band0 > band1;   // theta(0) >= theta_eq
+            double a = 0.0, b = 1.0;  // theta(a) on the side of theta(0)
             for (int it = 0; it < 60; ++it) {
                 const double mid = 0.5 * (a + b);
-                const bool am = (val(dense(y, st, h, 2, mid)) - kHalfPi) >= 0.0;
+                const bool am = (val(dense(y, st, h, 2, mid)) - th_eq) >= 0.0;
                 if (am == above0) a = mid; else b = mid;
             }
             const double s = 0.5 * (a + b);
-            // root as a function of the parameters: theta(s*) = pi/2 fixes
+            // root as a function of the parameters: theta(s*) = theta_eq fixes
             // ds* = -dtheta/theta_s (implicit-function theorem); its value is s
-            const T sT = root_of(s, dense(y, st, h, 2, s) - kHalfPi, st, h);
+            const T sT = root_of(s, dense(y, st, h, 2, s) - th_eq, st, h);
+            // theta_eq = -pi/2 (mod 2 pi) is the equator on the far side of the axis
+            const double phi_shift = std::fmod(std::fabs(kk), 2.0) == 1.0 ? kPi : 0.0;
             const T Rc = dense(y, st, h, 1, sT);
             const double pth = val(dense(y, st, h, 5, s));
             const double thdot = pth / (val(Rc) * val(Rc));  // eq. (60), Sigma = R^2 on the equator
@@ -768,7 +800,7 @@ void trace_ray(const OrcParams& p, const Phys<T>& q, const ImageSetup& S, double
                 const int n = r.ncross;
                 if (n < 3) {
                     rt.r_em[n] = Rc;
-                    rt.phi_em[n] = dense(y, st, h, 3, sT);
+                    rt.phi_em[n] = dense(y, st, h, 3, sT) + phi_shift;
                     rt.t_em[n] = dense(y, st, h, 0, sT);
                     const T g = redshift(p, q, Rc, E, L, obs_energy);
                     rt.g_em[n] = g;
@@ -895,6 +927,7 @@ void trace_ray_thick(const OrcParams& p, const ThickParams& t, const ImageSetup&
     f(y, k[0]);
     double h = p.h0;
     bool after_reject = false;
+    int nonfinite_run = 0;
     int32_t att = 0, st = RUNNING;
     const double A[6][5] = {{0, 0, 0, 0, 0}, {A21, 0, 0, 0, 0}, {A31, A32, 0, 0, 0},
                             {A41, A42, A43, 0, 0}, {A51, A52, A53, A54, 0},
@@ -927,12 +960,17 @@ void trace_ray_thick(const OrcParams& p, const ThickParams& t, const ImageSetup&
             const double qq = h * e / sc;
             acc += qq * qq;
         }
-        const double err = std::sqrt(acc / 7.0);
+        double err = std::sqrt(acc / 7.0);
+        if (att >= g_fault_from && att <= g_fault_to) err = kNaN;
         if (!(err < 1.0)) {
-            h *= std::isfinite(err) ? std::fmax(0.2, 0.9 * std::pow(err, -0.2)) : 0.2;
+            const bool finite = std::isfinite(err);
+            h *= finite ? std::fmax(0.2, 0.9 * std::pow(err, -0.2)) : 0.2;
             after_reject = true;
+            nonfinite_run = finite ? 0 : nonfinite_run + 1;
+            if (nonfinite_run >= kNonfiniteRun) { st = NONFINITE; break; }
             continue;
         }
+        nonfinite_run = 0;
         double factor = err == 0.0 ? 10.0 : std::fmin(10.0, 0.9 * std::pow(err, -0.2));
         if (after_reject) factor = std::fmin(1.0, factor);
         after_reject = false;
@@ -1122,6 +1160,13 @@ int orc_image_setup(const OrcParams* p, double* out) {
     if (!image_setup(*p, &S)) return -2;
     out[0] = S.r_plus; out[1] = S.r_stop; out[2] = S.r_esc; out[3] = S.r_in;
     return 0;
+}
+
+// Fault injection (tests of the failure handling): attempts from..to of
+// every later ray get a non-finite error estimate; from > to switches it off.
+void orc_set_fault(int from, int to) {
+    g_fault_from = from;
+    g_fault_to = to;
 }
 
 int orc_sizeof_params(void) { return static_cast<int>(sizeof(OrcParams)); }

@@ -1,14 +1,16 @@
 """The shadow-boundary search (rt_shadow_boundary, Sec. 4.1, eqs. (78)-(79))
-on the GPU against the oracle's multisection of the same definition, and
+on the GPU against the oracle's plain bisection in b along each direction, and
 against the exact finite-distance Kerr critical curve.
 
-Tolerance.  Both sides run the same multisection (64 samples per pass, the
-same sample points) and differ only in the rounding of the traced rays, which
-can change the fate of a ray only within about 1e-14 of the transition.  Both
-final brackets hold the transition and are at most b_tol wide, so their
-midpoints differ by at most b_tol (held to 1.5 b_tol here).  Against the exact
-Kerr curve the integrated flow's transition lies within ~3e-8 relative
-(rtol = atol = 1e-8): held to 2e-7, as the oracle's pins are.
+Tolerance.  The GPU narrows its bracket by multisection, the oracle by
+bisection: different sample points, the same transition.  Each final bracket
+holds the transition of its own traced flow and is at most its b_tol wide;
+the two flows are the same discrete algorithm and differ only in rounding,
+which moves the fate of a ray only within about 1e-14 of the transition.  So
+the two midpoints differ by at most (b_tol_gpu + b_tol_oracle)/2, held here to
+b_tol_gpu + b_tol_oracle.  Against the exact Kerr curve the integrated flow's
+transition lies within ~3e-8 relative (rtol = atol = 1e-8): held to 2e-7, as
+the oracle's pins are.
 """
 import math
 import sys
@@ -20,7 +22,8 @@ from paper_2605_05635_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
 
-TOL_B = 1e-9
+TOL_B = 1e-9     # the GPU search's bracket width
+TOL_ORC = 1e-9   # the oracle bisection's
 
 
 @pytest.fixture(scope="module")
@@ -59,11 +62,11 @@ def test_boundary_matches_oracle(rt, orc, label, img):
     out, st = rt.shadow_boundary(img, d, 2.0, 9.0, TOL_B)
     torch.cuda.synchronize()
     out, st = out.cpu().numpy(), st.cpu().numpy()
-    lo, hi, ok = orc.shadow_boundary(img, d, 2.0, 9.0, TOL_B)
+    lo, hi, ok = orc.shadow_boundary(img, d, 2.0, 9.0, TOL_ORC)
     assert np.all(st == 0) and ok.all()
     assert np.all(out[:, 1] - out[:, 0] <= TOL_B) and np.all(out[:, 1] > out[:, 0])
     mid_g, mid_o = out.mean(axis=1), 0.5 * (lo + hi)
-    assert np.abs(mid_g - mid_o).max() <= 1.5 * TOL_B, np.abs(mid_g - mid_o).max()
+    assert np.abs(mid_g - mid_o).max() <= TOL_B + TOL_ORC, np.abs(mid_g - mid_o).max()
 
 
 def test_kerr_boundary_against_critical_curve(rt):
@@ -125,7 +128,7 @@ def test_many_directions_sampled(rt, orc):
     assert np.abs(np.diff(np.r_[b, b[0]])).max() < 0.05
     pick = np.arange(0, n, n // 8) + 17
     lo, hi, ok = orc.shadow_boundary(img, d[pick], 2.0, 9.0, 1e-10)
-    assert ok.all() and np.abs(b[pick] - 0.5 * (lo + hi)).max() <= 1.5e-10
+    assert ok.all() and np.abs(b[pick] - 0.5 * (lo + hi)).max() <= 2e-10
 
 
 def test_attempt_counts_do_not_change_results(rt):
@@ -150,8 +153,8 @@ def test_attempt_counts_do_not_change_results(rt):
 @pytest.mark.parametrize("samples", [32, 16])
 def test_fewer_samples_per_direction(rt, orc, samples):
     """Two or four directions per wavefront, 32 or 16 samples each, against the
-    oracle's multisection with the same number of samples (an odd count of
-    directions leaves a partly filled wavefront)."""
+    oracle's bisection (an odd count of directions leaves a partly filled
+    wavefront)."""
     import torch
     img = W.cnfw_1024()
     psi = np.linspace(0.0, 2.0 * np.pi, 13, endpoint=False) + 0.1
@@ -159,10 +162,10 @@ def test_fewer_samples_per_direction(rt, orc, samples):
     out, st = rt.shadow_boundary(img, d, 2.0, 9.0, TOL_B, samples=samples)
     torch.cuda.synchronize()
     out, st = out.cpu().numpy(), st.cpu().numpy()
-    lo, hi, ok = orc.shadow_boundary(img, d, 2.0, 9.0, TOL_B, samples=samples)
+    lo, hi, ok = orc.shadow_boundary(img, d, 2.0, 9.0, TOL_ORC)
     assert np.all(st == 0) and ok.all()
     assert np.all(out[:, 1] - out[:, 0] <= TOL_B)
-    assert np.abs(out.mean(axis=1) - 0.5 * (lo + hi)).max() <= 1.5 * TOL_B
+    assert np.abs(out.mean(axis=1) - 0.5 * (lo + hi)).max() <= TOL_B + TOL_ORC
     # the same transition as with 64 samples
     out64, _ = rt.shadow_boundary(img, d, 2.0, 9.0, TOL_B)
     assert np.abs(out.mean(axis=1) - out64.cpu().numpy().mean(axis=1)).max() <= 2 * TOL_B

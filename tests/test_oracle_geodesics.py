@@ -247,6 +247,36 @@ def test_schwarzschild_transfer_map_quadrature(orc, th_deg, tol, bound):
     assert checked >= 6
 
 
+@pytest.mark.parametrize("th_deg", [17.0, 60.0, 163.0])
+def test_rays_over_the_pole(orc, th_deg):
+    """Pixels with X = 0 launch photons with l = 0: the ray's plane holds the
+    axis and it may pass over a pole, where Boyer-Lindquist theta leaves
+    (0, pi).  Its crossings are still the orbit's equatorial passages: the
+    radii match the quadrature, and the azimuths alternate between the
+    observer's side (phi = 0) and the far side of the axis (phi = pi), the
+    first on the far side exactly when the ray reaches a pole before the
+    equator (it starts towards the nearer pole: Y > 0 moves theta towards 0)."""
+    img = W.image(metric="kerr", spin=0.0, incl=math.radians(th_deg), rtol=1e-12, atol=1e-12)
+    setup = orc.image_setup(img)
+    th_o = img["incl"]
+    seen_far = 0
+    for Y in (4.2, -4.2, 5.6, -6.2, 7.3, -9.5):
+        want, fate = _schwarzschild_crossings(img["r_obs"], th_o, 0.0, Y, setup["r_stop"],
+                                              setup["r_esc"])
+        ray, _ = orc.trace_ray(img, 0.0, Y)
+        assert ray.L == 0.0
+        assert ray.status == (1 if fate == "captured" else 2)
+        assert ray.ncross == len(want) >= 1
+        towards_north = Y > 0
+        far_first = (towards_north and th_o < math.pi / 2) or (not towards_north and th_o > math.pi / 2)
+        for n, r in enumerate(want[:3]):
+            assert abs(ray.r_em[n] - r) < 2e-8
+            far = far_first != (n % 2 == 1)
+            assert ray.phi_em[n] == pytest.approx(math.pi if far else 0.0, abs=1e-12)
+            seen_far += far
+    assert seen_far >= 3
+
+
 # ---------------------------------------------------------- library integrator
 def test_step_sequence_matches_scipy_rk45(orc):
     """scipy's RK45 is the same Dormand-Prince pair with the same controller; with
