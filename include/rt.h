@@ -31,6 +31,10 @@
  *   - Return value: RT_OK (0) on success, a negative RT_ERR_* code otherwise;
  *     rt_last_error() then describes the failure (thread-local string).  On an
  *     error nothing has been launched.  The library never aborts or prints.
+ *   - Equatorial crossings: Boyer-Lindquist theta is continued through the
+ *     poles (a ray with l = 0, from a pixel with X = 0, passes over the axis),
+ *     so the equator is theta = pi/2 (mod pi); a crossing where theta = -pi/2
+ *     (mod 2 pi) reports its azimuth as phi + pi (the same point).
  *   - Screen layout: pixel (ix, iy), 0 <= ix < nx, 0 <= iy < ny, sits at the
  *     centre X = x_min + (ix + 1/2)(x_max - x_min)/nx,
  *                Y = y_min + (iy + 1/2)(y_max - y_min)/ny,
@@ -78,7 +82,9 @@ enum {
 enum {
   RT_RAY_CAPTURED = 1,    /* R <= r_stop_fac * R_+ at the end of an accepted step */
   RT_RAY_ESCAPED = 2,     /* R >= r_esc_fac * R_o at the end of an accepted step  */
-  RT_RAY_STEP_LIMIT = 3   /* max_attempts step attempts used                      */
+  RT_RAY_STEP_LIMIT = 3,  /* max_attempts step attempts used                      */
+  RT_RAY_NONFINITE = 4    /* 20 consecutive attempts with a non-finite error
+                             estimate (each rejected, the step shrunk by 0.2)     */
 };
 
 /* Parameters of one image (host memory). */
@@ -221,6 +227,25 @@ int rt_parameter_scan(const rt_scan_point *points, int32_t n, double *out, void 
 enum { RT_DIAG_COUNT = 14 };
 int rt_image_diagnostics(const double *intensity, const rt_image_params *params, double bin_width,
                          int32_t n_bins, double *out, double *profile, void *hip_stream);
+
+/* rt_image_diagnostics without any allocation, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the same kernels and the same results,
+ * bit for bit, with their partial sums in a file-scope device array of the
+ * library (about 533 KB on each device it runs on, held until the process
+ * ends) instead of stream-ordered scratch.  The array is shared by every call
+ * on a device and keeps the last call's contents (every value is written
+ * before it is read, so nothing is carried over): calls that overlap on one
+ * device, on different streams or threads, race and must be serialised by
+ * the caller.  Arguments and errors as for rt_image_diagnostics; without a
+ * profile buffer (profile NULL) the profile bins live in that array, so
+ * n_bins may be at most RT_DIAG_NOALLOC_MAX_BINS (RT_ERR_ARG otherwise).
+ * Calls no hipMalloc, hipFree or allocating library routine; the array's
+ * device address is looked up once per device on the first call there. */
+enum { RT_DIAG_NOALLOC_MAX_BINS = 65536 };
+int rt_image_diagnostics_noalloc(const double *intensity, const rt_image_params *params,
+                                 double bin_width, int32_t n_bins, double *out, double *profile,
+                                 void *hip_stream);
 
 /* Shadow boundary (Sec. 4.1, eqs. (78)-(79)): along each screen direction
  * (cos psi, sin psi), the impact parameter b at which the rays from

@@ -20,7 +20,7 @@ enum : int32_t { KERR = 0, EINASTO = 1, CNFW = 2 };
 // for images whose halo has |eta| <= dm::kExpm1Near (ImageConst::ex_near).
 constexpr int32_t CNFW_NEAR = 3;
 __host__ __device__ constexpr bool is_cnfw(int32_t m) { return m == CNFW || m == CNFW_NEAR; }
-enum : int32_t { RAY_CAPTURED = 1, RAY_ESCAPED = 2, RAY_STEP_LIMIT = 3 };
+enum : int32_t { RAY_CAPTURED = 1, RAY_ESCAPED = 2, RAY_STEP_LIMIT = 3, RAY_NONFINITE = 4 };
 
 // Everything a kernel needs to know about one image.  Passed by value as a
 // kernel argument (it lands in the kernarg segment and is read through the

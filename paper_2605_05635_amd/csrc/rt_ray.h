@@ -17,6 +17,12 @@ namespace rt {
 namespace ray {
 
 constexpr double kHalfPi = 1.5707963267948966;
+constexpr double kPi = 3.141592653589793;
+constexpr double kInvPi = 0.3183098861837907;
+// A ray whose error estimate is not finite on this many consecutive attempts
+// (its step shrunk by 0.2 each time, to ~1e-14 of where it started) ends with
+// RAY_NONFINITE.
+constexpr int32_t kNonfiniteRun = 20;
 
 __host__ __device__ __forceinline__ double rcp(double x) { return dm::recip1(x); }
 __host__ __device__ __forceinline__ float rcp(float x) { return dm::recip(x); }
@@ -275,7 +281,33 @@ __host__ __device__ __forceinline__ void start_ray(const ImageConst& c, const Ho
     start_ray_dir<METRIC>(c, k, screen_dir(c, pix), pix, r);
 }
 
-// Root of theta(s) = pi/2 on the step's continuous extension, s in (0, 1),
+// Equatorial passage of a step from theta0 to theta1 (Sec. 3.3).
+// Boyer-Lindquist theta is continued through the poles (a ray with l = 0
+// passes over the axis and leaves (0, pi); (theta, phi) and (-theta, phi + pi)
+// are one point), so the equator is theta = pi/2 (mod pi).  The band index
+// floor((theta - pi/2)/pi) changes exactly when a step crosses it; for theta
+// in (0, pi) that is a change of the boolean theta >= pi/2.  th_eq is the
+// crossed equator's theta, up0 whether theta0 lies above it, phi_shift the
+// azimuth to add where th_eq = -pi/2 (mod 2 pi) (the far side of the axis).
+struct Passage {
+    double th_eq, phi_shift;
+    bool up0;
+};
+
+__host__ __device__ __forceinline__ double equator_band(double th) {
+    return floor((th - kHalfPi) * kInvPi);
+}
+
+__host__ __device__ __forceinline__ Passage passage_of(double band0, double band1) {
+    const double kk = fmax(band0, band1);
+    Passage p;
+    p.th_eq = kHalfPi + kk * kPi;
+    p.phi_shift = (kk - 2.0 * floor(0.5 * kk)) != 0.0 ? kPi : 0.0;
+    p.up0 = band0 > band1;
+    return p;
+}
+
+// Root of theta(s) = th_eq on the step's continuous extension, s in (0, 1),
 // given theta(0) and theta(1) on opposite sides.  Writing the extension as
 // y0 + s (c1 + s (c2 + s (c3 + s c4))), Newton's method starts from the secant
 // root and is kept inside the shrinking sign bracket (bisection when a Newton
@@ -286,16 +318,17 @@ __host__ __device__ __forceinline__ void start_ray(const ImageConst& c, const Ho
 // bracket and would hand over to bisection).  The quotients use the
 // one-Newton-step reciprocal (2e-15): an error of that size in a Newton step
 // is corrected by the next.
-__host__ __device__ __forceinline__ double crossing_root(const DenseComp& d, bool up0) {
+__host__ __device__ __forceinline__ double crossing_root(const DenseComp& d, bool up0,
+                                                        double th_eq) {
     const double c1 = d.r2 + d.r3;
     const double c2 = d.r4 + d.r5 - d.r3;
     const double c3 = -d.r4 - 2.0 * d.r5;
     const double c4 = d.r5;
     double a = 0.0, b = 1.0;
-    double s = (kHalfPi - d.y0) * rcp(d.r2);
+    double s = (th_eq - d.y0) * rcp(d.r2);
     if (!(s > 0.0 && s < 1.0)) s = 0.5;
     for (int it = 0; it < 48; ++it) {
-        const double f = d.y0 + s * (c1 + s * (c2 + s * (c3 + s * c4))) - kHalfPi;
+        const double f = d.y0 + s * (c1 + s * (c2 + s * (c3 + s * c4))) - th_eq;
         if (f == 0.0) break;   // s is a root of the evaluated extension
         if ((f >= 0.0) == up0) a = s; else b = s;
         const double df = c1 + s * (2.0 * c2 + s * (3.0 * c3 + s * 4.0 * c4));
@@ -461,18 +494,21 @@ __host__ __device__ __forceinline__ int32_t attempt(const Hot& k, const OutPtrs&
     const double err2 = acc * (THICK ? 1.0 / 7.0 : 1.0 / 6.0);
     const double grow = 0.9 * dm::rpow_tenth(fmin(fmax(err2, 1e-12), 1e12));
     if (!(err2 < 1.0)) {  // reject; NaN lands here too
-        r.h = h * (__builtin_isfinite(err2) ? fmax(0.2, grow) : 0.2);
-        r.after_reject = 1;
-        return 0;
+        const bool finite = __builtin_isfinite(err2);
+        r.h = h * (finite ? fmax(0.2, grow) : 0.2);
+        // 1 after a rejection, plus 2 per consecutive non-finite estimate
+        r.after_reject = finite ? 1 : (r.after_reject | 1) + 2;
+        return r.after_reject >= 2 * kNonfiniteRun + 1 ? RAY_NONFINITE : 0;
     }
     double factor = err2 == 0.0 ? 10.0 : fmin(10.0, grow);
     if (r.after_reject) factor = fmin(1.0, factor);
     r.after_reject = 0;
 
-    // Equatorial crossing (Sec. 3.3): the sign of theta - pi/2 changes.
-    const bool up0 = (r.y[2] - kHalfPi) >= 0.0;
-    const bool up1 = (yn[2] - kHalfPi) >= 0.0;
-    if (up0 != up1) {
+    // Equatorial crossing (Sec. 3.3): theta's band index changes.
+    const double band0 = equator_band(r.y[2]);
+    const double band1 = equator_band(yn[2]);
+    if (band0 != band1) {
+        const Passage ps = passage_of(band0, band1);
         auto dense = [&](int i) {
             DenseComp d;
             d.y0 = r.y[i];
@@ -482,7 +518,7 @@ __host__ __device__ __forceinline__ int32_t attempt(const Hot& k, const OutPtrs&
             d.r5 = h * ad[i];
             return d;
         };
-        const double s = crossing_root(dense(2), up0);
+        const double s = crossing_root(dense(2), ps.up0, ps.th_eq);
         const double Rc = dense(1).at(s);
         const double pthc = dense(5).at(s);
         const double lc = r.lam + s * h;
@@ -497,7 +533,7 @@ __host__ __device__ __forceinline__ int32_t attempt(const Hot& k, const OutPtrs&
                 r.rc[1] = n == 1 ? Rc : r.rc[1];
                 r.rc[2] = n == 2 ? Rc : r.rc[2];
                 if (o.r_em) o.r_em[off] = Rc;
-                if (o.phi_em) o.phi_em[off] = dense(3).at(s);
+                if (o.phi_em) o.phi_em[off] = dense(3).at(s) + ps.phi_shift;
                 if (o.t_em) o.t_em[off] = dense(0).at(s);
             }
             if (r.ncross < 255) ++r.ncross;

@@ -158,9 +158,12 @@ __device__ __forceinline__ int32_t attempt32(const Hot32& k, const OutPtrs& o, i
     const float err2 = acc * (1.0f / 6.0f);
     const float grow = 0.9f * dm::rpow_tenth(fminf(fmaxf(err2, 1e-12f), 1e12f));
     if (!(err2 < 1.0f)) {
-        r.h = h * (__builtin_isfinite(err2) ? fmaxf(0.2f, grow) : 0.2f);
-        r.after_reject = 1;
-        return 0;
+        const bool finite = __builtin_isfinite(err2);
+        r.h = h * (finite ? fmaxf(0.2f, grow) : 0.2f);
+        // as in binary64; a ray that stays non-finite in binary32 is traced
+        // again in binary64, which decides its fate
+        r.after_reject = finite ? 1 : (r.after_reject | 1) + 2;
+        return r.after_reject >= 2 * kNonfiniteRun + 1 ? kRerun : 0;
     }
     // A step into the horizon zone goes to binary64, with the rest of the ray.
     if (wide(nhi[1], nlo[1]) < k.r_zone) return kHandOff;
@@ -171,9 +174,10 @@ __device__ __forceinline__ int32_t attempt32(const Hot32& k, const OutPtrs& o, i
     // Equatorial crossing, located in binary64 on the continuous extension
     // through the compensated end points.
     const double th0 = wide(r.hi[2], r.lo[2]), th1 = wide(nhi[2], nlo[2]);
-    const bool up0 = (th0 - kHalfPi) >= 0.0;
-    const bool up1 = (th1 - kHalfPi) >= 0.0;
-    if (up0 != up1) {
+    const double band0 = equator_band(th0);
+    const double band1 = equator_band(th1);
+    if (band0 != band1) {
+        const Passage ps = passage_of(band0, band1);
         const double hd = static_cast<double>(h);
         auto dense = [&](int i) {
             DenseComp d;
@@ -184,7 +188,7 @@ __device__ __forceinline__ int32_t attempt32(const Hot32& k, const OutPtrs& o, i
             d.r5 = hd * static_cast<double>(ad[i]);
             return d;
         };
-        const double s = crossing_root(dense(2), up0);
+        const double s = crossing_root(dense(2), ps.up0, ps.th_eq);
         const double Rc = dense(1).at(s);
         const double pthc = dense(5).at(s);
         const double lc = r.lam + s * hd;
@@ -196,7 +200,7 @@ __device__ __forceinline__ int32_t attempt32(const Hot32& k, const OutPtrs& o, i
                 r.rc[1] = n == 1 ? Rc : r.rc[1];
                 r.rc[2] = n == 2 ? Rc : r.rc[2];
                 if (o.r_em) o.r_em[off] = Rc;
-                if (o.phi_em) o.phi_em[off] = dense(3).at(s);
+                if (o.phi_em) o.phi_em[off] = dense(3).at(s) + ps.phi_shift;
                 if (o.t_em) o.t_em[off] = dense(0).at(s);
             }
             if (r.ncross < 255) ++r.ncross;

@@ -337,7 +337,8 @@ __host__ __device__ __forceinline__ bool emits(const ImageConst& c, const Hot& k
 // On entry xb is the adjoint of the state after the step, on return the
 // adjoint of x0.  If the step recorded a crossing (cross >= 0), its
 // intensity's cotangent Ib enters through the crossing radius, located on the
-// continuous extension at the root s* of theta(s) = pi/2: with
+// continuous extension at the root s* of theta(s) = theta_eq (pi/2, or the
+// equator's value beyond a pole): with
 //   y(s) = y0 + h sum_j beta_j(s) k_j,
 //   beta_j = (3s^2 - 2s^3) b_j + [j=1] s(1-s)^2 - [j=7] s^2(1-s) + s^2(1-s)^2 d_j,
 // R_c = R(s*) moves by dR - (R'(s*)/theta'(s*)) dtheta (implicit function
@@ -403,8 +404,8 @@ __host__ __device__ __forceinline__ void reverse_step(const ImageConst& c, const
             dc[i].r4 = dc[i].r2 - h * k7[i] - dc[i].r3;
             dc[i].r5 = h * ad;
         }
-        const bool up0 = (x0[1] - kHalfPi) >= 0.0;
-        const double s = crossing_root(dc[1], up0);
+        const Passage ps = passage_of(equator_band(x0[1]), equator_band(yn[1]));
+        const double s = crossing_root(dc[1], ps.up0, ps.th_eq);
         const double Rc = dc[0].at(s);
         double Rb = 0.0;
         emission_vjp<METRIC>(c, Rc, E, L, Ib, Rb, Eb, Lb, pb, rinb);

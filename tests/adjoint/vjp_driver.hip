@@ -157,7 +157,7 @@ int main(int argc, char** argv) {
             d.r3 = a[2];
             d.r4 = a[3];
             d.r5 = a[4];
-            out.push_back(ray::crossing_root(d, a[5] != 0.0));
+            out.push_back(ray::crossing_root(d, a[5] != 0.0, ray::kHalfPi));
         } else if (rhs_mode) {
             if (m == KERR) rhs_case<KERR>(a, out);
             else if (m == EINASTO) rhs_case<EINASTO>(a, out);

@@ -75,6 +75,30 @@ def test_ragged_screens(rt, orc, img):
     say(summary(g, o))
 
 
+@pytest.mark.parametrize("img", [
+    W.image(metric="kerr", spin=0.5, incl=math.radians(17), nx=1, ny=97, y_min=-10, y_max=10),
+    W.image(metric="kerr", spin=0.0, incl=math.radians(60), nx=1, ny=64),
+    W.image(metric="cnfw", spin=0.94, halo=(0.02, 10.0), incl=math.radians(163), nx=3, ny=61,
+            x_min=-0.1, x_max=0.1, y_min=-10, y_max=10),
+], ids=["kerr-17-axis", "schwarzschild-60-axis", "cnfw-163-axis"])
+def test_rays_over_the_pole(rt, orc, img):
+    """Screens whose centre column is X = 0 exactly: those photons have l = 0
+    and may pass over a pole, where theta leaves (0, pi); their crossings
+    continue on the equator's far side (azimuth phi + pi)."""
+    g, o = run_full(rt, orc, img)
+    assert_parity(g, o)
+    # the case holds rays whose theta leaves (0, pi) (logged by the oracle)
+    X, Y = orc.pixel_xy(img, np.arange(img["nx"] * img["ny"]))
+    axis = X == 0.0
+    assert axis.sum() >= img["ny"]
+    over = 0
+    for x, y in zip(X[axis][::2], Y[axis][::2]):
+        _, log = orc.trace_ray(img, x, y, log_cap=20000)
+        over += bool(((log[:, 4] <= 0.0) | (log[:, 4] >= math.pi)).any())
+    assert over >= 5, "no ray passes over a pole in this case"
+    say(summary(g, o) + f"; {over} sampled rays over a pole")
+
+
 def test_transfer_maps_only(rt, orc):
     img = W.image(metric="cnfw", spin=0.7, halo=(0.03, 12.0), incl=math.radians(50), nx=40,
                   ny=36)
