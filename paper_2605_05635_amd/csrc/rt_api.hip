@@ -937,6 +937,78 @@ int image_vjp(const rt_image_params* params, const double* dl_dI, int32_t basis,
     return RT_OK;
 }
 
+// Arguments of the diagnostics entry points: validated, screen constants in c.
+int diagnostics_args(const double* intensity, const rt_image_params* params, double bin_width,
+                     int32_t n_bins, const double* out, const double* profile, rt::ImageConst* c) {
+    if (!intensity || !params || !out) return fail(RT_ERR_ARG, "null intensity, params or out");
+    if (n_bins < 1 || n_bins > (1 << 20)) return fail(RT_ERR_ARG, "n_bins must lie in [1, 2^20]");
+    if (!std::isfinite(bin_width) || !(bin_width > 0.0))
+        return fail(RT_ERR_ARG, "bin_width must be finite and positive");
+    const rt_image_params* p = params;
+    if (p->nx < 1 || p->ny < 1 || static_cast<int64_t>(p->nx) * p->ny >= (int64_t(1) << 31))
+        return fail(RT_ERR_ARG, "bad screen size %d x %d", p->nx, p->ny);
+    if (!finite_all({p->x_min, p->x_max, p->y_min, p->y_max}) || !(p->x_min < p->x_max) ||
+        !(p->y_min < p->y_max))
+        return fail(RT_ERR_ARG, "bad screen extent");
+    std::memset(c, 0, sizeof *c);
+    c->nx = p->nx;
+    c->ny = p->ny;
+    c->n_pix = static_cast<int64_t>(p->nx) * p->ny;
+    c->x0 = p->x_min;
+    c->dx = (p->x_max - p->x_min) / p->nx;
+    c->y0 = p->y_min;
+    c->dy = (p->y_max - p->y_min) / p->ny;
+    int rc;
+    if ((rc = check_device_ptr(intensity, "intensity", 0)) || (rc = check_device_ptr(out, "out", 0)) ||
+        (rc = check_device_ptr(profile, "profile", 0)))
+        return rc;
+    return RT_OK;
+}
+
+int image_diagnostics(const double* intensity, const rt_image_params* params, double bin_width,
+                      int32_t n_bins, double* out, double* profile, void* hip_stream) {
+    rt::ImageConst c;
+    int rc = diagnostics_args(intensity, params, bin_width, n_bins, out, profile, &c);
+    if (rc != RT_OK) return rc;
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    const size_t bytes = sizeof(double) * rt::diagnostics_scratch_doubles(n_bins);
+    void* scratch = nullptr;
+    hipError_t e = hipMallocAsync(&scratch, bytes, stream);
+    if (e != hipSuccess || !scratch) {
+        (void)hipGetLastError();
+        return fail(RT_ERR_ALLOC, "stream-ordered allocation of %zu scratch bytes failed", bytes);
+    }
+    e = rt::launch_diagnostics(c, intensity, bin_width, n_bins, out, profile,
+                               static_cast<double*>(scratch), stream);
+    const hipError_t ef = hipFreeAsync(scratch, stream);
+    if (e != hipSuccess) return hip_fail(e, "diagnostics kernel launch");
+    if (ef != hipSuccess) return hip_fail(ef, "hipFreeAsync");
+    return RT_OK;
+}
+
+// As image_diagnostics, with the file-scope work array of rt_diagnostics.hip
+// in place of stream-ordered scratch: no allocation of any kind.
+int image_diagnostics_noalloc(const double* intensity, const rt_image_params* params,
+                              double bin_width, int32_t n_bins, double* out, double* profile,
+                              void* hip_stream) {
+    rt::ImageConst c;
+    int rc = diagnostics_args(intensity, params, bin_width, n_bins, out, profile, &c);
+    if (rc != RT_OK) return rc;
+    if (!profile && n_bins > rt::kNoAllocMaxBins)
+        return fail(RT_ERR_ARG, "without a profile buffer n_bins may be at most %d",
+                    rt::kNoAllocMaxBins);
+    double* work = nullptr;
+    size_t have = 0;
+    hipError_t e = rt::diagnostics_static_work(&work, &have);
+    if (e != hipSuccess) return hip_fail(e, "static work array lookup");
+    if (rt::diagnostics_scratch_doubles(profile ? 0 : n_bins) > have)
+        return fail(RT_ERR_ARG, "static work array too small");
+    e = rt::launch_diagnostics(c, intensity, bin_width, n_bins, out, profile, work,
+                               static_cast<hipStream_t>(hip_stream));
+    if (e != hipSuccess) return hip_fail(e, "diagnostics kernel launch");
+    return RT_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1015,43 +1087,15 @@ int rt_parameter_scan(const rt_scan_point* points, int32_t n, double* out, void*
 int rt_image_diagnostics(const double* intensity, const rt_image_params* params, double bin_width,
                          int32_t n_bins, double* out, double* profile, void* hip_stream) {
     g_last_error.clear();
-    if (!intensity || !params || !out) return fail(RT_ERR_ARG, "null intensity, params or out");
-    if (n_bins < 1 || n_bins > (1 << 20)) return fail(RT_ERR_ARG, "n_bins must lie in [1, 2^20]");
-    if (!std::isfinite(bin_width) || !(bin_width > 0.0))
-        return fail(RT_ERR_ARG, "bin_width must be finite and positive");
-    const rt_image_params* p = params;
-    if (p->nx < 1 || p->ny < 1 || static_cast<int64_t>(p->nx) * p->ny >= (int64_t(1) << 31))
-        return fail(RT_ERR_ARG, "bad screen size %d x %d", p->nx, p->ny);
-    if (!finite_all({p->x_min, p->x_max, p->y_min, p->y_max}) || !(p->x_min < p->x_max) ||
-        !(p->y_min < p->y_max))
-        return fail(RT_ERR_ARG, "bad screen extent");
-    rt::ImageConst c;
-    std::memset(&c, 0, sizeof c);
-    c.nx = p->nx;
-    c.ny = p->ny;
-    c.n_pix = static_cast<int64_t>(p->nx) * p->ny;
-    c.x0 = p->x_min;
-    c.dx = (p->x_max - p->x_min) / p->nx;
-    c.y0 = p->y_min;
-    c.dy = (p->y_max - p->y_min) / p->ny;
-    int rc;
-    if ((rc = check_device_ptr(intensity, "intensity", 0)) || (rc = check_device_ptr(out, "out", 0)) ||
-        (rc = check_device_ptr(profile, "profile", 0)))
-        return rc;
-    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
-    const size_t bytes = sizeof(double) * rt::diagnostics_scratch_doubles(n_bins);
-    void* scratch = nullptr;
-    hipError_t e = hipMallocAsync(&scratch, bytes, stream);
-    if (e != hipSuccess || !scratch) {
-        (void)hipGetLastError();
-        return fail(RT_ERR_ALLOC, "stream-ordered allocation of %zu scratch bytes failed", bytes);
-    }
-    e = rt::launch_diagnostics(c, intensity, bin_width, n_bins, out, profile,
-                               static_cast<double*>(scratch), stream);
-    const hipError_t ef = hipFreeAsync(scratch, stream);
-    if (e != hipSuccess) return hip_fail(e, "diagnostics kernel launch");
-    if (ef != hipSuccess) return hip_fail(ef, "hipFreeAsync");
-    return RT_OK;
+    return image_diagnostics(intensity, params, bin_width, n_bins, out, profile, hip_stream);
+}
+
+int rt_image_diagnostics_noalloc(const double* intensity, const rt_image_params* params,
+                                 double bin_width, int32_t n_bins, double* out, double* profile,
+                                 void* hip_stream) {
+    g_last_error.clear();
+    return image_diagnostics_noalloc(intensity, params, bin_width, n_bins, out, profile,
+                                     hip_stream);
 }
 
 int rt_shadow_boundary(const rt_image_params* params, const double* dirs, int32_t n,

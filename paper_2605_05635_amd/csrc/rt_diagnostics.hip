@@ -10,6 +10,8 @@
 // profile (its threads take whole rows and visit only the columns that can
 // reach its annulus, keeping the pixels whose bin is exactly its own), and one
 // workgroup that picks the first bin of largest mean.
+#include <mutex>
+
 #include "rt_kernels.h"
 
 namespace rt {
@@ -249,10 +251,43 @@ size_t diagnostics_scratch_doubles(int32_t n_bins) {
     return 3 + 3 * kReduceBlocks + kA * kReduceBlocks + kReduceBlocks + static_cast<size_t>(n_bins);
 }
 
+// Work memory of rt_image_diagnostics_noalloc: the partial sums and, when the
+// caller passes no profile, up to kNoAllocMaxBins profile bins (~533 KB).
+// Each device the library runs on holds its own copy until the process ends.
+// In host code `scratch` names a host-side stand-in, never a device address:
+// kernels get the address that hipGetSymbolAddress returns for the current
+// device.
+constexpr size_t kStaticWorkDoubles = 3 + (3 + kA + 1) * kReduceBlocks + kNoAllocMaxBins;
+static __device__ __align__(256) double scratch[kStaticWorkDoubles];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_static_work_mu;
+double* g_static_work[kMaxDevices] = {};   // device address of `scratch` per device
+}  // namespace
+
+hipError_t diagnostics_static_work(double** ptr, size_t* doubles) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_static_work_mu);
+    if (!g_static_work[dev]) {
+        double* p = nullptr;
+        e = hipGetSymbolAddress(reinterpret_cast<void**>(&p), HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_static_work[dev] = p;
+    }
+    *ptr = g_static_work[dev];
+    *doubles = kStaticWorkDoubles;
+    return hipSuccess;
+}
+
 hipError_t launch_diagnostics(const ImageConst& c, const double* intensity, double bw,
-                              int32_t n_bins, double* out, double* profile, double* scratch,
+                              int32_t n_bins, double* out, double* profile, double* work,
                               hipStream_t stream) {
-    double* fc = scratch;                            // F, X_c, Y_c
+    double* fc = work;                               // F, X_c, Y_c
     double* p3 = fc + 3;                             // flux / centroid partials
     double* pa = p3 + 3 * kReduceBlocks;
     double* pb = pa + kA * kReduceBlocks;

@@ -75,12 +75,18 @@ hipError_t launch_trace_thick(const ImageConst& c, const OutPtrs& o, unsigned lo
 hipError_t launch_scan(const ::rt_scan_point* pts, int32_t n, double* out, hipStream_t stream);
 
 // Image diagnostics of `intensity` on the screen of c (rt_image_diagnostics):
-// out[0..14); profile[n_bins] (or scratch when null); scratch holds
-// diagnostics_scratch_doubles(n_bins) doubles.  Deterministic.
+// out[0..14); profile[n_bins] (or work memory when null); `work` holds
+// diagnostics_scratch_doubles(n_bins) doubles, every one written before it is
+// read (nothing needs clearing).  Deterministic.
 size_t diagnostics_scratch_doubles(int32_t n_bins);
 hipError_t launch_diagnostics(const ImageConst& c, const double* intensity, double bw,
-                              int32_t n_bins, double* out, double* profile, double* scratch,
+                              int32_t n_bins, double* out, double* profile, double* work,
                               hipStream_t stream);
+// The diagnostics' file-scope device work array for the entry point that
+// allocates nothing: its device address on the current device (looked up
+// once per device) and its size in doubles.
+constexpr int32_t kNoAllocMaxBins = 65536;
+hipError_t diagnostics_static_work(double** ptr, size_t* doubles);
 
 // Shadow-boundary search: `samples` (64, 32 or 16) lanes per direction
 // dirs[2i], dirs[2i+1] (cos psi, sin psi); out[2i], out[2i+1] = the final bracket of b, status[i]

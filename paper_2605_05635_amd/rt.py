@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(PKG, "libgeodesic_rt.so")
 RT_KERR, RT_EINASTO, RT_CNFW = 0, 1, 2
 RT_FP64, RT_MIXED = 0, 1
 RT_OK, RT_ERR_ARG, RT_ERR_NO_HORIZON, RT_ERR_HIP, RT_ERR_ALLOC = 0, -1, -2, -3, -4
-RT_RAY_CAPTURED, RT_RAY_ESCAPED, RT_RAY_STEP_LIMIT = 1, 2, 3
+RT_RAY_CAPTURED, RT_RAY_ESCAPED, RT_RAY_STEP_LIMIT, RT_RAY_NONFINITE = 1, 2, 3, 4
 RT_GRAD_NATIVE, RT_GRAD_DENSITY = 0, 1
 RT_ORDER_CENTRE, RT_ORDER_SCREEN = 0, 1
 METRIC_ID = {"kerr": RT_KERR, "einasto": RT_EINASTO, "cnfw": RT_CNFW}
@@ -94,6 +94,8 @@ def _load():
     lib.rt_image_diagnostics.argtypes = [C.c_void_p, P, C.c_double, C.c_int32, C.c_void_p,
                                          C.c_void_p, C.c_void_p]
     lib.rt_image_diagnostics.restype = C.c_int
+    lib.rt_image_diagnostics_noalloc.argtypes = lib.rt_image_diagnostics.argtypes
+    lib.rt_image_diagnostics_noalloc.restype = C.c_int
     lib.rt_shadow_boundary.argtypes = [P, C.c_void_p, C.c_int32, C.c_int32, C.c_double, C.c_double,
                                        C.c_double, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
     lib.rt_shadow_boundary.restype = C.c_int
@@ -276,6 +278,7 @@ def parameter_scan(metric, spin, halo0, halo1, theta, stream=None):
 
 
 RT_DIAG_COUNT = 14
+RT_DIAG_NOALLOC_MAX_BINS = 65536
 DIAG_KEYS = ("F", "X_c", "Y_c", "C", "rho_bar", "d_img", "w_img", "w_over_d", "A_LR",
              "I_max", "I_mean_emitting", "P", "rho_peak", "d_peak")
 
@@ -288,6 +291,16 @@ def rt_image_diagnostics(intensity, params: rt_image_params, bin_width: float, n
                                      bin_width, n_bins, C.c_void_p(out.data_ptr()),
                                      None if profile is None else C.c_void_p(profile.data_ptr()),
                                      _stream_handle(stream)))
+
+
+def rt_image_diagnostics_noalloc(intensity, params: rt_image_params, bin_width: float,
+                                 n_bins: int, out, profile=None, stream=None) -> None:
+    """Calls rt_image_diagnostics_noalloc (the entry point that allocates
+    nothing) on device tensors, as rt_image_diagnostics."""
+    _check(_lib.rt_image_diagnostics_noalloc(
+        C.c_void_p(intensity.data_ptr()), C.byref(params), bin_width, n_bins,
+        C.c_void_p(out.data_ptr()), None if profile is None else C.c_void_p(profile.data_ptr()),
+        _stream_handle(stream)))
 
 
 def image_diagnostics(img: dict, intensity, bin_width: float, n_bins: int, stream=None):
@@ -445,10 +458,10 @@ def image_vjp(img: dict, dl_dI, basis: str = "native", per_pixel: bool = False, 
 
 __all__ = ["rt_mixed_stats", "rt_image_vjp", "rt_set_tape_budget", "rt_vjp_stats", "image_vjp", "rt_trace_image", "rt_transfer_maps", "rt_image_setup", "rt_set_kernel_timing",
            "rt_set_launch_config", "rt_get_launch_config", "rt_visibility_dft", "visibility",
-           "rt_shadow_boundary", "rt_shadow_boundary_samples", "shadow_boundary", "rt_image_diagnostics", "image_diagnostics",
+           "rt_shadow_boundary", "rt_shadow_boundary_samples", "shadow_boundary", "rt_image_diagnostics", "rt_image_diagnostics_noalloc", "image_diagnostics",
            "rt_parameter_scan", "parameter_scan", "rt_scan_point",
            "rt_trace_thick", "trace_thick", "rt_thick_disc",
-           "RT_DIAG_COUNT", "DIAG_KEYS",
+           "RT_DIAG_COUNT", "RT_DIAG_NOALLOC_MAX_BINS", "DIAG_KEYS",
            "rt_version",
            "rt_last_error", "trace", "trace_many", "params_from", "out_from", "alloc_outputs",
            "RTError"]
