@@ -25,6 +25,8 @@ if ROOT not in sys.path:
 
 METRIC = "geodesic rays/s at 1024² (FP64 vs mixed); adjoint image-gradient ms"
 FP64_VECTOR_PEAK_TFLOPS = 78.6   # MI355X: 256 CUs x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
+FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X, packed binary32 (two FMAs per lane per cycle)
+HOST_THREADS = 16                # the host cores one GPU of the box comes with
 
 
 def log(msg: str) -> None:
@@ -44,19 +46,69 @@ def measured_traffic(kernel_hash: str):
     return d.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(img: dict, stride: int) -> dict:
+def host_cpu() -> dict:
+    """The host this runs on: CPU model, logical CPUs of the machine and of
+    this process's affinity mask."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = os.cpu_count() or 1
+    return {"cpu_model": model, "nproc": usable, "cpu_count": os.cpu_count() or 1}
+
+
+def oracle_threads() -> int:
+    return max(1, min(HOST_THREADS, host_cpu()["nproc"]))
+
+
+def cpu_baseline(img: dict, stride: int):
+    """The oracle timed on the host's cores on the same screen (every
+    `stride`-th pixel in x and y).  Returns the baseline object and the
+    oracle's outputs with their pixel indices, from which the bench reports
+    the GPU images' per-pixel error against the oracle."""
     from oracle import oracle as O
     from paper_2605_05635_amd import workloads as W
-    threads = max(1, min(16, os.cpu_count() or 1))
+    threads = oracle_threads()
     idx = W.subsample_indices(img["nx"], img["ny"], stride)
     log(f"cpu baseline: oracle on {idx.size} pixels with {threads} threads")
     t0 = time.perf_counter()
-    O.trace_pixels(img, idx, threads=threads)
+    ref = O.trace_pixels(img, idx, threads=threads)
     dt = time.perf_counter() - t0
-    return {"value": idx.size / dt, "unit": "rays/s", "cores": threads, "kind": "oracle",
-            "sample": (f"every {stride}th pixel in x and y of" if stride > 1 else "every pixel of")
-                      + " the same screen "
-                      f"({idx.size} rays, {dt:.1f} s)"}
+    res = {"value": idx.size / dt, "unit": "rays/s", "cores": threads, "kind": "oracle",
+           "sample": (f"every {stride}th pixel in x and y of" if stride > 1 else "every pixel of")
+                     + " the same screen "
+                     f"({idx.size} rays, {dt:.1f} s)", **host_cpu()}
+    return res, ref, idx
+
+
+def error_vs_oracle(outs: dict, ref: dict, idx) -> dict:
+    """Per-pixel difference of a GPU image from the oracle's trace of the same
+    pixels: as image_error, plus the fraction of pixels whose intensity is
+    within the binary64 parity bar (1e-6 relative, exact zeros)."""
+    import numpy as np
+    import torch
+    ii = torch.as_tensor(np.asarray(idx), device=outs["ncross"].device)
+    take = lambda t: t.reshape(-1)[ii] if t.dim() == 2 else t.reshape(3, -1)[:, ii]  # noqa: E731
+    g = {k: take(outs[k]) for k in ("ncross", "status", "intensity", "r_em")}
+    o = {"ncross": torch.as_tensor(ref["ncross"], device=ii.device),
+         "status": torch.as_tensor(ref["status"], device=ii.device),
+         "intensity": torch.as_tensor(ref["intensity"], device=ii.device),
+         "r_em": torch.as_tensor(ref["r_em"], device=ii.device)}
+    res = image_error(g, o)
+    same = (g["ncross"].long() == o["ncross"].long()) & (g["status"].long() == o["status"].long())
+    Io, Ig = o["intensity"], g["intensity"]
+    ok = torch.where(Io != 0, (Ig - Io).abs() <= 1e-6 * Io.abs(), Ig == 0) & same
+    res["pixels"] = int(ii.numel())
+    res["intensity_within_1e-6_frac"] = float(ok.double().mean().item())
+    return res
 
 
 def batch_measurement(steps: int) -> dict:
@@ -161,16 +213,51 @@ def mixed_measurement(steps: int, ref64: dict) -> dict:
     accuracy-matched comparison -- the error of the mixed image and of FP64
     images at tolerances 1e-6 ... 1e-9 against an FP64 reference at 1e-11,
     with each one's rays/s."""
-    from paper_2605_05635_amd import rt, workloads as W
+    import numpy as np
+    import torch
+
+    from paper_2605_05635_amd import census, rt, workloads as W
     img = W.cnfw_1024("mixed")
     n = img["nx"] * img["ny"]
-    outs, ms = timed_trace(img, steps)
+    splits = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    for ev in splits + starts:
+        ev.record()
+    outs = rt.alloc_outputs(img)
+    p, o = [rt.params_from(img)], [rt.out_from(outs)]
+    stream = torch.cuda.current_stream()
+    rt.rt_trace_image(p, o, stream)
+    stops = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    for ev in stops:
+        ev.record(stream)
+    torch.cuda.synchronize()
+    for k in range(steps):
+        rt.rt_set_kernel_timing(starts[k], stops[k])
+        rt.rt_set_split_timing(splits[k])
+        rt.rt_trace_image(p, o, stream)
+    rt.rt_set_kernel_timing(None, None)
+    rt.rt_set_split_timing(None)
+    torch.cuda.synchronize()
+    ms = float(np.mean([a.elapsed_time(b) for a, b in zip(starts, stops)]))
+    bulk_ms = float(np.mean([a.elapsed_time(b) for a, b in zip(starts, splits)]))
     stats = rt.rt_mixed_stats()
-    log(f"mixed: kernel {ms:.3f} ms, {stats['binary64']} rays finished in FP64 "
-        f"({stats['rerun']} traced again)")
+    log(f"mixed: kernel {ms:.3f} ms (binary32 pass {bulk_ms:.3f} ms), {stats['binary64']} rays "
+        f"finished in FP64 ({stats['rerun']} traced again)")
+    # the binary32 pass's algorithmic flops (binary32 arithmetic; its crossings,
+    # located in binary64, not counted) against the packed binary32 peak
+    f32 = stats["attempts32"] * (6 * census.flops_rhs(img["metric"])
+                                 + census.flops_step_overhead32())
+    t32 = f32 / (bulk_ms * 1e-3) / 1e12
     res = {"rays_per_s": n / (ms * 1e-3), "kernel_ms": ms, "fp64_finished": stats["binary64"],
            "fp64_reruns": stats["rerun"],
            "attempts_per_ray": float(outs["attempts"].double().mean().item()),
+           "binary32_pass": {"kernel": "trace32_kernel<CNFW_NEAR>", "kernel_ms": bulk_ms,
+                             "attempts": stats["attempts32"],
+                             "algorithmic_tflops": t32, "peak": FP32_VECTOR_PEAK_TFLOPS,
+                             "frac_of_fp32_vector_peak": t32 / FP32_VECTOR_PEAK_TFLOPS,
+                             "frac_of_unpacked_fp32_rate": t32 / FP64_VECTOR_PEAK_TFLOPS},
+           "binary64_pass": {"kernel": "resume_kernel<CNFW_NEAR>", "kernel_ms": ms - bulk_ms,
+                             "attempts": stats["attempts64"]},
            "error_vs_fp64_1e-8": image_error(outs, ref64)}
     tight = dict(W.cnfw_1024(), rtol=1e-11, atol=1e-11)
     ref, ref_ms = timed_trace(tight, 1)
@@ -192,7 +279,7 @@ def mixed_measurement(steps: int, ref64: dict) -> dict:
     res["speedup_vs_fp64_1e-8"] = res["rays_per_s"] / next(
         s_["rays_per_s"] for s_ in sweep if s_["tol"] == 1e-8)
     res["speedup_vs_fp64_matched"] = res["rays_per_s"] / match["rays_per_s"] if match else None
-    return res
+    return res, outs
 
 
 def adjoint_measurement(steps: int, cpu: bool) -> dict:
@@ -245,7 +332,7 @@ def adjoint_measurement(steps: int, cpu: bool) -> dict:
            "tape_bytes": stats["tape_bytes"]}
     if cpu:
         from oracle import oracle as O
-        threads = max(1, min(16, os.cpu_count() or 1))
+        threads = oracle_threads()
         idx = W.subsample_indices(img["nx"], img["ny"], 8)
         t0 = time.perf_counter()
         O.trace_grad_pixels(img, idx, threads=threads)
@@ -338,7 +425,7 @@ def thick_measurement(steps: int, cpu: bool) -> dict:
     if cpu:
         from oracle import oracle as O
         idx = W.subsample_indices(img["nx"], img["ny"], 16)
-        threads = max(1, min(16, os.cpu_count() or 1))
+        threads = oracle_threads()
         t0 = time.perf_counter()
         O.trace_thick_pixels(img, (8.0, 0.2, 0.1), idx, threads=threads)
         dt = time.perf_counter() - t0
@@ -439,7 +526,7 @@ def shadow_measurement(steps: int, cpu: bool) -> dict:
            "b_mean": float(bc.mean()), "b_min": float(bc.min()), "b_max": float(bc.max())}
     if cpu:
         from oracle import oracle as O
-        threads = max(1, min(16, os.cpu_count() or 1))
+        threads = oracle_threads()
         pick = np.arange(0, n, n // 16)
         t0 = time.perf_counter()
         O.shadow_boundary(img, dirs[pick], b_lo, b_hi, b_tol, threads=threads)
@@ -547,8 +634,9 @@ def main() -> int:
         "attempts_per_ray": attempts / n_rays,
         "roofline": roofline,
     }
+    mixed_outs = None
     if not args.no_mixed:
-        line["mixed"] = mixed_measurement(max(2, args.steps // 2), outs)
+        line["mixed"], mixed_outs = mixed_measurement(max(2, args.steps // 2), outs)
         line["mixed_rays_per_s"] = line["mixed"]["rays_per_s"]
     if not args.no_batch:
         line["batch_64"] = batch_measurement(max(2, args.steps // 4))
@@ -572,7 +660,12 @@ def main() -> int:
         line["calibration_copy_bytes"] = nbytes
         log(f"calibration copy: {nbytes} bytes read and {nbytes} bytes written")
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(img, args.cpu_stride)
+        line["cpu_baseline"], ref, idx = cpu_baseline(img, args.cpu_stride)
+        # the oracle's trace of the same pixels, against the GPU images
+        line["fp64_error_vs_oracle"] = error_vs_oracle(outs, ref, idx)
+        if mixed_outs is not None:
+            line["mixed"]["error_vs_oracle"] = error_vs_oracle(mixed_outs, ref, idx)
+        log(f"error vs oracle: fp64 {line['fp64_error_vs_oracle']}")
     print(json.dumps(line), flush=True)
     return 0
 

@@ -345,9 +345,16 @@ int rt_image_vjp(const rt_image_params *params, const double *dl_dI, int32_t bas
 /* Counters of the last mixed-precision image traced on this thread and the
  * current device: out[0] = rays finished in binary64 (continued from the
  * horizon zone or traced again), out[1] = of those, rays traced again from the
- * screen.  Synchronous (waits for that call's work).  Both 0 before any such
- * call. */
+ * screen, out[2] = step attempts made in binary32, out[3] = step attempts made
+ * by the binary64 pass.  `out` holds 4 values.  Synchronous (waits for that
+ * call's work).  All 0 before any such call. */
 int rt_mixed_stats(int64_t *out);
+
+/* Profiling hook beside rt_set_kernel_timing: when non-NULL (a hipEvent_t),
+ * every later rt_trace_image call on this thread records it on its stream
+ * between the binary32 pass and the binary64 pass of each mixed-precision
+ * image.  NULL switches it off.  The event stays owned by the caller. */
+int rt_set_split_timing(void *event);
 
 /* Device memory the gradient may use for tapes (thread-local, bytes, at least
  * 1 MiB; default 16 GiB).  A smaller budget only moves rays to the packed

@@ -122,6 +122,14 @@ def flops_step_overhead() -> int:
     return n
 
 
+def flops_step_overhead32() -> int:
+    """The binary32 attempt of the mixed-precision bulk: as
+    flops_step_overhead, with each of the six state updates y + h sum b_i k_i
+    done as an error-free (two-sum) addition into the compensated pair hi + lo
+    (10 operations in place of the one addition)."""
+    return flops_step_overhead() + 6 * 9
+
+
 def flops_crossing(newton: int = 3) -> int:
     """Locating one crossing (trace kernel): dense coefficients for theta, R,
     p_theta, phi and T; the safeguarded Newton iteration on theta(s) (`newton`

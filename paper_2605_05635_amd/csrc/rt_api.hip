@@ -20,6 +20,7 @@ namespace {
 
 thread_local std::string g_last_error;
 thread_local hipEvent_t g_timing_start = nullptr, g_timing_stop = nullptr;
+thread_local hipEvent_t g_timing_split = nullptr;   // after each mixed image's binary32 pass
 thread_local rt_launch_config g_launch = {0, 0, 0, 0, 0};
 
 int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
@@ -392,11 +393,11 @@ int mixed_stats_buffer(long long** out) {
     if (dev < 0 || dev >= 64) return fail(RT_ERR_HIP, "device index %d out of range", dev);
     if (!g_mixed_stats[dev]) {
         void* p = nullptr;
-        if ((e = hipMalloc(&p, 2 * sizeof(long long))) != hipSuccess || !p) {
+        if ((e = hipMalloc(&p, 4 * sizeof(long long))) != hipSuccess || !p) {
             (void)hipGetLastError();
             return fail(RT_ERR_ALLOC, "mixed-precision statistics buffer allocation failed");
         }
-        const long long zeros[2] = {0, 0};
+        const long long zeros[4] = {0, 0, 0, 0};
         if ((e = hipMemcpy(p, zeros, sizeof zeros, hipMemcpyHostToDevice)) != hipSuccess)
             return hip_fail(e, "statistics buffer initialisation");
         g_mixed_stats[dev] = static_cast<long long*>(p);
@@ -581,6 +582,7 @@ int trace_common(const rt_image_params* params, int32_t n_images, const rt_image
             (e = rt::launch_trace32(c, optrs[i], q, sh,
                                     grid_for(c.n_pix, rt::mixed_blocks_per_cu(c.metric, 0)),
                                     records, counters, stream)) != hipSuccess ||
+            (g_timing_split && (e = hipEventRecord(g_timing_split, stream)) != hipSuccess) ||
             (e = rt::launch_resume(c, optrs[i], records, counters, q + 1, 16,
                                    grid_for(c.n_pix, rt::mixed_blocks_per_cu(c.metric, 1)),
                                    stream)) != hipSuccess ||
@@ -1151,6 +1153,12 @@ int rt_image_setup(const rt_image_params* params, double* setup) {
     return RT_OK;
 }
 
+int rt_set_split_timing(void* event) {
+    g_last_error.clear();
+    g_timing_split = static_cast<hipEvent_t>(event);
+    return RT_OK;
+}
+
 int rt_set_kernel_timing(void* start_event, void* stop_event) {
     g_last_error.clear();
     if ((start_event == nullptr) != (stop_event == nullptr))
@@ -1245,11 +1253,10 @@ int rt_mixed_stats(int64_t* out) {
     long long* d = nullptr;
     int rc = mixed_stats_buffer(&d);
     if (rc != RT_OK) return rc;
-    long long h[2] = {0, 0};
+    long long h[4] = {0, 0, 0, 0};
     const hipError_t e = hipMemcpy(h, d, sizeof h, hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(e, "statistics read-back");
-    out[0] = h[0];
-    out[1] = h[1];
+    for (int i = 0; i < 4; ++i) out[i] = h[i];
     return RT_OK;
 }
 

@@ -128,11 +128,13 @@ void* blas_create();
 // Mixed precision.  trace32: the binary32 pass over the screen (order of
 // `shape`); rays leaving binary32 append a record of mixed_record_bytes() to
 // `records` (room for n_pix) and bump counters[0] (records) and counters[1]
-// (of which traced again from the screen); counters and *queue start at 0.
-// resume: the binary64 pass over the counters[0] records (count read on the
-// device); a continued ray reaching two crossings is traced again from the
-// screen and counted in counters[1].  copy_counters: stats[0..2) = counters[0..2).  `pass` of
-// mixed_blocks_per_cu: 0 trace32, 1 resume.
+// (of which traced again from the screen); counters (32 u32: [0], [1], then
+// u64 totals of step attempts at u32 offsets 4 (binary32) and 6 (binary64))
+// and *queue start at 0.  resume: the binary64 pass over the counters[0]
+// records (count read on the device); a continued ray reaching two crossings
+// is traced again from the screen and counted in counters[1].
+// copy_counters: stats[0..4) = {counters[0], counters[1], binary32 attempts,
+// binary64 attempts}.  `pass` of mixed_blocks_per_cu: 0 trace32, 1 resume.
 size_t mixed_record_bytes();
 hipError_t launch_trace32(const ImageConst& c, const OutPtrs& o, unsigned long long* queue,
                           const LaunchShape& shape, int32_t grid, double* records,

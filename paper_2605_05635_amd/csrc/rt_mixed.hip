@@ -12,6 +12,14 @@ namespace {
 using namespace ray;
 using namespace ray32;
 
+// Adds the wave's sum of v to *total (one atomic per wave, from lane 0).
+// Called by every lane of the wave, converged.
+__device__ __forceinline__ void add_wave_total(uint32_t v, unsigned long long* total) {
+    unsigned long long s = v;
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    if (__lane_id() == 0) atomicAdd(total, s);
+}
+
 // Register-allocated for four waves per SIMD (128 VGPRs, a few spilled):
 // measured 6 % faster than three.
 template <int METRIC>
@@ -29,11 +37,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
         start_ray32<METRIC>(c, k, claimed_pixel(shape, c.nx, c.ny, tc, ordinal), r);
     };
     const int lane = __lane_id();
+    uint32_t tried = 0;   // this lane's binary32 step attempts
     for (;;) {
         if (!exhausted) refill(active, exhausted, next, end, claim, take);
         if (__ballot(active) == 0ull) break;
         int32_t leave = 0;
         if (active) {
+            ++tried;
             const int32_t st = attempt32<METRIC>(k, o, c.n_pix, r);
             if (st > 0) {
                 Ray w;
@@ -69,13 +79,16 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
             }
         }
     }
+    add_wave_total(tried, reinterpret_cast<unsigned long long*>(counters + 4));
 }
 
 // A continued ray that reaches its second crossing is traced again from the
 // screen as well (and counted in counters[1]), so that every ray with two
-// crossings has its binary64 outputs.
+// crossings has its binary64 outputs.  Register-allocated for three waves per
+// SIMD, as the binary64 trace kernel: the pass is short (a third of the rays)
+// and ends on its longest rays, so it needs every wave it can keep resident.
 template <int METRIC>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 8))) void resume_kernel(
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) void resume_kernel(
     ImageConst c, OutPtrs o, const double* __restrict__ records, unsigned int* counters,
     unsigned long long* queue, int32_t chunk) {
     const Hot k = hot_of(c);
@@ -90,10 +103,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 8))) 
         load_record<METRIC>(c, k, rec, r);
         fresh = rec[18] != 0.0;
     };
+    uint32_t tried = 0;   // this lane's binary64 step attempts
     for (;;) {
         if (!exhausted) refill(active, exhausted, next, end, claim, take);
         if (__ballot(active) == 0ull) break;
         if (active) {
+            ++tried;
             const int32_t st = attempt<METRIC>(k, o, c.n_pix, r);
             if (!fresh && r.ncross >= kRerunCrossings) {
                 start_ray<METRIC>(c, k, r.pix, r);
@@ -105,11 +120,15 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 8))) 
             }
         }
     }
+    add_wave_total(tried, reinterpret_cast<unsigned long long*>(counters + 6));
 }
 
 __global__ void copy_counters(const unsigned int* __restrict__ counters,
                               long long* __restrict__ stats) {
+    const unsigned long long* wide = reinterpret_cast<const unsigned long long*>(counters + 4);
     if (threadIdx.x < 2) stats[threadIdx.x] = static_cast<long long>(counters[threadIdx.x]);
+    if (threadIdx.x >= 2 && threadIdx.x < 4)
+        stats[threadIdx.x] = static_cast<long long>(wide[threadIdx.x - 2]);
 }
 
 template <class Kern>

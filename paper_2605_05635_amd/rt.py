@@ -107,6 +107,8 @@ def _load():
     lib.rt_get_launch_config.restype = C.c_int
     lib.rt_set_kernel_timing.argtypes = [C.c_void_p, C.c_void_p]
     lib.rt_set_kernel_timing.restype = C.c_int
+    lib.rt_set_split_timing.argtypes = [C.c_void_p]
+    lib.rt_set_split_timing.restype = C.c_int
     lib.rt_image_vjp.argtypes = [P, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]
     lib.rt_image_vjp.restype = C.c_int
     lib.rt_mixed_stats.argtypes = [C.POINTER(C.c_int64)]
@@ -382,9 +384,16 @@ def rt_image_vjp(params: rt_image_params, dl_dI, grad, grad_pix=None,
 
 def rt_mixed_stats() -> dict:
     """Counters of the last mixed-precision image traced on this thread."""
-    buf = (C.c_int64 * 2)()
+    buf = (C.c_int64 * 4)()
     _check(_lib.rt_mixed_stats(buf))
-    return dict(binary64=buf[0], rerun=buf[1], handed_off=buf[0] - buf[1])
+    return dict(binary64=buf[0], rerun=buf[1], handed_off=buf[0] - buf[1],
+                attempts32=buf[2], attempts64=buf[3])
+
+
+def rt_set_split_timing(event) -> None:
+    """Record `event` (torch.cuda.Event, created) between the binary32 and the
+    binary64 pass of each later mixed-precision image; None switches it off."""
+    _check(_lib.rt_set_split_timing(None if event is None else C.c_void_p(event.cuda_event)))
 
 
 def rt_set_tape_budget(nbytes: int) -> None:
@@ -456,7 +465,7 @@ def image_vjp(img: dict, dl_dI, basis: str = "native", per_pixel: bool = False, 
     return (grad, gp) if per_pixel else grad
 
 
-__all__ = ["rt_mixed_stats", "rt_image_vjp", "rt_set_tape_budget", "rt_vjp_stats", "image_vjp", "rt_trace_image", "rt_transfer_maps", "rt_image_setup", "rt_set_kernel_timing",
+__all__ = ["rt_mixed_stats", "rt_image_vjp", "rt_set_tape_budget", "rt_vjp_stats", "image_vjp", "rt_trace_image", "rt_transfer_maps", "rt_image_setup", "rt_set_kernel_timing", "rt_set_split_timing",
            "rt_set_launch_config", "rt_get_launch_config", "rt_visibility_dft", "visibility",
            "rt_shadow_boundary", "rt_shadow_boundary_samples", "shadow_boundary", "rt_image_diagnostics", "rt_image_diagnostics_noalloc", "image_diagnostics",
            "rt_parameter_scan", "parameter_scan", "rt_scan_point",
