@@ -126,12 +126,16 @@ def batch_measurement(steps: int) -> dict:
     ouv = [rt.out_from(o) for o in outs]
     uvs = [torch.tensor(W.uv_points(1000 + j, 2000), device="cuda") for j in range(len(imgs))]
     amps = [torch.empty(2000, dtype=torch.float64, device="cuda") for _ in imgs]
+    vdesc = [rt.vis_image_from(img, o["intensity"], uv, amp)
+             for img, o, uv, amp in zip(imgs, outs, uvs, amps)]
     stream = torch.cuda.current_stream()
+
+    def visibilities():
+        rt.rt_visibility_dft_batch(vdesc, stream)
 
     def one_batch():
         rt.rt_trace_image(params, ouv, stream)
-        for img, o, uv, amp in zip(imgs, outs, uvs, amps):
-            rt.rt_visibility_dft(o["intensity"], rt.params_from(img), uv, amp=amp, stream=stream)
+        visibilities()
 
     one_batch()
     torch.cuda.synchronize()
@@ -142,8 +146,7 @@ def batch_measurement(steps: int) -> dict:
         rt.rt_trace_image(params, ouv, stream)
     ev[1].record(stream)
     for _ in range(steps):
-        for img, o, uv, amp in zip(imgs, outs, uvs, amps):
-            rt.rt_visibility_dft(o["intensity"], rt.params_from(img), uv, amp=amp, stream=stream)
+        visibilities()
     ev[2].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -152,9 +155,16 @@ def batch_measurement(steps: int) -> dict:
     rt.rt_set_launch_config(reset=True)
     attempts = sum(o["attempts"].double().sum().item() for o in outs)
     log(f"batch: trace {trace_ms:.2f} ms, visibilities {dft_ms:.2f} ms per batch")
+    # the visibility contraction: 2 K nx ny complex-by-real multiply-adds = 4 K nx ny flops
+    vis_flops = sum(4.0 * 2000 * i["nx"] * i["ny"] for i in imgs)
+    vis_tflops = vis_flops / (dft_ms * 1e-3) / 1e12
     return {"workload": "64 images, res in {128..768}^2, mixed metrics, one launch; "
-                        "2000 (u,v) visibility amplitudes per image",
+                        "2000 (u,v) visibility amplitudes per image (one batched call)",
             "rays": rays, "steps": steps, "trace_ms": trace_ms, "visibility_ms": dft_ms,
+            "visibility_roofline": {"bound": "alu", "achieved": vis_tflops,
+                                    "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                    "frac": vis_tflops / FP64_VECTOR_PEAK_TFLOPS,
+                                    "flops": vis_flops, "kernel": "vis_partial_kernel"},
             "ms_per_batch": wall * 1e3 / steps, "rays_per_s": rays / (trace_ms * 1e-3),
             "attempts_per_ray": attempts / rays,
             "launch_config": {k: best[k] for k in ("chunk", "tile_w", "tile_h", "blocks_per_cu")},

@@ -228,6 +228,15 @@ enum { RT_DIAG_COUNT = 14 };
 int rt_image_diagnostics(const double *intensity, const rt_image_params *params, double bin_width,
                          int32_t n_bins, double *out, double *profile, void *hip_stream);
 
+/* Relative deviations of image diagnostics from a reference image's (Sec.
+ * 6.2: a dark-matter-dressed model against Kerr under the same emission):
+ * delta[i] = (q[i] - ref[i]) / ref[i] for i < n, IEEE arithmetic (ref[i] = 0
+ * gives +-inf or NaN).  q, ref, delta are device [n] (e.g. two outputs of
+ * rt_image_diagnostics); delta may alias q.  Asynchronous, no scratch.
+ * RT_ERR_ARG for null pointers or n outside [1, 2^24]. */
+int rt_relative_deviation(const double *q, const double *ref, int32_t n, double *delta,
+                          void *hip_stream);
+
 /* rt_image_diagnostics without any allocation, for callers that cannot
  * allocate device memory (code under HIP graph capture, tight serving loops,
  * harnesses that forbid hipMalloc): the same kernels and the same results,
@@ -298,11 +307,47 @@ int rt_set_kernel_timing(void *start_event, void *stop_event);
  *   uv         device [K][2] (u, v) pairs
  *   amp        device [K] normalised amplitudes, or NULL
  *   vis        device [K][2] (Re V, Im V), or NULL (not both NULL)
- * Internally one FP64 GEMM (rocBLAS) of the phase table with the image plus a
- * fixed-order reduction; deterministic.  Scratch (about 16 K (nx + ny) bytes)
- * is stream-ordered.  RT_ERR_ARG for a bad screen, K < 1 or K > 2^22. */
+ * Binary64 on the vector ALU, the phases generated in registers (no phase
+ * table in memory); fixed summation order, deterministic.  Scratch (16 K ny/16
+ * bytes of partial sums and a few KB) is stream-ordered.  RT_ERR_ARG for a bad
+ * screen, K < 1 or K > 2^22. */
 int rt_visibility_dft(const double *intensity, const rt_image_params *params, const double *uv,
                       int32_t K, double *amp, double *vis, void *hip_stream);
+
+/* One image of a batched visibility call: as the arguments of
+ * rt_visibility_dft (device pointers; the screen given directly). */
+typedef struct rt_vis_image {
+  const double *intensity;  /* device [ny][nx]                                       */
+  const double *uv;         /* device [K][2] (u, v) in cycles per M                  */
+  double *amp;              /* device [K] |V| / |V(0,0)|, or NULL                    */
+  double *vis;              /* device [K][2] (Re V, Im V), or NULL (not both NULL)   */
+  int32_t nx, ny;           /* screen pixels                                         */
+  int32_t K;                /* points, 1 <= K <= 2^22                                */
+  int32_t reserved;         /* must be 0                                             */
+  double x_min, x_max, y_min, y_max;   /* screen extent                              */
+} rt_vis_image;
+
+/* rt_visibility_dft for n_images images (host array `images`) in one launch
+ * sequence: the work of all images shares the device, so small images do not
+ * leave it idle.  Results equal n_images single calls bit for bit.
+ * RT_ERR_ARG as for rt_visibility_dft (naming the image), or n_images outside
+ * [1, 2^16]. */
+int rt_visibility_dft_batch(const rt_vis_image *images, int32_t n_images, void *hip_stream);
+
+/* The compact Fourier-domain summaries of Sec. 6.4: the azimuthally averaged
+ * normalised amplitude V(q) and the horizontal cut V(|u|, 0), at n_q radii
+ * q (device [n_q], cycles per M, q >= 0).  The average is taken over n_angles
+ * equally spaced directions phi_a = 2 pi a / n_angles, a = 0..n_angles-1, of
+ * the (u, v) plane (the trapezoid rule of the angular mean, exact for
+ * angular harmonics below n_angles): avg[j] = mean_a |V(q_j cos phi_a,
+ * q_j sin phi_a)| / |V(0,0)|; the cut is the amplitude at phi = 0:
+ * cut[j] = |V(q_j, 0)| / |V(0,0)|.  avg and cut are device [n_q] or NULL (not
+ * both).  Scratch (24 n_q n_angles bytes plus that of rt_visibility_dft) is
+ * stream-ordered.  RT_ERR_ARG for null pointers, n_q or n_angles < 1 or
+ * n_q n_angles > 2^22, or a bad screen. */
+int rt_visibility_rings(const double *intensity, const rt_image_params *params, const double *q,
+                        int32_t n_q, int32_t n_angles, double *avg, double *cut,
+                        void *hip_stream);
 
 /* Bases of the image gradient: the parameters as rt_image_params holds them,
  * q = (spin, incl, halo[0], halo[1]), or for the cored-NFW halo its density

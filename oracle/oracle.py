@@ -355,17 +355,47 @@ def flux_centroid(img: dict, intensity: np.ndarray):
     return F, Xc, Yc
 
 
-def visibility_amplitude(img: dict, intensity: np.ndarray, uv: np.ndarray) -> np.ndarray:
-    """|V(u,v)| / |V(0,0)| with V = int I exp(-2 pi i (uX + vY)) dX dY (Sec. 6.4),
-    as a direct sum over pixel centres."""
+def visibility(img: dict, intensity: np.ndarray, uv: np.ndarray) -> np.ndarray:
+    """V(u,v) = int I exp(-2 pi i (uX + vY)) dX dY (Sec. 6.4) as a direct sum
+    over the pixel centres (complex [K])."""
     X, Y, dx, dy = screen_axes(img)
     I = np.asarray(intensity, dtype=np.float64).reshape(img["ny"], img["nx"])
-    out = np.zeros(len(uv))
-    V0 = abs(I.sum() * dx * dy)
-    for k, (u, v) in enumerate(np.asarray(uv, dtype=np.float64)):
+    out = np.zeros(len(uv), dtype=np.complex128)
+    for k, (u, v) in enumerate(np.asarray(uv, dtype=np.float64).reshape(-1, 2)):
         ex = np.exp(-2j * math.pi * u * X)[None, :] * np.exp(-2j * math.pi * v * Y)[:, None]
-        out[k] = abs((I * ex).sum() * dx * dy) / V0
+        out[k] = (I * ex).sum() * dx * dy
     return out
+
+
+def visibility_amplitude(img: dict, intensity: np.ndarray, uv: np.ndarray) -> np.ndarray:
+    """|V(u,v)| / |V(0,0)| (Sec. 6.4), V(0,0) the flux."""
+    X, Y, dx, dy = screen_axes(img)
+    I = np.asarray(intensity, dtype=np.float64).reshape(img["ny"], img["nx"])
+    return np.abs(visibility(img, I, uv)) / abs(I.sum() * dx * dy)
+
+
+def visibility_rings(img: dict, intensity: np.ndarray, q, n_angles: int):
+    """The compact Fourier-domain summaries of Sec. 6.4 at radii q (cycles/M):
+    the azimuthally averaged normalised amplitude V(q), taken as the mean of
+    |V(u,v)|/|V(0,0)| over the n_angles directions phi_a = 2 pi a / n_angles,
+    a = 0..n_angles-1, of the (u, v) plane, and the horizontal cut V(|u|, 0),
+    the amplitude at (u, v) = (q, 0).  Returns (avg [n_q], cut [n_q])."""
+    q = np.asarray(q, dtype=np.float64).reshape(-1)
+    phi = 2.0 * math.pi * np.arange(n_angles) / n_angles
+    uv = np.stack([(q[:, None] * np.cos(phi)[None, :]).reshape(-1),
+                   (q[:, None] * np.sin(phi)[None, :]).reshape(-1)], axis=1)
+    amp = visibility_amplitude(img, intensity, uv).reshape(len(q), n_angles)
+    cut = visibility_amplitude(img, intensity, np.stack([q, np.zeros_like(q)], axis=1))
+    return amp.mean(axis=1), cut
+
+
+def relative_to_reference(values, reference) -> np.ndarray:
+    """delta Q_i = (Q_i - Q_ref,i) / Q_ref,i (Sec. 6.2: a diagnostic of a
+    dark-matter-dressed image relative to the Kerr one), element by element."""
+    v = np.asarray(values, dtype=np.float64)
+    r = np.asarray(reference, dtype=np.float64)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        return (v - r) / r
 
 
 def shadow_boundary(img: dict, dirs, b_lo: float, b_hi: float, b_tol: float,

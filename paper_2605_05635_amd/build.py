@@ -38,7 +38,7 @@ def build(verbose: bool = False, extra: list[str] | None = None) -> str:
     cmd = [HIPCC, *DEVICE_FLAGS, *CODEGEN_FLAGS, "-O3", "-std=c++17", "-fPIC", "-shared", "-Wall",
            "-I", os.path.join(ROOT, "include"), "-I", os.path.join(PKG, "csrc"),
            *(extra or []), "-o", LIB + ".tmp", *srcs,
-           "-L/opt/rocm/lib", "-Wl,-rpath,/opt/rocm/lib", "-lrocblas"]
+           "-L/opt/rocm/lib", "-Wl,-rpath,/opt/rocm/lib"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -1011,6 +1011,85 @@ int image_diagnostics_noalloc(const double* intensity, const rt_image_params* pa
     return RT_OK;
 }
 
+// Normalised visibility amplitudes of n images (rt_visibility_dft and its
+// batch form): validation, the work layout, one stream-ordered scratch block
+// (image table, flux partials, partial sums) and three kernel launches.
+int visibility_images(const rt_vis_image* imgs, int32_t n, hipStream_t stream) {
+    std::vector<rt::VisImage> tab(n);
+    int32_t max_k = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        const rt_vis_image& g = imgs[i];
+        if (!g.intensity || !g.uv || (!g.amp && !g.vis))
+            return fail(RT_ERR_ARG, "image %d: null intensity, uv or both outputs", i);
+        if (g.reserved != 0) return fail(RT_ERR_ARG, "image %d: reserved field must be 0", i);
+        if (g.K < 1 || g.K > (1 << 22)) return fail(RT_ERR_ARG, "image %d: K must lie in [1, 2^22]", i);
+        if (g.nx < 1 || g.ny < 1 || static_cast<int64_t>(g.nx) * g.ny >= (int64_t(1) << 31))
+            return fail(RT_ERR_ARG, "image %d: bad screen size %d x %d", i, g.nx, g.ny);
+        if (!finite_all({g.x_min, g.x_max, g.y_min, g.y_max}) || !(g.x_min < g.x_max) ||
+            !(g.y_min < g.y_max))
+            return fail(RT_ERR_ARG, "image %d: bad screen extent", i);
+        rt::VisImage& m = tab[i];
+        std::memset(&m, 0, sizeof m);
+        m.I = g.intensity;
+        m.uv = g.uv;
+        m.amp = g.amp;
+        m.vis = g.vis;
+        m.nx = g.nx;
+        m.ny = g.ny;
+        m.K = g.K;
+        m.x0 = g.x_min;
+        m.dx = (g.x_max - g.x_min) / g.nx;
+        m.y0 = g.y_min;
+        m.dy = (g.y_max - g.y_min) / g.ny;
+        max_k = std::max(max_k, g.K);
+    }
+    for (int32_t i = 0; i < n; ++i) {
+        const rt_vis_image& g = imgs[i];
+        int rc;
+        if ((rc = check_device_ptr(g.intensity, "intensity", i)) ||
+            (rc = check_device_ptr(g.uv, "uv", i)) || (rc = check_device_ptr(g.amp, "amp", i)) ||
+            (rc = check_device_ptr(g.vis, "vis", i)))
+            return rc;
+    }
+    int64_t items = 0;
+    for (const rt::VisImage& m : tab)
+        items += static_cast<int64_t>((m.K + 63) / 64) * ((m.nx + rt::kVisCols - 1) / rt::kVisCols);
+    if (items >= (int64_t(1) << 31)) return fail(RT_ERR_ARG, "too much visibility work for one call");
+    int32_t n_items = 0;
+    int64_t n_part = 0;
+    rt::vis_layout(tab.data(), n, &n_items, &n_part);
+    auto up256 = [](size_t b) { return (b + 255) / 256 * 256; };
+    const size_t tab_bytes = up256(sizeof(rt::VisImage) * n);
+    const size_t flux_bytes = up256(sizeof(double) * rt::kVisFluxBlocks * n);
+    const size_t part_bytes = up256(sizeof(double2) * static_cast<size_t>(n_part));
+    void* mem = nullptr;
+    hipError_t e = hipMallocAsync(&mem, tab_bytes + flux_bytes + part_bytes, stream);
+    if (e != hipSuccess || !mem) {
+        (void)hipGetLastError();
+        return fail(RT_ERR_ALLOC, "stream-ordered allocation of %zu visibility bytes failed",
+                    tab_bytes + flux_bytes + part_bytes);
+    }
+    char* base = static_cast<char*>(mem);
+    auto bail = [&](int code) {
+        (void)hipFreeAsync(mem, stream);
+        return code;
+    };
+    void* host = nullptr;
+    int rc = staging_reserve(sizeof(rt::VisImage) * n, &host);
+    if (rc != RT_OK) return bail(rc);
+    std::memcpy(host, tab.data(), sizeof(rt::VisImage) * n);
+    if ((e = hipMemcpyAsync(base, host, sizeof(rt::VisImage) * n, hipMemcpyHostToDevice,
+                            stream)) != hipSuccess ||
+        (e = hipEventRecord(g_staging.ready, stream)) != hipSuccess)
+        return bail(hip_fail(e, "visibility table upload"));
+    e = rt::launch_visibility(reinterpret_cast<const rt::VisImage*>(base), n, n_items, max_k,
+                              reinterpret_cast<double2*>(base + tab_bytes + flux_bytes),
+                              reinterpret_cast<double*>(base + tab_bytes), stream);
+    if (e != hipSuccess) return bail(hip_fail(e, "visibility kernel launch"));
+    if ((e = hipFreeAsync(mem, stream)) != hipSuccess) return hip_fail(e, "hipFreeAsync");
+    return RT_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1092,6 +1171,20 @@ int rt_image_diagnostics(const double* intensity, const rt_image_params* params,
     return image_diagnostics(intensity, params, bin_width, n_bins, out, profile, hip_stream);
 }
 
+int rt_relative_deviation(const double* q, const double* ref, int32_t n, double* delta,
+                          void* hip_stream) {
+    g_last_error.clear();
+    if (!q || !ref || !delta) return fail(RT_ERR_ARG, "null q, ref or delta");
+    if (n < 1 || n > (1 << 24)) return fail(RT_ERR_ARG, "n must lie in [1, 2^24]");
+    int rc;
+    if ((rc = check_device_ptr(q, "q", 0)) || (rc = check_device_ptr(ref, "ref", 0)) ||
+        (rc = check_device_ptr(delta, "delta", 0)))
+        return rc;
+    const hipError_t e = rt::launch_relative(q, ref, n, delta, static_cast<hipStream_t>(hip_stream));
+    if (e != hipSuccess) return hip_fail(e, "relative deviation kernel launch");
+    return RT_OK;
+}
+
 int rt_image_diagnostics_noalloc(const double* intensity, const rt_image_params* params,
                                  double bin_width, int32_t n_bins, double* out, double* profile,
                                  void* hip_stream) {
@@ -1171,53 +1264,54 @@ int rt_set_kernel_timing(void* start_event, void* stop_event) {
 int rt_visibility_dft(const double* intensity, const rt_image_params* params, const double* uv,
                       int32_t K, double* amp, double* vis, void* hip_stream) {
     g_last_error.clear();
-    if (!intensity || !params || !uv || (!amp && !vis))
-        return fail(RT_ERR_ARG, "null intensity, params, uv or both outputs");
-    if (K < 1 || K > (1 << 22)) return fail(RT_ERR_ARG, "K must lie in [1, 2^22]");
-    const rt_image_params* p = params;
-    if (p->nx < 1 || p->ny < 1 || static_cast<int64_t>(p->nx) * p->ny >= (int64_t(1) << 31))
-        return fail(RT_ERR_ARG, "bad screen size %d x %d", p->nx, p->ny);
-    if (!finite_all({p->x_min, p->x_max, p->y_min, p->y_max}) || !(p->x_min < p->x_max) ||
-        !(p->y_min < p->y_max))
-        return fail(RT_ERR_ARG, "bad screen extent");
-    rt::ImageConst c;
-    std::memset(&c, 0, sizeof c);
-    c.nx = p->nx;
-    c.ny = p->ny;
-    c.n_pix = static_cast<int64_t>(p->nx) * p->ny;
-    c.x0 = p->x_min;
-    c.dx = (p->x_max - p->x_min) / p->nx;
-    c.y0 = p->y_min;
-    c.dy = (p->y_max - p->y_min) / p->ny;
+    if (!params) return fail(RT_ERR_ARG, "null params");
+    const rt_vis_image img{intensity, uv, amp, vis, params->nx, params->ny, K, 0,
+                           params->x_min, params->x_max, params->y_min, params->y_max};
+    return visibility_images(&img, 1, static_cast<hipStream_t>(hip_stream));
+}
+
+int rt_visibility_dft_batch(const rt_vis_image* images, int32_t n_images, void* hip_stream) {
+    g_last_error.clear();
+    if (!images) return fail(RT_ERR_ARG, "null images");
+    if (n_images < 1 || n_images > (1 << 16)) return fail(RT_ERR_ARG, "n_images must lie in [1, 2^16]");
+    return visibility_images(images, n_images, static_cast<hipStream_t>(hip_stream));
+}
+
+int rt_visibility_rings(const double* intensity, const rt_image_params* params, const double* q,
+                        int32_t n_q, int32_t n_angles, double* avg, double* cut,
+                        void* hip_stream) {
+    g_last_error.clear();
+    if (!intensity || !params || !q || (!avg && !cut))
+        return fail(RT_ERR_ARG, "null intensity, params, q or both outputs");
+    if (n_q < 1 || n_angles < 1 || static_cast<int64_t>(n_q) * n_angles > (int64_t(1) << 22))
+        return fail(RT_ERR_ARG, "need n_q >= 1, n_angles >= 1, n_q n_angles <= 2^22");
     int rc;
-    if ((rc = check_device_ptr(intensity, "intensity", 0)) || (rc = check_device_ptr(uv, "uv", 0)) ||
-        (rc = check_device_ptr(amp, "amp", 0)) || (rc = check_device_ptr(vis, "vis", 0)))
+    if ((rc = check_device_ptr(q, "q", 0)) || (rc = check_device_ptr(avg, "avg", 0)) ||
+        (rc = check_device_ptr(cut, "cut", 0)))
         return rc;
-    int dev = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
-    static thread_local void* handles[64] = {};
-    if (dev < 0 || dev >= 64) return fail(RT_ERR_HIP, "device index %d out of range", dev);
-    if (!handles[dev] && !(handles[dev] = rt::blas_create()))
-        return fail(RT_ERR_HIP, "rocblas_create_handle failed");
     hipStream_t stream = static_cast<hipStream_t>(hip_stream);
-    const size_t vis_bytes = rt::visibility_scratch_bytes(K, p->nx, p->ny);
-    const size_t bytes = vis_bytes + sizeof(double) * (4 + 3 * rt::kReduceBlocks);
-    void* scratch = nullptr;
-    e = hipMallocAsync(&scratch, bytes, stream);
-    if (e != hipSuccess || !scratch) {
+    const int64_t n = static_cast<int64_t>(n_q) * n_angles;
+    void* mem = nullptr;
+    hipError_t e = hipMallocAsync(&mem, sizeof(double) * 3 * n, stream);
+    if (e != hipSuccess || !mem) {
         (void)hipGetLastError();
-        return fail(RT_ERR_ALLOC, "stream-ordered allocation of %zu scratch bytes failed", bytes);
+        return fail(RT_ERR_ALLOC, "stream-ordered allocation of the ring points failed");
     }
-    double* base = static_cast<double*>(scratch);
-    double* flux = base + vis_bytes / sizeof(double);
-    double* partials = flux + 4;
-    const char* what = "";
-    e = rt::launch_visibility(handles[dev], c, intensity, uv, K, flux, amp, vis, base, partials,
-                              stream, &what);
-    const hipError_t f = hipFreeAsync(scratch, stream);
-    if (e != hipSuccess) return hip_fail(e, what);
-    if (f != hipSuccess) return hip_fail(f, "hipFreeAsync");
+    double* uv = static_cast<double*>(mem);
+    double* amp = uv + 2 * n;
+    auto bail = [&](int code) {
+        (void)hipFreeAsync(mem, stream);
+        return code;
+    };
+    if ((e = rt::launch_ring_points(q, n_q, n_angles, uv, stream)) != hipSuccess)
+        return bail(hip_fail(e, "ring point kernel launch"));
+    const rt_vis_image img{intensity, uv, amp, nullptr, params->nx, params->ny,
+                           static_cast<int32_t>(n), 0, params->x_min, params->x_max,
+                           params->y_min, params->y_max};
+    if ((rc = visibility_images(&img, 1, stream)) != RT_OK) return bail(rc);
+    if ((e = rt::launch_ring_average(amp, n_q, n_angles, avg, cut, stream)) != hipSuccess)
+        return bail(hip_fail(e, "ring average kernel launch"));
+    if ((e = hipFreeAsync(mem, stream)) != hipSuccess) return hip_fail(e, "hipFreeAsync");
     return RT_OK;
 }
 

@@ -245,7 +245,21 @@ __global__ __launch_bounds__(kThreads) void peak_kernel(const double* __restrict
     }
 }
 
+// delta[i] = (q[i] - ref[i]) / ref[i].
+__global__ void relative_kernel(const double* __restrict__ q, const double* __restrict__ ref,
+                                int32_t n, double* __restrict__ delta) {
+    const int32_t i = static_cast<int32_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) delta[i] = (q[i] - ref[i]) / ref[i];
+}
+
 }  // namespace
+
+hipError_t launch_relative(const double* q, const double* ref, int32_t n, double* delta,
+                           hipStream_t stream) {
+    hipLaunchKernelGGL(relative_kernel, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0,
+                       stream, q, ref, n, delta);
+    return hipGetLastError();
+}
 
 size_t diagnostics_scratch_doubles(int32_t n_bins) {
     return 3 + 3 * kReduceBlocks + kA * kReduceBlocks + kReduceBlocks + static_cast<size_t>(n_bins);

@@ -87,6 +87,9 @@ hipError_t launch_diagnostics(const ImageConst& c, const double* intensity, doub
 // once per device) and its size in doubles.
 constexpr int32_t kNoAllocMaxBins = 65536;
 hipError_t diagnostics_static_work(double** ptr, size_t* doubles);
+// delta[i] = (q[i] - ref[i]) / ref[i] for i < n (rt_relative_deviation).
+hipError_t launch_relative(const double* q, const double* ref, int32_t n, double* delta,
+                           hipStream_t stream);
 
 // Shadow-boundary search: `samples` (64, 32 or 16) lanes per direction
 // dirs[2i], dirs[2i+1] (cos psi, sin psi); out[2i], out[2i+1] = the final bracket of b, status[i]
@@ -111,19 +114,37 @@ constexpr int kReduceBlocks = 256;
 hipError_t launch_reduce(const ImageConst& c, const double* intensity, double* partials,
                          double* out, hipStream_t stream);
 
-// Normalised visibility amplitudes (Sec. 6.4) of the image `intensity` on
-// the screen of c at K points uv[K][2]: amp[k] = |V_k| / |V(0,0)|, and the
-// unnormalised V_k into vis[K][2] when vis is not null.  `blas` is a rocBLAS
-// handle (blas_create), `scratch` holds visibility_scratch_bytes(K, nx, ny),
-// `flux` one double (receives F, with x_c, y_c after it: 3 doubles), and
-// reduce_partials 3 kReduceBlocks doubles.  On failure returns an error and
-// names the failing step in *what.
-size_t visibility_scratch_bytes(int32_t K, int32_t nx, int32_t ny);
-hipError_t launch_visibility(void* blas, const ImageConst& c, const double* intensity,
-                             const double* uv, int32_t K, double* flux, double* amp, double* vis,
-                             double* scratch, double* reduce_partials, hipStream_t stream,
-                             const char** what);
-void* blas_create();
+// Normalised visibility amplitudes (Sec. 6.4) of n_img images in one launch
+// sequence.  VisImage holds one image (device pointers I [ny][nx], uv [K][2],
+// amp [K] or null, vis [K][2] or null; the screen of its pixel centres);
+// vis_layout fills the work-item and partial-sum offsets of a host table and
+// returns the totals.  launch_visibility runs the flux partials (fpart:
+// kVisFluxBlocks doubles per image), the partial sums (part: n_part double2)
+// and the finish on the device copy d_tab of that table; max_k is the
+// largest K.  Deterministic.
+constexpr int kVisCols = 16;          // image columns per work item
+constexpr int kVisFluxBlocks = 64;    // flux partials per image
+struct VisImage {
+    const double* I;
+    const double* uv;
+    double* amp;
+    double* vis;
+    int32_t nx, ny, K;
+    int32_t nkg, ncb;                 // point groups of 64, column blocks of kVisCols
+    int32_t item0;                    // first work item (wavefront) of the image
+    int64_t part0;                    // first partial sum: [ncb][K]
+    double x0, dx, y0, dy;
+};
+void vis_layout(VisImage* tab, int32_t n_img, int32_t* n_items, int64_t* n_part);
+hipError_t launch_visibility(const VisImage* d_tab, int32_t n_img, int32_t n_items, int32_t max_k,
+                             double2* part, double* fpart, hipStream_t stream);
+// Points on n_q rings (radius q[j], device) at n_angles angles 2 pi a / n_angles:
+// uv [n_q n_angles][2]; and the average of amp over each ring's angles (avg)
+// with its amplitude at angle 0 (cut), either output optional.
+hipError_t launch_ring_points(const double* q, int32_t n_q, int32_t n_angles, double* uv,
+                              hipStream_t stream);
+hipError_t launch_ring_average(const double* amp, int32_t n_q, int32_t n_angles, double* avg,
+                               double* cut, hipStream_t stream);
 
 // Mixed precision.  trace32: the binary32 pass over the screen (order of
 // `shape`); rays leaving binary32 append a record of mixed_record_bytes() to

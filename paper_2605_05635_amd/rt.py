@@ -65,6 +65,13 @@ class rt_scan_point(C.Structure):
                 ("halo", C.c_double * 2), ("theta", C.c_double)]
 
 
+class rt_vis_image(C.Structure):
+    _fields_ = [("intensity", C.c_void_p), ("uv", C.c_void_p), ("amp", C.c_void_p),
+                ("vis", C.c_void_p), ("nx", C.c_int32), ("ny", C.c_int32), ("K", C.c_int32),
+                ("reserved", C.c_int32), ("x_min", C.c_double), ("x_max", C.c_double),
+                ("y_min", C.c_double), ("y_max", C.c_double)]
+
+
 class RTError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"rt error {code}: {msg}")
@@ -87,6 +94,12 @@ def _load():
     lib.rt_visibility_dft.argtypes = [C.c_void_p, C.POINTER(rt_image_params), C.c_void_p,
                                       C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]
     lib.rt_visibility_dft.restype = C.c_int
+    lib.rt_visibility_dft_batch.argtypes = [C.POINTER(rt_vis_image), C.c_int32, C.c_void_p]
+    lib.rt_visibility_dft_batch.restype = C.c_int
+    lib.rt_visibility_rings.argtypes = [C.c_void_p, C.POINTER(rt_image_params), C.c_void_p,
+                                        C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
+                                        C.c_void_p]
+    lib.rt_visibility_rings.restype = C.c_int
     lib.rt_trace_thick.argtypes = [P, C.POINTER(rt_thick_disc), O, C.c_void_p]
     lib.rt_trace_thick.restype = C.c_int
     lib.rt_parameter_scan.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]
@@ -94,6 +107,9 @@ def _load():
     lib.rt_image_diagnostics.argtypes = [C.c_void_p, P, C.c_double, C.c_int32, C.c_void_p,
                                          C.c_void_p, C.c_void_p]
     lib.rt_image_diagnostics.restype = C.c_int
+    lib.rt_relative_deviation.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p,
+                                          C.c_void_p]
+    lib.rt_relative_deviation.restype = C.c_int
     lib.rt_image_diagnostics_noalloc.argtypes = lib.rt_image_diagnostics.argtypes
     lib.rt_image_diagnostics_noalloc.restype = C.c_int
     lib.rt_shadow_boundary.argtypes = [P, C.c_void_p, C.c_int32, C.c_int32, C.c_double, C.c_double,
@@ -228,6 +244,60 @@ def visibility(img: dict, intensity, uv, stream=None):
     return amp
 
 
+def rt_visibility_dft_batch(images: list, stream=None) -> None:
+    """Calls rt_visibility_dft_batch on a list of rt_vis_image descriptors."""
+    arr = _array(rt_vis_image, images)
+    _check(_lib.rt_visibility_dft_batch(arr, len(images), _stream_handle(stream)))
+
+
+def vis_image_from(img: dict, intensity, uv, amp=None, vis=None) -> rt_vis_image:
+    """The batched-visibility descriptor of a traced image (device tensors)."""
+    return rt_vis_image(
+        intensity=intensity.data_ptr(), uv=uv.data_ptr(),
+        amp=None if amp is None else amp.data_ptr(), vis=None if vis is None else vis.data_ptr(),
+        nx=int(img["nx"]), ny=int(img["ny"]), K=int(uv.shape[0]), reserved=0,
+        x_min=img["x_min"], x_max=img["x_max"], y_min=img["y_min"], y_max=img["y_max"])
+
+
+def visibility_many(imgs: list, intensities: list, uvs: list, stream=None) -> list:
+    """Normalised amplitudes of several images in one batched call; returns a
+    device tensor [K_i] per image."""
+    import torch
+    keep, descs, amps = [], [], []
+    for img, I, uv in zip(imgs, intensities, uvs):
+        uv_t = torch.as_tensor(uv, dtype=torch.float64, device=I.device).contiguous()
+        amp = torch.empty(uv_t.shape[0], dtype=torch.float64, device=I.device)
+        Ic = I.contiguous()
+        keep += [uv_t, Ic]
+        amps.append(amp)
+        descs.append(vis_image_from(img, Ic, uv_t, amp=amp))
+    rt_visibility_dft_batch(descs, stream)
+    return amps
+
+
+def rt_visibility_rings(intensity, params: rt_image_params, q, n_angles: int, avg=None, cut=None,
+                        stream=None) -> None:
+    """Calls rt_visibility_rings on device tensors: q [n_q] f64, avg and/or cut
+    [n_q] f64 (outputs)."""
+    _check(_lib.rt_visibility_rings(C.c_void_p(intensity.data_ptr()), C.byref(params),
+                                    C.c_void_p(q.data_ptr()), int(q.shape[0]), int(n_angles),
+                                    None if avg is None else C.c_void_p(avg.data_ptr()),
+                                    None if cut is None else C.c_void_p(cut.data_ptr()),
+                                    _stream_handle(stream)))
+
+
+def visibility_rings(img: dict, intensity, q, n_angles: int = 64, stream=None):
+    """The azimuthally averaged amplitude V(q) over n_angles directions and the
+    horizontal cut V(|u|, 0) of a traced image at radii q; returns (avg, cut)
+    device tensors [n_q]."""
+    import torch
+    q_t = torch.as_tensor(q, dtype=torch.float64, device=intensity.device).contiguous()
+    avg = torch.empty_like(q_t)
+    cut = torch.empty_like(q_t)
+    rt_visibility_rings(intensity.contiguous(), params_from(img), q_t, n_angles, avg, cut, stream)
+    return avg, cut
+
+
 def rt_trace_thick(params: rt_image_params, thick: rt_thick_disc, out: rt_image_out,
                    stream=None) -> None:
     """Calls rt_trace_thick (one image)."""
@@ -303,6 +373,21 @@ def rt_image_diagnostics_noalloc(intensity, params: rt_image_params, bin_width: 
         C.c_void_p(intensity.data_ptr()), C.byref(params), bin_width, n_bins,
         C.c_void_p(out.data_ptr()), None if profile is None else C.c_void_p(profile.data_ptr()),
         _stream_handle(stream)))
+
+
+def rt_relative_deviation(q, ref, delta, stream=None) -> None:
+    """Calls rt_relative_deviation on device f64 tensors of equal length."""
+    _check(_lib.rt_relative_deviation(C.c_void_p(q.data_ptr()), C.c_void_p(ref.data_ptr()),
+                                      int(q.numel()), C.c_void_p(delta.data_ptr()),
+                                      _stream_handle(stream)))
+
+
+def relative_to_reference(q, ref, stream=None):
+    """delta Q = (Q - Q_ref)/Q_ref of two device tensors (Sec. 6.2)."""
+    import torch
+    delta = torch.empty_like(q)
+    rt_relative_deviation(q.contiguous(), ref.contiguous(), delta, stream)
+    return delta
 
 
 def image_diagnostics(img: dict, intensity, bin_width: float, n_bins: int, stream=None):
@@ -467,7 +552,10 @@ def image_vjp(img: dict, dl_dI, basis: str = "native", per_pixel: bool = False, 
 
 __all__ = ["rt_mixed_stats", "rt_image_vjp", "rt_set_tape_budget", "rt_vjp_stats", "image_vjp", "rt_trace_image", "rt_transfer_maps", "rt_image_setup", "rt_set_kernel_timing", "rt_set_split_timing",
            "rt_set_launch_config", "rt_get_launch_config", "rt_visibility_dft", "visibility",
+           "rt_visibility_dft_batch", "rt_vis_image", "vis_image_from", "visibility_many",
+           "rt_visibility_rings", "visibility_rings",
            "rt_shadow_boundary", "rt_shadow_boundary_samples", "shadow_boundary", "rt_image_diagnostics", "rt_image_diagnostics_noalloc", "image_diagnostics",
+           "rt_relative_deviation", "relative_to_reference",
            "rt_parameter_scan", "parameter_scan", "rt_scan_point",
            "rt_trace_thick", "trace_thick", "rt_thick_disc",
            "RT_DIAG_COUNT", "RT_DIAG_NOALLOC_MAX_BINS", "DIAG_KEYS",

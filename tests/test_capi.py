@@ -169,6 +169,42 @@ def test_visibility_argument_errors(rt):
                                  None, None) == rt.RT_ERR_ARG
 
 
+def test_batch_visibility_layout_and_errors(rt, tmp_path):
+    """rt_vis_image has the header's layout; batched and ring calls reject bad
+    arguments before any device work."""
+    fields = [f for f, _ in rt.rt_vis_image._fields_]
+    src = ['#include <stdio.h>', '#include <stddef.h>', '#include "rt.h"', "int main(void){",
+           'printf("%zu\\n", sizeof(rt_vis_image));']
+    src += [f'printf("%zu\\n", offsetof(rt_vis_image, {f}));' for f in fields]
+    src += ["return 0;}"]
+    c = tmp_path / "vis.c"
+    c.write_text("\n".join(src))
+    exe = tmp_path / "vis"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(c), "-o", str(exe)], check=True)
+    vals = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True,
+                                           check=True).stdout.split()]
+    assert vals[0] == C.sizeof(rt.rt_vis_image)
+    assert vals[1:] == [getattr(rt.rt_vis_image, f).offset for f in fields]
+    lib = rt.lib()
+    d = C.c_void_p(8)
+    good = dict(intensity=8, uv=8, amp=8, vis=None, nx=4, ny=4, K=3, reserved=0, x_min=-1.0,
+                x_max=1.0, y_min=-1.0, y_max=1.0)
+    for change in (dict(intensity=None), dict(K=0), dict(K=(1 << 22) + 1), dict(nx=0),
+                   dict(reserved=1), dict(x_max=-2.0), dict(amp=None), dict(y_min=float("nan"))):
+        arr = (rt.rt_vis_image * 2)(rt.rt_vis_image(**good), rt.rt_vis_image(**dict(good, **change)))
+        assert lib.rt_visibility_dft_batch(arr, 2, None) == rt.RT_ERR_ARG, change
+        assert "image 1" in rt.rt_last_error()
+    arr = (rt.rt_vis_image * 1)(rt.rt_vis_image(**good))
+    assert lib.rt_visibility_dft_batch(arr, 0, None) == rt.RT_ERR_ARG
+    assert lib.rt_visibility_dft_batch(None, 1, None) == rt.RT_ERR_ARG
+    p = rt.params_from(W.kerr_small())
+    assert lib.rt_visibility_rings(None, C.byref(p), d, 4, 8, d, d, None) == rt.RT_ERR_ARG
+    assert lib.rt_visibility_rings(d, C.byref(p), d, 0, 8, d, d, None) == rt.RT_ERR_ARG
+    assert lib.rt_visibility_rings(d, C.byref(p), d, 4, 0, d, d, None) == rt.RT_ERR_ARG
+    assert lib.rt_visibility_rings(d, C.byref(p), d, 4, 8, None, None, None) == rt.RT_ERR_ARG
+    assert lib.rt_visibility_rings(d, C.byref(p), d, 1 << 12, 1 << 11, d, d, None) == rt.RT_ERR_ARG
+
+
 def test_vjp_argument_errors(rt):
     lib = rt.lib()
     cn = rt.params_from(W.cnfw_adjoint_256())
