@@ -117,7 +117,7 @@ def batch_measurement(steps: int) -> dict:
     import torch
 
     from paper_2605_05635_amd import autotune, rt, workloads as W
-    imgs = W.batch_64()
+    imgs = W.batch_64(rt.einasto_extremal_spin)
     rays = sum(i["nx"] * i["ny"] for i in imgs)
     log(f"batch: 64 images, {rays} rays; autotuning the launch configuration")
     best = autotune.tune(imgs, log=log)

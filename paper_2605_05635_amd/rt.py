@@ -349,6 +349,14 @@ def parameter_scan(metric, spin, halo0, halo1, theta, stream=None):
     return out
 
 
+def einasto_extremal_spin(lam_e: float) -> float:
+    """The extremal spin of the Einasto seed with lambda_E = lam_e, from
+    rt_parameter_scan (synchronous); 0 when no horizon exists at any spin."""
+    import math
+    v = float(parameter_scan(["einasto"], 0.0, lam_e, 0.0, 1.0)[0, 2].item())
+    return v if math.isfinite(v) else 0.0
+
+
 RT_DIAG_COUNT = 14
 RT_DIAG_NOALLOC_MAX_BINS = 65536
 DIAG_KEYS = ("F", "X_c", "Y_c", "C", "rho_bar", "d_img", "w_img", "w_over_d", "A_LR",
@@ -556,7 +564,7 @@ __all__ = ["rt_mixed_stats", "rt_image_vjp", "rt_set_tape_budget", "rt_vjp_stats
            "rt_visibility_rings", "visibility_rings",
            "rt_shadow_boundary", "rt_shadow_boundary_samples", "shadow_boundary", "rt_image_diagnostics", "rt_image_diagnostics_noalloc", "image_diagnostics",
            "rt_relative_deviation", "relative_to_reference",
-           "rt_parameter_scan", "parameter_scan", "rt_scan_point",
+           "rt_parameter_scan", "parameter_scan", "rt_scan_point", "einasto_extremal_spin",
            "rt_trace_thick", "trace_thick", "rt_thick_disc",
            "RT_DIAG_COUNT", "RT_DIAG_NOALLOC_MAX_BINS", "DIAG_KEYS",
            "rt_version",

@@ -93,13 +93,16 @@ def adjoint_target_signs(seed: int = 4) -> np.ndarray:
     return np.where(rng.integers(0, 2, size=4) == 0, -1.0, 1.0)
 
 
-def batch_64(seed: int = 5, n_images: int = 64) -> list[dict]:
+def batch_64(einasto_extremal_spin, seed: int = 5, n_images: int = 64) -> list[dict]:
     """64 images of mixed resolution and metric for one batched launch.
 
     res ~ U{128, 256, 512, 768}^2, chi ~ U[0, 0.99], theta_o ~ U[5, 85] deg,
-    metric ~ U{Kerr, Einasto, cored NFW}; Einasto lambda_E ~ U[0.05, 0.10]
-    (extremal spin above 0.997 on that range), cored NFW eta ~ U[0.005, 0.05],
-    lambda_c ~ U[5, 20]; screen +-12 M."""
+    metric ~ U{Kerr, Einasto, cored NFW}; Einasto lambda_E drawn from
+    U[0.05, 0.30] again until the spacetime keeps a horizon with a margin,
+    einasto_extremal_spin(lambda_E) >= chi + 0.005 (the caller supplies the
+    extremal spin of the Einasto seed: this module computes nothing of the
+    spacetimes); cored NFW eta ~ U[0.005, 0.05], lambda_c ~ U[5, 20] (extremal
+    spin above 1 there); screen +-12 M."""
     rng = np.random.default_rng(seed)
     out = []
     for _ in range(n_images):
@@ -108,7 +111,11 @@ def batch_64(seed: int = 5, n_images: int = 64) -> list[dict]:
         incl = math.radians(float(rng.uniform(5.0, 85.0)))
         metric = METRICS[int(rng.integers(0, 3))]
         if metric == "einasto":
-            halo = (float(rng.uniform(0.05, 0.10)), 0.0)
+            while True:
+                lam = float(rng.uniform(0.05, 0.30))
+                if einasto_extremal_spin(lam) >= chi + 0.005:
+                    break
+            halo = (lam, 0.0)
         elif metric == "cnfw":
             halo = (float(rng.uniform(0.005, 0.05)), float(rng.uniform(5.0, 20.0)))
         else:

@@ -9,6 +9,7 @@ import subprocess
 
 import pytest
 
+from conftest import oracle_einasto_extremal_spin
 from paper_2605_05635_amd import workloads as W
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -123,7 +124,7 @@ def test_no_horizon_beyond_extremal_spin(rt):
 def test_image_setup_matches_oracle(rt, orc):
     """The library's host setup finds the same outer horizon as the oracle."""
     cases = [(W.kerr_small(), 1e-14), (W.einasto_512(), 1e-14), (W.cnfw_1024(), 1e-14),
-             (W.cnfw_adjoint_256(), 1e-14)] + [(b, 1e-14) for b in W.batch_64()[:12]]
+             (W.cnfw_adjoint_256(), 1e-14)] + [(b, 1e-14) for b in W.batch_64(oracle_einasto_extremal_spin)[:12]]
     # 1e-4 below the extremal spin Delta is nearly a double root, and rounding
     # noise in Delta moves its zero by ~sqrt(eps) relative
     cases.append((W.image(metric="einasto", halo=(0.3, 0.0), spin=0.6395), 1e-7))

@@ -246,7 +246,8 @@ def test_large_mixed_batch_equals_single_images(rt):
     """130 small images of all metrics: two batched launches (128 + 2 images),
     each image bit-identical to its own single-image trace."""
     import torch
-    base = W.batch_64(seed=9, n_images=64)
+    from conftest import oracle_einasto_extremal_spin
+    base = W.batch_64(oracle_einasto_extremal_spin, seed=9, n_images=64)
     imgs = []
     for j in range(130):
         b = dict(base[j % 64])
@@ -259,6 +260,31 @@ def test_large_mixed_batch_equals_single_images(rt):
     for j, (a, b) in enumerate(zip(singles, many)):
         for k in a:
             assert np.array_equal(a[k].cpu().numpy(), b[k].cpu().numpy(), equal_nan=True), (j, k)
+
+
+def test_batch_64_workload_sampled(rt, orc, batch64):
+    """The benchmark's 64-image batch (14 M rays, all three metrics, Einasto
+    halos up to lambda_E = 0.3) traced as bench.py traces it -- one persistent
+    launch under the autotuned launch configuration -- on 24 seeded pixels of
+    every image against the oracle.  The library's own draw of the workload
+    (its extremal spin deciding the Einasto rejections) is the same list."""
+    import torch
+    from paper_2605_05635_amd import autotune
+    assert W.batch_64(rt.einasto_extremal_spin) == batch64
+    say("[parity] batch_64: autotune, one launch, 24 pixels per image")
+    best = autotune.tune(batch64, log=say)
+    try:
+        many = rt.trace_many(batch64)
+        torch.cuda.synchronize()
+    finally:
+        rt.rt_set_launch_config(reset=True)
+    say(f"[parity] batch_64 traced with {best}")
+    for j, (img, outs) in enumerate(zip(batch64, many)):
+        idx = W.random_pixels(img["nx"], img["ny"], 24, 500 + j)
+        g = gpu_to_numpy(outs, idx)
+        o = orc.trace_pixels(img, idx)
+        bad = compare(g, o)
+        assert not bad, (j, img["metric"], bad)
 
 
 def test_batch_parity_with_oracle(rt, orc):

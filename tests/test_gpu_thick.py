@@ -1,11 +1,13 @@
 """The thick-disc image (rt_trace_thick, Sec. 5.1-5.2) on the GPU against the
 oracle's seventh-component integration of the same definition.
 
-Bar: the parity bar of the thin-disc intensity: status identical; intensity
-within 1e-6 of the image's largest (both sides integrate I with the same
-error-controlled steps, so they agree to ~1e-10 unless a rounding-level
-difference flips an accept/reject decision, which changes I at the tolerance
-level, 1e-8); step attempts identical on at least 97 % of the pixels.
+Bar: status identical on every pixel.  Where both sides took the same step
+attempts (the same accept/reject decisions), the intensity agrees within
+1e-6 relative per pixel, as the thin disc's (both integrate I with the same
+error-controlled steps: ~1e-10 in practice), and is exactly 0 on both sides
+where the oracle's is.  A rounding-level difference can flip an accept/reject
+decision, which changes I at the tolerance level (1e-8): such pixels (at most
+3 %) are held to 1e-6 of the image's largest intensity.
 """
 import math
 import sys
@@ -44,10 +46,15 @@ def check(rt, orc, img, idx=None):
         idx = np.arange(img["nx"] * img["ny"])
     o = orc.trace_thick_pixels(img, THICK, idx)
     assert np.array_equal(st[idx], o["status"])
-    scale = max(np.abs(o["intensity"]).max(), 1e-300)
-    assert np.abs(I[idx] - o["intensity"]).max() <= 1e-6 * scale
-    assert (att[idx] == o["attempts"]).mean() >= 0.97
-    assert o["intensity"].max() > 0.0
+    same = att[idx] == o["attempts"]
+    assert same.mean() >= 0.97
+    Ig, Io = I[idx], o["intensity"]
+    nz = same & (Io != 0)
+    assert np.all(np.abs(Ig[nz] - Io[nz]) <= 1e-6 * np.abs(Io[nz]))
+    assert np.all(Ig[same & (Io == 0)] == 0)
+    scale = max(np.abs(Io).max(), 1e-300)
+    assert np.abs(Ig[~same] - Io[~same]).max(initial=0.0) <= 1e-6 * scale
+    assert Io.max() > 0.0 and nz.sum() >= 0.1 * len(idx)
     return I, o
 
 
@@ -66,7 +73,7 @@ def test_thick_full_screen(rt, orc, label, img):
 
 def test_thick_bench_screen_sampled(rt, orc):
     img = dict(W.cnfw_1024(), emis_pow=2.0)
-    idx = W.subsample_indices(img["nx"], img["ny"], 64)
+    idx = W.subsample_indices(img["nx"], img["ny"], 16)
     say(f"[thick] cnfw 1024^2: {len(idx)} sampled pixels")
     I, o = check(rt, orc, img, idx)
     assert np.all(I >= -1e-12)

@@ -109,12 +109,12 @@ def test_rings_closed_form_and_oracle(rt, orc):
     assert np.abs(cut.cpu().numpy() - oc).max() <= TOL
 
 
-def test_batch_64_workload_sampled(rt, orc):
+def test_batch_64_workload_sampled(rt, orc, batch64):
     """The benchmark's 64-image batch, traced as one launch, then its 2000
     visibilities per image in one batched call; 12 points of every image
     against the oracle's direct sum over the same image."""
     import torch
-    imgs = W.batch_64()
+    imgs = batch64
     say("[vis] batch_64: trace + batched visibilities, 12 sampled points per image")
     many = rt.trace_many(imgs)
     uvs = [W.uv_points(1000 + j, 2000) for j in range(len(imgs))]

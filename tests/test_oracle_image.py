@@ -34,7 +34,7 @@ def test_visibility_of_gaussian(orc):
     assert np.allclose(amp, np.exp(-2 * math.pi ** 2 * s * s * q2), rtol=0, atol=1e-10)
 
 
-def test_pixel_centres_and_workloads():
+def test_pixel_centres_and_workloads(batch64):
     img = W.kerr_small()
     assert (img["x_max"] - img["x_min"]) / img["nx"] == 0.375
     from oracle import oracle as O
@@ -43,9 +43,14 @@ def test_pixel_centres_and_workloads():
     assert Y[3] == 12 - 0.1875
     a, b = W.einasto_512(), W.einasto_512()
     assert a == b and 0.10 <= a["halo"][0] <= 0.18
-    batch = W.batch_64()
+    batch = batch64
     assert len(batch) == 64 and {d["metric"] for d in batch} == {"kerr", "einasto", "cnfw"}
     assert all(d["nx"] in (128, 256, 512, 768) for d in batch)
+    # the Einasto halos span the drawn range, each with a horizon at its spin
+    from conftest import oracle_einasto_extremal_spin as ce
+    lam = [d["halo"][0] for d in batch if d["metric"] == "einasto"]
+    assert min(lam) < 0.08 and max(lam) > 0.25
+    assert all(ce(d["halo"][0]) >= d["spin"] + 0.005 for d in batch if d["metric"] == "einasto")
 
 
 def elliptical_gaussian(img, x0, y0, sx, sy):
