@@ -296,9 +296,10 @@ def adjoint_measurement(steps: int, cpu: bool) -> dict:
     """Image gradient of the cored-NFW 256x256 tapered-disc image (chi = 0.94,
     theta_o = 60 deg, (eta, lambda_c) = (0.02, 10)) for the loss
     L = sum (I - I_target)^2, I_target traced at a 1 % change of
-    (chi, theta_o, rho_s, r_s): wall time of rt_image_vjp per call (all its
-    passes and its one host synchronisation), beside the forward trace of the
-    same image."""
+    (chi, theta_o, rho_s, r_s): time of rt_image_vjp per call (all its
+    passes, stream-ordered with no host synchronisation, HIP events on the
+    stream), beside the forward trace of the same image.  The same gradient
+    of the image at 1024x1024 is timed too, with the scratch it took."""
     import math
 
     import numpy as np
@@ -320,13 +321,14 @@ def adjoint_measurement(steps: int, cpu: bool) -> dict:
     grad = torch.empty(4, dtype=torch.float64, device="cuda")
     rt.rt_image_vjp(p[0], dl, grad, None, rt.RT_GRAD_DENSITY, stream)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
     for _ in range(steps):
         rt.rt_image_vjp(p[0], dl, grad, None, rt.RT_GRAD_DENSITY, stream)
+    b.record(stream)
     torch.cuda.synchronize()
-    adj_ms = (time.perf_counter() - t0) * 1e3 / steps
+    adj_ms = a.elapsed_time(b) / steps
     stats = rt.rt_vjp_stats()
-    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     a.record(stream)
     for _ in range(steps):
         rt.rt_trace_image(p, o, stream)
@@ -338,8 +340,29 @@ def adjoint_measurement(steps: int, cpu: bool) -> dict:
     res = {"workload": "cored-NFW 256x256, tapered disc, L2 loss vs a 1 % parameter change",
            "adjoint_ms": adj_ms, "forward_ms": fwd_ms, "ratio": adj_ms / fwd_ms,
            "steps": steps, "loss": loss, "grad_chi_theta_rho_rs": grad.cpu().tolist(),
-           "taped_rays": stats["rays"], "tape_steps": stats["steps"],
-           "tape_bytes": stats["tape_bytes"]}
+           "reversed_rays": stats["rays"], "reversed_steps": stats["steps"],
+           "checkpoint_slots": stats["slots"], "scratch_bytes": stats["scratch_bytes"]}
+    big = dict(img, nx=1024, ny=1024)
+    outs_b = rt.trace(big)
+    tgt_b = rt.trace(dict(tgt, nx=1024, ny=1024))
+    dl_b = 2.0 * (outs_b["intensity"] - tgt_b["intensity"])
+    del outs_b, tgt_b
+    rt.rt_image_vjp(rt.params_from(big), dl_b, grad, None, rt.RT_GRAD_DENSITY, stream)
+    torch.cuda.synchronize()
+    n_big = 2
+    a.record(stream)
+    for _ in range(n_big):
+        rt.rt_image_vjp(rt.params_from(big), dl_b, grad, None, rt.RT_GRAD_DENSITY, stream)
+    b.record(stream)
+    torch.cuda.synchronize()
+    st_b = rt.rt_vjp_stats()
+    res["full_screen"] = {"workload": "the same image at 1024x1024",
+                          "adjoint_ms": a.elapsed_time(b) / n_big, "calls": n_big,
+                          "reversed_rays": st_b["rays"], "reversed_steps": st_b["steps"],
+                          "checkpoint_slots": st_b["slots"],
+                          "scratch_bytes": st_b["scratch_bytes"], "diverged": st_b["diverged"]}
+    log(f"adjoint 1024^2: {res['full_screen']['adjoint_ms']:.1f} ms, "
+        f"{st_b['scratch_bytes'] / 2**30:.2f} GiB scratch")
     if cpu:
         from oracle import oracle as O
         threads = oracle_threads()

@@ -26,8 +26,7 @@
  *     null stream).  Outputs are valid once that stream has reached the point
  *     of the call.  Scratch memory (work-queue counters and intermediate
  *     buffers) is allocated stream-ordered and released before the work
- *     completes; the image gradient keeps its tape workspace between calls
- *     (see rt_image_vjp).
+ *     completes.
  *   - Return value: RT_OK (0) on success, a negative RT_ERR_* code otherwise;
  *     rt_last_error() then describes the failure (thread-local string).  On an
  *     error nothing has been launched.  The library never aborts or prints.
@@ -371,19 +370,19 @@ enum { RT_GRAD_NATIVE = 0, RT_GRAD_DENSITY = 1 };
  *   grad      device [4]: dL/dq = sum over pixels of dl_dI dI/dq (fixed order,
  *             deterministic)
  *   grad_pix  device [ny][nx][4] per-pixel dl_dI dI/dq, or NULL
- * Pixels with dl_dI = 0 are not traced.  Internally a trace that tapes every
- * accepted step (240 bytes: its start state, size, crossing and six stage
- * derivatives) of each contributing ray into a tape region of its own pixel
- * (up to 1024 steps, fewer if the tape budget requires), then a reverse sweep
- * over the tapes; the rare rays needing longer tapes are counted exactly and
- * taped packed, longest first, in slices within the budget.  The dense tape
- * memory is kept by the library per thread and device between calls (grown
- * on demand; n_pix x steps x 240 bytes, at most the tape budget).
- * Unlike the trace calls this one synchronises `hip_stream` once (twice when
- * long rays occur) to read pass counters, and allocates stream-ordered device
- * memory of about 4 n_pix (2 + 8) bytes.  Errors as for rt_trace_image;
- * RT_ERR_ARG for an unknown basis or the density basis on a metric other than
- * RT_CNFW. */
+ * Pixels with dl_dI = 0 are not traced.  Internally, by checkpointed
+ * recomputation: a forward trace stores a checkpoint of every contributing ray
+ * before every 32nd accepted step (up to 32 slots per pixel, fewer if the
+ * checkpoint budget requires, at least 4; a ray that runs out of slots keeps
+ * every other checkpoint and doubles its interval, so rays of any length
+ * fit), then a backward pass restores each segment's checkpoint from the last
+ * to the first, recomputes its steps -- bit for bit the traced ones -- and
+ * reverses them.  Memory: 128 bytes per checkpoint slot and pixel, plus
+ * 7.5 KiB per resident lane of the backward pass, all stream-ordered and
+ * released by the end of the call; nothing is kept between calls and the
+ * stream is not synchronised (the call is fully asynchronous).
+ * Errors as for rt_trace_image; RT_ERR_ARG for an unknown basis or the
+ * density basis on a metric other than RT_CNFW. */
 int rt_image_vjp(const rt_image_params *params, const double *dl_dI, int32_t basis,
                  double *grad, double *grad_pix, void *hip_stream);
 
@@ -401,14 +400,18 @@ int rt_mixed_stats(int64_t *out);
  * image.  NULL switches it off.  The event stays owned by the caller. */
 int rt_set_split_timing(void *event);
 
-/* Device memory the gradient may use for tapes (thread-local, bytes, at least
- * 1 MiB; default 16 GiB).  A smaller budget only moves rays to the packed
- * tapes and splits those into more slices; results are unchanged. */
-int rt_set_tape_budget(int64_t bytes);
+/* Device memory the gradient's checkpoints may use (thread-local, bytes, at
+ * least 1 MiB; default 16 GiB): the slots per pixel are the most of 32 whose
+ * 128 bytes each fit n_pix times in the budget, at least 4 (a soft limit for
+ * very large screens).  Fewer slots only make long rays double their
+ * checkpoint interval sooner and recompute more; results are unchanged. */
+int rt_set_checkpoint_budget(int64_t bytes);
 
-/* Statistics of the last rt_image_vjp call on this thread: out[0..3] = {rays
- * reversed, tape records reversed, slices of packed tapes (0 if no ray needed
- * them), bytes of the largest tape area}. */
+/* Statistics of the last rt_image_vjp call on this thread and the current
+ * device: out[0..4] = {rays reversed, accepted steps reversed, checkpoint
+ * slots per pixel, bytes of scratch memory the call used, recomputations that
+ * diverged from the trace (0: a non-zero count means a wrong gradient)}.
+ * `out` holds 5 values.  Synchronous (waits for that call's work). */
 int rt_vjp_stats(int64_t *out);
 
 /* How the persistent trace kernels hand out work (thread-local setting,

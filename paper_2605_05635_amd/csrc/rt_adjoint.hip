@@ -1,24 +1,28 @@
 // rt_adjoint.hip -- gfx950 kernels of the image gradient: reverse mode
 // through the computed discrete map of every ray (the per-ray pieces are in
-// rt_vjp.h).  Two persistent passes, each lane owning one ray at a time:
+// rt_vjp.h), with checkpointed recomputation so that memory grows with the
+// number of checkpoints, not of steps.  Two persistent passes, each lane
+// owning one ray at a time:
 //
-//  1. tape:    trace every pixel whose loss cotangent is non-zero, writing each
-//              accepted step's start state, size and crossing index into the
-//              pixel's own tape region (cap steps), and record how many steps
-//              matter: up to and including the last one whose crossing emits
-//              (nothing after it reaches the intensity).  A ray that needs
-//              more than cap steps is marked (count -1) and counted;
-//  2. reverse: walk each tape backwards with reverse_step, then chain the
-//              adjoint of the initial state through the screen map and write
-//              the pixel's gradient along the four image parameters.
+//  1. forward:  trace every pixel whose loss cotangent is non-zero and store a
+//               checkpoint of the ray before every kVjpSeg-th accepted step
+//               (a fixed number of slots per pixel: when they run out the
+//               interval doubles and every other checkpoint is dropped); record
+//               how many steps matter -- up to and including the last one whose
+//               crossing emits (nothing after it reaches the intensity);
+//  2. backward: for each segment from the last to the first, restore its
+//               checkpoint, recompute its accepted steps (with their stage
+//               derivatives) into the lane's buffer -- at most kVjpBuf at a time,
+//               taken from the segment's end -- and reverse them with
+//               reverse_step; finally chain the adjoint of the initial state
+//               through the screen map into the pixel's four gradient terms.
 //
-// The marked rays (rare: long photon-ring orbits) go through a list-driven
-// variant of the same passes, with tapes sized exactly by a counting pass and
-// packed longest first.  The tape holds each step's stage derivatives as well
-// (240 bytes per step), so that the reverse pass does not recompute the six
-// right-hand sides of a step (measured 5 % faster per gradient than a 48-byte
-// tape with recomputation).  A last pair of kernels sums the per-pixel
-// gradients in a fixed order.
+// The recomputation repeats the forward pass's attempts exactly (the same
+// code on the same state), so the steps reversed are the steps traced.  Within
+// a wavefront the lanes recompute together, then reverse together (two
+// ballot-driven phases per round), so the two kinds of work do not interleave
+// instruction by instruction.  A last pair of kernels sums the per-pixel
+// gradients in a fixed order.  No pass needs a result on the host.
 #include "rt_vjp.h"
 
 namespace rt {
@@ -29,32 +33,50 @@ using vjp::kRecDoubles;
 
 static_assert(vjp::kPrims == kVjpPrims, "parameter-adjoint count");
 static_assert(kRecDoubles * 8 == kVjpRecBytes, "tape record size");
+static_assert(vjp::kCkptDoubles == kVjpCkptDoubles, "checkpoint size");
+static_assert(kVjpSeg % kVjpBuf == 0, "segments split into whole buffers");
 
-struct ListShape {
-    int32_t chunk;
-};
+// Adds the wave's sums of a and b to total[0], total[1] (lane 0; converged).
+__device__ __forceinline__ void add_wave_totals(uint32_t a, uint32_t b,
+                                                unsigned long long* total) {
+    unsigned long long x = a, y = b;
+    for (int off = 32; off > 0; off >>= 1) {
+        x += __shfl_xor(x, off);
+        y += __shfl_xor(y, off);
+    }
+    if (__lane_id() == 0 && (x | y) != 0ull) {
+        atomicAdd(&total[0], x);
+        atomicAdd(&total[1], y);
+    }
+}
 
+// Pass 1.
 template <int METRIC>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 8))) void vjp_count_kernel(
-    ImageConst c, const double* __restrict__ dl_dI, int32_t* __restrict__ count,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) void vjp_forward_kernel(
+    ImageConst c, const double* __restrict__ dl_dI, int32_t slots, double* __restrict__ ckpt,
+    int32_t* __restrict__ count, int32_t* __restrict__ kseg, unsigned long long* counters,
     unsigned long long* queue, LaunchShape shape) {
-    // Only the pixels whose count is -1 on entry are traced (the rays the
-    // dense tape could not hold); every other count is set to 0.
     const Hot k = hot_of(c);
     const OutPtrs none{};
     Ray r;
-    int32_t acc = 0, last = -1;
+    int32_t acc = 0, last = -1, K = kVjpSeg, used = 0;
+    double* mine = ckpt;
     bool live = false;
     bool active = false, exhausted = false;
     int64_t next = 0, end = 0;
     TileClaim tc{0, 0, 1};
+    uint32_t rays = 0, steps = 0;
     auto claim = [&]() { return claim_screen(shape, c.nx, c.ny, queue, next, end, tc); };
     auto take = [&](int64_t ordinal) {
         const int64_t pix = claimed_pixel(shape, c.nx, c.ny, tc, ordinal);
         start_ray<METRIC>(c, k, pix, r);
         acc = 0;
         last = -1;
-        live = count[pix] < 0 && dl_dI[pix] != 0.0;
+        K = kVjpSeg;
+        live = dl_dI[pix] != 0.0;
+        mine = ckpt + pix * static_cast<int64_t>(slots) * kVjpCkptDoubles;
+        if (live) vjp::store_checkpoint(mine, r, 0);
+        used = 1;
     };
     for (;;) {
         if (!exhausted) refill(active, exhausted, next, end, claim, take);
@@ -64,192 +86,83 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 8))) 
             if (live) {
                 const int32_t n0 = r.ncross;
                 const int32_t st = attempt<METRIC>(k, none, c.n_pix, r);
-                if (st != RAY_STEP_LIMIT && r.after_reject == 0) {
+                if (st != RAY_STEP_LIMIT && r.after_reject == 0) {   // accepted
                     if (r.ncross != n0 && n0 < 3) {
                         const double Rc = n0 == 0 ? r.rc[0] : (n0 == 1 ? r.rc[1] : r.rc[2]);
                         if (vjp::emits<METRIC>(c, k, Rc, r.E, r.L)) last = acc;
                     }
                     ++acc;
+                    if (st == 0 && r.ncross < 3 && acc % K == 0) {
+                        if (used == slots) {   // out of slots: keep every other one
+                            for (int32_t i = 1; i < slots / 2; ++i)
+                                for (int j = 0; j < kVjpCkptDoubles; ++j)
+                                    mine[i * kVjpCkptDoubles + j] = mine[2 * i * kVjpCkptDoubles + j];
+                            used = slots / 2;
+                            K *= 2;
+                        }
+                        vjp::store_checkpoint(mine + used * kVjpCkptDoubles, r, acc);
+                        ++used;
+                    }
                 }
                 done = st != 0 || r.ncross >= 3;
             }
             if (done) {
                 count[r.pix] = last + 1;
-                active = false;
-            }
-        }
-    }
-}
-
-template <int METRIC>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 8))) void vjp_tape_kernel(
-    ImageConst c, const int32_t* __restrict__ list_pix, const int64_t* __restrict__ list_off,
-    const int32_t* __restrict__ count, int64_t n_list, int64_t rec_base,
-    double* __restrict__ tape, int32_t* __restrict__ taped, unsigned long long* queue,
-    ListShape shape) {
-    const Hot k = hot_of(c);
-    const OutPtrs none{};
-    Ray r;
-    int64_t entry = 0, rec = 0;
-    int32_t acc = 0, want = 0;
-    bool active = false, exhausted = false;
-    int64_t next = 0, end = 0;
-    auto claim = [&]() { return claim_chunk(queue, shape.chunk, n_list, next, end); };
-    auto take = [&](int64_t e) {
-        entry = e;
-        const int64_t pix = list_pix[e];
-        start_ray<METRIC>(c, k, pix, r);
-        rec = list_off[e] - rec_base;
-        want = count[pix];
-        acc = 0;
-    };
-    for (;;) {
-        if (!exhausted) refill(active, exhausted, next, end, claim, take);
-        if (__ballot(active) == 0ull) break;
-        if (active) {
-            const double x0 = r.y[1], x1 = r.y[2], x2 = r.y[4], x3 = r.y[5], h = r.h;
-            const int32_t n0 = r.ncross;
-            double* const slot = tape + (rec + acc) * kRecDoubles;
-            const int32_t st = attempt<METRIC>(k, none, c.n_pix, r, vjp::TapeStages{slot});
-            if (st != RAY_STEP_LIMIT && r.after_reject == 0) {
-                double2* p = reinterpret_cast<double2*>(slot);
-                const double cross = (r.ncross != n0 && n0 < 3) ? static_cast<double>(n0) : -1.0;
-                p[0] = make_double2(x0, x1);
-                p[1] = make_double2(x2, x3);
-                p[2] = make_double2(h, cross);
-                ++acc;
-            }
-            if (acc >= want || st != 0) {
-                taped[entry] = acc;
-                active = false;
-            }
-        }
-    }
-}
-
-// Pass 1 of the common path.  counters[0] += marked rays, counters[1] += rays
-// with a non-zero count, counters[2] += their steps (one atomic per wave each).
-template <int METRIC>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 8))) void vjp_tape_dense_kernel(
-    ImageConst c, const double* __restrict__ dl_dI, int32_t cap, double* __restrict__ tape,
-    double* overflow, int32_t* __restrict__ count, unsigned int* counters,
-    unsigned long long* queue, LaunchShape shape) {
-    const Hot k = hot_of(c);
-    const OutPtrs none{};
-    Ray r;
-    int32_t acc = 0, last = -1;
-    bool live = false;
-    bool active = false, exhausted = false;
-    int64_t next = 0, end = 0;
-    TileClaim tc{0, 0, 1};
-    auto claim = [&]() { return claim_screen(shape, c.nx, c.ny, queue, next, end, tc); };
-    auto take = [&](int64_t ordinal) {
-        const int64_t pix = claimed_pixel(shape, c.nx, c.ny, tc, ordinal);
-        start_ray<METRIC>(c, k, pix, r);
-        acc = 0;
-        last = -1;
-        live = dl_dI[pix] != 0.0;
-    };
-    const int lane = __lane_id();
-    for (;;) {
-        if (!exhausted) refill(active, exhausted, next, end, claim, take);
-        if (__ballot(active) == 0ull) break;
-        int32_t finished = 0;   // 0: none; 1: counted ray; 2: marked ray
-        int32_t nsteps = 0;
-        if (active) {
-            bool done = !live;
-            if (live) {
-                const double x0 = r.y[1], x1 = r.y[2], x2 = r.y[4], x3 = r.y[5], h = r.h;
-                const int32_t n0 = r.ncross;
-                // steps past the pixel's region write their stages to a scratch
-                // record that nothing reads (a branch-free store target)
-                double* const slot =
-                    acc < cap ? tape + (r.pix * static_cast<int64_t>(cap) + acc) * kRecDoubles
-                              : overflow;
-                const int32_t st = attempt<METRIC>(k, none, c.n_pix, r, vjp::TapeStages{slot});
-                if (st != RAY_STEP_LIMIT && r.after_reject == 0) {
-                    const bool crossed = r.ncross != n0 && n0 < 3;
-                    if (acc < cap) {
-                        double2* p = reinterpret_cast<double2*>(slot);
-                        p[0] = make_double2(x0, x1);
-                        p[1] = make_double2(x2, x3);
-                        p[2] = make_double2(h, crossed ? static_cast<double>(n0) : -1.0);
-                    }
-                    if (crossed) {
-                        const double Rc = n0 == 0 ? r.rc[0] : (n0 == 1 ? r.rc[1] : r.rc[2]);
-                        if (vjp::emits<METRIC>(c, k, Rc, r.E, r.L)) last = acc;
-                    }
-                    ++acc;
-                }
-                done = st != 0 || r.ncross >= 3;
-            }
-            if (done) {
-                nsteps = last + 1;
-                if (nsteps > cap) {
-                    count[r.pix] = -1;
-                    finished = 2;
-                } else {
-                    count[r.pix] = nsteps;
-                    finished = nsteps > 0 ? 1 : 0;
+                kseg[r.pix] = K;
+                if (last >= 0) {
+                    ++rays;
+                    steps += static_cast<uint32_t>(last + 1);
                 }
                 active = false;
             }
         }
-        const unsigned long long mark = __ballot(finished == 2);
-        const unsigned long long kept = __ballot(finished == 1);
-        if ((mark | kept) != 0ull) {
-            unsigned int s = finished == 1 ? static_cast<unsigned int>(nsteps) : 0u;
-            for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-            if (lane == 0) {
-                if (mark) atomicAdd(&counters[0], static_cast<unsigned int>(__popcll(mark)));
-                if (kept) {
-                    atomicAdd(&counters[1], static_cast<unsigned int>(__popcll(kept)));
-                    atomicAdd(&counters[2], s);
-                }
-            }
-        }
     }
+    add_wave_totals(rays, steps, counters);
 }
 
 struct JacArg {
     double m[kVjpPrims][4];
 };
 
-// Pass 2.  DENSE: items are the screen's pixels in the order of `shape`, the
-// pixel's tape at pix * cap records, steps[pix] of them (none if <= 0).
-// Otherwise items are list entries: pixel list_pix[e], tape at list_off[e] -
-// rec_base, steps[e] records.
-template <int METRIC, bool DENSE>
-__global__ __launch_bounds__(kBlock) void vjp_reverse_kernel(
-    ImageConst c, const double* __restrict__ dl_dI, const int32_t* __restrict__ list_pix,
-    const int64_t* __restrict__ list_off, const int32_t* __restrict__ steps, int64_t n_items,
-    int64_t rec_base, int32_t cap, const double* __restrict__ tape, JacArg J,
-    double* __restrict__ grad_pix, unsigned long long* queue, LaunchShape shape) {
+// Pass 2.
+template <int METRIC>
+__global__ __launch_bounds__(kBlock) void vjp_backward_kernel(
+    ImageConst c, const double* __restrict__ dl_dI, const int32_t* __restrict__ count,
+    const int32_t* __restrict__ kseg, int32_t slots, const double* __restrict__ ckpt,
+    double* __restrict__ lane_buf, JacArg J, double* __restrict__ grad_pix,
+    unsigned long long* counters, unsigned long long* queue, LaunchShape shape) {
     const Hot k = hot_of(c);
-    int64_t pix = 0, rec = 0;
-    int32_t step = 0;
-    bool skip = false;
+    const OutPtrs none{};
+    double* const buf = lane_buf + (static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x) *
+                                       (static_cast<int64_t>(kVjpBuf) * kRecDoubles);
+    Ray r;
+    int64_t pix = 0;
+    const double* mine = ckpt;
+    int32_t K = kVjpSeg, seg = 0, seg_len = 0, chunk = 0, acc = 0, rec_lo = 0, rec_hi = 0;
+    int32_t n_rec = 0;
+    bool fwd = false;
     double E = 0.0, L = 0.0, Ib = 0.0;
     ScreenDir dir{0.0, 0.0, 0.0};
     double xb[4], Eb, Lb, pb[4], rinb;
     bool active = false, exhausted = false;
     int64_t next = 0, end = 0;
     TileClaim tc{0, 0, 1};
-    auto claim = [&]() {
-        if constexpr (DENSE) return claim_screen(shape, c.nx, c.ny, queue, next, end, tc);
-        return claim_chunk(queue, shape.chunk, n_items, next, end);
+    // (re)start the recomputation of chunk `chunk` of segment `seg`
+    auto begin_chunk = [&]() {
+        vjp::load_checkpoint<METRIC>(mine + seg * kVjpCkptDoubles, k, E, L, pix, r);
+        acc = 0;
+        rec_lo = chunk * kVjpBuf;
+        rec_hi = rec_lo + kVjpBuf < seg_len ? rec_lo + kVjpBuf : seg_len;
+        n_rec = 0;
+        fwd = true;
     };
-    auto take = [&](int64_t e) {
-        if constexpr (DENSE) {
-            pix = claimed_pixel(shape, c.nx, c.ny, tc, e);
-            rec = pix * static_cast<int64_t>(cap);
-            step = steps[pix] - 1;
-        } else {
-            pix = list_pix[e];
-            rec = list_off[e] - rec_base;
-            step = steps[e] - 1;
-        }
-        skip = step < 0;
+    auto claim = [&]() { return claim_screen(shape, c.nx, c.ny, queue, next, end, tc); };
+    auto take = [&](int64_t ordinal) {
+        pix = claimed_pixel(shape, c.nx, c.ny, tc, ordinal);
+        const int32_t cnt = count[pix];
+        fwd = false;
+        n_rec = 0;
+        if (cnt <= 0) return;   // nothing reaches the intensity: the zero gradient stands
         dir = screen_dir(c, pix);
         E = c.obs_N - c.obs_gTph_over_sq_gphph * dir.nph;
         L = c.obs_sq_gphph * dir.nph;
@@ -259,13 +172,50 @@ __global__ __launch_bounds__(kBlock) void vjp_reverse_kernel(
             pb[i] = 0.0;
         }
         Eb = Lb = rinb = 0.0;
+        K = kseg[pix];
+        mine = ckpt + pix * static_cast<int64_t>(slots) * kVjpCkptDoubles;
+        seg = (cnt - 1) / K;
+        seg_len = cnt - seg * K;
+        chunk = (seg_len - 1) / kVjpBuf;
+        begin_chunk();
     };
     for (;;) {
         if (!exhausted) refill(active, exhausted, next, end, claim, take);
         if (__ballot(active) == 0ull) break;
-        if (active) {
-            if (step >= 0) {
-                const double* rp = tape + (rec + step) * kRecDoubles;
+        if (active && !fwd && n_rec == 0) active = false;   // an empty ray
+        // Recompute: the lanes with a chunk to fill run attempts, recording the
+        // accepted steps rec_lo..rec_hi-1 of their segment.
+        while (__ballot(active && fwd) != 0ull) {
+            if (active && fwd) {
+                double* slot = buf + n_rec * kRecDoubles;
+                const double x0 = r.y[1], x1 = r.y[2], x2 = r.y[4], x3 = r.y[5], h = r.h;
+                const int32_t n0 = r.ncross;
+                const int32_t st = attempt<METRIC>(k, none, c.n_pix, r, vjp::TapeStages{slot});
+                if (st != RAY_STEP_LIMIT && r.after_reject == 0) {   // accepted
+                    if (acc >= rec_lo) {
+                        const bool crossed = r.ncross != n0 && n0 < 3;
+                        double2* p = reinterpret_cast<double2*>(slot);
+                        p[0] = make_double2(x0, x1);
+                        p[1] = make_double2(x2, x3);
+                        p[2] = make_double2(h, crossed ? static_cast<double>(n0) : -1.0);
+                        ++n_rec;
+                    }
+                    ++acc;
+                    if (acc == rec_hi) fwd = false;
+                }
+                // The recomputation repeats the traced attempts, so the ray
+                // cannot end before rec_hi; should it ever (a recomputation that
+                // diverged from the trace), stop and count it rather than spin.
+                if (fwd && st != 0) {
+                    fwd = false;
+                    atomicAdd(&counters[2], 1ull);
+                }
+            }
+        }
+        // Reverse: the lanes with recorded steps walk them backwards.
+        while (__ballot(active && n_rec > 0) != 0ull) {
+            if (active && n_rec > 0) {
+                const double* rp = buf + (n_rec - 1) * kRecDoubles;
                 const double2* p = reinterpret_cast<const double2*>(rp);
                 const double2 a = p[0], b = p[1], hc = p[2];
                 const double x0[4] = {a.x, a.y, b.x, b.y};
@@ -278,34 +228,47 @@ __global__ __launch_bounds__(kBlock) void vjp_reverse_kernel(
                 }
                 vjp::reverse_step<METRIC>(c, k, E, L, x0, hc.x, static_cast<int>(hc.y), kin, Ib,
                                           xb, Eb, Lb, pb, rinb);
-                --step;
-            }
-            if (step < 0 && skip) {
-                active = false;   // no step matters: the zero-filled gradient stands
-            } else if (step < 0) {
-                // Initial state (0, R_o, theta_o, 0, sqrt(g_RR) n_R, sqrt(g_thth) n_theta),
-                // E = N_o - (g_Tphi/sqrt(g_phiphi)) n_phi, l = sqrt(g_phiphi) n_phi.
-                double prim[kVjpPrims];
-                prim[vjp::P_CHI] = pb[0];
-                prim[vjp::P_M0] = pb[1];
-                prim[vjp::P_M1] = pb[2];
-                prim[vjp::P_M2] = pb[3];
-                prim[vjp::P_RIN] = rinb;
-                prim[vjp::P_OBS_N] = Eb;
-                prim[vjp::P_OBS_TPH] = -Eb * dir.nph;
-                prim[vjp::P_OBS_PH] = Lb * dir.nph;
-                prim[vjp::P_OBS_R] = xb[2] * dir.nR;
-                prim[vjp::P_OBS_TH] = xb[3] * dir.nth;
-                prim[vjp::P_INCL] = xb[1];
-                for (int j = 0; j < 4; ++j) {
-                    double g = 0.0;
-                    for (int m = 0; m < kVjpPrims; ++m) g += prim[m] * J.m[m][j];
-                    grad_pix[pix * 4 + j] = g;
+                if (--n_rec == 0) {
+                    if (chunk > 0) {
+                        --chunk;
+                        begin_chunk();
+                    } else if (seg > 0) {
+                        --seg;
+                        seg_len = K;
+                        chunk = K / kVjpBuf - 1;
+                        begin_chunk();
+                    } else {
+                        // Initial state (0, R_o, theta_o, 0, sqrt(g_RR) n_R,
+                        // sqrt(g_thth) n_theta), E = N_o - (g_Tphi/sqrt(g_phiphi)) n_phi,
+                        // l = sqrt(g_phiphi) n_phi.
+                        double prim[kVjpPrims];
+                        prim[vjp::P_CHI] = pb[0];
+                        prim[vjp::P_M0] = pb[1];
+                        prim[vjp::P_M1] = pb[2];
+                        prim[vjp::P_M2] = pb[3];
+                        prim[vjp::P_RIN] = rinb;
+                        prim[vjp::P_OBS_N] = Eb;
+                        prim[vjp::P_OBS_TPH] = -Eb * dir.nph;
+                        prim[vjp::P_OBS_PH] = Lb * dir.nph;
+                        prim[vjp::P_OBS_R] = xb[2] * dir.nR;
+                        prim[vjp::P_OBS_TH] = xb[3] * dir.nth;
+                        prim[vjp::P_INCL] = xb[1];
+                        for (int j = 0; j < 4; ++j) {
+                            double g = 0.0;
+                            for (int m = 0; m < kVjpPrims; ++m) g += prim[m] * J.m[m][j];
+                            grad_pix[pix * 4 + j] = g;
+                        }
+                        active = false;
+                    }
                 }
-                active = false;
             }
         }
     }
+}
+
+__global__ void copy_vjp_stats(const unsigned long long* __restrict__ counters,
+                               long long* __restrict__ stats) {
+    if (threadIdx.x < 3) stats[threadIdx.x] = static_cast<long long>(counters[threadIdx.x]);
 }
 
 __global__ void fill_zero(double* __restrict__ p, int64_t n) {
@@ -356,112 +319,54 @@ int occupancy(Kern kern, size_t lds = 0) {
 
 }  // namespace
 
-hipError_t launch_vjp_count(const ImageConst& c, const double* dl_dI, int32_t* count,
-                            unsigned long long* queue, const LaunchShape& shape, int32_t grid,
-                            hipStream_t stream) {
+hipError_t launch_vjp_forward(const ImageConst& c, const double* dl_dI, int32_t slots,
+                              double* ckpt, int32_t* count, int32_t* kseg,
+                              unsigned long long* counters, unsigned long long* queue,
+                              const LaunchShape& shape, int32_t grid, hipStream_t stream) {
     if (c.metric == KERR)
-        hipLaunchKernelGGL(vjp_count_kernel<KERR>, dim3(grid), dim3(kBlock), 0, stream, c, dl_dI,
-                           count, queue, shape);
+        hipLaunchKernelGGL(vjp_forward_kernel<KERR>, dim3(grid), dim3(kBlock), 0, stream, c,
+                           dl_dI, slots, ckpt, count, kseg, counters, queue, shape);
     else if (c.metric == EINASTO)
-        hipLaunchKernelGGL(vjp_count_kernel<EINASTO>, dim3(grid), dim3(kBlock), 0, stream, c,
-                           dl_dI, count, queue, shape);
+        hipLaunchKernelGGL(vjp_forward_kernel<EINASTO>, dim3(grid), dim3(kBlock), 0, stream, c,
+                           dl_dI, slots, ckpt, count, kseg, counters, queue, shape);
     else if (c.ex_near)
-        hipLaunchKernelGGL(vjp_count_kernel<CNFW_NEAR>, dim3(grid), dim3(kBlock), 0, stream, c, dl_dI,
-                           count, queue, shape);
+        hipLaunchKernelGGL(vjp_forward_kernel<CNFW_NEAR>, dim3(grid), dim3(kBlock), 0, stream, c,
+                           dl_dI, slots, ckpt, count, kseg, counters, queue, shape);
     else
-        hipLaunchKernelGGL(vjp_count_kernel<CNFW>, dim3(grid), dim3(kBlock), 0, stream, c, dl_dI,
-                           count, queue, shape);
+        hipLaunchKernelGGL(vjp_forward_kernel<CNFW>, dim3(grid), dim3(kBlock), 0, stream, c,
+                           dl_dI, slots, ckpt, count, kseg, counters, queue, shape);
     return hipGetLastError();
 }
 
-hipError_t launch_vjp_tape(const ImageConst& c, const int32_t* list_pix, const int64_t* list_off,
-                           const int32_t* count, int64_t n_list, int64_t rec_base, double* tape,
-                           int32_t* taped, unsigned long long* queue, int32_t chunk,
-                           int32_t grid, hipStream_t stream) {
-    const ListShape sh{chunk};
-    if (c.metric == KERR)
-        hipLaunchKernelGGL(vjp_tape_kernel<KERR>, dim3(grid), dim3(kBlock), 0, stream, c,
-                           list_pix, list_off, count, n_list, rec_base, tape, taped, queue, sh);
-    else if (c.metric == EINASTO)
-        hipLaunchKernelGGL(vjp_tape_kernel<EINASTO>, dim3(grid), dim3(kBlock), 0, stream, c,
-                           list_pix, list_off, count, n_list, rec_base, tape, taped, queue, sh);
-    else if (c.ex_near)
-        hipLaunchKernelGGL(vjp_tape_kernel<CNFW_NEAR>, dim3(grid), dim3(kBlock), 0, stream, c,
-                           list_pix, list_off, count, n_list, rec_base, tape, taped, queue, sh);
-    else
-        hipLaunchKernelGGL(vjp_tape_kernel<CNFW>, dim3(grid), dim3(kBlock), 0, stream, c,
-                           list_pix, list_off, count, n_list, rec_base, tape, taped, queue, sh);
-    return hipGetLastError();
-}
-
-hipError_t launch_vjp_tape_dense(const ImageConst& c, const double* dl_dI, int32_t cap,
-                                 double* tape, double* overflow, int32_t* count,
-                                 unsigned int* counters,
-                                 unsigned long long* queue, const LaunchShape& shape,
-                                 int32_t grid, hipStream_t stream) {
-    if (c.metric == KERR)
-        hipLaunchKernelGGL(vjp_tape_dense_kernel<KERR>, dim3(grid), dim3(kBlock), 0, stream, c,
-                           dl_dI, cap, tape, overflow, count, counters, queue, shape);
-    else if (c.metric == EINASTO)
-        hipLaunchKernelGGL(vjp_tape_dense_kernel<EINASTO>, dim3(grid), dim3(kBlock), 0, stream, c,
-                           dl_dI, cap, tape, overflow, count, counters, queue, shape);
-    else if (c.ex_near)
-        hipLaunchKernelGGL(vjp_tape_dense_kernel<CNFW_NEAR>, dim3(grid), dim3(kBlock), 0, stream, c,
-                           dl_dI, cap, tape, overflow, count, counters, queue, shape);
-    else
-        hipLaunchKernelGGL(vjp_tape_dense_kernel<CNFW>, dim3(grid), dim3(kBlock), 0, stream, c,
-                           dl_dI, cap, tape, overflow, count, counters, queue, shape);
-    return hipGetLastError();
-}
-
-namespace {
-template <bool DENSE>
-hipError_t reverse_launch(const ImageConst& c, const double* dl_dI, const int32_t* list_pix,
-                          const int64_t* list_off, const int32_t* steps, int64_t n_items,
-                          int64_t rec_base, int32_t cap, const double* tape,
-                          const double (&jac)[kVjpPrims][4], double* grad_pix,
-                          unsigned long long* queue, const LaunchShape& shape, int32_t grid,
-                          hipStream_t stream) {
+hipError_t launch_vjp_backward(const ImageConst& c, const double* dl_dI, const int32_t* count,
+                               const int32_t* kseg, int32_t slots, const double* ckpt,
+                               double* lane_buf, const double (&jac)[kVjpPrims][4],
+                               double* grad_pix, unsigned long long* counters,
+                               unsigned long long* queue, const LaunchShape& shape, int32_t grid,
+                               hipStream_t stream) {
     JacArg J;
     for (int m = 0; m < kVjpPrims; ++m)
         for (int j = 0; j < 4; ++j) J.m[m][j] = jac[m][j];
     if (c.metric == KERR)
-        hipLaunchKernelGGL((vjp_reverse_kernel<KERR, DENSE>), dim3(grid), dim3(kBlock),
-                           0, stream, c, dl_dI, list_pix, list_off, steps, n_items,
-                           rec_base, cap, tape, J, grad_pix, queue, shape);
+        hipLaunchKernelGGL(vjp_backward_kernel<KERR>, dim3(grid), dim3(kBlock), 0, stream, c,
+                           dl_dI, count, kseg, slots, ckpt, lane_buf, J, grad_pix, counters, queue, shape);
     else if (c.metric == EINASTO)
-        hipLaunchKernelGGL((vjp_reverse_kernel<EINASTO, DENSE>), dim3(grid), dim3(kBlock),
-                           0, stream, c, dl_dI, list_pix, list_off, steps, n_items,
-                           rec_base, cap, tape, J, grad_pix, queue, shape);
+        hipLaunchKernelGGL(vjp_backward_kernel<EINASTO>, dim3(grid), dim3(kBlock), 0, stream, c,
+                           dl_dI, count, kseg, slots, ckpt, lane_buf, J, grad_pix, counters, queue, shape);
     else if (c.ex_near)
-        hipLaunchKernelGGL((vjp_reverse_kernel<CNFW_NEAR, DENSE>), dim3(grid), dim3(kBlock),
-                           0, stream, c, dl_dI, list_pix, list_off, steps, n_items,
-                           rec_base, cap, tape, J, grad_pix, queue, shape);
+        hipLaunchKernelGGL(vjp_backward_kernel<CNFW_NEAR>, dim3(grid), dim3(kBlock), 0, stream,
+                           c, dl_dI, count, kseg, slots, ckpt, lane_buf, J, grad_pix, counters,
+                           queue, shape);
     else
-        hipLaunchKernelGGL((vjp_reverse_kernel<CNFW, DENSE>), dim3(grid), dim3(kBlock),
-                           0, stream, c, dl_dI, list_pix, list_off, steps, n_items,
-                           rec_base, cap, tape, J, grad_pix, queue, shape);
+        hipLaunchKernelGGL(vjp_backward_kernel<CNFW>, dim3(grid), dim3(kBlock), 0, stream, c,
+                           dl_dI, count, kseg, slots, ckpt, lane_buf, J, grad_pix, counters, queue, shape);
     return hipGetLastError();
 }
-}  // namespace
 
-hipError_t launch_vjp_reverse(const ImageConst& c, const double* dl_dI, const int32_t* list_pix,
-                              const int64_t* list_off, const int32_t* taped, int64_t n_list,
-                              int64_t rec_base, const double* tape,
-                              const double (&jac)[kVjpPrims][4], double* grad_pix,
-                              unsigned long long* queue, int32_t chunk, int32_t grid,
-                              hipStream_t stream) {
-    return reverse_launch<false>(c, dl_dI, list_pix, list_off, taped, n_list, rec_base, 0, tape,
-                                 jac, grad_pix, queue, LaunchShape{chunk, 1, 1}, grid, stream);
-}
-
-hipError_t launch_vjp_reverse_dense(const ImageConst& c, const double* dl_dI,
-                                    const int32_t* count, int32_t cap, const double* tape,
-                                    const double (&jac)[kVjpPrims][4], double* grad_pix,
-                                    unsigned long long* queue, const LaunchShape& shape,
-                                    int32_t grid, hipStream_t stream) {
-    return reverse_launch<true>(c, dl_dI, nullptr, nullptr, count, c.n_pix, 0, cap, tape, jac,
-                                grad_pix, queue, shape, grid, stream);
+hipError_t launch_copy_vjp_stats(const unsigned long long* counters, long long* stats,
+                                 hipStream_t stream) {
+    hipLaunchKernelGGL(copy_vjp_stats, dim3(1), dim3(64), 0, stream, counters, stats);
+    return hipGetLastError();
 }
 
 hipError_t launch_fill_zero(double* p, int64_t n, hipStream_t stream) {
@@ -483,23 +388,13 @@ hipError_t launch_grad_reduce(const double* grad_pix, int64_t n_pix, double* par
 
 int vjp_blocks_per_cu(int metric, int pass) {
     if (pass == 0) {
-        if (metric == KERR) return occupancy(vjp_count_kernel<KERR>);
-        if (metric == EINASTO) return occupancy(vjp_count_kernel<EINASTO>);
-        return occupancy(vjp_count_kernel<CNFW>);
+        if (metric == KERR) return occupancy(vjp_forward_kernel<KERR>);
+        if (metric == EINASTO) return occupancy(vjp_forward_kernel<EINASTO>);
+        return occupancy(vjp_forward_kernel<CNFW>);
     }
-    if (pass == 1) {
-        if (metric == KERR) return occupancy(vjp_tape_kernel<KERR>);
-        if (metric == EINASTO) return occupancy(vjp_tape_kernel<EINASTO>);
-        return occupancy(vjp_tape_kernel<CNFW>);
-    }
-    if (pass == 3) {
-        if (metric == KERR) return occupancy(vjp_tape_dense_kernel<KERR>);
-        if (metric == EINASTO) return occupancy(vjp_tape_dense_kernel<EINASTO>);
-        return occupancy(vjp_tape_dense_kernel<CNFW>);
-    }
-    if (metric == KERR) return occupancy(vjp_reverse_kernel<KERR, true>);
-    if (metric == EINASTO) return occupancy(vjp_reverse_kernel<EINASTO, true>);
-    return occupancy(vjp_reverse_kernel<CNFW, true>);
+    if (metric == KERR) return occupancy(vjp_backward_kernel<KERR>);
+    if (metric == EINASTO) return occupancy(vjp_backward_kernel<EINASTO>);
+    return occupancy(vjp_backward_kernel<CNFW>);
 }
 
 }  // namespace rt

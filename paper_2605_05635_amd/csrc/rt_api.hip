@@ -619,8 +619,13 @@ int trace_common(const rt_image_params* params, int32_t n_images, const rt_image
 
 
 // ------------------------------------------------------------ image gradient
-thread_local int64_t g_tape_budget = int64_t(16) << 30;
-thread_local int64_t g_vjp_stats[4] = {0, 0, 0, 0};   // rays, tape steps, list slices, tape bytes
+thread_local int64_t g_ckpt_budget = int64_t(16) << 30;
+
+// Per-thread, per-device copy of the last gradient's counters (rays reversed,
+// steps reversed, recomputations that diverged), written by the device at the
+// end of each call.
+thread_local long long* g_vjp_stats_dev[64] = {};
+thread_local int64_t g_vjp_slots = 0, g_vjp_bytes = 0;
 
 // jac[m][j]: derivative of per-ray parameter m (the kernel's order: chi, three
 // mass constants, window inner edge, five observer-frame constants,
@@ -676,66 +681,40 @@ int vjp_jacobian(const rt_image_params* p, const rt::ImageConst& c, double r_plu
     return RT_OK;
 }
 
-// Pinned host memory for the counts read back by the gradient, reused.
-thread_local void* g_readback = nullptr;
-thread_local size_t g_readback_cap = 0;
-
-int readback_reserve(size_t bytes, void** out) {
-    if (g_readback_cap < bytes) {
-        if (g_readback) (void)hipHostFree(g_readback);
-        g_readback = nullptr;
-        g_readback_cap = 0;
-        if (hipHostMalloc(&g_readback, bytes, hipHostMallocDefault) != hipSuccess || !g_readback) {
-            (void)hipGetLastError();
-            g_readback = nullptr;
-            return fail(RT_ERR_ALLOC, "pinned read-back allocation of %zu bytes failed", bytes);
-        }
-        g_readback_cap = bytes;
-    }
-    *out = g_readback;
-    return RT_OK;
-}
-
-// Device memory for the dense tapes, kept per thread and device and grown on
-// demand: a gradient is usually taken many times on one screen.
-struct TapeWorkspace {
-    void* ptr = nullptr;
-    size_t bytes = 0;
-};
-thread_local TapeWorkspace g_tape_ws[64];
-
-int tape_workspace(size_t bytes, void** out) {
+// Device counters of the gradient statistics (4 long longs per device).
+int vjp_stats_buffer(long long** out) {
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
     if (dev < 0 || dev >= 64) return fail(RT_ERR_HIP, "device index %d out of range", dev);
-    TapeWorkspace& w = g_tape_ws[dev];
-    if (w.bytes < bytes) {
-        if (w.ptr) {
-            // earlier calls' kernels may still read the old tapes
-            if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
-            (void)hipFree(w.ptr);
-            w.ptr = nullptr;
-            w.bytes = 0;
-        }
-        if ((e = hipMalloc(&w.ptr, bytes)) != hipSuccess || !w.ptr) {
+    if (!g_vjp_stats_dev[dev]) {
+        void* p = nullptr;
+        if ((e = hipMalloc(&p, 4 * sizeof(long long))) != hipSuccess || !p) {
             (void)hipGetLastError();
-            w.ptr = nullptr;
-            return fail(RT_ERR_ALLOC, "tape workspace allocation of %zu bytes failed", bytes);
+            return fail(RT_ERR_ALLOC, "gradient statistics buffer allocation failed");
         }
-        w.bytes = bytes;
+        const long long zeros[4] = {0, 0, 0, 0};
+        if ((e = hipMemcpy(p, zeros, sizeof zeros, hipMemcpyHostToDevice)) != hipSuccess)
+            return hip_fail(e, "statistics buffer initialisation");
+        g_vjp_stats_dev[dev] = static_cast<long long*>(p);
     }
-    *out = w.ptr;
+    *out = g_vjp_stats_dev[dev];
     return RT_OK;
 }
 
-constexpr int64_t kTapeCapMax = 1024;   // steps per pixel of the dense tape
-constexpr int64_t kTapeCapMin = 16;
+// Checkpoint slots per pixel for a screen of n_pix pixels within the budget:
+// the most of kMaxSlots that fit, at least kMinSlots, even.
+constexpr int64_t kMaxSlots = 32, kMinSlots = 4;
+int32_t checkpoint_slots(int64_t n_pix) {
+    const int64_t per = static_cast<int64_t>(sizeof(double)) * rt::kVjpCkptDoubles;
+    int64_t s = g_ckpt_budget / (n_pix * per);
+    s = std::max<int64_t>(kMinSlots, std::min<int64_t>(kMaxSlots, s));
+    return static_cast<int32_t>(s & ~int64_t(1));
+}
 
 int image_vjp(const rt_image_params* params, const double* dl_dI, int32_t basis, double* grad,
               double* grad_pix, void* hip_stream) {
     g_last_error.clear();
-    for (int64_t& v : g_vjp_stats) v = 0;
     if (!params || !dl_dI || !grad) return fail(RT_ERR_ARG, "null params, dl_dI or grad");
     if (basis != RT_GRAD_NATIVE && basis != RT_GRAD_DENSITY)
         return fail(RT_ERR_ARG, "unknown gradient basis %d", basis);
@@ -754,49 +733,11 @@ int image_vjp(const rt_image_params* params, const double* dl_dI, int32_t basis,
         return rc;
     DeviceInfo info;
     if ((rc = device_info(&info)) != RT_OK) return rc;
+    long long* stats = nullptr;
+    if ((rc = vjp_stats_buffer(&stats)) != RT_OK) return rc;
     hipStream_t stream = static_cast<hipStream_t>(hip_stream);
     const int64_t n_pix = c.n_pix;
     auto up256 = [](size_t b) { return (b + 255) / 256 * 256; };
-
-    // Dense tape: cap steps per pixel within the budget (none below kTapeCapMin:
-    // then the dense pass only marks the rays and all go through the list).
-    int64_t cap = std::min<int64_t>(kTapeCapMax, g_tape_budget / (n_pix * rt::kVjpRecBytes));
-    if (cap < kTapeCapMin) cap = 0;
-    void* dense_tape = nullptr;
-    if (cap > 0 &&
-        (rc = tape_workspace(static_cast<size_t>(n_pix * cap * rt::kVjpRecBytes), &dense_tape)) !=
-            RT_OK)
-        return rc;
-
-    // Scratch: queue counters (dense tape, dense reverse, count, then tape and
-    // reverse of the list), pass counters, the dense tape's overflow record,
-    // counts, gradient partials, per-pixel gradients (when the caller passes
-    // none).
-    const size_t q_bytes = 768;
-    const size_t cnt_bytes = up256(sizeof(int32_t) * n_pix);
-    const size_t part_bytes = up256(sizeof(double) * 4 * rt::kGradBlocks);
-    const size_t gp_bytes = grad_pix ? 0 : up256(sizeof(double) * 4 * n_pix);
-    void* scratch = nullptr;
-    hipError_t e = hipMallocAsync(&scratch, q_bytes + cnt_bytes + part_bytes + gp_bytes, stream);
-    if (e != hipSuccess || !scratch) {
-        (void)hipGetLastError();
-        return fail(RT_ERR_ALLOC, "stream-ordered allocation of gradient scratch failed");
-    }
-    char* base = static_cast<char*>(scratch);
-    unsigned long long* queue = reinterpret_cast<unsigned long long*>(base);
-    unsigned int* counters = reinterpret_cast<unsigned int*>(base + 256);
-    static_assert(rt::kVjpRecBytes <= 256, "overflow record fits its scratch slot");
-    double* overflow = reinterpret_cast<double*>(base + 512);
-    int32_t* count = reinterpret_cast<int32_t*>(base + q_bytes);
-    double* partials = reinterpret_cast<double*>(base + q_bytes + cnt_bytes);
-    double* gp = grad_pix ? grad_pix
-                          : reinterpret_cast<double*>(base + q_bytes + cnt_bytes + part_bytes);
-    void* tape_mem = nullptr;
-    auto bail = [&](int code) {
-        if (tape_mem) (void)hipFreeAsync(tape_mem, stream);
-        (void)hipFreeAsync(scratch, stream);
-        return code;
-    };
     auto grid_of = [&](int pass, int64_t items) {
         const int64_t want = (items + rt::kBlock - 1) / rt::kBlock;
         int per_cu = rt::vjp_blocks_per_cu(c.metric, pass);
@@ -805,136 +746,62 @@ int image_vjp(const rt_image_params* params, const double* dl_dI, int32_t basis,
         const int64_t resident = static_cast<int64_t>(info.cus) * per_cu;
         return static_cast<int32_t>(std::max<int64_t>(1, std::min(want, resident)));
     };
+    const int32_t slots = checkpoint_slots(n_pix);
+    const int32_t grid_fwd = grid_of(0, n_pix), grid_bwd = grid_of(1, n_pix);
+
+    // Scratch (stream-ordered, released at the end of the call): queue
+    // counters, gradient counters, count and interval per pixel, the
+    // checkpoints, the backward lanes' step buffers, gradient partials and the
+    // per-pixel gradients when the caller passes none.
+    const size_t q_bytes = 512;
+    const size_t cnt_bytes = up256(sizeof(int32_t) * n_pix);
+    const size_t ck_bytes =
+        up256(sizeof(double) * rt::kVjpCkptDoubles * static_cast<size_t>(slots) * n_pix);
+    const size_t buf_bytes = up256(static_cast<size_t>(rt::kVjpRecBytes) * rt::kVjpBuf *
+                                   static_cast<size_t>(grid_bwd) * rt::kBlock);
+    const size_t part_bytes = up256(sizeof(double) * 4 * rt::kGradBlocks);
+    const size_t gp_bytes = grad_pix ? 0 : up256(sizeof(double) * 4 * n_pix);
+    const size_t total = q_bytes + 2 * cnt_bytes + ck_bytes + buf_bytes + part_bytes + gp_bytes;
+    void* scratch = nullptr;
+    hipError_t e = hipMallocAsync(&scratch, total, stream);
+    if (e != hipSuccess || !scratch) {
+        (void)hipGetLastError();
+        return fail(RT_ERR_ALLOC, "stream-ordered allocation of %zu gradient bytes failed", total);
+    }
+    char* base = static_cast<char*>(scratch);
+    unsigned long long* queue = reinterpret_cast<unsigned long long*>(base);
+    unsigned long long* counters = reinterpret_cast<unsigned long long*>(base + 256);
+    int32_t* count = reinterpret_cast<int32_t*>(base + q_bytes);
+    int32_t* kseg = reinterpret_cast<int32_t*>(base + q_bytes + cnt_bytes);
+    double* ckpt = reinterpret_cast<double*>(base + q_bytes + 2 * cnt_bytes);
+    double* lane_buf = reinterpret_cast<double*>(base + q_bytes + 2 * cnt_bytes + ck_bytes);
+    double* partials =
+        reinterpret_cast<double*>(base + q_bytes + 2 * cnt_bytes + ck_bytes + buf_bytes);
+    double* gp = grad_pix ? grad_pix
+                          : reinterpret_cast<double*>(base + q_bytes + 2 * cnt_bytes + ck_bytes +
+                                                      buf_bytes + part_bytes);
+    auto bail = [&](int code) {
+        (void)hipFreeAsync(scratch, stream);
+        return code;
+    };
     rt::LaunchShape shape;
     if ((rc = image_shape(c, &shape)) != RT_OK) return bail(rc);
-
-    // Common path: dense tape, then its reverse sweep.
     if ((e = rt::launch_zero(queue, 64, stream)) != hipSuccess)
         return bail(hip_fail(e, "queue reset launch"));
     if ((e = rt::launch_fill_zero(gp, 4 * n_pix, stream)) != hipSuccess)
         return bail(hip_fail(e, "gradient fill launch"));
-    if ((e = rt::launch_vjp_tape_dense(c, dl_dI, static_cast<int32_t>(cap),
-                                       static_cast<double*>(dense_tape), overflow, count, counters,
-                                       queue, shape, grid_of(3, n_pix), stream)) != hipSuccess)
-        return bail(hip_fail(e, "tape kernel launch"));
-    if (cap > 0 &&
-        (e = rt::launch_vjp_reverse_dense(c, dl_dI, count, static_cast<int32_t>(cap),
-                                          static_cast<const double*>(dense_tape), jac, gp,
-                                          queue + 1, shape, grid_of(2, n_pix), stream)) !=
-            hipSuccess)
-        return bail(hip_fail(e, "reverse kernel launch"));
-    void* host = nullptr;
-    if ((rc = readback_reserve(std::max<size_t>(16, sizeof(int32_t) * n_pix), &host)) != RT_OK)
-        return bail(rc);
-    if ((e = hipMemcpyAsync(host, counters, 3 * sizeof(unsigned int), hipMemcpyDeviceToHost,
-                            stream)) != hipSuccess ||
-        (e = hipStreamSynchronize(stream)) != hipSuccess)
-        return bail(hip_fail(e, "counter read-back"));
-    const unsigned int* hc = static_cast<const unsigned int*>(host);
-    const int64_t marked = hc[0];
-    g_vjp_stats[0] = hc[1];
-    g_vjp_stats[1] = hc[2];
-    g_vjp_stats[3] = n_pix * cap * rt::kVjpRecBytes;
-
-    // The marked rays: exact counts, tapes packed longest first (counting
-    // sort, stable in the pixel index), in slices that fit the budget.
-    if (marked > 0) {
-        if ((e = rt::launch_vjp_count(c, dl_dI, count, queue + 2, shape, grid_of(0, n_pix),
-                                      stream)) != hipSuccess)
-            return bail(hip_fail(e, "count kernel launch"));
-        if ((e = hipMemcpyAsync(host, count, sizeof(int32_t) * n_pix, hipMemcpyDeviceToHost,
-                                stream)) != hipSuccess ||
-            (e = hipStreamSynchronize(stream)) != hipSuccess)
-            return bail(hip_fail(e, "count read-back"));
-        const int32_t* cnt = static_cast<const int32_t*>(host);
-        int32_t cmax = 0;
-        int64_t n_list = 0;
-        for (int64_t i = 0; i < n_pix; ++i) {
-            cmax = std::max(cmax, cnt[i]);
-            n_list += cnt[i] > 0;
-        }
-        if (n_list > 0) {
-            std::vector<int64_t> start(static_cast<size_t>(cmax) + 2, 0);
-            for (int64_t i = 0; i < n_pix; ++i)
-                if (cnt[i] > 0) ++start[cmax - cnt[i] + 1];
-            for (size_t b = 1; b < start.size(); ++b) start[b] += start[b - 1];
-            const size_t list_bytes = up256(sizeof(int32_t) * n_list) +
-                                      up256(sizeof(int64_t) * n_list) +
-                                      up256(sizeof(int32_t) * n_list);
-            void* host_list = nullptr;
-            if ((rc = staging_reserve(list_bytes, &host_list)) != RT_OK) return bail(rc);
-            char* hl = static_cast<char*>(host_list);
-            int32_t* h_pix = reinterpret_cast<int32_t*>(hl);
-            int64_t* h_off = reinterpret_cast<int64_t*>(hl + up256(sizeof(int32_t) * n_list));
-            for (int64_t i = 0; i < n_pix; ++i)
-                if (cnt[i] > 0) h_pix[start[cmax - cnt[i]]++] = static_cast<int32_t>(i);
-            int64_t total = 0;
-            for (int64_t e2 = 0; e2 < n_list; ++e2) {
-                h_off[e2] = total;
-                total += cnt[h_pix[e2]];
-            }
-            const int64_t rec_budget = std::max<int64_t>(g_tape_budget / rt::kVjpRecBytes, cmax);
-            std::vector<int64_t> cuts{0};
-            for (int64_t e2 = 0; e2 < n_list; ++e2) {
-                const int64_t used = h_off[e2] + cnt[h_pix[e2]] - h_off[cuts.back()];
-                if (used > rec_budget) cuts.push_back(e2);
-            }
-            cuts.push_back(n_list);
-            int64_t max_slice = 0;
-            for (size_t sl = 0; sl + 1 < cuts.size(); ++sl) {
-                const int64_t hi_rec = cuts[sl + 1] < n_list ? h_off[cuts[sl + 1]] : total;
-                max_slice = std::max(max_slice, hi_rec - h_off[cuts[sl]]);
-            }
-            const size_t tape_bytes = static_cast<size_t>(max_slice) * rt::kVjpRecBytes;
-            e = hipMallocAsync(&tape_mem, list_bytes + tape_bytes, stream);
-            if (e != hipSuccess || !tape_mem) {
-                (void)hipGetLastError();
-                tape_mem = nullptr;
-                return bail(fail(RT_ERR_ALLOC, "tape allocation of %zu bytes failed",
-                                 list_bytes + tape_bytes));
-            }
-            char* dl = static_cast<char*>(tape_mem);
-            const int32_t* d_pix = reinterpret_cast<const int32_t*>(dl);
-            const int64_t* d_off =
-                reinterpret_cast<const int64_t*>(dl + up256(sizeof(int32_t) * n_list));
-            int32_t* d_taped = reinterpret_cast<int32_t*>(dl + up256(sizeof(int32_t) * n_list) +
-                                                          up256(sizeof(int64_t) * n_list));
-            double* d_tape = reinterpret_cast<double*>(dl + list_bytes);
-            const size_t up_bytes =
-                up256(sizeof(int32_t) * n_list) + up256(sizeof(int64_t) * n_list);
-            if ((e = hipMemcpyAsync(tape_mem, host_list, up_bytes, hipMemcpyHostToDevice,
-                                    stream)) != hipSuccess ||
-                (e = hipEventRecord(g_staging.ready, stream)) != hipSuccess)
-                return bail(hip_fail(e, "ray list upload"));
-            const int32_t chunk = g_launch.chunk > 0 ? g_launch.chunk : 32;
-            const int n_slices = static_cast<int>(cuts.size()) - 1;
-            for (int sl = 0; sl < n_slices; ++sl) {
-                const int64_t lo = cuts[sl], hi = cuts[sl + 1];
-                const int64_t rec_base = h_off[lo];
-                if (sl > 0 && (e = rt::launch_zero(queue + 3, 2, stream)) != hipSuccess)
-                    return bail(hip_fail(e, "queue reset launch"));
-                if ((e = rt::launch_vjp_tape(c, d_pix + lo, d_off + lo, count, hi - lo, rec_base,
-                                             d_tape, d_taped + lo, queue + 3, chunk,
-                                             grid_of(1, hi - lo), stream)) != hipSuccess)
-                    return bail(hip_fail(e, "tape kernel launch"));
-                if ((e = rt::launch_vjp_reverse(c, dl_dI, d_pix + lo, d_off + lo, d_taped + lo,
-                                                hi - lo, rec_base, d_tape, jac, gp, queue + 4,
-                                                chunk, grid_of(2, hi - lo), stream)) !=
-                    hipSuccess)
-                    return bail(hip_fail(e, "reverse kernel launch"));
-            }
-            g_vjp_stats[0] += n_list;
-            g_vjp_stats[1] += total;
-            g_vjp_stats[2] = n_slices;
-            g_vjp_stats[3] = std::max<int64_t>(g_vjp_stats[3], static_cast<int64_t>(tape_bytes));
-        }
-    }
+    if ((e = rt::launch_vjp_forward(c, dl_dI, slots, ckpt, count, kseg, counters, queue, shape,
+                                    grid_fwd, stream)) != hipSuccess)
+        return bail(hip_fail(e, "forward checkpoint kernel launch"));
+    if ((e = rt::launch_vjp_backward(c, dl_dI, count, kseg, slots, ckpt, lane_buf, jac, gp,
+                                     counters, queue + 1, shape, grid_bwd, stream)) != hipSuccess)
+        return bail(hip_fail(e, "backward kernel launch"));
     if ((e = rt::launch_grad_reduce(gp, n_pix, partials, grad, stream)) != hipSuccess)
         return bail(hip_fail(e, "gradient reduction launch"));
-    if (tape_mem && (e = hipFreeAsync(tape_mem, stream)) != hipSuccess) {
-        (void)hipFreeAsync(scratch, stream);
-        return hip_fail(e, "hipFreeAsync");
-    }
+    if ((e = rt::launch_copy_vjp_stats(counters, stats, stream)) != hipSuccess)
+        return bail(hip_fail(e, "statistics copy launch"));
+    g_vjp_slots = slots;
+    g_vjp_bytes = static_cast<int64_t>(total);
     if ((e = hipFreeAsync(scratch, stream)) != hipSuccess) return hip_fail(e, "hipFreeAsync");
     return RT_OK;
 }
@@ -1354,17 +1221,27 @@ int rt_mixed_stats(int64_t* out) {
     return RT_OK;
 }
 
-int rt_set_tape_budget(int64_t bytes) {
+int rt_set_checkpoint_budget(int64_t bytes) {
     g_last_error.clear();
-    if (bytes < (int64_t(1) << 20)) return fail(RT_ERR_ARG, "tape budget below 1 MiB");
-    g_tape_budget = bytes;
+    if (bytes < (int64_t(1) << 20)) return fail(RT_ERR_ARG, "checkpoint budget below 1 MiB");
+    g_ckpt_budget = bytes;
     return RT_OK;
 }
 
 int rt_vjp_stats(int64_t* out) {
     g_last_error.clear();
     if (!out) return fail(RT_ERR_ARG, "null stats pointer");
-    for (int i = 0; i < 4; ++i) out[i] = g_vjp_stats[i];
+    long long* d = nullptr;
+    const int rc = vjp_stats_buffer(&d);
+    if (rc != RT_OK) return rc;
+    long long h[3] = {0, 0, 0};
+    const hipError_t e = hipMemcpy(h, d, sizeof h, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "statistics read-back");
+    out[0] = h[0];
+    out[1] = h[1];
+    out[2] = g_vjp_slots;
+    out[3] = g_vjp_bytes;
+    out[4] = h[2];
     return RT_OK;
 }
 

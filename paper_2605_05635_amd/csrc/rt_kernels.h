@@ -167,53 +167,47 @@ hipError_t launch_copy_counters(const unsigned int* counters, long long* stats,
                                 hipStream_t stream);
 int mixed_blocks_per_cu(int metric, int pass);
 
-// Image gradient (reverse mode through every ray's discrete map).
-// Common path:
-//   tape_dense: for each pixel with dl_dI != 0 (screen order of `shape`), the
-//            ray's accepted steps taped at tape + pix * cap records
-//            (kVjpRecBytes each), count[pix] = steps up to the last emitting
-//            crossing (0 if none), or -1 if that exceeds cap; counters[0] +=
-//            such rays, counters[1] += rays with count > 0, counters[2] += the
-//            sum of their counts.
-//   reverse_dense: walks those tapes backwards and writes grad_pix[pix][4] =
-//            dL/dq for the pixels with count > 0, with jac[m][j] the derivative
-//            of per-ray parameter m along the image parameter q_j.
-// Path for the rays marked -1:
-//   count:   traces the pixels whose count is -1 on entry and sets their count
-//            (every other count becomes 0);
-//   tape:    list entries e < n_list (pixel list_pix[e], first record at
-//            list_off[e] - rec_base of `tape`) traced again and taped;
-//            taped[e] = records written;
-//   reverse: as reverse_dense over the list.
-// Each persistent pass needs its zeroed queue counter.  `pass` of
-// vjp_blocks_per_cu: 0 count, 1 tape, 2 reverse, 3 tape_dense.
+// Image gradient (reverse mode through every ray's discrete map), with
+// checkpointed recomputation:
+//   forward:  for each pixel with dl_dI != 0 (screen order of `shape`), traces
+//             the ray and stores a checkpoint (kVjpCkptDoubles) of its state
+//             before every kseg-th accepted step into its `slots` slots at
+//             ckpt + pix * slots checkpoints (kseg starts at kVjpSeg and
+//             doubles, the slots thinned to every other one, whenever they
+//             run out); count[pix] = accepted steps up to the last emitting
+//             crossing (0 if none), kseg[pix] = the final interval;
+//             counters[0] += rays with count > 0, counters[1] += their counts;
+//   backward: for those pixels, restores each segment's checkpoint from the
+//             last to the first, recomputes its steps (at most kVjpBuf at a
+//             time, into the calling lane's buffer of kVjpBuf records of
+//             kVjpRecBytes at lane_buf + global thread index * kVjpBuf
+//             records) and reverses them, then writes grad_pix[pix][4] = dL/dq
+//             with jac[m][j] the derivative of per-ray parameter m along the
+//             image parameter q_j.
+// Each pass needs its zeroed queue counter; `grid` blocks of kBlock threads
+// (the backward pass's lane buffers must cover grid * kBlock lanes).
+// The backward pass adds 1 to counters[2] for a recomputation that ended
+// before its steps (never, unless it diverged from the trace; it then stops).
+// `pass` of vjp_blocks_per_cu: 0 forward, 1 backward.  copy_vjp_stats:
+// stats[0..3) = counters[0..3).
 constexpr int kVjpPrims = 11;
 constexpr int kVjpRecBytes = 240;
+constexpr int kVjpCkptDoubles = 16;
+constexpr int kVjpSeg = 32;     // accepted steps per segment before any thinning
+constexpr int kVjpBuf = 32;     // step records recomputed at a time
 constexpr int kGradBlocks = 256;
-// `overflow`: one writable tape record (kVjpRecBytes) that takes the stage
-// derivatives of steps past a pixel's region.
-hipError_t launch_vjp_tape_dense(const ImageConst& c, const double* dl_dI, int32_t cap,
-                                 double* tape, double* overflow, int32_t* count,
-                                 unsigned int* counters, unsigned long long* queue,
-                                 const LaunchShape& shape, int32_t grid, hipStream_t stream);
-hipError_t launch_vjp_reverse_dense(const ImageConst& c, const double* dl_dI,
-                                    const int32_t* count, int32_t cap, const double* tape,
-                                    const double (&jac)[kVjpPrims][4], double* grad_pix,
-                                    unsigned long long* queue, const LaunchShape& shape,
-                                    int32_t grid, hipStream_t stream);
-hipError_t launch_vjp_count(const ImageConst& c, const double* dl_dI, int32_t* count,
-                            unsigned long long* queue, const LaunchShape& shape, int32_t grid,
-                            hipStream_t stream);
-hipError_t launch_vjp_tape(const ImageConst& c, const int32_t* list_pix, const int64_t* list_off,
-                           const int32_t* count, int64_t n_list, int64_t rec_base, double* tape,
-                           int32_t* taped, unsigned long long* queue, int32_t chunk,
-                           int32_t grid, hipStream_t stream);
-hipError_t launch_vjp_reverse(const ImageConst& c, const double* dl_dI, const int32_t* list_pix,
-                              const int64_t* list_off, const int32_t* taped, int64_t n_list,
-                              int64_t rec_base, const double* tape,
-                              const double (&jac)[kVjpPrims][4], double* grad_pix,
-                              unsigned long long* queue, int32_t chunk, int32_t grid,
-                              hipStream_t stream);
+hipError_t launch_vjp_forward(const ImageConst& c, const double* dl_dI, int32_t slots,
+                              double* ckpt, int32_t* count, int32_t* kseg,
+                              unsigned long long* counters, unsigned long long* queue,
+                              const LaunchShape& shape, int32_t grid, hipStream_t stream);
+hipError_t launch_vjp_backward(const ImageConst& c, const double* dl_dI, const int32_t* count,
+                               const int32_t* kseg, int32_t slots, const double* ckpt,
+                               double* lane_buf, const double (&jac)[kVjpPrims][4],
+                               double* grad_pix, unsigned long long* counters,
+                               unsigned long long* queue, const LaunchShape& shape, int32_t grid,
+                               hipStream_t stream);
+hipError_t launch_copy_vjp_stats(const unsigned long long* counters, long long* stats,
+                                 hipStream_t stream);
 int vjp_blocks_per_cu(int metric, int pass);
 // p[0..n) = 0 (a fill kernel).
 hipError_t launch_fill_zero(double* p, int64_t n, hipStream_t stream);

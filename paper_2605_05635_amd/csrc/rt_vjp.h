@@ -58,6 +58,56 @@ struct TapeStages {
     }
 };
 
+// A checkpoint of a ray between two accepted steps: everything `attempt`
+// reads besides the image constants, the photon's E and l (recomputed from
+// the pixel) and k1 (the right-hand side at y, recomputed bit for bit):
+// y[6], h, lam, last_cross, rc[3], and as exact doubles attempts, the
+// accepted-step index, after_reject and ncross: 16 doubles.
+constexpr int kCkptDoubles = 16;
+
+__host__ __device__ __forceinline__ void store_checkpoint(double* slot, const Ray& r, int32_t acc) {
+    double2* q = reinterpret_cast<double2*>(slot);
+    q[0] = double2{r.y[0], r.y[1]};
+    q[1] = double2{r.y[2], r.y[3]};
+    q[2] = double2{r.y[4], r.y[5]};
+    q[3] = double2{r.h, r.lam};
+    q[4] = double2{r.last_cross, r.rc[0]};
+    q[5] = double2{r.rc[1], r.rc[2]};
+    q[6] = double2{static_cast<double>(r.attempts), static_cast<double>(acc)};
+    q[7] = double2{static_cast<double>(r.after_reject), static_cast<double>(r.ncross)};
+}
+
+// Restores the checkpoint `slot` into r (pixel pix, constants E, l) for the
+// metric's right-hand side; returns its accepted-step index.
+template <int METRIC>
+__host__ __device__ __forceinline__ int32_t load_checkpoint(const double* slot, const Hot& k,
+                                                            double E, double L, int64_t pix,
+                                                            Ray& r) {
+    const double2* q = reinterpret_cast<const double2*>(slot);
+    const double2 a = q[0], b = q[1], c = q[2], d = q[3], e = q[4], f = q[5], g = q[6],
+                  h = q[7];
+    r.y[0] = a.x;
+    r.y[1] = a.y;
+    r.y[2] = b.x;
+    r.y[3] = b.y;
+    r.y[4] = c.x;
+    r.y[5] = c.y;
+    r.h = d.x;
+    r.lam = d.y;
+    r.last_cross = e.x;
+    r.rc[0] = e.y;
+    r.rc[1] = f.x;
+    r.rc[2] = f.y;
+    r.attempts = static_cast<int32_t>(g.x);
+    r.after_reject = static_cast<int32_t>(h.x);
+    r.ncross = static_cast<int32_t>(h.y);
+    r.E = E;
+    r.L = L;
+    r.pix = pix;
+    rhs<METRIC>(k, E, L, r.y[1], r.y[2], r.y[4], r.y[5], r.k1);
+    return static_cast<int32_t>(g.y);
+}
+
 // F(R), dF/dR (mass_function) and the reverse mode of both: mass_eval gives
 // the values and keeps what the reverse pass needs; mass_vjp adds the
 // cotangents (Fb, dFb) times the derivatives along R to Rb and along the

@@ -129,8 +129,8 @@ def _load():
     lib.rt_image_vjp.restype = C.c_int
     lib.rt_mixed_stats.argtypes = [C.POINTER(C.c_int64)]
     lib.rt_mixed_stats.restype = C.c_int
-    lib.rt_set_tape_budget.argtypes = [C.c_int64]
-    lib.rt_set_tape_budget.restype = C.c_int
+    lib.rt_set_checkpoint_budget.argtypes = [C.c_int64]
+    lib.rt_set_checkpoint_budget.restype = C.c_int
     lib.rt_vjp_stats.argtypes = [C.POINTER(C.c_int64)]
     lib.rt_vjp_stats.restype = C.c_int
     lib.rt_last_error.argtypes = []
@@ -489,14 +489,15 @@ def rt_set_split_timing(event) -> None:
     _check(_lib.rt_set_split_timing(None if event is None else C.c_void_p(event.cuda_event)))
 
 
-def rt_set_tape_budget(nbytes: int) -> None:
-    _check(_lib.rt_set_tape_budget(int(nbytes)))
+def rt_set_checkpoint_budget(nbytes: int) -> None:
+    _check(_lib.rt_set_checkpoint_budget(int(nbytes)))
 
 
 def rt_vjp_stats() -> dict:
-    buf = (C.c_int64 * 4)()
+    """Statistics of the last gradient on this thread (synchronous)."""
+    buf = (C.c_int64 * 5)()
     _check(_lib.rt_vjp_stats(buf))
-    return dict(rays=buf[0], steps=buf[1], slices=buf[2], tape_bytes=buf[3])
+    return dict(rays=buf[0], steps=buf[1], slots=buf[2], scratch_bytes=buf[3], diverged=buf[4])
 
 
 def rt_version() -> int:
@@ -558,7 +559,7 @@ def image_vjp(img: dict, dl_dI, basis: str = "native", per_pixel: bool = False, 
     return (grad, gp) if per_pixel else grad
 
 
-__all__ = ["rt_mixed_stats", "rt_image_vjp", "rt_set_tape_budget", "rt_vjp_stats", "image_vjp", "rt_trace_image", "rt_transfer_maps", "rt_image_setup", "rt_set_kernel_timing", "rt_set_split_timing",
+__all__ = ["rt_mixed_stats", "rt_image_vjp", "rt_set_checkpoint_budget", "rt_vjp_stats", "image_vjp", "rt_trace_image", "rt_transfer_maps", "rt_image_setup", "rt_set_kernel_timing", "rt_set_split_timing",
            "rt_set_launch_config", "rt_get_launch_config", "rt_visibility_dft", "visibility",
            "rt_visibility_dft_batch", "rt_vis_image", "vis_image_from", "visibility_many",
            "rt_visibility_rings", "visibility_rings",

@@ -1,7 +1,7 @@
 """The image gradient (rt_image_vjp, the discrete adjoint) on the GPU against
 the oracle's forward-mode dual-number gradient of the same frozen discrete
 map, plus its internal consistency: the total is the fixed-order sum of the
-per-pixel terms, slicing the tapes changes nothing, repeated calls are
+per-pixel terms, the checkpoint budget changes nothing, repeated calls are
 bit-identical, the density basis is the chain rule of the native one, and
 the autograd binding returns what the C ABI returns.
 
@@ -46,6 +46,7 @@ def gpu_pixel_grads(rt, img):
     n = img["nx"] * img["ny"]
     ones = torch.ones((img["ny"], img["nx"]), dtype=torch.float64, device="cuda")
     grad, gp = rt.image_vjp(img, ones, per_pixel=True)
+    assert rt.rt_vjp_stats()["diverged"] == 0
     outs = rt.trace(img)
     torch.cuda.synchronize()
     return (grad.cpu().numpy(), gp.cpu().numpy().reshape(n, 4),
@@ -113,7 +114,9 @@ def test_adjoint_workload_sampled(rt, orc):
     gp = gp.cpu().numpy().reshape(-1, 4)
     dln = dl.cpu().numpy().reshape(-1)
     stats = rt.rt_vjp_stats()
-    say(f"[vjp] taped rays {stats['rays']}, steps {stats['steps']}")
+    assert stats["diverged"] == 0
+    say(f"[vjp] reversed rays {stats['rays']}, steps {stats['steps']}, "
+        f"scratch {stats['scratch_bytes']} bytes")
     live = np.nonzero(dln)[0]
     idx = np.sort(np.random.default_rng(7).choice(live, size=min(96, live.size), replace=False))
     Io, Go = orc.trace_grad_pixels(img, idx)
@@ -133,42 +136,74 @@ def test_adjoint_workload_sampled(rt, orc):
     np.testing.assert_allclose(grad.cpu().numpy(), gp.sum(axis=0), rtol=1e-12)
 
 
-def test_repeat_and_slices_bitwise(rt):
+def test_repeat_and_checkpoint_slots_bitwise(rt):
+    """Repeated calls, every checkpoint budget (32 slots per pixel down to the
+    minimum of 4, which makes the long rays double their interval and thin
+    their checkpoints) and the work hand-out all give the same bits: the
+    recomputed steps are the traced ones."""
     import torch
     img = W.image(metric="cnfw", spin=0.94, halo=(0.02, 10.0), incl=math.radians(60), nx=64,
                   ny=48, sigma_in=0.5, sigma_out=0.5)
-    say("[vjp] repeat and tape slices")
+    say("[vjp] repeat, checkpoint slots and hand-out")
     rng = np.random.default_rng(3)
     dl = torch.tensor(rng.normal(size=(48, 64)), dtype=torch.float64, device="cuda")
     g1, p1 = rt.image_vjp(img, dl, per_pixel=True)
     g2, p2 = rt.image_vjp(img, dl, per_pixel=True)
     one = rt.rt_vjp_stats()
-    rt.rt_set_tape_budget(1 << 20)
+    per_slot = 128 * 64 * 48
+    results = []
     try:
-        g3, p3 = rt.image_vjp(img, dl, per_pixel=True)
-        sliced = rt.rt_vjp_stats()
-        # 24 steps per pixel in place: short rays stay, the others are packed
-        rt.rt_set_tape_budget(64 * 48 * 24 * 48)
-        g4, p4 = rt.image_vjp(img, dl, per_pixel=True)
-        split = rt.rt_vjp_stats()
-        rt.rt_set_tape_budget(16 << 30)
+        for slots in (12, 6, 4):
+            rt.rt_set_checkpoint_budget(max(1 << 20, slots * per_slot))
+            g, p = rt.image_vjp(img, dl, per_pixel=True)
+            results.append((g, p, rt.rt_vjp_stats()))
+        rt.rt_set_checkpoint_budget(16 << 30)
         rt.rt_set_launch_config(chunk=5, order=rt.RT_ORDER_SCREEN)
         g5, p5 = rt.image_vjp(img, dl, per_pixel=True)
     finally:
-        rt.rt_set_tape_budget(16 << 30)
+        rt.rt_set_checkpoint_budget(16 << 30)
         rt.rt_set_launch_config(reset=True)
     torch.cuda.synchronize()
-    say(f"[vjp] slices {one['slices']} -> {sliced['slices']} / {split['slices']}, "
-        f"steps {one['steps']}")
-    # the default budget holds every ray's tape in place; 1 MiB sends all of
-    # them to packed tapes in several slices
-    assert one["slices"] == 0 and sliced["slices"] > 1 and split["slices"] >= 1
-    assert sliced["steps"] == one["steps"] and sliced["rays"] == one["rays"]
-    assert split["steps"] == one["steps"] and split["rays"] == one["rays"]
+    say(f"[vjp] rays {one['rays']}, steps {one['steps']}, slots {one['slots']} -> "
+        f"{[r[2]['slots'] for r in results]}")
+    assert one["slots"] == 32 and [r[2]["slots"] for r in results][-1] == 4
     assert torch.equal(g1, g2) and torch.equal(p1, p2)
-    assert torch.equal(g1, g4) and torch.equal(p1, p4)
+    for g, p, st in results:
+        assert st["steps"] == one["steps"] and st["rays"] == one["rays"] and st["diverged"] == 0
+        assert torch.equal(g1, g) and torch.equal(p1, p)
     assert torch.equal(g1, g5) and torch.equal(p1, p5)
-    assert torch.equal(g1, g3) and torch.equal(p1, p3)
+
+
+def test_long_rays_thin_their_checkpoints(rt, orc):
+    """Rays much longer than 4 slots of 32 steps (photon-ring orbits near the
+    critical curve of a near-extremal Kerr hole at a tight tolerance, and a
+    small budget) must thin their checkpoints several times; their gradients still match the
+    oracle's dual numbers."""
+    import torch
+    img = W.image(metric="kerr", spin=0.998, incl=math.radians(80), nx=64, ny=32,
+                  x_min=-3.6, x_max=-1.6, y_min=-0.6, y_max=0.6, sigma_in=0.3, sigma_out=0.3,
+                  rtol=1e-11, atol=1e-11)
+    say("[vjp] long rays with 4 checkpoint slots")
+    rt.rt_set_checkpoint_budget(1 << 20)   # 4 slots of 128 bytes for 2048 pixels
+    try:
+        grad, gp = rt.image_vjp(img, torch.ones((32, 64), dtype=torch.float64, device="cuda"),
+                                per_pixel=True)
+        st = rt.rt_vjp_stats()
+    finally:
+        rt.rt_set_checkpoint_budget(16 << 30)
+    outs = rt.trace(img)
+    torch.cuda.synchronize()
+    assert st["slots"] == 4 and st["diverged"] == 0
+    att = outs["attempts"].cpu().numpy().reshape(-1)
+    assert att.max() > 4 * 32 * 4   # some rays needed at least two thinnings
+    idx = np.arange(img["nx"] * img["ny"])
+    Io, Go = orc.trace_grad_pixels(img, idx)
+    o = orc.trace_pixels(img, idx)
+    gp = gp.cpu().numpy().reshape(-1, 4)
+    same = (o["attempts"] == att) & (o["ncross"] == outs["ncross"].cpu().numpy().reshape(-1))
+    scale = np.maximum(np.abs(Go).max(axis=1), np.abs(gp).max(axis=1))
+    rel = np.where(scale > 0, np.abs(gp - Go).max(axis=1) / np.where(scale > 0, scale, 1.0), 0.0)
+    assert same.mean() > 0.9 and rel[same].max() <= GRAD_SAME
 
 
 def test_cotangent_weights_and_zero(rt):
