@@ -7,8 +7,8 @@ arithmetic, the coefficients then rounded to binary64.  The printed bound is
 the largest relative error of the resulting function value (before the
 rounding of its binary64 evaluation), measured on a 4000-point grid:
 
-    sin r = r + r z S(z),            z = r^2 in [0, (pi/4)^2]
-    cos r = 1 + z C(z)
+    sin r = r + r z S(z),            z = r^2 in [0, (pi/2)^2]  (binary32: [0, (pi/4)^2])
+    cos r = 1 + z C(z)               (its bound is absolute: cos r reaches 0)
     e^r - 1 = r + r^2 E(r),          |r| <= ln(2)/2 (+1e-9)
     log m = 2 (t + t z L(z)),        t = (m-1)/(m+1), m in [sqrt(1/2), sqrt(2)), z = t^2
 
@@ -21,6 +21,7 @@ import mpmath as mp
 
 mp.mp.dps = 60
 PIO4_2 = (mp.pi / 4) ** 2 * (1 + mp.mpf("1e-12"))
+PIO2_2 = (mp.pi / 2) ** 2 * (1 + mp.mpf("1e-12"))
 LN2_2 = mp.log(2) / 2 + mp.mpf("1e-9")
 T_MAX = (mp.sqrt(2) - 1) / (mp.sqrt(2) + 1)
 Z_LOG = T_MAX ** 2 * (1 + mp.mpf("1e-12"))
@@ -45,20 +46,29 @@ def _L(z):
 
 
 KERNELS = {   # name: (auxiliary function, interval, degree, value of the kernel's function)
-    "S": (_S, (0, PIO4_2), 6, lambda x, p: (mp.sqrt(x) * (1 + x * p), mp.sin(mp.sqrt(x)))),
-    "C": (_C, (0, PIO4_2), 6, lambda x, p: (1 + x * p, mp.cos(mp.sqrt(x)))),
+    "S": (_S, (0, PIO2_2), 7, lambda x, p: (mp.sqrt(x) * (1 + x * p), mp.sin(mp.sqrt(x)))),
+    "C": (_C, (0, PIO2_2), 7, lambda x, p: (1 + x * p, mp.cos(mp.sqrt(x)))),
     "E": (_E, (-LN2_2, LN2_2), 10, lambda x, p: (x + x * x * p, mp.expm1(x))),
     "L": (_L, (0, Z_LOG), 6, lambda x, p: (2 * mp.sqrt(x) * (1 + x * p), 2 * mp.atanh(mp.sqrt(x)))),
 }
+# Kernels whose bound is the absolute error of the function value.
+ABSOLUTE = {"C"}
 
-
-# Degrees of the binary32 kernels (the single-precision bulk trace); their
-# coefficients are rounded to binary32.
+# Degrees of the binary32 kernels (the single-precision bulk trace, whose sine
+# and cosine reduce by pi/2); their coefficients are rounded to binary32.
 DEGREES32 = {"S": 3, "C": 3, "E": 5, "L": 2}
+INTERVALS32 = {"S": (0, PIO4_2), "C": (0, PIO4_2)}
+
+
+def interval(name, binary32=False):
+    if binary32 and name in INTERVALS32:
+        return INTERVALS32[name]
+    return KERNELS[name][1]
 
 
 def coefficients(name, binary32=False):
-    f, (a, b), deg, _ = KERNELS[name]
+    f, _, deg, _ = KERNELS[name]
+    a, b = interval(name, binary32)
     if binary32:
         deg = DEGREES32[name]
     cs = mp.chebyfit(f, [a, b], deg + 1)
@@ -68,8 +78,10 @@ def coefficients(name, binary32=False):
     return [float(c) for c in cs]
 
 
-def max_rel_error(name, cs, n=4000):
-    f, (a, b), _, value = KERNELS[name]
+def max_rel_error(name, cs, n=4000, binary32=False):
+    """The largest relative error (absolute for the kernels in ABSOLUTE)."""
+    f, _, _, value = KERNELS[name]
+    a, b = interval(name, binary32)
     worst = mp.mpf(0)
     for i in range(1, n):
         x = a + (b - a) * mp.mpf(i) / n
@@ -79,7 +91,7 @@ def max_rel_error(name, cs, n=4000):
         for c in cs[1:]:
             p = p * x + mp.mpf(c)
         got, exact = value(x, p)
-        worst = max(worst, abs((got - exact) / exact))
+        worst = max(worst, abs(got - exact) if name in ABSOLUTE else abs((got - exact) / exact))
     return float(worst)
 
 
@@ -88,6 +100,7 @@ if __name__ == "__main__":
         for name in KERNELS:
             cs = coefficients(name, binary32)
             kind = "binary32" if binary32 else "binary64"
+            what = "abs" if name in ABSOLUTE else "rel"
             print(f"// {name} ({kind}): degree {len(cs) - 1}, "
-                  f"max rel err {max_rel_error(name, cs):.2e}")
+                  f"max {what} err {max_rel_error(name, cs, binary32=binary32):.2e}")
             print("    " + ",\n    ".join(repr(c) + ("f" if binary32 else "") for c in cs))

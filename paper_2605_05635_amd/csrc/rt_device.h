@@ -9,6 +9,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <type_traits>
 
 #include "rt_dual.h"
 #include "rt_math.h"
@@ -71,6 +72,30 @@ __host__ __device__ inline S expm1_ex(const S& x, bool) {
     return dm::expm1(x);
 }
 
+// The cored-NFW halo terms 1/R, 1/(R + lambda_c) and log(1 + R/lambda_c) in
+// binary64 from one reciprocal: with 1 + R/lambda_c = m 2^e (dm::log_split;
+// the sum is one fused operation), 1/(R (R + lambda_c) (m + 1)) gives both
+// reciprocals and the logarithm kernel's quotient (m - 1)/(m + 1) by
+// multiplications.  Errors as dm::log1p_fast's: half an ulp of 1 + R/lambda_c
+// absolute in the logarithm, plus the one-step reciprocal's 2.2e-15 relative
+// in all three.
+struct CnfwTerms {
+    double iR, iRl, lg;
+};
+__host__ __device__ inline CnfwTerms cnfw_terms(double R, double lam_c, double inv_lam_c) {
+    const double Rl = R + lam_c;
+    const dm::LogSplit s = dm::log_split(fma(R, inv_lam_c, 1.0));
+    const double d = R * Rl;
+    const double inv = dm::recip1(fma(d, s.m, d));
+    const double a = fma(s.m, inv, inv);   // 1/(R (R + lambda_c))
+    CnfwTerms t;
+    t.iR = Rl * a;
+    t.iRl = R * a;
+    const double q = (s.m - 1.0) * (d * inv);
+    t.lg = fma(s.e, dm::kLn2Hi, fma(s.e, dm::kLn2Lo, dm::log_kernel(q)));
+    return t;
+}
+
 // F(R) = 2 R mu(R) (eq. (24)) and dF/dR for the chosen seed.  The mass
 // functions mu_E (from eq. (9)) and mu_cNFW (from eq. (13)) are written in
 // cancellation-free forms: mu_E = 1 - e^{-x}(1 + x + x^2/2) with x = R/lambda_E,
@@ -91,12 +116,20 @@ __host__ __device__ inline void mass_function(const K& c, const S& R, S& F, S& d
         F = two * R * mu;
         dF = two * (mu + R * dmu);
     } else {
-        // 1/R and 1/(R + lambda_c) from one reciprocal of their product
-        const S Rl = R + c.lam_c;
-        const S inv = dm::recip1(R * Rl);
-        const S iR = Rl * inv;
-        const S iRl = R * inv;
-        const S lg = dm::log1p_fast(R * c.inv_lam_c);
+        S iR, iRl, lg;
+        if constexpr (std::is_same<S, double>::value) {
+            const CnfwTerms t = cnfw_terms(R, c.lam_c, c.inv_lam_c);
+            iR = t.iR;
+            iRl = t.iRl;
+            lg = t.lg;
+        } else {
+            // 1/R and 1/(R + lambda_c) from one reciprocal of their product
+            const S Rl = R + c.lam_c;
+            const S inv = dm::recip1(R * Rl);
+            iR = Rl * inv;
+            iRl = R * inv;
+            lg = dm::log1p_fast(R * c.inv_lam_c);
+        }
         const S ex = c.eta_lc * (iRl - two * iR * lg);
         const S dex = c.eta_lc * (two * iR * (iR * lg - iRl) - iRl * iRl);
         const S em1 = expm1_ex(ex, METRIC == CNFW_NEAR);

@@ -96,8 +96,9 @@ __host__ __device__ __forceinline__ void rhs(const K& k, const S& E, const S& L,
     // 1/Sigma, 1/Delta and 1/sin(theta) from one reciprocal of their product
     const S SD = Sig * Del;
     const S inv = rcp(SD * s);
-    const S iS = Del * s * inv;
-    const S iD = Sig * s * inv;
+    const S sinv = s * inv;
+    const S iS = Del * sinv;
+    const S iD = Sig * sinv;
     const S is = SD * inv;
     const S P = R2c * E - k.chi * L;
     const S PiD = P * iD;
@@ -109,8 +110,9 @@ __host__ __device__ __forceinline__ void rhs(const K& k, const S& E, const S& L,
     d[1] = Del * pR * iS;
     d[2] = pth * iS;
     d[3] = (k.chi * PiD + Lis2 - k.chi * E) * iS;
-    d[4] = (N * R * iS - half * dN) * iS;
-    d[5] = co * iS * (W * (Lis2 + k.chi * E) - k.chi2 * s * N * iS);
+    const S NiS = N * iS;
+    d[4] = (R * NiS - half * dN) * iS;
+    d[5] = co * iS * (W * (Lis2 + k.chi * E) - k.chi2 * s * NiS);
 }
 
 // ------------------------------------------------ Dormand-Prince 5(4) tableau

@@ -3,11 +3,13 @@
 // host) on the doubles read from stdin and writes the results to stdout.
 //   usage: devmath_driver <function>   (sincos | exp | expm1 | log1p | log1p_fast | rpow_tenth, and the
 //          binary32 versions sincosf | expf | expm1f | log1pf of the arguments rounded
-//          to binary32)
+//          to binary32; cnfw_terms reads (R, lambda_c) pairs and writes 1/R,
+//          1/(R + lambda_c) and log(1 + R/lambda_c))
 #include <cstdio>
 #include <cstring>
 #include <vector>
 
+#include "rt_device.h"
 #include "rt_math.h"
 
 int main(int argc, char** argv) {
@@ -16,6 +18,16 @@ int main(int argc, char** argv) {
     double v;
     while (std::fread(&v, sizeof v, 1, stdin) == 1) x.push_back(v);
     std::vector<double> out;
+    if (!std::strcmp(argv[1], "cnfw_terms")) {
+        for (size_t i = 0; i + 1 < x.size(); i += 2) {
+            const rt::CnfwTerms t = rt::cnfw_terms(x[i], x[i + 1], 1.0 / x[i + 1]);
+            out.push_back(t.iR);
+            out.push_back(t.iRl);
+            out.push_back(t.lg);
+        }
+        std::fwrite(out.data(), sizeof(double), out.size(), stdout);
+        return 0;
+    }
     for (double a : x) {
         if (!std::strcmp(argv[1], "sincos")) {
             double s, c;

@@ -5,6 +5,7 @@ Measured in units in the last place (ulp) of the exact result, over the
 argument ranges the trace uses: theta in (-2 pi, 3 pi), exp of R/lambda_E
 arguments down to underflow, expm1 of the cored-NFW exponent, log1p of
 R/lambda_c, and the step controller's x^(-1/10)."""
+import math
 import os
 import subprocess
 
@@ -109,6 +110,57 @@ def test_log1p_fast(driver):
     # small; from u = 1 on it stays within a few ulp
     big = x >= 1.0
     assert ulp_err(out[big], [e for e, b in zip(ex, big) if b]).max() < 4
+
+
+def test_cnfw_halo_terms(driver):
+    """The cored-NFW mass function's 1/R, 1/(R + lambda_c) and
+    log(1 + R/lambda_c) from one reciprocal and the integer split of
+    1 + R/lambda_c (host build: exact division).  Bounds as log1p_fast's: the
+    logarithm within half an ulp of 1 + R/lambda_c absolute plus a few ulp, the
+    reciprocals within a few ulp; R over the traced range, lambda_c over the
+    workloads' (including arguments right at the split's powers of two)."""
+    rng = np.random.default_rng(6)
+    R = np.concatenate([10.0 ** rng.uniform(-0.2, 3.1, 3000), [1.0, 1.5, 1100.0]])
+    lc = np.concatenate([rng.uniform(2.0, 25.0, 3000), [10.0, 10.0, 10.0]])
+    # 1 + R/lambda_c at and beside sqrt(2) 2^j and 2^j
+    for j in range(0, 7):
+        for m in (math.sqrt(2.0), 2.0):
+            u = m * 2.0 ** j - 1.0
+            for f in (1 - 1e-15, 1.0, 1 + 1e-15):
+                R = np.append(R, 10.0 * u * f)
+                lc = np.append(lc, 10.0)
+    out = run(driver, "cnfw_terms", np.stack([R, lc], axis=1).ravel()).reshape(-1, 3)
+    ex_iR = [1 / mp.mpf(r) for r in R]
+    ex_iRl = [1 / (mp.mpf(r) + mp.mpf(l)) for r, l in zip(R, lc)]
+    ex_lg = [mp.log1p(mp.mpf(r) / mp.mpf(l)) for r, l in zip(R, lc)]
+    assert ulp_err(out[:, 0], ex_iR).max() < 4
+    assert ulp_err(out[:, 1], ex_iRl).max() < 4
+    d = np.array([float(abs(mp.mpf(g) - e)) for g, e in zip(out[:, 2], ex_lg)])
+    exf = np.abs(np.array([float(e) for e in ex_lg]))
+    assert np.all(d <= 2.0 ** -53 + 4 * np.spacing(exf))
+
+
+def test_kernel_coefficients_match_generator():
+    """The polynomial coefficients written in rt_math.h are the ones
+    poly_coeffs.py generates (binary64 and binary32), in Horner order."""
+    import importlib.util
+    import re
+    spec = importlib.util.spec_from_file_location("poly_coeffs", os.path.join(INC, "poly_coeffs.py"))
+    pc = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(pc)
+    src = open(os.path.join(INC, "rt_math.h")).read()
+    nums = [float(v) for v in re.findall(r"fmaf?\(\w+, \w+, (-?[0-9.]+e?-?[0-9]*)f?\)", src)]
+    inits = [float(v) for v in re.findall(r"(?:double|float) p\w* = (-?[0-9.]+e?-?[0-9]*)f?;", src)]
+    for binary32 in (False, True):
+        for name in pc.KERNELS:
+            cs = pc.coefficients(name, binary32)
+            # the first coefficient initialises the accumulator, the others are
+            # the additive terms of consecutive fused multiply-adds
+            assert cs[0] in inits, (name, binary32)
+            text = ", ".join(repr(c) for c in cs[1:])
+            seq = [c for c in cs[1:]]
+            found = any(nums[i:i + len(seq)] == seq for i in range(len(nums)))
+            assert found, (name, binary32, text)
 
 
 def test_rpow_tenth(driver):
