@@ -650,7 +650,7 @@ def main() -> int:
     roofline = {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
                 "traffic": measured_traffic(khash),
-                "kernel": "trace_kernel<CNFW_NEAR> (cored NFW, |eta| <= 0.34)",
+                "kernel": "trace_kernel<CNFW_NEAR> (cored NFW, 0 <= eta <= 0.34)",
                 "kernel_ms": float(np.mean(kernel_ms)),
                 "flops_per_launch": flops, "kernel_source_hash": khash}
 

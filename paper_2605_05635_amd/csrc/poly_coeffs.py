@@ -10,6 +10,7 @@ rounding of its binary64 evaluation), measured on a 4000-point grid:
     sin r = r + r z S(z),            z = r^2 in [0, (pi/2)^2]  (binary32: [0, (pi/4)^2])
     cos r = 1 + z C(z)               (its bound is absolute: cos r reaches 0)
     e^r - 1 = r + r^2 E(r),          |r| <= ln(2)/2 (+1e-9)
+    e^x - 1 = x + x^2 EN(x),         x in [-0.34, 0] (+-1e-9; the cored-NFW exponent)
     log m = 2 (t + t z L(z)),        t = (m-1)/(m+1), m in [sqrt(1/2), sqrt(2)), z = t^2
 
 Run `python poly_coeffs.py` to print the tables in the order rt_math.h
@@ -25,6 +26,7 @@ PIO2_2 = (mp.pi / 2) ** 2 * (1 + mp.mpf("1e-12"))
 LN2_2 = mp.log(2) / 2 + mp.mpf("1e-9")
 T_MAX = (mp.sqrt(2) - 1) / (mp.sqrt(2) + 1)
 Z_LOG = T_MAX ** 2 * (1 + mp.mpf("1e-12"))
+EX_NEAR = mp.mpf("0.34")
 
 
 def _S(z):
@@ -49,6 +51,8 @@ KERNELS = {   # name: (auxiliary function, interval, degree, value of the kernel
     "S": (_S, (0, PIO2_2), 7, lambda x, p: (mp.sqrt(x) * (1 + x * p), mp.sin(mp.sqrt(x)))),
     "C": (_C, (0, PIO2_2), 7, lambda x, p: (1 + x * p, mp.cos(mp.sqrt(x)))),
     "E": (_E, (-LN2_2, LN2_2), 10, lambda x, p: (x + x * x * p, mp.expm1(x))),
+    "EN": (_E, (-EX_NEAR - mp.mpf("1e-9"), mp.mpf("1e-9")), 8,
+           lambda x, p: (x + x * x * p, mp.expm1(x))),
     "L": (_L, (0, Z_LOG), 6, lambda x, p: (2 * mp.sqrt(x) * (1 + x * p), 2 * mp.atanh(mp.sqrt(x)))),
 }
 # Kernels whose bound is the absolute error of the function value.
@@ -56,7 +60,7 @@ ABSOLUTE = {"C"}
 
 # Degrees of the binary32 kernels (the single-precision bulk trace, whose sine
 # and cosine reduce by pi/2); their coefficients are rounded to binary32.
-DEGREES32 = {"S": 3, "C": 3, "E": 5, "L": 2}
+DEGREES32 = {"S": 3, "C": 3, "E": 5, "L": 2}   # (EN has no binary32 version)
 INTERVALS32 = {"S": (0, PIO4_2), "C": (0, PIO4_2)}
 
 
@@ -98,6 +102,8 @@ def max_rel_error(name, cs, n=4000, binary32=False):
 if __name__ == "__main__":
     for binary32 in (False, True):
         for name in KERNELS:
+            if binary32 and name not in DEGREES32:
+                continue
             cs = coefficients(name, binary32)
             kind = "binary32" if binary32 else "binary64"
             what = "abs" if name in ABSOLUTE else "rel"

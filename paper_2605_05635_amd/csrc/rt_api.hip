@@ -296,9 +296,10 @@ int setup_image(const rt_image_params* p, int index, bool emission, rt::ImageCon
         c->lam_c = p->halo[1];
         c->inv_lam_c = 1.0 / p->halo[1];
         c->eta_lc = p->halo[0] * p->halo[1];
-        // |exponent of eq. (13)| = |eta| lambda_c |P(R)| <= |eta|: P(R) = 1/(R + lambda_c)
-        // - (2/R) log(1 + R/lambda_c) increases from -1/lambda_c (R -> 0) to 0
-        c->ex_near = std::fabs(p->halo[0]) <= rt::dm::kExpm1Near ? 1 : 0;
+        // exponent of eq. (13) = eta lambda_c P(R) in [-eta, 0] for eta >= 0: P(R) =
+        // 1/(R + lambda_c) - (2/R) log(1 + R/lambda_c) increases from -1/lambda_c
+        // (R -> 0) to 0
+        c->ex_near = (p->halo[0] >= 0.0 && p->halo[0] <= rt::dm::kExpm1Near) ? 1 : 0;
     }
     double r_plus = 0.0;
     if (!outer_horizon(*c, &r_plus))

@@ -18,7 +18,7 @@ namespace rt {
 
 enum : int32_t { KERR = 0, EINASTO = 1, CNFW = 2 };
 // Kernel variant of CNFW (a template argument only, never an image's metric)
-// for images whose halo has |eta| <= dm::kExpm1Near (ImageConst::ex_near).
+// for images whose halo has 0 <= eta <= dm::kExpm1Near (ImageConst::ex_near).
 constexpr int32_t CNFW_NEAR = 3;
 __host__ __device__ constexpr bool is_cnfw(int32_t m) { return m == CNFW || m == CNFW_NEAR; }
 enum : int32_t { RAY_CAPTURED = 1, RAY_ESCAPED = 2, RAY_STEP_LIMIT = 3, RAY_NONFINITE = 4 };
@@ -62,9 +62,9 @@ struct ImageConst {
     double thick_rs, thick_h0, thick_h;
 };
 
-// e^x - 1 of the cored-NFW exponent: in binary64 and binary32 without the
-// argument reduction when `near` (the same result for |x| <= kExpm1Near);
-// dual numbers use the general function.
+// e^x - 1 of the cored-NFW exponent: in binary64 by the kernel of the near
+// range x in [-kExpm1Near, 0] when `near` (binary32: without the argument
+// reduction, exact there); dual numbers use the general function.
 __host__ __device__ inline double expm1_ex(double x, bool near) { return dm::expm1(x, near); }
 __host__ __device__ inline float expm1_ex(float x, bool near) { return dm::expm1(x, near); }
 template <class S>

@@ -311,26 +311,39 @@ __host__ __device__ __forceinline__ Passage passage_of(double band0, double band
 
 // Root of theta(s) = th_eq on the step's continuous extension, s in (0, 1),
 // given theta(0) and theta(1) on opposite sides.  Writing the extension as
-// y0 + s (c1 + s (c2 + s (c3 + s c4))), Newton's method starts from the secant
-// root and is kept inside the shrinking sign bracket (bisection when a Newton
-// step would leave it); it stops after a step below 1e-10 (Newton's quadratic
-// convergence leaves the new iterate ~1e-20 c2/c1 from the root), when the
-// bracket is exhausted, or at once where the extension evaluates to exactly
-// pi/2 (the zero Newton step from there would not lie strictly inside the
-// bracket and would hand over to bisection).  The quotients use the
-// one-Newton-step reciprocal (2e-15): an error of that size in a Newton step
-// is corrected by the next.
-__host__ __device__ __forceinline__ double crossing_root(const DenseComp& d, bool up0,
-                                                        double th_eq) {
+// y0 + s (c1 + s (c2 + s (c3 + s c4))):
+//
+// crossing_root_safe: Newton's method from the secant root, kept inside the
+// shrinking sign bracket (bisection when a Newton step would leave it); it
+// stops after a step below 1e-10 (Newton's quadratic convergence leaves the
+// new iterate ~1e-20 c2/c1 from the root), when the bracket is exhausted, or at
+// once where the extension evaluates to exactly th_eq (the zero Newton step
+// from there would not lie strictly inside the bracket).  The quotients use
+// the one-Newton-step reciprocal (2e-15): an error of that size in a Newton
+// step is corrected by the next.
+//
+// crossing_root: four plain Newton steps from the secant root, each dividing
+// by the derivative through the hardware reciprocal estimate (2^-24 relative;
+// the error then contracts as e <- C e^2 + 6e-8 e, from the secant root's
+// ~1e-2 to ~1e-20 on a step the controller accepted), then the same
+// acceptance as the safeguarded search: an iterate inside (0, 1) whose last
+// step is at most 1e-10.  A lane that fails it (an extension that turns near
+// the crossing, a poor start, a non-finite derivative) runs the safeguarded
+// search.  The plain steps carry no bracket bookkeeping: about a third of the
+// instructions per iteration, and a wavefront runs them whenever one of its
+// lanes crosses the equator.
+__host__ __device__ __forceinline__ double crossing_root_safe(const DenseComp& d, bool up0,
+                                                             double th_eq) {
     const double c1 = d.r2 + d.r3;
     const double c2 = d.r4 + d.r5 - d.r3;
     const double c3 = -d.r4 - 2.0 * d.r5;
     const double c4 = d.r5;
+    const double f0 = d.y0 - th_eq;   // exact: theta(0) lies within pi/2 of th_eq
     double a = 0.0, b = 1.0;
-    double s = (th_eq - d.y0) * rcp(d.r2);
+    double s = -f0 * rcp(d.r2);
     if (!(s > 0.0 && s < 1.0)) s = 0.5;
     for (int it = 0; it < 48; ++it) {
-        const double f = d.y0 + s * (c1 + s * (c2 + s * (c3 + s * c4))) - th_eq;
+        const double f = f0 + s * (c1 + s * (c2 + s * (c3 + s * c4)));
         if (f == 0.0) break;   // s is a root of the evaluated extension
         if ((f >= 0.0) == up0) a = s; else b = s;
         const double df = c1 + s * (2.0 * c2 + s * (3.0 * c3 + s * 4.0 * c4));
@@ -341,6 +354,27 @@ __host__ __device__ __forceinline__ double crossing_root(const DenseComp& d, boo
         if (step <= 1e-10 || b - a <= 1e-15) break;
     }
     return s;
+}
+
+__host__ __device__ __forceinline__ double crossing_root(const DenseComp& d, bool up0,
+                                                        double th_eq) {
+    const double c1 = d.r2 + d.r3;
+    const double c2 = d.r4 + d.r5 - d.r3;
+    const double c3 = -d.r4 - 2.0 * d.r5;
+    const double c4 = d.r5;
+    const double f0 = d.y0 - th_eq;   // exact: theta(0) lies within pi/2 of th_eq
+    const double dc2 = 2.0 * c2, dc3 = 3.0 * c3, dc4 = 4.0 * c4;
+    double s = -f0 * dm::recip_estimate(d.r2);
+    if (!(s > 0.0 && s < 1.0)) s = 0.5;
+    double step = 0.0;
+    for (int it = 0; it < 4; ++it) {
+        const double f = f0 + s * (c1 + s * (c2 + s * (c3 + s * c4)));
+        const double df = c1 + s * (dc2 + s * (dc3 + s * dc4));
+        step = f * dm::recip_estimate(df);
+        s -= step;
+    }
+    if (s > 0.0 && s < 1.0 && fabs(step) <= 1e-10) return s;
+    return crossing_root_safe(d, up0, th_eq);
 }
 
 // dI/dlambda = g^3 j of the thick disc (Sec. 5.1-5.2) at (R, theta) for a

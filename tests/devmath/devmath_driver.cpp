@@ -1,7 +1,7 @@
 // Host driver for tests/test_devmath.py: evaluates the trace kernels' compact
 // elementary functions (paper_2605_05635_amd/csrc/rt_math.h, compiled for the
 // host) on the doubles read from stdin and writes the results to stdout.
-//   usage: devmath_driver <function>   (sincos | exp | expm1 | log1p | log1p_fast | rpow_tenth, and the
+//   usage: devmath_driver <function>   (sincos | exp | expm1 | expm1_near | log1p | log1p_fast | rpow_tenth, and the
 //          binary32 versions sincosf | expf | expm1f | log1pf of the arguments rounded
 //          to binary32; cnfw_terms reads (R, lambda_c) pairs and writes 1/R,
 //          1/(R + lambda_c) and log(1 + R/lambda_c))
@@ -38,6 +38,8 @@ int main(int argc, char** argv) {
             out.push_back(rt::dm::exp(a));
         } else if (!std::strcmp(argv[1], "expm1")) {
             out.push_back(rt::dm::expm1(a));
+        } else if (!std::strcmp(argv[1], "expm1_near")) {
+            out.push_back(rt::dm::expm1_near(a));
         } else if (!std::strcmp(argv[1], "log1p")) {
             out.push_back(rt::dm::log1p(a));
         } else if (!std::strcmp(argv[1], "log1p_fast")) {
