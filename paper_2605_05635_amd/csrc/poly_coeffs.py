@@ -11,7 +11,8 @@ rounding of its binary64 evaluation), measured on a 4000-point grid:
     cos r = 1 + z C(z)               (its bound is absolute: cos r reaches 0)
     e^r - 1 = r + r^2 E(r),          |r| <= ln(2)/2 (+1e-9)
     e^x - 1 = x + x^2 EN(x),         x in [-0.34, 0] (+-1e-9; the cored-NFW exponent)
-    log m = 2 (t + t z L(z)),        t = (m-1)/(m+1), m in [sqrt(1/2), sqrt(2)), z = t^2
+    log m = w (1 + v LW(v)),         w = 2 (m-1)/(m+1), m in [sqrt(1/2), sqrt(2)), v = w^2
+    (binary32: log m = 2 (t + t z L(z)), t = w/2, z = t^2)
 
 Run `python poly_coeffs.py` to print the tables in the order rt_math.h
 evaluates them (highest degree first): the binary64 kernels, then the
@@ -47,6 +48,11 @@ def _L(z):
     return (mp.atanh(t) / t - 1) / z
 
 
+def _LW(v):
+    w = mp.sqrt(v)
+    return (2 * mp.atanh(w / 2) / w - 1) / v
+
+
 KERNELS = {   # name: (auxiliary function, interval, degree, value of the kernel's function)
     "S": (_S, (0, PIO2_2), 7, lambda x, p: (mp.sqrt(x) * (1 + x * p), mp.sin(mp.sqrt(x)))),
     "C": (_C, (0, PIO2_2), 7, lambda x, p: (1 + x * p, mp.cos(mp.sqrt(x)))),
@@ -54,13 +60,17 @@ KERNELS = {   # name: (auxiliary function, interval, degree, value of the kernel
     "EN": (_E, (-EX_NEAR - mp.mpf("1e-9"), mp.mpf("1e-9")), 8,
            lambda x, p: (x + x * x * p, mp.expm1(x))),
     "L": (_L, (0, Z_LOG), 6, lambda x, p: (2 * mp.sqrt(x) * (1 + x * p), 2 * mp.atanh(mp.sqrt(x)))),
+    "LW": (_LW, (0, 4 * Z_LOG), 6,
+           lambda x, p: (mp.sqrt(x) * (1 + x * p), 2 * mp.atanh(mp.sqrt(x) / 2))),
 }
+# The kernels of the binary64 functions (rt_math.h); L is binary32 only.
+USED64 = ("S", "C", "E", "EN", "LW")
 # Kernels whose bound is the absolute error of the function value.
 ABSOLUTE = {"C"}
 
 # Degrees of the binary32 kernels (the single-precision bulk trace, whose sine
 # and cosine reduce by pi/2); their coefficients are rounded to binary32.
-DEGREES32 = {"S": 3, "C": 3, "E": 5, "L": 2}   # (EN has no binary32 version)
+DEGREES32 = {"S": 3, "C": 3, "E": 5, "L": 2}
 INTERVALS32 = {"S": (0, PIO4_2), "C": (0, PIO4_2)}
 
 
@@ -101,9 +111,7 @@ def max_rel_error(name, cs, n=4000, binary32=False):
 
 if __name__ == "__main__":
     for binary32 in (False, True):
-        for name in KERNELS:
-            if binary32 and name not in DEGREES32:
-                continue
+        for name in (DEGREES32 if binary32 else USED64):
             cs = coefficients(name, binary32)
             kind = "binary32" if binary32 else "binary64"
             what = "abs" if name in ABSOLUTE else "rel"

@@ -64,7 +64,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
     bool live = false;
     bool active = false, exhausted = false;
     int64_t next = 0, end = 0;
-    TileClaim tc{0, 0, 1};
+    TileClaim tc{0, 0, 1, 1.0f};
     uint32_t rays = 0, steps = 0;
     auto claim = [&]() { return claim_screen(shape, c.nx, c.ny, queue, next, end, tc); };
     auto take = [&](int64_t ordinal) {
@@ -146,7 +146,7 @@ __global__ __launch_bounds__(kBlock) void vjp_backward_kernel(
     double xb[4], Eb, Lb, pb[4], rinb;
     bool active = false, exhausted = false;
     int64_t next = 0, end = 0;
-    TileClaim tc{0, 0, 1};
+    TileClaim tc{0, 0, 1, 1.0f};
     // (re)start the recomputation of chunk `chunk` of segment `seg`
     auto begin_chunk = [&]() {
         vjp::load_checkpoint<METRIC>(mine + seg * kVjpCkptDoubles, k, E, L, pix, r);

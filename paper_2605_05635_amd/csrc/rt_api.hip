@@ -468,14 +468,19 @@ int trace_common(const rt_image_params* params, int32_t n_images, const rt_image
     size_t mixed_bytes = 0;
     for (int i : mixed)
         mixed_bytes += 256 + up256(rt::mixed_record_bytes() * static_cast<size_t>(consts[i].n_pix));
-    // The emission pass reads ncross and r_em: images that do not return them
-    // get scratch ones.
+    // The pass after the trace (the emission, and the NaN transfer-map records
+    // beyond each pixel's crossings, which the binary64 trace kernels leave to
+    // it) runs whenever either is wanted.  It reads ncross, and with emission
+    // r_em: images that do not return them get scratch ones.
+    bool maps = false;
+    for (int i = 0; i < n_images; ++i) maps = maps || out[i].r_em || out[i].phi_em || out[i].t_em;
+    const bool after_pass = emission || maps;
     size_t emit_bytes = 0;
-    if (emission)
-        for (int i = 0; i < n_images; ++i) {
-            if (!out[i].ncross) emit_bytes += up256(static_cast<size_t>(consts[i].n_pix));
-            if (!out[i].r_em) emit_bytes += up256(sizeof(double) * 3 * static_cast<size_t>(consts[i].n_pix));
-        }
+    for (int i = 0; i < n_images; ++i) {
+        if (after_pass && !out[i].ncross) emit_bytes += up256(static_cast<size_t>(consts[i].n_pix));
+        if (emission && !out[i].r_em)
+            emit_bytes += up256(sizeof(double) * 3 * static_cast<size_t>(consts[i].n_pix));
+    }
     const size_t scratch_bytes = queue_bytes + part_bytes + table_bytes + mixed_bytes + emit_bytes;
     void* scratch = nullptr;
     hipError_t e = hipMallocAsync(&scratch, scratch_bytes, stream);
@@ -494,17 +499,16 @@ int trace_common(const rt_image_params* params, int32_t n_images, const rt_image
         (void)hipFreeAsync(scratch, stream);
         return code;
     };
-    if (emission)
-        for (int i = 0; i < n_images; ++i) {
-            if (!optrs[i].ncross) {
-                optrs[i].ncross = reinterpret_cast<uint8_t*>(emit_area);
-                emit_area += up256(static_cast<size_t>(consts[i].n_pix));
-            }
-            if (!optrs[i].r_em) {
-                optrs[i].r_em = reinterpret_cast<double*>(emit_area);
-                emit_area += up256(sizeof(double) * 3 * static_cast<size_t>(consts[i].n_pix));
-            }
+    for (int i = 0; i < n_images; ++i) {
+        if (after_pass && !optrs[i].ncross) {
+            optrs[i].ncross = reinterpret_cast<uint8_t*>(emit_area);
+            emit_area += up256(static_cast<size_t>(consts[i].n_pix));
         }
+        if (emission && !optrs[i].r_em) {
+            optrs[i].r_em = reinterpret_cast<double*>(emit_area);
+            emit_area += up256(sizeof(double) * 3 * static_cast<size_t>(consts[i].n_pix));
+        }
+    }
 
     rt::ImageConst* d_table = nullptr;
     rt::OutPtrs* d_outs = nullptr;
@@ -591,11 +595,11 @@ int trace_common(const rt_image_params* params, int32_t n_images, const rt_image
             return bail(hip_fail(e, "mixed-precision kernel launch"));
     }
     if (g_timing_stop) (void)hipEventRecord(g_timing_stop, stream);
-    if (emission) {
+    if (after_pass) {
+        e = hipSuccess;
         if (nf == 1) {
             e = rt::launch_emission(consts[order[0]], optrs[order[0]], stream);
-        } else {
-            e = hipSuccess;
+        } else if (nf > 1) {
             for (int l = 0; l < n_launch && e == hipSuccess; ++l) {
                 const int lo = l * kMaxBatch, hi = std::min(nf, lo + kMaxBatch);
                 int64_t max_pix = 0;
@@ -603,7 +607,8 @@ int trace_common(const rt_image_params* params, int32_t n_images, const rt_image
                 e = rt::launch_emission_batch(d_table + lo, d_outs + lo, hi - lo, max_pix, stream);
             }
         }
-        for (size_t m = 0; m < mixed.size() && e == hipSuccess; ++m)
+        // (the mixed-precision kernels write their own NaN records)
+        for (size_t m = 0; m < mixed.size() && emission && e == hipSuccess; ++m)
             e = rt::launch_emission(consts[mixed[m]], optrs[mixed[m]], stream);
         if (e != hipSuccess) return bail(hip_fail(e, "emission kernel launch"));
     }

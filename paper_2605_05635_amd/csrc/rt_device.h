@@ -75,7 +75,7 @@ __host__ __device__ inline S expm1_ex(const S& x, bool) {
 // The cored-NFW halo terms 1/R, 1/(R + lambda_c) and log(1 + R/lambda_c) in
 // binary64 from one reciprocal: with 1 + R/lambda_c = m 2^e (dm::log_split;
 // the sum is one fused operation), 1/(R (R + lambda_c) (m + 1)) gives both
-// reciprocals and the logarithm kernel's quotient (m - 1)/(m + 1) by
+// reciprocals and the logarithm kernel's quotient 2 (m - 1)/(m + 1) by
 // multiplications.  Errors as dm::log1p_fast's: half an ulp of 1 + R/lambda_c
 // absolute in the logarithm, plus the one-step reciprocal's 2.2e-15 relative
 // in all three.
@@ -91,8 +91,8 @@ __host__ __device__ inline CnfwTerms cnfw_terms(double R, double lam_c, double i
     CnfwTerms t;
     t.iR = Rl * a;
     t.iRl = R * a;
-    const double q = (s.m - 1.0) * (d * inv);
-    t.lg = fma(s.e, dm::kLn2Hi, fma(s.e, dm::kLn2Lo, dm::log_kernel(q)));
+    const double w = fma(s.m, 2.0, -2.0) * (d * inv);   // 2 (m - 1)/(m + 1)
+    t.lg = fma(s.e, dm::kLn2Hi, fma(s.e, dm::kLn2Lo, dm::log_kernel(w)));
     return t;
 }
 

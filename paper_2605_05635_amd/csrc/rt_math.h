@@ -102,6 +102,24 @@ __host__ __device__ inline double recip_estimate(double x) {
 #endif
 }
 
+// 1/sqrt(x) for positive normal x: on the device the hardware estimate
+// refined by two Newton steps y <- y + y (1 - x y^2)/2, each of which squares
+// its relative error (to a few ulp from the estimate's ~2^-23); on the host
+// 1/sqrt(x).  Eleven instructions where the division of a correctly rounded
+// square root takes about thirty.
+__host__ __device__ inline double rsqrt(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    double y = __builtin_amdgcn_rsq(x);
+    for (int it = 0; it < 2; ++it) {
+        const double r = fma(-x * y, y, 1.0);
+        y = fma(y, 0.5 * r, y);
+    }
+    return y;
+#else
+    return 1.0 / std::sqrt(x);
+#endif
+}
+
 // sin and cos of x, |x| < 3.2e6: x = k pi + r with |r| <= pi/2, so that
 // sin x = (-1)^k sin r and cos x = (-1)^k cos r.  Reducing by pi rather than
 // pi/2 leaves a sign flip of both results in place of the quadrant's swap and
@@ -209,19 +227,21 @@ __host__ __device__ inline double expm1(double x, bool near) {
     return near ? expm1_near(x) : expm1(x);
 }
 
-// log m = 2 atanh(t) = 2 (t + t z L(z)), z = t^2, for m = (1 + t)/(1 - t) in
-// [sqrt(1/2), sqrt(2)), i.e. |t| <= 0.1715729: a polynomial kernel of degree
-// 6 in z (generated by poly_coeffs.py; 4.5e-18 relative).
-__host__ __device__ inline double log_kernel(double t) {
-    const double z = t * t;
-    double p = 0.07308224842522382;
-    p = fma(p, z, 0.07665860800277965);
-    p = fma(p, z, 0.09091444562630863);
-    p = fma(p, z, 0.1111110556739754);
-    p = fma(p, z, 0.14285714312987743);
-    p = fma(p, z, 0.19999999999949752);
-    p = fma(p, z, 0.3333333333333335);
-    return 2.0 * fma(t * z, p, t);
+// log m = 2 atanh(w/2) = w (1 + v LW(v)), v = w^2, for w = 2 (m - 1)/(m + 1)
+// with m in [sqrt(1/2), sqrt(2)), i.e. |w| <= 0.3431458: a polynomial kernel
+// of degree 6 in v (generated by poly_coeffs.py; 4.5e-18 relative).  Taking
+// the quotient with the factor 2 (2m - 2 is exact) saves the doubling of the
+// result.
+__host__ __device__ inline double log_kernel(double w) {
+    const double v = w * w;
+    double p = 4.460586451734852e-06;
+    p = fma(p, v, 1.8715480469428627e-05);
+    p = fma(p, v, 8.878363830694202e-05);
+    p = fma(p, v, 0.0004340275612264664);
+    p = fma(p, v, 0.002232142861404335);
+    p = fma(p, v, 0.012499999999968595);
+    p = fma(p, v, 0.08333333333333337);
+    return fma(w * v, p, w);
 }
 
 // v = m 2^e for a positive normal v, with m in [0.70710677, 1.41421354): the
@@ -229,7 +249,7 @@ __host__ __device__ inline double log_kernel(double t) {
 // high word 0x3fe6a09e, just below sqrt(1/2) (the argument reduction of the
 // classic fdlibm logarithm).  Integer operations on the high word and one
 // conversion, where frexp, the comparison with sqrt(1/2) and the selects of m
-// and e take nine instructions.  (The kernel's t then reaches 1e-7 relative
+// and e take nine instructions.  (The kernel's w then reaches 1e-7 relative
 // beyond its interval's end, where the interpolant's error is still its bound.)
 struct LogSplit {
     double m, e;
@@ -268,8 +288,8 @@ __host__ __device__ inline double log1p_impl(double u) {
         m *= 2.0;
         e -= 1;
     }
-    const double t = (m - 1.0) * (CORRECT ? recip(m + 1.0) : recip1(m + 1.0));
-    const double logm = log_kernel(t);
+    const double w = fma(m, 2.0, -2.0) * (CORRECT ? recip(m + 1.0) : recip1(m + 1.0));
+    const double logm = log_kernel(w);
     const double de = static_cast<double>(e);
     return fma(de, kLn2Hi, logm + fma(de, kLn2Lo, corr));
 }

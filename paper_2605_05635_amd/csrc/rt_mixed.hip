@@ -31,7 +31,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
     Ray32 r;
     bool active = false, exhausted = false;
     int64_t next = 0, end = 0;
-    TileClaim tc{0, 0, 1};
+    TileClaim tc{0, 0, 1, 1.0f};
     auto claim = [&]() { return claim_screen(shape, c.nx, c.ny, queue, next, end, tc); };
     auto take = [&](int64_t ordinal) {
         start_ray32<METRIC>(c, k, claimed_pixel(shape, c.nx, c.ny, tc, ordinal), r);

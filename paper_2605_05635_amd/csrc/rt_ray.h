@@ -234,8 +234,16 @@ struct ScreenDir {
 
 // The direction of screen point (X, Y).
 __host__ __device__ __forceinline__ ScreenDir screen_dir_xy(const ImageConst& c, double X, double Y) {
-    const double inv = 1.0 / sqrt(c.r_obs * c.r_obs + X * X + Y * Y);
+    const double inv = dm::rsqrt(c.r_obs * c.r_obs + X * X + Y * Y);
     return ScreenDir{-c.r_obs * inv, -Y * inv, -X * inv};
+}
+
+// The direction of the centre of pixel (ix, iy).
+__host__ __device__ __forceinline__ ScreenDir screen_dir_ij(const ImageConst& c, int32_t ix,
+                                                           int32_t iy) {
+    const double X = c.x0 + (static_cast<double>(ix) + 0.5) * c.dx;
+    const double Y = c.y0 + (static_cast<double>(iy) + 0.5) * c.dy;
+    return screen_dir_xy(c, X, Y);
 }
 
 // The direction of pixel pix's centre.
@@ -243,10 +251,7 @@ __host__ __device__ __forceinline__ ScreenDir screen_dir(const ImageConst& c, in
     // 32-bit index arithmetic: screens hold fewer than 2^31 pixels
     const int32_t p = static_cast<int32_t>(pix);
     const int32_t iy = p / c.nx;
-    const int32_t ix = p - iy * c.nx;
-    const double X = c.x0 + (static_cast<double>(ix) + 0.5) * c.dx;
-    const double Y = c.y0 + (static_cast<double>(iy) + 0.5) * c.dy;
-    return screen_dir_xy(c, X, Y);
+    return screen_dir_ij(c, p - iy * c.nx, iy);
 }
 
 // The photon's conserved E and l of pixel pix.
@@ -281,6 +286,18 @@ __host__ __device__ __forceinline__ void start_ray_dir(const ImageConst& c, cons
 template <int METRIC>
 __host__ __device__ __forceinline__ void start_ray(const ImageConst& c, const Hot& k, int64_t pix, Ray& r) {
     start_ray_dir<METRIC>(c, k, screen_dir(c, pix), pix, r);
+}
+
+// A pixel as its index and its column and row.
+struct Pixel {
+    int64_t pix;
+    int32_t ix, iy;
+};
+
+template <int METRIC>
+__host__ __device__ __forceinline__ void start_ray(const ImageConst& c, const Hot& k, const Pixel& px,
+                                                   Ray& r) {
+    start_ray_dir<METRIC>(c, k, screen_dir_ij(c, px.ix, px.iy), px.pix, r);
 }
 
 // Equatorial passage of a step from theta0 to theta1 (Sec. 3.3).
@@ -511,7 +528,7 @@ __host__ __device__ __forceinline__ int32_t attempt(const Hot& k, const OutPtrs&
         ae[i] += e7 * kk[i];
         ad[i] += d7 * kk[i];
         const double sc = k.atol + k.rtol * fmax(fabs(r.y[i]), fabs(yn[i]));
-        const double q = h * ae[i] * rcp(sc);
+        const double q = ae[i] * rcp(sc);
         acc += q * q;
     }
     double ynI = 0.0, kI7 = 0.0;
@@ -520,14 +537,15 @@ __host__ __device__ __forceinline__ int32_t attempt(const Hot& k, const OutPtrs&
         aeI += e7 * kI7;
         ynI = r.I + h * abI;
         const double sc = k.atol + k.rtol * fmax(fabs(r.I), fabs(ynI));
-        const double q = h * aeI * rcp(sc);
+        const double q = aeI * rcp(sc);
         acc += q * q;
     }
-    // err^2 = mean of the squared scaled errors; the step is accepted when
+    // err^2 = mean of the squared scaled errors (h e_i/sc_i)^2, with h^2 taken
+    // out of the sum; the step is accepted when
     // err < 1 and the size factor is 0.9 err^(-1/5) = 0.9 (err^2)^(-1/10),
     // clipped to [0.2, 10] (err = 0 gives the maximum, a non-finite err the
     // minimum).  Outside err^2 in [1e-12, 1e12] the clip decides the factor.
-    const double err2 = acc * (THICK ? 1.0 / 7.0 : 1.0 / 6.0);
+    const double err2 = (h * h) * acc * (THICK ? 1.0 / 7.0 : 1.0 / 6.0);
     const double grow = 0.9 * dm::rpow_tenth(fmin(fmax(err2, 1e-12), 1e12));
     if (!(err2 < 1.0)) {  // reject; NaN lands here too
         const bool finite = __builtin_isfinite(err2);
@@ -593,31 +611,40 @@ __host__ __device__ __forceinline__ int32_t attempt(const Hot& k, const OutPtrs&
 }
 
 // Ray epilogue: the per-pixel transfer-map outputs.  Records n >=
-// min(N_cross, 3) are NaN.  The emission is a separate pass (emit_pixel).
+// min(N_cross, 3) are NaN: written here when FILL_NAN, else by the per-pixel
+// pass after the trace (emit_pixel), which the trace kernels of one image and
+// of a batch leave it to: a wavefront runs this epilogue whenever one of its
+// rays ends, about a third of its step attempts.  The emission is that pass
+// too.
+template <bool FILL_NAN = true>
 __device__ __forceinline__ void finish_ray(const ImageConst& c, const OutPtrs& o, const Ray& r,
                                            int32_t status) {
     const int64_t p = r.pix;
-    const int64_t n_pix = c.n_pix;
-    const int nrec = r.ncross < 3 ? r.ncross : 3;
-    const double nan = __builtin_nan("");
     if (o.ncross) o.ncross[p] = static_cast<uint8_t>(r.ncross);
     if (o.status) o.status[p] = static_cast<uint8_t>(status);
     if (o.attempts) o.attempts[p] = r.attempts;
-    for (int n = nrec; n < 3; ++n) {
-        const int64_t off = static_cast<int64_t>(n) * n_pix + p;
-        if (o.r_em) o.r_em[off] = nan;
-        if (o.phi_em) o.phi_em[off] = nan;
-        if (o.t_em) o.t_em[off] = nan;
+    if constexpr (FILL_NAN) {
+        const int64_t n_pix = c.n_pix;
+        const int nrec = r.ncross < 3 ? r.ncross : 3;
+        const double nan = __builtin_nan("");
+        for (int n = nrec; n < 3; ++n) {
+            const int64_t off = static_cast<int64_t>(n) * n_pix + p;
+            if (o.r_em) o.r_em[off] = nan;
+            if (o.phi_em) o.phi_em[off] = nan;
+            if (o.t_em) o.t_em[off] = nan;
+        }
     }
 }
 
-// Emission of pixel p (Sec. 5.2) from its recorded crossings: the redshift
+// The pass after the trace, pixel p: NaN in the transfer-map records n >=
+// min(N_cross, 3) (finish_ray<false> leaves them), then, for an image with
+// emission, the emission (Sec. 5.2) of its recorded crossings: the redshift
 // (eq. (89)) and disc intensity of each of the first min(N_cross, 3) crossing
 // radii, their sum, NaN for the records beyond.  Reads o.ncross and o.r_em as
 // the trace wrote them and recomputes the photon's E and l from the screen
 // map, so it gives what the ray's own epilogue would.  One thread per pixel
-// after the trace: the trace's wavefronts then do not carry the emission code
-// through their divergent epilogue, where it cost most of the lanes' time.
+// after the trace: the trace's wavefronts then do not carry this code through
+// their divergent epilogue, where it cost most of the lanes' time.
 template <int METRIC>
 __device__ __forceinline__ void emit_pixel(const ImageConst& c, const Hot& k, const OutPtrs& o,
                                            int64_t p) {
@@ -625,6 +652,13 @@ __device__ __forceinline__ void emit_pixel(const ImageConst& c, const Hot& k, co
     const int ncr = o.ncross[p];
     const int nrec = ncr < 3 ? ncr : 3;
     const double nan = __builtin_nan("");
+    for (int n = nrec; n < 3; ++n) {
+        const int64_t off = static_cast<int64_t>(n) * n_pix + p;
+        if (o.r_em) o.r_em[off] = nan;
+        if (o.phi_em) o.phi_em[off] = nan;
+        if (o.t_em) o.t_em[off] = nan;
+    }
+    if (!c.emission) return;
     double E, L;
     photon_constants(c, screen_dir(c, p), E, L);
     double intensity = 0.0;
@@ -691,6 +725,7 @@ __device__ __forceinline__ bool claim_chunk(unsigned long long* queue, int32_t c
 // A wave's current claim in tile-order hand-out (wave-uniform).
 struct TileClaim {
     int32_t x0, y0, w;
+    float inv_w;   // 1/w, for the row of an ordinal inside the tile
 };
 
 // Next claim of a screen's pixels by the whole wave: a chunk of ordinals of
@@ -712,19 +747,38 @@ __device__ __forceinline__ bool claim_screen(const LaunchShape& shape, int32_t n
     t.x0 = (id - ty * tiles_x) * shape.tile_w;
     t.y0 = ty * shape.tile_h;
     t.w = nx - t.x0 < shape.tile_w ? nx - t.x0 : shape.tile_w;
+    t.inv_w = 1.0f / static_cast<float>(t.w);
     const int32_t h = ny - t.y0 < shape.tile_h ? ny - t.y0 : shape.tile_h;
     next = 0;
     end = static_cast<int64_t>(t.w) * h;
     return true;
 }
 
+// Pixel of ordinal p of the current claim.  Inside a tile the row is
+// floor((p + 1/2)/w) in binary32: exact, since the quotient's fraction stays
+// 1/(2w) away from an integer and its rounding error is ~1e-7 (p/w)
+// (tiles are far smaller than 2^15 pixels), which saves an integer division.
+__device__ __forceinline__ Pixel claimed(const LaunchShape& shape, int32_t nx, int32_t ny,
+                                         const TileClaim& t, int64_t p) {
+    Pixel px;
+    if (!shape.order) {
+        px.pix = tile_pixel(p, nx, ny, shape.tile_w, shape.tile_h);
+        px.iy = static_cast<int32_t>(px.pix) / nx;
+        px.ix = static_cast<int32_t>(px.pix) - px.iy * nx;
+        return px;
+    }
+    const int32_t o = static_cast<int32_t>(p);
+    const int32_t row = static_cast<int32_t>((static_cast<float>(o) + 0.5f) * t.inv_w);
+    px.ix = t.x0 + (o - row * t.w);
+    px.iy = t.y0 + row;
+    px.pix = static_cast<int64_t>(px.iy) * nx + px.ix;
+    return px;
+}
+
 // Pixel index of ordinal p of the current claim.
 __device__ __forceinline__ int64_t claimed_pixel(const LaunchShape& shape, int32_t nx, int32_t ny,
                                                  const TileClaim& t, int64_t p) {
-    if (!shape.order) return tile_pixel(p, nx, ny, shape.tile_w, shape.tile_h);
-    const int32_t o = static_cast<int32_t>(p);
-    const int32_t iy = o / t.w;
-    return static_cast<int64_t>(t.y0 + iy) * nx + t.x0 + (o - iy * t.w);
+    return claimed(shape, nx, ny, t, p).pix;
 }
 
 }  // namespace ray

@@ -15,7 +15,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 8))) 
     Ray r;
     bool active = false, exhausted = false;
     int64_t next = 0, end = 0;
-    TileClaim tc{0, 0, 1};
+    TileClaim tc{0, 0, 1, 1.0f};
     auto claim = [&]() { return claim_screen(shape, c.nx, c.ny, queue, next, end, tc); };
     auto take = [&](int64_t ordinal) {
         start_ray_thick<METRIC>(c, k, claimed_pixel(shape, c.nx, c.ny, tc, ordinal), r);

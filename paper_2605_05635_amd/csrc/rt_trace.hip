@@ -6,7 +6,8 @@
 // equatorial crossings on the step's continuous extension (Sec. 3.3, 4.2) and
 // records the transfer maps of the first three crossings (Sec. 4.3, eq. (82)).
 // A second, one-thread-per-pixel pass computes the redshifted thin-disc
-// intensity of the recorded crossings (Sec. 5.2, eqs. (89)-(91)).
+// intensity of the recorded crossings (Sec. 5.2, eqs. (89)-(91)) and writes NaN
+// into the transfer-map records beyond them.
 //
 // Launch shape: a persistent grid.  Each wavefront claims chunks of pixels
 // from a global counter with one atomic per chunk; a lane whose ray ends takes
@@ -30,6 +31,7 @@ using namespace ray;
 // NFW spills two): measured 5-10 % faster than two.
 constexpr int kTraceWaves = 3;
 
+
 // Persistent trace kernel for one image (pixels handed out as shape says).
 template <int METRIC>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kTraceWaves, 8))) void trace_kernel(
@@ -38,10 +40,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kTraceWa
     Ray r;
     bool active = false, exhausted = false;
     int64_t next = 0, end = 0;   // wave-uniform: claimed ordinals not yet started
-    TileClaim tc{0, 0, 1};
+    TileClaim tc{0, 0, 1, 1.0f};
     auto claim = [&]() { return claim_screen(shape, c.nx, c.ny, queue, next, end, tc); };
     auto take = [&](int64_t ordinal) {
-        start_ray<METRIC>(c, k, claimed_pixel(shape, c.nx, c.ny, tc, ordinal), r);
+        start_ray<METRIC>(c, k, claimed(shape, c.nx, c.ny, tc, ordinal), r);
     };
     for (;;) {
         if (!exhausted) refill(active, exhausted, next, end, claim, take);
@@ -49,7 +51,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kTraceWa
         if (active) {
             const int32_t st = attempt<METRIC>(k, o, c.n_pix, r);
             if (st != 0) {
-                finish_ray(c, o, r, st);
+                finish_ray<false>(c, o, r, st);
                 active = false;
             }
         }
@@ -125,7 +127,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
             else if (metric == EINASTO) st = attempt<EINASTO>(k, o, n_pix, r);
             else st = attempt<KERR>(k, o, n_pix, r);
             if (st != 0) {
-                finish_ray(lt[img], o, r, st);
+                finish_ray<false>(lt[img], o, r, st);
                 active = false;
             }
         }
