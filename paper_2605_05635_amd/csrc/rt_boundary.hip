@@ -5,7 +5,8 @@
 // (S = 64, 32 or 16 samples per pass); each pass traces one ray per lane at
 // the S interior points of its direction's bracket and keeps the interval
 // around the first escaping one, so the bracket shrinks (S + 1)-fold per pass
-// instead of 2-fold per traced ray.  Fewer samples per direction trace fewer
+// instead of 2-fold per traced ray.  The directions of a wavefront advance
+// independently, each from pass to pass as soon as its own rays end.  Fewer samples per direction trace fewer
 // rays in all and put more directions in flight; more samples need fewer
 // passes.
 #include "rt_ray.h"
@@ -39,7 +40,15 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
     bool done = !mine;
     // Pass -1 checks the bracket (sample 0 at b_lo must stay inside, sample 1
     // at b_hi must escape); passes 0, 1, ... sample b_j = lo + j w, j = sl + 1.
-    for (int pass = -1; __ballot(!done) != 0ull; ++pass) {
+    // Each group runs its passes on its own: when the last of its rays ends it
+    // narrows its bracket and starts its next pass at once, while the other
+    // groups' rays are still in flight (a pass no longer waits for the
+    // slowest ray of the whole wavefront).
+    int pass = -1;
+    Ray r;
+    bool active = false;     // this lane's ray is in flight
+    bool escaped = false;    // the fate of its ray in the group's current pass
+    auto start_pass = [&]() {
         const double w = (hi - lo) / (S + 1);
         double b;
         if (pass < 0) {
@@ -48,20 +57,25 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
             const double t = static_cast<double>(sl + 1) * w;   // no contraction
             b = lo + t;
         }
-        const bool live = !done && (pass >= 0 || sl < 2);
-        Ray r;
-        bool active = live;
-        int32_t st = 0;
-        if (live) start_ray_dir<METRIC>(c, k, screen_dir_xy(c, b * ux, b * uy), 0, r);
-        while (__ballot(active) != 0ull) {
-            if (active) {
-                st = attempt<METRIC>(k, none, 0, r);
-                if (st != 0) active = false;
+        active = pass >= 0 || sl < 2;
+        escaped = false;
+        if (active) start_ray_dir<METRIC>(c, k, screen_dir_xy(c, b * ux, b * uy), 0, r);
+    };
+    if (!done) start_pass();
+    while (__ballot(!done) != 0ull) {
+        if (active) {
+            const int32_t st = attempt<METRIC>(k, none, 0, r);
+            if (st != 0) {
+                active = false;
+                escaped = st == RAY_ESCAPED;
+                used += r.attempts;
             }
         }
-        if (live) used += r.attempts;
-        const unsigned long long esc = (__ballot(live && st == RAY_ESCAPED) >> (grp * S)) & gmask;
-        if (!done) {
+        const unsigned long long busy = (__ballot(active) >> (grp * S)) & gmask;
+        const unsigned long long esc = (__ballot(escaped) >> (grp * S)) & gmask;
+        if (!done && busy == 0ull) {
+            // the group's pass is complete: the same bracket update as a
+            // lockstep search would make
             if (pass < 0) {
                 if ((esc & 1ull) || !(esc & 2ull)) {
                     done = true;
@@ -69,6 +83,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
                     result = 0;
                 }
             } else {
+                const double w = (hi - lo) / (S + 1);
                 double nlo, nhi;
                 if (esc == 0ull) {
                     const double t = S * w;
@@ -88,6 +103,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
                 }
             }
             if (pass + 1 >= kMaxPasses || !(hi - lo > b_tol)) done = true;
+            ++pass;
+            if (!done) start_pass();
         }
     }
     // the group's attempt total, in a fixed order

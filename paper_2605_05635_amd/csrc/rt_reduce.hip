@@ -38,10 +38,13 @@ __global__ __launch_bounds__(kReduceThreads) void reduce_partial(ImageConst c,
     const int64_t per = (c.n_pix + kReduceBlocks - 1) / kReduceBlocks;
     const int64_t lo = per * blockIdx.x;
     const int64_t hi = lo + per < c.n_pix ? lo + per : c.n_pix;
+    // the row by an exact binary64 quotient, floor((p + 1/2)/nx), not a 64-bit
+    // integer division (emulated in software)
+    const double inv_nx = 1.0 / static_cast<double>(c.nx);
     double f = 0.0, fx = 0.0, fy = 0.0;
     for (int64_t p = lo + threadIdx.x; p < hi; p += kReduceThreads) {
         const double v = I[p];
-        const int64_t iy = p / c.nx;
+        const int64_t iy = static_cast<int64_t>((static_cast<double>(p) + 0.5) * inv_nx);
         const int64_t ix = p - iy * c.nx;
         f += v;
         fx += (c.x0 + (static_cast<double>(ix) + 0.5) * c.dx) * v;
