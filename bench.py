@@ -377,10 +377,56 @@ def adjoint_measurement(steps: int, cpu: bool) -> dict:
     return res
 
 
+def _diagnostics_graph(rt, I, p, bw, nb, out, prof, steps, nbytes) -> dict:
+    """Ten calls of rt_image_diagnostics_noalloc captured in one HIP graph and
+    replayed: time per call, and whether every replay (with eager work between
+    them) equals the eager call bit for bit."""
+    import torch
+    stream = torch.cuda.current_stream()
+    ref_out, ref_prof = out.clone(), prof.clone()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    g_out = torch.empty_like(out)
+    g_prof = torch.empty_like(prof)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        rt.rt_image_diagnostics_noalloc(I, p, bw, nb, g_out, g_prof, side)   # first call: set-up
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    per_graph = 10
+    with torch.cuda.graph(graph, capture_error_mode="relaxed"):
+        gs = torch.cuda.current_stream()
+        for _ in range(per_graph):
+            rt.rt_image_diagnostics_noalloc(I, p, bw, nb, g_out, g_prof, gs)
+    same = True
+    reps = max(3, steps // per_graph)
+    a.record(stream)
+    for _ in range(reps):
+        graph.replay()
+    b.record(stream)
+    torch.cuda.synchronize()
+    gms = a.elapsed_time(b) / (reps * per_graph)
+    for _ in range(3):   # replays interleaved with eager work, each checked
+        g_out.zero_()
+        g_prof.zero_()
+        graph.replay()
+        torch.cuda.synchronize()
+        same = same and torch.equal(g_out, ref_out) and bool(
+            torch.equal(torch.nan_to_num(g_prof, nan=-1.0), torch.nan_to_num(ref_prof, nan=-1.0)))
+    log(f"diagnostics in a graph: {gms * 1e3:.1f} us per image (replays equal: {same})")
+    return {"graph_us": gms * 1e3, "graph_replays_equal_eager": same,
+            "graph_image_reads_GBps": nbytes / (gms * 1e-3) / 1e9}
+
+
 def diagnostics_measurement(steps: int, outs: dict, img: dict, cpu: bool) -> dict:
     """Image diagnostics (Sec. 6.2-6.3) of the bench's traced 1024x1024 image:
     wall time of rt_image_diagnostics per call (HIP events on the stream),
-    300 radial bins of 0.05 M."""
+    300 radial bins of 0.05 M.  Back-to-back calls from Python leave the GPU
+    waiting for the host between kernels, so the same work is also timed as
+    a HIP graph of ten calls of rt_image_diagnostics_noalloc (which allocates
+    nothing and can be captured), replayed; every replay's results must equal
+    the eager call's bit for bit."""
     import torch
 
     from paper_2605_05635_amd import rt
@@ -407,6 +453,13 @@ def diagnostics_measurement(steps: int, outs: dict, img: dict, cpu: bool) -> dic
     res = {"workload": "image diagnostics of the 1024x1024 cored-NFW image, 300 bins of 0.05 M",
            "us": ms * 1e3, "steps": steps, "values": vals,
            "image_reads_GBps": nbytes / (ms * 1e-3) / 1e9}
+    # the same calls captured in a graph (no host work between the kernels)
+    try:
+        res.update(_diagnostics_graph(rt, I, p, bw, nb, out, prof, steps, nbytes))
+    except Exception as exc:   # a capture the runtime refuses is reported, not fatal
+        res["graph_error"] = f"{type(exc).__name__}: {exc}"
+        log(f"diagnostics in a graph: {res['graph_error']}")
+
     if cpu:
         from oracle import oracle as O
         In = I.cpu().numpy()
