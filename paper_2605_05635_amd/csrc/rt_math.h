@@ -29,11 +29,10 @@
 namespace rt {
 namespace dm {
 
-// pi and ln 2 as sums of three and two doubles (each the nearest double to the
-// remainder of the previous ones).
+// pi and ln 2 as sums of two doubles (each the nearest double to the
+// remainder of the previous one).
 constexpr double kPiHi = 3.141592653589793;
 constexpr double kPiMid = 1.2246467991473532e-16;
-constexpr double kPiLo = -2.9947698097183397e-33;
 constexpr double kInvPi = 0.3183098861837907;
 constexpr double kLn2Hi = 0.6931471805599453;
 constexpr double kLn2Lo = 2.3190468138462996e-17;
@@ -124,15 +123,16 @@ __host__ __device__ inline double rsqrt(double x) {
 // sin x = (-1)^k sin r and cos x = (-1)^k cos r.  Reducing by pi rather than
 // pi/2 leaves a sign flip of both results in place of the quadrant's swap and
 // negations (one shift and two exclusive-ors where the swap took about 16
-// instructions), at one more polynomial degree each.  sin keeps its relative
-// accuracy near multiples of pi; cos is accurate to 2e-17 absolute (relative
-// only away from its zeros).
+// instructions), at one more polynomial degree each.  The two-double pi
+// leaves an absolute error of |k| 3e-33 in r: near the multiples of pi with
+// |k| <= 16 (so throughout the polar angle's range) sin keeps its relative
+// accuracy (the extra error is below 0.12 ulp); cos is accurate to 2e-17
+// absolute (relative only away from its zeros).
 __host__ __device__ inline void sincos(double x, double* s_out, double* c_out) {
     const NearestInt n = nearest_int(x, kInvPi);
     const double k = n.k;
     double r = fma(-k, kPiHi, x);
     r = fma(-k, kPiMid, r);
-    r = fma(-k, kPiLo, r);
     const double z = r * r;
     // sin r = r + r z S(z), cos r = 1 + z C(z) on |r| <= pi/2: polynomial
     // kernels of degree 7 in z (generated by poly_coeffs.py; 3.6e-17 relative

@@ -80,9 +80,11 @@ __host__ __device__ __forceinline__ Hot hot_of(const ImageConst& c) {
 //   dp_R/dl = -dH/dR = (N R/Sigma - dN/dR / 2) / Sigma                  (61)
 //   dp_th/dl= -dH/dth = cos/Sigma [W (l/sin^2 + chi E) - chi^2 sin N/Sigma]  (62)
 // The N dSigma terms keep the full derivative of H off the constraint shell.
+// chiE and chiL are chi E and chi l, constants of the ray.
 template <int METRIC, class K, class S>
-__host__ __device__ __forceinline__ void rhs(const K& k, const S& E, const S& L, const S& R, const S& th,
-                                    const S& pR, const S& pth, S d[6]) {
+__host__ __device__ __forceinline__ void rhs_c(const K& k, const S& E, const S& L, const S& chiE,
+                                              const S& chiL, const S& R, const S& th,
+                                              const S& pR, const S& pth, S d[6]) {
     const S half(0.5), two(2.0), four(4.0);
     S s, co;
     dm::sincos(th, &s, &co);
@@ -100,19 +102,27 @@ __host__ __device__ __forceinline__ void rhs(const K& k, const S& E, const S& L,
     const S iS = Del * sinv;
     const S iD = Sig * sinv;
     const S is = SD * inv;
-    const S P = R2c * E - k.chi * L;
+    const S P = R2c * E - chiL;
     const S PiD = P * iD;
     const S Lis2 = L * is * is;
-    const S W = L * is - k.chi * E * s;
+    const S W = L * is - chiE * s;
     const S N = Del * pR * pR + pth * pth - P * PiD + W * W;
     const S dN = dDel * (pR * pR + PiD * PiD) - four * R * E * PiD;
-    d[0] = (PiD * R2c + k.chi * (L - k.chi * E * s * s)) * iS;
+    d[0] = (PiD * R2c + k.chi * (L - chiE * s * s)) * iS;
     d[1] = Del * pR * iS;
     d[2] = pth * iS;
-    d[3] = (k.chi * PiD + Lis2 - k.chi * E) * iS;
+    d[3] = (k.chi * PiD + Lis2 - chiE) * iS;
     const S NiS = N * iS;
     d[4] = (R * NiS - half * dN) * iS;
-    d[5] = co * iS * (W * (Lis2 + k.chi * E) - k.chi2 * s * NiS);
+    d[5] = co * iS * (W * (Lis2 + chiE) - k.chi2 * s * NiS);
+}
+
+// The same, forming chi E and chi l here (callers that evaluate many steps of
+// one ray pass them in, formed once).
+template <int METRIC, class K, class S>
+__host__ __device__ __forceinline__ void rhs(const K& k, const S& E, const S& L, const S& R, const S& th,
+                                    const S& pR, const S& pth, S d[6]) {
+    rhs_c<METRIC>(k, E, L, S(k.chi * E), S(k.chi * L), R, th, pR, pth, d);
 }
 
 // ------------------------------------------------ Dormand-Prince 5(4) tableau
@@ -187,13 +197,22 @@ struct Ray {
     double y[6];    // T, R, theta, phi, p_R, p_theta
     double k1[6];   // f(y), first-same-as-last
     double I, kI;   // thick disc: intensity so far and g^3 j at y (THICK attempts only)
-    double E, L;
+    double E, L, chiE, chiL;
     double h, lam, last_cross;
     double rc[3];   // radii of the first three trusted crossings
     int32_t attempts, ncross;
     int32_t after_reject;
     int64_t pix;
 };
+
+// E and l of a ray, with the products chi E and chi l that its steps use:
+// every writer of a ray's constants of motion goes through here.
+__host__ __device__ __forceinline__ void set_constants(double chi, double E, double L, Ray& r) {
+    r.E = E;
+    r.L = L;
+    r.chiE = chi * E;
+    r.chiL = chi * L;
+}
 
 // Pixel index of the p-th pixel of an nx x ny screen in tile order: tiles of
 // tw x th pixels, taken row by row; pixels inside a tile row by row; tiles on
@@ -265,7 +284,9 @@ __host__ __device__ __forceinline__ void photon_constants(const ImageConst& c, c
 template <int METRIC>
 __host__ __device__ __forceinline__ void start_ray_dir(const ImageConst& c, const Hot& k,
                                                        const ScreenDir& n, int64_t pix, Ray& r) {
-    photon_constants(c, n, r.E, r.L);
+    double E, L;
+    photon_constants(c, n, E, L);
+    set_constants(k.chi, E, L, r);
     r.y[0] = 0.0;
     r.y[1] = c.r_obs;
     r.y[2] = c.incl;
@@ -492,7 +513,7 @@ __host__ __device__ __forceinline__ int32_t attempt(const Hot& k, const OutPtrs&
     }
 #define RT_STAGE(expr, out)                                                      \
     for (int i = 0; i < 6; ++i) t[i] = r.y[i] + h * (expr);                       \
-    rhs<METRIC>(k, r.E, r.L, t[1], t[2], t[4], t[5], out);
+    rhs_c<METRIC>(k, r.E, r.L, r.chiE, r.chiL, t[1], t[2], t[4], t[5], out);
 #define RT_ACC(bb, ee, dd, kv)                                                   \
     for (int i = 0; i < 6; ++i) {                                                \
         ab[i] += bb * kv[i];                                                     \
@@ -522,7 +543,7 @@ __host__ __device__ __forceinline__ int32_t attempt(const Hot& k, const OutPtrs&
 #undef RT_ACC_I
     double yn[6];
     for (int i = 0; i < 6; ++i) yn[i] = r.y[i] + h * ab[i];
-    rhs<METRIC>(k, r.E, r.L, yn[1], yn[2], yn[4], yn[5], kk);   // k7 (first-same-as-last)
+    rhs_c<METRIC>(k, r.E, r.L, r.chiE, r.chiL, yn[1], yn[2], yn[4], yn[5], kk);   // k7 (first-same-as-last)
     double acc = 0.0;
     for (int i = 0; i < 6; ++i) {
         ae[i] += e7 * kk[i];

@@ -225,8 +225,7 @@ __device__ __forceinline__ int32_t attempt32(const Hot32& k, const OutPtrs& o, i
 // The binary64 ray at a binary32 ray's current state (all but k1).
 __device__ __forceinline__ void widen(const ImageConst& c, const Ray32& r, Ray& w) {
     const ScreenDir n = screen_dir(c, r.pix);
-    w.E = c.obs_N - c.obs_gTph_over_sq_gphph * n.nph;
-    w.L = c.obs_sq_gphph * n.nph;
+    ray::set_constants(c.chi, c.obs_N - c.obs_gTph_over_sq_gphph * n.nph, c.obs_sq_gphph * n.nph, w);
     for (int i = 0; i < 6; ++i) w.y[i] = wide(r.hi[i], r.lo[i]);
     w.h = static_cast<double>(r.h);
     w.lam = r.lam;
@@ -285,8 +284,7 @@ __device__ __forceinline__ void load_record(const ImageConst& c, const Hot& k64,
     w.rc[0] = rec[9];
     w.rc[1] = rec[10];
     w.rc[2] = rec[11];
-    w.E = rec[12];
-    w.L = rec[13];
+    ray::set_constants(k64.chi, rec[12], rec[13], w);
     w.attempts = static_cast<int32_t>(rec[14]);
     w.ncross = static_cast<int32_t>(rec[15]);
     w.after_reject = static_cast<int32_t>(rec[16]);

@@ -101,8 +101,7 @@ __host__ __device__ __forceinline__ int32_t load_checkpoint(const double* slot, 
     r.attempts = static_cast<int32_t>(g.x);
     r.after_reject = static_cast<int32_t>(h.x);
     r.ncross = static_cast<int32_t>(h.y);
-    r.E = E;
-    r.L = L;
+    set_constants(k.chi, E, L, r);
     r.pix = pix;
     rhs<METRIC>(k, E, L, r.y[1], r.y[2], r.y[4], r.y[5], r.k1);
     return static_cast<int32_t>(g.y);

@@ -99,8 +99,7 @@ void step_case(const double* a, std::vector<double>& out) {
 
     ray::Ray r;
     std::memset(&r, 0, sizeof r);
-    r.E = E;
-    r.L = L;
+    ray::set_constants(k.chi, E, L, r);
     r.y[1] = x[0];
     r.y[2] = x[1];
     r.y[4] = x[2];

@@ -43,8 +43,7 @@ void ray_case(const double* a, std::vector<double>& out) {
     bad.chi = std::nan("");
     ray::Ray r;
     std::memset(&r, 0, sizeof r);
-    r.E = a[5];
-    r.L = a[6];
+    ray::set_constants(good.chi, a[5], a[6], r);
     r.y[1] = a[7];
     r.y[2] = a[8];
     r.y[4] = a[9];

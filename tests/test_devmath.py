@@ -57,6 +57,21 @@ def test_sincos(driver):
     assert ulp_err(out[big, 0], [e for e, b in zip(es, big) if b]).max() < 4
 
 
+def test_sincos_near_multiples_of_pi(driver):
+    # the doubles nearest k pi and their neighbours, |k| <= 16: sin must keep
+    # its relative accuracy where it is tiny (pi is carried as two doubles)
+    x = []
+    for k in range(-16, 17):
+        if k == 0:
+            continue
+        c = float(k * mp.pi)
+        x += [np.nextafter(c, -np.inf), c, np.nextafter(c, np.inf)]
+    x = np.array(x)
+    out = run(driver, "sincos", x).reshape(-1, 2)
+    es = [mp.sin(mp.mpf(v)) for v in x]
+    assert ulp_err(out[:, 0], es).max() < 4
+
+
 def test_exp(driver):
     rng = np.random.default_rng(1)
     x = np.concatenate([rng.uniform(-740, 700, 2000), rng.uniform(-1, 1, 1000),
