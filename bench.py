@@ -628,7 +628,9 @@ def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    # the GPU's clock settles over the first launches of a run (a cold first
+    # trace ~2x, then ~10 % above the steady time for another four or five)
+    ap.add_argument("--warmup", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-stride", type=int, default=1)
     ap.add_argument("--no-batch", action="store_true",

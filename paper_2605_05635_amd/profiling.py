@@ -1,13 +1,17 @@
 """Summaries of rocprofv3 output for the committed profiles.
 
     python -m paper_2605_05635_amd.profiling stats KERNEL_STATS_CSV --command CMD --out TXT
+        [--trace KERNEL_TRACE_CSV --skip N]
     python -m paper_2605_05635_amd.profiling counters COUNTER_CSV --kernel SUBSTRING
         --command CMD --out TXT
     python -m paper_2605_05635_amd.profiling traffic --fetch CSV --write CSV
         --kernel SUBSTRING --copy-bytes N --command CMD --out JSON
 
 `stats` condenses a `rocprofv3 --kernel-trace --stats --output-format csv`
-kernel_stats table (calls, total and average duration per kernel).
+kernel_stats table (calls, total and average duration per kernel); with
+`--trace KERNEL_TRACE_CSV --skip N` (the same run's kernel_trace table) it adds
+each kernel's average over its dispatches after the first N, the untimed
+warm-up launches of a bench run, while the GPU's clock settles.
 `traffic` turns two `rocprofv3 --pmc FETCH_SIZE` / `--pmc WRITE_SIZE` runs
 (KiB per dispatch) into HBM bytes per launch of one kernel, each counter
 scaled by what it reads for a plain device-to-device copy of known size run
@@ -65,6 +69,28 @@ def stats_text(path: str, command: str, top: int = 20) -> str:
     return "\n".join(lines) + "\n"
 
 
+def settled_text(trace_csv: str, skip: int, top: int = 8) -> str:
+    """Per-kernel average duration over the dispatches after the first `skip`
+    of each kernel (dispatch order), from a kernel_trace table."""
+    runs: dict[str, list[tuple[int, float]]] = {}
+    for r in _rows(trace_csv):
+        d = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-6
+        runs.setdefault(r["Kernel_Name"], []).append((int(r["Dispatch_Id"]), d))
+    rows = []
+    for name, v in runs.items():
+        v.sort()
+        kept = [d for _, d in v[skip:]]
+        if kept:
+            rows.append((sum(kept), len(kept), min(kept), max(kept), name))
+    rows.sort(key=lambda t: -t[0])
+    lines = ["", f"after the first {skip} dispatches of each kernel (from the kernel trace):",
+             f"{'calls':>6} {'avg ms':>10} {'min ms':>10} {'max ms':>10}  kernel"]
+    for tot, n, lo, hi, name in rows[:top]:
+        name = name if len(name) <= 110 else name[:107] + "..."
+        lines.append(f"{n:>6} {tot / n:>10.4f} {lo:>10.4f} {hi:>10.4f}  {name}")
+    return "\n".join(lines) + "\n"
+
+
 def _counter(path: str, name: str) -> list[tuple[str, float]]:
     return [(r["Kernel_Name"], float(r["Counter_Value"])) for r in _rows(path)
             if r["Counter_Name"] == name]
@@ -115,6 +141,8 @@ def main() -> int:
     a.add_argument("csv")
     a.add_argument("--command", required=True)
     a.add_argument("--out", required=True)
+    a.add_argument("--trace")
+    a.add_argument("--skip", type=int, default=0)
     c = sub.add_parser("counters")
     c.add_argument("csv")
     c.add_argument("--kernel", required=True)
@@ -131,6 +159,8 @@ def main() -> int:
     if args.cmd == "stats":
         with open(args.out, "w") as f:
             f.write(stats_text(args.csv, args.command))
+            if args.trace:
+                f.write(settled_text(args.trace, args.skip))
         return 0
     if args.cmd == "counters":
         with open(args.out, "w") as f:
