@@ -37,7 +37,8 @@ struct Hot {
     int32_t max_attempts;
     // thick-disc source (read by the THICK attempts only)
     int32_t taper;
-    double r_in, r_out, emis_pow, sigma_in, sigma_out, thick_rs, thick_h0, thick_h;
+    double r_in, r_out, emis_pow, thick_h0, thick_h;
+    double inv_r_in, inv_rs, tin, tout;   // 1/r_in, 1/R_s, 2/sigma_in, 2/sigma_out
 };
 
 __host__ __device__ __forceinline__ Hot hot_of(const ImageConst& c) {
@@ -57,11 +58,12 @@ __host__ __device__ __forceinline__ Hot hot_of(const ImageConst& c) {
     k.r_in = c.r_in;
     k.r_out = c.r_out;
     k.emis_pow = c.emis_pow;
-    k.sigma_in = c.sigma_in;
-    k.sigma_out = c.sigma_out;
-    k.thick_rs = c.thick_rs;
     k.thick_h0 = c.thick_h0;
     k.thick_h = c.thick_h;
+    k.inv_r_in = 1.0 / c.r_in;
+    k.inv_rs = 1.0 / c.thick_rs;
+    k.tin = 2.0 / c.sigma_in;
+    k.tout = 2.0 / c.sigma_out;
     return k;
 }
 
@@ -421,7 +423,9 @@ __host__ __device__ __forceinline__ double crossing_root(const DenseComp& d, boo
 // window of the image (tapers of eqs. (85)-(86) or hard edges); the emitter
 // moves with the circular equatorial angular velocity of eq. (91) at the same
 // R, its u^T from u.u = -1 with the metric at (R, theta) (eqs. (89)-(90)); no
-// emission where that has no solution.
+// emission where that has no solution.  The quotients go through reciprocals
+// of their denominators (g^3 = A^(3/2) (1/den)^3).  The early returns stay:
+// a branch-free version kept more values live and spilled.
 template <int METRIC>
 __host__ __device__ inline double thick_source(const Hot& k, double R, double th, double E, double L) {
     double s, co;
@@ -430,36 +434,39 @@ __host__ __device__ inline double thick_source(const Hot& k, double R, double th
     if (!(rho > 0.0)) return 0.0;
     double w;
     if (k.taper) {
-        // (1 + tanh u)/2 = 1/(1 + e^{-2u}), (1 - tanh u)/2 = 1/(1 + e^{2u}); a
-        // division, which gives 0 for an infinite e^{...} far outside the edges
-        w = (1.0 / (1.0 + dm::exp(-2.0 * (rho - k.r_in) / k.sigma_in))) *
-            (1.0 / (1.0 + dm::exp(2.0 * (rho - k.r_out) / k.sigma_out)));
+        // (1 + tanh u)/2 = 1/(1 + e^{-2u}), (1 - tanh u)/2 = 1/(1 + e^{2u}): one
+        // reciprocal of the product, 0 where it is infinite (far outside the edges)
+        const double p = (1.0 + dm::exp(-(rho - k.r_in) * k.tin)) *
+                         (1.0 + dm::exp((rho - k.r_out) * k.tout));
+        w = p < INFINITY ? rcp(p) : 0.0;
     } else {
         w = (rho >= k.r_in && rho <= k.r_out) ? 1.0 : 0.0;
     }
     if (w == 0.0) return 0.0;
     const double H = k.thick_h0 + k.thick_h * rho;
+    const double zH = z * rcp(H);
     // the three factors of eq. (84) as one exponential
-    const double j = dm::exp(-k.emis_pow * dm::log1p(rho / k.r_in - 1.0) - (rho - k.r_in) / k.thick_rs -
-                             z * z / (2.0 * H * H)) *
+    const double j = dm::exp(-k.emis_pow * dm::log1p(rho * k.inv_r_in - 1.0) -
+                             (rho - k.r_in) * k.inv_rs - 0.5 * zH * zH) *
                      w;
     double F, dF;
     mass_function<METRIC>(k, R, F, dF);
-    const double G = (dF - 2.0 * F / R) / (R * R);   // d(F/R^2)/dR
+    const double iR = rcp(R);
+    const double G = (dF - 2.0 * F * iR) * (iR * iR);   // d(F/R^2)/dR
     const double disc = -2.0 * R * G;
     if (!(disc >= 0.0)) return 0.0;
-    const double Om = (k.chi * G + sqrt(disc)) / (2.0 * R + k.chi2 * G);
-    const double Sig = R * R + k.chi2 * co * co;
+    const double Om = (k.chi * G + sqrt(disc)) * rcp(2.0 * R + k.chi2 * G);
+    const double FiS = F * rcp(R * R + k.chi2 * co * co);   // F/Sigma
     const double s2 = s * s;
-    const double gTT = -(1.0 - F / Sig);
-    const double gTph = -F * k.chi * s2 / Sig;
-    const double gphph = (R * R + k.chi2 + F * k.chi2 * s2 / Sig) * s2;
+    const double gTT = -(1.0 - FiS);
+    const double gTph = -FiS * k.chi * s2;
+    const double gphph = (R * R + k.chi2 + FiS * k.chi2 * s2) * s2;
     const double A = -(gTT + 2.0 * Om * gTph + Om * Om * gphph);
     if (!(A > 0.0)) return 0.0;
     const double den = E - Om * L;
     if (!(den > 0.0)) return 0.0;
-    const double g = sqrt(A) / den;
-    return g * g * g * j;
+    const double id = rcp(den);
+    return A * sqrt(A) * (id * id * id) * j;
 }
 
 // A thick-disc ray: as start_ray, with I = 0 and its source at the start.
