@@ -11,7 +11,8 @@
 kernel_stats table (calls, total and average duration per kernel); with
 `--trace KERNEL_TRACE_CSV --skip N` (the same run's kernel_trace table) it adds
 each kernel's average over its dispatches after the first N, the untimed
-warm-up launches of a bench run, while the GPU's clock settles.
+warm-up launches of a bench run, while the GPU's clock settles, and each
+kernel's launch resources.
 `traffic` turns two `rocprofv3 --pmc FETCH_SIZE` / `--pmc WRITE_SIZE` runs
 (KiB per dispatch) into HBM bytes per launch of one kernel, each counter
 scaled by what it reads for a plain device-to-device copy of known size run
@@ -91,6 +92,26 @@ def settled_text(trace_csv: str, skip: int, top: int = 8) -> str:
     return "\n".join(lines) + "\n"
 
 
+def resources_text(trace_csv: str, top: int = 8) -> str:
+    """Per-kernel launch resources as the kernel trace records them (register
+    counts as rocprofv3 reports them, LDS and scratch bytes, workgroup and grid
+    sizes) and the wavefronts per SIMD the grid puts on a 256-CU, 4-SIMD
+    device when every workgroup is resident at once (the persistent kernels)."""
+    seen: dict[str, dict] = {}
+    for r in _rows(trace_csv):
+        seen.setdefault(r["Kernel_Name"], r)
+    lines = ["", "launch resources (from the kernel trace; waves/SIMD = grid wavefronts / 1024 SIMDs):",
+             f"{'VGPR':>5} {'SGPR':>5} {'LDS B':>7} {'scratch':>8} {'wg':>5} {'grid':>9} "
+             f"{'waves/SIMD':>10}  kernel"]
+    for name, r in list(seen.items())[:top]:
+        grid = int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"])
+        name = name if len(name) <= 90 else name[:87] + "..."
+        lines.append(f"{r['VGPR_Count']:>5} {r['SGPR_Count']:>5} {r['LDS_Block_Size']:>7} "
+                     f"{r['Scratch_Size']:>8} {r['Workgroup_Size_X']:>5} {grid:>9} "
+                     f"{grid / 64 / 1024:>10.2f}  {name}")
+    return "\n".join(lines) + "\n"
+
+
 def _counter(path: str, name: str) -> list[tuple[str, float]]:
     return [(r["Kernel_Name"], float(r["Counter_Value"])) for r in _rows(path)
             if r["Counter_Name"] == name]
@@ -161,6 +182,7 @@ def main() -> int:
             f.write(stats_text(args.csv, args.command))
             if args.trace:
                 f.write(settled_text(args.trace, args.skip))
+                f.write(resources_text(args.trace))
         return 0
     if args.cmd == "counters":
         with open(args.out, "w") as f:
