@@ -125,6 +125,36 @@ def batch_64(einasto_extremal_spin, seed: int = 5, n_images: int = 64) -> list[d
     return out
 
 
+def random_small_images(seed: int, n: int) -> list[dict]:
+    """n small screens (5-14 x 4-12 pixels, possibly off-centre) with seeded
+    draws over the parameter space: metric, spin in [-0.9, 0.9] (below every
+    halo's extremal spin for these halo ranges), inclination in [3, 177] deg,
+    observer radius in [300, 1000], tolerance 10^U[-10, -6], emission window,
+    exponent and tapers; Einasto lambda_E in [0.10, 0.18], cored-NFW eta in
+    [0, 0.3] and lambda_c in [3, 20]."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n):
+        m = METRICS[int(rng.integers(3))]
+        halo = ((float(rng.uniform(0.10, 0.18)), 0.0) if m == "einasto" else
+                (float(rng.uniform(0.0, 0.3)), float(rng.uniform(3.0, 20.0))) if m == "cnfw" else
+                (0.0, 0.0))
+        half = float(rng.uniform(4.0, 15.0))
+        cx, cy = rng.uniform(-3.0, 3.0, size=2)
+        tol = float(10.0 ** rng.uniform(-10.0, -6.0))
+        taper = bool(rng.integers(2))
+        sig = float(rng.uniform(0.2, 1.0))
+        out.append(image(
+            metric=m, spin=float(rng.uniform(-0.9, 0.9)), halo=halo,
+            incl=math.radians(float(rng.uniform(3.0, 177.0))), r_obs=float(rng.uniform(300.0, 1000.0)),
+            nx=int(rng.integers(5, 15)), ny=int(rng.integers(4, 13)),
+            x_min=float(cx - half), x_max=float(cx + half), y_min=float(cy - half), y_max=float(cy + half),
+            rtol=tol, atol=tol, r_in=float(rng.uniform(2.0, 6.0)) if rng.integers(2) else 0.0,
+            r_out=float(rng.uniform(12.0, 30.0)), emis_pow=float(rng.uniform(2.0, 3.5)),
+            sigma_in=sig if taper else 0.0, sigma_out=sig if taper else 0.0))
+    return out
+
+
 def uv_points(seed: int, k: int = 2000) -> np.ndarray:
     """k seeded (u, v) baselines [cycles/M]: |q| ~ U[0, 0.5], angle ~ U[0, 2 pi)."""
     rng = np.random.default_rng(seed)

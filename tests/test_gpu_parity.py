@@ -75,6 +75,18 @@ def test_ragged_screens(rt, orc, img):
     say(summary(g, o))
 
 
+@pytest.mark.parametrize("k", range(16))
+def test_random_configurations(rt, orc, k):
+    """Seeded draws over metrics, spins (prograde and retrograde),
+    inclinations, observer radii, tolerances and emission windows: every
+    pixel at the parity bar."""
+    img = W.random_small_images(21, 16)[k]
+    say(f"[parity] random {k}: incl {math.degrees(img['incl']):.1f} deg, r_obs {img['r_obs']:.0f}, "
+        f"tol {img['rtol']:.1e}, halo {img['halo']}, taper {img['sigma_in']:.2f}")
+    g, o = run_full(rt, orc, img)
+    assert_parity(g, o)
+
+
 @pytest.mark.parametrize("img", [
     W.image(metric="kerr", spin=0.5, incl=math.radians(17), nx=1, ny=97, y_min=-10, y_max=10),
     W.image(metric="kerr", spin=0.0, incl=math.radians(60), nx=1, ny=64),
