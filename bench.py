@@ -155,12 +155,26 @@ def batch_measurement(steps: int) -> dict:
     rt.rt_set_launch_config(reset=True)
     attempts = sum(o["attempts"].double().sum().item() for o in outs)
     log(f"batch: trace {trace_ms:.2f} ms, visibilities {dft_ms:.2f} ms per batch")
+    # the trace's algorithmic flops, as for the single-image trace kernel, per image's metric
+    from paper_2605_05635_amd import census
+    trace_flops = 0.0
+    for img, o in zip(imgs, outs):
+        m, n = img["metric"], img["nx"] * img["ny"]
+        trace_flops += (o["attempts"].double().sum().item()
+                        * (6 * census.flops_rhs(m) + census.flops_step_overhead())
+                        + o["ncross"].double().sum().item() * census.flops_crossing()
+                        + n * (20 + census.flops_rhs(m)))
+    trace_tflops = trace_flops / (trace_ms * 1e-3) / 1e12
     # the visibility contraction: 2 K nx ny complex-by-real multiply-adds = 4 K nx ny flops
     vis_flops = sum(4.0 * 2000 * i["nx"] * i["ny"] for i in imgs)
     vis_tflops = vis_flops / (dft_ms * 1e-3) / 1e12
     return {"workload": "64 images, res in {128..768}^2, mixed metrics, one launch; "
                         "2000 (u,v) visibility amplitudes per image (one batched call)",
             "rays": rays, "steps": steps, "trace_ms": trace_ms, "visibility_ms": dft_ms,
+            "trace_roofline": {"bound": "alu", "achieved": trace_tflops,
+                               "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                               "frac": trace_tflops / FP64_VECTOR_PEAK_TFLOPS,
+                               "flops": trace_flops, "kernel": "trace_batch_kernel"},
             "visibility_roofline": {"bound": "alu", "achieved": vis_tflops,
                                     "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                                     "frac": vis_tflops / FP64_VECTOR_PEAK_TFLOPS,
