@@ -339,6 +339,9 @@ int setup_image(const rt_image_params* p, int index, bool emission, rt::ImageCon
     c->sigma_in = p->sigma_in;
     c->sigma_out = p->sigma_out;
     c->taper = (p->sigma_in > 0.0 && p->sigma_out > 0.0) ? 1 : 0;
+    c->inv_r_in = 1.0 / c->r_in;
+    c->tin = c->taper ? 2.0 / p->sigma_in : 0.0;
+    c->tout = c->taper ? 2.0 / p->sigma_out : 0.0;
     c->emission = emission ? 1 : 0;
     return RT_OK;
 }
@@ -993,6 +996,7 @@ int rt_trace_thick(const rt_image_params* params, const rt_thick_disc* thick,
     int rc = setup_image(params, 0, true, &c, nullptr);
     if (rc != RT_OK) return rc;
     c.thick_rs = thick->r_scale;
+    c.inv_thick_rs = 1.0 / thick->r_scale;
     c.thick_h0 = thick->h0;
     c.thick_h = thick->h_slope;
     const rt_image_out& o = *out;

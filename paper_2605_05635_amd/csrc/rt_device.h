@@ -60,6 +60,9 @@ struct ImageConst {
     int32_t ex_near;
     // thick disc (Sec. 5.1): radial scale R_s and height H = H_0 + h rho of eqs. (84)-(85)
     double thick_rs, thick_h0, thick_h;
+    // the thick-disc source's divisors inverted on the host: 1/r_in, 1/R_s,
+    // 2/sigma_in and 2/sigma_out (the last two 0 without tapers)
+    double inv_r_in, inv_thick_rs, tin, tout;
 };
 
 // e^x - 1 of the cored-NFW exponent: in binary64 by the kernel of the near

@@ -60,10 +60,10 @@ __host__ __device__ __forceinline__ Hot hot_of(const ImageConst& c) {
     k.emis_pow = c.emis_pow;
     k.thick_h0 = c.thick_h0;
     k.thick_h = c.thick_h;
-    k.inv_r_in = 1.0 / c.r_in;
-    k.inv_rs = 1.0 / c.thick_rs;
-    k.tin = 2.0 / c.sigma_in;
-    k.tout = 2.0 / c.sigma_out;
+    k.inv_r_in = c.inv_r_in;
+    k.inv_rs = c.inv_thick_rs;
+    k.tin = c.tin;
+    k.tout = c.tout;
     return k;
 }
 

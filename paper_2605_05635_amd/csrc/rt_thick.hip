@@ -8,25 +8,42 @@ namespace {
 
 using namespace ray;
 
+// The image's constants reloaded from the kernel-argument segment (scalar
+// loads through the scalar cache) where they are used, instead of held in
+// scalar registers across the step loop: the thick attempt needs those
+// registers for its own constants (held, ~90 scalar registers spilled into
+// vector-register lanes, a tenth of its vector instructions reading them
+// back).  The empty asm hides the pointer's value from the compiler, so the
+// loads stay where they are written.  `c`, the kernel's first argument, sits
+// at the segment's start.
+__device__ __forceinline__ const ImageConst& reloaded_args() {
+    const ImageConst* q = (const ImageConst*)__builtin_amdgcn_kernarg_segment_ptr();
+    asm volatile("" : "+s"(q));
+    return *q;
+}
+
 template <int METRIC>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 8))) void trace_thick_kernel(
     ImageConst c, OutPtrs o, unsigned long long* queue, LaunchShape shape) {
-    const Hot k = hot_of(c);
     Ray r;
     bool active = false, exhausted = false;
     int64_t next = 0, end = 0;
     TileClaim tc{0, 0, 1, 1.0f};
-    auto claim = [&]() { return claim_screen(shape, c.nx, c.ny, queue, next, end, tc); };
+    auto claim = [&]() {
+        const ImageConst& a = reloaded_args();
+        return claim_screen(shape, a.nx, a.ny, queue, next, end, tc);
+    };
     auto take = [&](int64_t ordinal) {
-        start_ray_thick<METRIC>(c, k, claimed_pixel(shape, c.nx, c.ny, tc, ordinal), r);
+        const ImageConst& a = reloaded_args();
+        start_ray_thick<METRIC>(a, hot_of(a), claimed_pixel(shape, a.nx, a.ny, tc, ordinal), r);
     };
     for (;;) {
         if (!exhausted) refill(active, exhausted, next, end, claim, take);
         if (__ballot(active) == 0ull) break;
         if (active) {
-            const int32_t st = attempt<METRIC, StageNone, true>(k, o, c.n_pix, r);
+            const int32_t st = attempt<METRIC, StageNone, true>(hot_of(reloaded_args()), o, c.n_pix, r);
             if (st != 0) {
-                finish_ray(c, o, r, st);
+                finish_ray(reloaded_args(), o, r, st);
                 o.intensity[r.pix] = r.I;
                 active = false;
             }
