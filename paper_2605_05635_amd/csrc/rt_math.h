@@ -81,6 +81,9 @@ __host__ __device__ inline double recip(double x) {
 __host__ __device__ inline double recip1(double x) {
 #if defined(__HIP_DEVICE_COMPILE__)
     const double r = __builtin_amdgcn_rcp(x);
+#elif defined(RT_HOST_RECIP1_ESTIMATE_ERROR)
+    // host test builds: a starting estimate with the hardware estimate's error
+    const double r = (1.0 / x) * (1.0 + RT_HOST_RECIP1_ESTIMATE_ERROR);
 #else
     const double r = 1.0 / x;
 #endif

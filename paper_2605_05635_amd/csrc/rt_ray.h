@@ -216,30 +216,54 @@ __host__ __device__ __forceinline__ void set_constants(double chi, double E, dou
     r.chiL = chi * L;
 }
 
+// floor(a / b) for 0 <= a < 2^31 and 1 <= b < 2^31 without an integer
+// division (which the GPU emulates in about 25 instructions): (a + 1/2)/b lies
+// at least 1/(2b) from an integer, and its binary64 value through the
+// one-Newton-step reciprocal (2.3e-15 relative) is within (a + 1/2) 2.3e-15 / b
+// of it, below 1/(2b) for every a < 2^31.
+__host__ __device__ __forceinline__ int32_t quotient(int32_t a, int32_t b) {
+    return static_cast<int32_t>((static_cast<double>(a) + 0.5) * dm::recip1(static_cast<double>(b)));
+}
+
+// The two ways of dividing the screen indices: integer division, and
+// quotient() (fewer instructions, a few more registers: the batched kernel,
+// whose lanes start rays of any image, takes it; in the single-image kernel it
+// cost more in spills than it saved).
+struct IntQuotient {
+    __host__ __device__ int32_t operator()(int32_t a, int32_t b) const { return a / b; }
+};
+struct FpQuotient {
+    __host__ __device__ int32_t operator()(int32_t a, int32_t b) const { return quotient(a, b); }
+};
+
 // Pixel index of the p-th pixel of an nx x ny screen in tile order: tiles of
 // tw x th pixels, taken row by row; pixels inside a tile row by row; tiles on
 // the right and bottom edges are clipped to the screen.  tw = nx, th = 1 is
-// plain row-major order.  A bijection of [0, nx ny).
-__device__ __forceinline__ int64_t tile_pixel(int64_t p64, int32_t nx, int32_t ny, int32_t tw,
-                                              int32_t th) {
+// plain row-major order.  A bijection of [0, nx ny) for 1 <= tw <= nx and
+// 1 <= th <= ny (the launch clamps the tile to the screen).
+template <class Q = IntQuotient>
+__host__ __device__ __forceinline__ int64_t tile_pixel(int64_t p64, int32_t nx, int32_t ny,
+                                                       int32_t tw, int32_t th, Q div = Q{}) {
     // 32-bit index arithmetic: screens hold fewer than 2^31 pixels
     const int32_t p = static_cast<int32_t>(p64);
     const int32_t band = th * nx;                  // pixels per full tile row
-    const int32_t r = p / band;                    // tile row
+    const int32_t r = div(p, band);                // tile row
     const int32_t h = (r + 1) * th <= ny ? th : ny - r * th;
     const int32_t q = p - r * band;                // index inside the tile row
-    const int32_t full = nx / tw;                  // unclipped tiles per row
-    const int32_t j = q / (tw * h);
+    const int32_t full = div(nx, tw);              // unclipped tiles per row
+    const int32_t j = div(q, tw * h);
     int32_t ix, iy;
     if (j < full) {
         const int32_t off = q - j * tw * h;
-        iy = r * th + off / tw;
-        ix = j * tw + off % tw;
+        const int32_t oy = div(off, tw);
+        iy = r * th + oy;
+        ix = j * tw + (off - oy * tw);
     } else {
         const int32_t w = nx - full * tw;
         const int32_t off = q - full * tw * h;
-        iy = r * th + off / w;
-        ix = full * tw + off % w;
+        const int32_t oy = div(off, w);
+        iy = r * th + oy;
+        ix = full * tw + (off - oy * w);
     }
     return static_cast<int64_t>(iy) * nx + ix;
 }

@@ -109,11 +109,15 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
         const ImageConst& c = lt[img];
         metric = (c.metric == CNFW && c.ex_near) ? CNFW_NEAR : c.metric;
         k = hot_of(c);
-        const int64_t pix = tile_pixel(ordinal, c.nx, c.ny, shape.tile_w, shape.tile_h);
-        if (metric == CNFW_NEAR) start_ray<CNFW_NEAR>(c, k, pix, r);
-        else if (metric == CNFW) start_ray<CNFW>(c, k, pix, r);
-        else if (metric == EINASTO) start_ray<EINASTO>(c, k, pix, r);
-        else start_ray<KERR>(c, k, pix, r);
+        // (the pixel's row and column by quotient(): no integer division)
+        Pixel px;
+        px.pix = tile_pixel(ordinal, c.nx, c.ny, shape.tile_w, shape.tile_h, FpQuotient{});
+        px.iy = quotient(static_cast<int32_t>(px.pix), c.nx);
+        px.ix = static_cast<int32_t>(px.pix) - px.iy * c.nx;
+        if (metric == CNFW_NEAR) start_ray<CNFW_NEAR>(c, k, px, r);
+        else if (metric == CNFW) start_ray<CNFW>(c, k, px, r);
+        else if (metric == EINASTO) start_ray<EINASTO>(c, k, px, r);
+        else start_ray<KERR>(c, k, px, r);
     };
     for (;;) {
         if (!exhausted) refill(active, exhausted, next, end, claim, take);
