@@ -26,7 +26,7 @@ if ROOT not in sys.path:
 METRIC = "geodesic rays/s at 1024² (FP64 vs mixed); adjoint image-gradient ms"
 FP64_VECTOR_PEAK_TFLOPS = 78.6   # MI355X: 256 CUs x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
 FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X, packed binary32 (two FMAs per lane per cycle)
-HOST_THREADS = 16                # the host cores one GPU of the box comes with
+HOST_THREADS = 16                # host threads the CPU baseline uses at most (one GPU's share of the host)
 
 
 def log(msg: str) -> None:
@@ -668,7 +668,7 @@ def main() -> int:
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: the ray tracer runs on a single MI355X "
-              "(rays are independent; see DESIGN.md for how the screen would shard)",
+              "(rays are independent: across GPUs the screen's tiles would be split)",
               file=sys.stderr)
         return 2
 

@@ -19,7 +19,7 @@
 // State of a ray: y = (T, R, theta, phi, p_R, p_theta); E = -p_T and
 // l = p_phi are constants of motion (Sec. 3.1, eq. (48)).
 //
-// Readings where the paper is silent (each is listed in the design doc):
+// Readings where the paper is silent:
 //  * integrator: Dormand-Prince 5(4) with its 4th-order continuous extension
 //    (Dormand & Prince 1980; Hairer, Norsett & Wanner, Solving ODEs I, II.5-6),
 //    standard step controller (safety 0.9, factor in [0.2, 10], exponent -1/5,
