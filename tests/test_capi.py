@@ -82,6 +82,8 @@ def _err(rt, img_or_params, n=None, outs=None):
     dict(max_attempts=0), dict(x_min=1.0, x_max=1.0), dict(r_obs=15.0),
     dict(metric="einasto", halo=(0.0, 0.0)), dict(metric="cnfw", halo=(0.02, 0.0)),
     dict(metric="cnfw", halo=(-0.1, 10.0)), dict(r_in=25.0),
+    # screens of 2^31 pixels or more (pixel indices are 32-bit in the kernels)
+    dict(nx=65536, ny=32768), dict(nx=46341, ny=46341), dict(nx=2**31 - 1, ny=2),
 ])
 def test_invalid_arguments_rejected(rt, change):
     assert _err(rt, W.image(**change)) == rt.RT_ERR_ARG
