@@ -163,6 +163,24 @@ def test_cnfw_1024_sampled(rt, orc):
     assert np.isfinite(I).all() and (I >= 0).all()
 
 
+@pytest.mark.parametrize("shape", [(1_048_579, 3), (3, 1_048_579)])
+def test_long_thin_screens_sampled(rt, orc, shape):
+    """Screens of 3.1 M pixels, one side 2^20 + 3 and the other 3 (ragged
+    tiles clamped to the short side), sampled against the oracle."""
+    nx, ny = shape
+    wide = nx > ny
+    img = dict(W.cnfw_1024(), nx=nx, ny=ny,
+               x_min=-10.0 if wide else -0.4, x_max=10.0 if wide else 0.4,
+               y_min=-0.4 if wide else -10.0, y_max=0.4 if wide else 10.0)
+    g, o, outs = _sampled(rt, orc, img, 400, 41 if wide else 43)
+    assert_parity(g, o)
+    say(summary(g, o))
+    st = outs["status"].cpu().numpy()
+    assert set(np.unique(st).tolist()) <= {1, 2}
+    I = outs["intensity"].cpu().numpy()
+    assert np.isfinite(I).all() and (I >= 0).all()
+
+
 def test_reduce_flux_centroid(rt, orc):
     img = W.image(metric="einasto", spin=0.9, halo=(0.14, 0.0), incl=math.radians(60),
                   nx=96, ny=80, x_min=-10, x_max=10, y_min=-10, y_max=10)
