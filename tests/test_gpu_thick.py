@@ -35,16 +35,16 @@ def say(msg):
     sys.stdout.flush()
 
 
-def check(rt, orc, img, idx=None):
+def check(rt, orc, img, idx=None, thick=THICK, emitting=True):
     import torch
-    outs = rt.trace_thick(img, *THICK)
+    outs = rt.trace_thick(img, *thick)
     torch.cuda.synchronize()
     I = outs["intensity"].cpu().numpy().ravel()
     st = outs["status"].cpu().numpy().ravel()
     att = outs["attempts"].cpu().numpy().ravel()
     if idx is None:
         idx = np.arange(img["nx"] * img["ny"])
-    o = orc.trace_thick_pixels(img, THICK, idx)
+    o = orc.trace_thick_pixels(img, thick, idx)
     assert np.array_equal(st[idx], o["status"])
     same = att[idx] == o["attempts"]
     assert same.mean() >= 0.97
@@ -54,7 +54,8 @@ def check(rt, orc, img, idx=None):
     assert np.all(Ig[same & (Io == 0)] == 0)
     scale = max(np.abs(Io).max(), 1e-300)
     assert np.abs(Ig[~same] - Io[~same]).max(initial=0.0) <= 1e-6 * scale
-    assert Io.max() > 0.0 and nz.sum() >= 0.1 * len(idx)
+    if emitting:
+        assert Io.max() > 0.0 and nz.sum() >= 0.1 * len(idx)
     return I, o
 
 
@@ -77,3 +78,32 @@ def test_thick_bench_screen_sampled(rt, orc):
     say(f"[thick] cnfw 1024^2: {len(idx)} sampled pixels")
     I, o = check(rt, orc, img, idx)
     assert np.all(I >= -1e-12)
+
+
+# Degenerate screens, a retrograde spin and other disc shapes: a constant
+# scale height (h = 0), a thin flaring disc, a thick short one.
+@pytest.mark.parametrize("label,img,thick,emitting", [
+    ("1x1 centre", W.image(metric="cnfw", spin=0.94, halo=(0.02, 10.0), nx=1, ny=1,
+                           x_min=-0.1, x_max=0.1, y_min=-0.1, y_max=0.1, emis_pow=2.0), THICK, False),
+    ("1x37 column", W.image(metric="kerr", spin=0.5, incl=math.radians(60), nx=1, ny=37,
+                            x_min=2.0, x_max=2.5, y_min=-12.0, y_max=12.0, emis_pow=2.0), THICK, True),
+    ("41x1 row", W.image(metric="einasto", spin=0.9, halo=(0.15, 0.0), incl=math.radians(80),
+                         nx=41, ny=1, x_min=-12.0, x_max=12.0, y_min=0.3, y_max=0.8,
+                         emis_pow=2.0), THICK, True),
+    ("retrograde", W.image(metric="kerr", spin=-0.7, incl=math.radians(45), nx=19, ny=17,
+                           x_min=-10.0, x_max=10.0, y_min=-9.0, y_max=9.0, emis_pow=3.0),
+     THICK, True),
+    ("constant height", W.image(metric="cnfw", spin=0.6, halo=(0.1, 5.0), incl=math.radians(75),
+                                nx=21, ny=19, x_min=-10.0, x_max=10.0, y_min=-9.0, y_max=9.0,
+                                emis_pow=2.0), (4.0, 0.5, 0.0), True),
+    ("thin flaring", W.image(metric="kerr", spin=0.9, incl=math.radians(85), nx=23, ny=15,
+                             x_min=-12.0, x_max=12.0, y_min=-6.0, y_max=6.0, emis_pow=1.5,
+                             sigma_in=0.5, sigma_out=1.0), (20.0, 0.05, 0.3), True),
+])
+def test_thick_edge_cases(rt, orc, label, img, thick, emitting):
+    say(f"[thick] {label}: {img['nx']}x{img['ny']}, (R_s, H_0, h) = {thick}")
+    I, o = check(rt, orc, img, thick=thick, emitting=emitting)
+    # I is integrated under error control (atol on each step), so a ray that
+    # meets only a narrow sliver of the source can end a tolerance-level amount
+    # below zero, the oracle's alike (the check above holds it to the oracle)
+    assert I.min() >= -100.0 * img["atol"]
