@@ -35,7 +35,8 @@ def log(msg: str) -> None:
 
 def measured_traffic(kernel_hash: str):
     """HBM bytes per launch from the committed rocprofv3 counter summary, or None
-    when it is missing or was taken on a different kernel source."""
+    when it is missing or was taken on different kernel code (comments and
+    layout aside)."""
     path = os.path.join(ROOT, "profiles", "trace_kernel_cnfw_1024_traffic.json")
     if not os.path.exists(path):
         return None

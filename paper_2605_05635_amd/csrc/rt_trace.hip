@@ -27,8 +27,8 @@ namespace {
 
 using namespace ray;
 
-// The register allocation aims at three waves per SIMD (168 VGPRs; the cored
-// NFW spills two): measured 5-10 % faster than two.
+// The register allocation aims at three waves per SIMD (at most 168 VGPRs;
+// the cored NFW spills three values): measured 5-10 % faster than two.
 constexpr int kTraceWaves = 3;
 
 
@@ -63,7 +63,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kTraceWa
 // images (images ordered by metric, so a wavefront's lanes share a metric
 // except at the two metric boundaries).  Each lane keeps its image index and
 // the step-loop constants of that image in registers.  Register-allocated for
-// three waves per SIMD (168 VGPRs, 23 spilled): 5 % faster than two.
+// three waves per SIMD (167 VGPRs, 21 values spilled): 5 % faster than two.
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) void trace_batch_kernel(
     const ImageConst* __restrict__ table, const OutPtrs* __restrict__ outs,
     const int64_t* __restrict__ chunk_start, int32_t n_images, unsigned long long* queue,

@@ -33,12 +33,40 @@ TRACE_SOURCES = ("rt_trace.hip", "rt_ray.h", "rt_device.h", "rt_math.h", "rt_dua
                  "rt_kernels.h")
 
 
+def code_tokens(text: str) -> str:
+    """C++ source without its comments, its whitespace runs collapsed to one
+    space: what the compiler sees, so that an edit of comments or layout
+    keeps the hash (string and character literals are kept as written)."""
+    out = []
+    i, n = 0, len(text)
+    while i < n:
+        c = text[i]
+        if text.startswith("//", i):
+            j = text.find("\n", i)
+            i = n if j < 0 else j
+        elif text.startswith("/*", i):
+            j = text.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+            out.append(" ")
+        elif c in "\"'":
+            j = i + 1
+            while j < n and text[j] != c:
+                j += 2 if text[j] == "\\" else 1
+            out.append(text[i:j + 1])
+            i = j + 1
+        else:
+            out.append(c)
+            i += 1
+    return " ".join("".join(out).split())
+
+
 def trace_source_hash() -> str:
-    """Hash of the sources the single-image trace kernel is compiled from."""
+    """Hash of the code (comments and layout aside) of the sources the
+    single-image trace kernel is compiled from."""
     h = hashlib.sha256()
     for name in TRACE_SOURCES:
-        with open(os.path.join(PKG, "csrc", name), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(PKG, "csrc", name), encoding="utf-8") as f:
+            h.update(code_tokens(f.read()).encode())
     return h.hexdigest()[:16]
 
 
