@@ -252,6 +252,64 @@ def trace_pixels(img: dict, idx=None, threads: int | None = None, chunk: int = 6
     return out
 
 
+def trace_points(img: dict, xy, threads: int | None = None) -> dict:
+    """Trace the screen points xy ([n][2]: X, Y in units of M) of the observer
+    of img, one ray each as for a pixel centre, on `threads` host threads.
+    Returns numpy arrays indexed by point, as trace_pixels, and each ray's E
+    and l."""
+    xy = np.asarray(xy, dtype=np.float64).reshape(-1, 2)
+    n = xy.shape[0]
+    out = dict(ncross=np.zeros(n, np.int32), status=np.zeros(n, np.int32),
+               attempts=np.zeros(n, np.int32),
+               r_em=np.zeros((3, n)), phi_em=np.zeros((3, n)), t_em=np.zeros((3, n)),
+               g_em=np.zeros((3, n)), i_n=np.zeros((3, n)), intensity=np.zeros(n),
+               E=np.zeros(n), L=np.zeros(n))
+
+    def one(k: int) -> None:
+        r, _ = trace_ray(img, float(xy[k, 0]), float(xy[k, 1]))
+        out["ncross"][k], out["status"][k], out["attempts"][k] = r.ncross, r.status, r.attempts
+        out["E"][k], out["L"][k] = r.E, r.L
+        for key in ("r_em", "phi_em", "t_em", "g_em", "i_n"):
+            out[key][:, k] = list(getattr(r, key))
+        out["intensity"][k] = r.intensity
+
+    threads = threads or os.cpu_count() or 1
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        list(ex.map(one, range(n)))
+    return out
+
+
+def refine_points(img: dict, ncross, status, sub: int):
+    """Screen refinement near the lensing-band boundaries (Sec. 4: the screen
+    refined where the image classification changes; Sec. 4.2: bands by
+    N_cross).  A pixel is marked when a 4-neighbour on the screen has another
+    N_cross or another status.  Returns (pix, xy): the marked pixel indices in
+    increasing order and, pixel by pixel, the centres of its sub x sub
+    subpixels row by row, X = x_min + (ix + (a + 1/2)(1/sub)) dX (and Y alike
+    with b), dX = (x_max - x_min)/nx."""
+    nx, ny = int(img["nx"]), int(img["ny"])
+    nc = np.asarray(ncross).reshape(ny, nx).astype(np.int64)
+    st = np.asarray(status).reshape(ny, nx).astype(np.int64)
+    mark = np.zeros((ny, nx), dtype=bool)
+    for a in (nc, st):
+        d = a[:, 1:] != a[:, :-1]          # differs from the right-hand neighbour
+        mark[:, :-1] |= d
+        mark[:, 1:] |= d
+        d = a[1:, :] != a[:-1, :]          # differs from the neighbour above
+        mark[:-1, :] |= d
+        mark[1:, :] |= d
+    pix = np.flatnonzero(mark.ravel())
+    dX = (img["x_max"] - img["x_min"]) / nx
+    dY = (img["y_max"] - img["y_min"]) / ny
+    u = (np.arange(sub) + 0.5) * (1.0 / sub)
+    ix, iy = pix % nx, pix // nx
+    X = img["x_min"] + (ix[:, None, None] + u[None, None, :]) * dX
+    Y = img["y_min"] + (iy[:, None, None] + u[None, :, None]) * dY
+    X, Y = np.broadcast_arrays(X, Y)
+    xy = np.stack([X.reshape(-1), Y.reshape(-1)], axis=1)
+    return pix, xy
+
+
 def _parallel(n: int, chunk: int, threads: int | None, fn) -> None:
     starts = list(range(0, n, chunk))
     threads = threads or os.cpu_count() or 1

@@ -163,6 +163,29 @@ def uv_points(seed: int, k: int = 2000) -> np.ndarray:
     return np.stack([q * np.cos(a), q * np.sin(a)], axis=1)
 
 
+def screen_points(seed: int, n: int, half_width: float = 10.0) -> np.ndarray:
+    """n seeded screen points (X, Y) [M]: half uniform over the square
+    [-half_width, half_width]^2, half in the annulus 4 <= sqrt(X^2 + Y^2) <= 6
+    around the photon ring (where rays cross the equator more than once)."""
+    rng = np.random.default_rng(seed)
+    m = n // 2
+    sq = rng.uniform(-half_width, half_width, size=(m, 2))
+    r = np.sqrt(rng.uniform(16.0, 36.0, size=n - m))
+    a = rng.uniform(0.0, 2.0 * math.pi, size=n - m)
+    return np.concatenate([sq, np.stack([r * np.cos(a), r * np.sin(a)], axis=1)])
+
+
+def band_maps(seed: int, nx: int, ny: int, block: int = 3) -> tuple[np.ndarray, np.ndarray]:
+    """Seeded synthetic N_cross and status maps ([ny][nx] uint8) made of
+    block x block runs of equal values, so that band edges and interiors both
+    occur (inputs for the screen refinement)."""
+    rng = np.random.default_rng(seed)
+    by, bx = (ny + block - 1) // block, (nx + block - 1) // block
+    nc = np.repeat(np.repeat(rng.integers(0, 4, (by, bx)), block, 0), block, 1)[:ny, :nx]
+    st = np.repeat(np.repeat(rng.integers(1, 3, (by, bx)), block + 1, 0), block + 1, 1)[:ny, :nx]
+    return nc.astype(np.uint8), st.astype(np.uint8)
+
+
 def subsample_indices(nx: int, ny: int, stride: int, offset: int = 0) -> np.ndarray:
     """Row-major pixel indices of a strided sub-grid (every `stride`-th pixel in
     x and y), used to sample a large screen."""
