@@ -1,6 +1,6 @@
 """Throughput benchmark of the backward geodesic ray tracer on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-<leg> ...]
 
 One step = one full trace of the 1024x1024 cored-NFW screen (chi = 0.94,
 (eta, lambda_c) = (0.02, 10), theta_o = 163 deg, R_o = 1000, +-10 M, FP64
@@ -484,6 +484,67 @@ def diagnostics_measurement(steps: int, outs: dict, img: dict, cpu: bool) -> dic
     return res
 
 
+def adaptive_measurement(steps: int, outs: dict, img: dict, cpu: bool) -> dict:
+    """Adaptive screen (Sec. 4: the screen refined where the image
+    classification changes) of the bench's traced 1024x1024 image: its
+    band-edge pixels (a 4-neighbour with another N_cross or status) each
+    refined into 4 x 4 subpixels by rt_refine_points, and the subpixel rays
+    traced by rt_trace_points with their emission; HIP-event time of each call
+    on the stream."""
+    import torch
+
+    from paper_2605_05635_amd import census, rt
+    sub = 4
+    p = rt.params_from(img)
+    stream = torch.cuda.current_stream()
+    xy, pix = rt.refine_points(img, outs["ncross"], outs["status"], sub)
+    n_pts = int(xy.shape[0])
+    n_marked = torch.zeros(1, dtype=torch.int64, device="cuda")
+    pts = rt.alloc_point_outputs(n_pts)
+    o = rt.out_from(pts)
+    rt.rt_trace_points(p, xy, o, stream)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    ev[0].record(stream)
+    for _ in range(steps):
+        rt.rt_refine_points(p, outs["ncross"], outs["status"], sub, n_pts, xy, pix, n_marked, stream)
+    ev[1].record(stream)
+    for _ in range(steps):
+        rt.rt_trace_points(p, xy, o, stream)
+    ev[2].record(stream)
+    torch.cuda.synchronize()
+    refine_ms = ev[0].elapsed_time(ev[1]) / steps
+    trace_ms = ev[1].elapsed_time(ev[2]) / steps
+    att = pts["attempts"].double().sum().item()
+    crossings = pts["ncross"].double().sum().item()
+    flops = (att * (6 * census.flops_rhs(img["metric"]) + census.flops_step_overhead())
+             + crossings * census.flops_crossing()
+             + n_pts * (20 + census.flops_rhs(img["metric"])))
+    tflops = flops / (trace_ms * 1e-3) / 1e12
+    n_pix = img["nx"] * img["ny"]
+    log(f"adaptive screen: {n_pts // (sub * sub)} band-edge pixels, {n_pts} subpixel rays in "
+        f"{trace_ms:.2f} ms (refinement {refine_ms * 1e3:.0f} us)")
+    res = {"workload": "band-edge pixels of the 1024x1024 cored-NFW image, 4 x 4 subpixels each",
+            "band_edge_pixels": n_pts // (sub * sub), "subpixel_rays": n_pts,
+            "refine_us": refine_ms * 1e3, "trace_ms": trace_ms, "steps": steps,
+            "rays_per_s": n_pts / trace_ms * 1e3, "attempts_per_ray": att / max(n_pts, 1),
+            "refine_image_reads_GBps": 2.0 * n_pix / (refine_ms * 1e-3) / 1e9,
+            "trace_roofline": {"bound": "alu", "achieved": tflops, "peak": FP64_VECTOR_PEAK_TFLOPS,
+                               "unit": "TFLOP/s", "frac": tflops / FP64_VECTOR_PEAK_TFLOPS,
+                               "kernel": "trace_points_kernel"},
+            "higher_order_fraction": float((pts["ncross"] >= 2).double().mean().item())}
+    if cpu:
+        from oracle import oracle as O
+        sample = xy[::64].cpu().numpy()
+        threads = oracle_threads()
+        t0 = time.perf_counter()
+        O.trace_points(img, sample, threads=threads)
+        dt = time.perf_counter() - t0
+        res["cpu_oracle"] = {"rays_per_s": len(sample) / dt, "cores": threads, "kind": "oracle",
+                             "sample": f"every 64th subpixel ray ({len(sample)} rays, {dt:.1f} s)"}
+    return res
+
+
 def thick_measurement(steps: int, cpu: bool) -> dict:
     """Thick-disc image (Sec. 5.1-5.2) of the 1024x1024 cored-NFW screen with
     (R_s, H_0, h) = (8, 0.2, 0.1), p = 2: kernel time per image (HIP events on
@@ -662,6 +723,8 @@ def main() -> int:
                     help="skip the shadow-boundary measurement")
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the image-gradient measurement")
+    ap.add_argument("--no-adaptive", action="store_true",
+                    help="skip the adaptive-screen (band-edge refinement) measurement")
     ap.add_argument("--calibration-copy-mib", type=int, default=0,
                     help="after the timed steps, run one plain device-to-device copy of this "
                          "many MiB (the reference kernel for HBM byte counters) and report it")
@@ -747,6 +810,9 @@ def main() -> int:
         line["adjoint"] = adjoint_measurement(max(2, args.steps // 2), not args.no_cpu_baseline)
     if not args.no_diagnostics:
         line["diagnostics"] = diagnostics_measurement(args.steps, outs, img, not args.no_cpu_baseline)
+    if not args.no_adaptive:
+        line["adaptive_screen"] = adaptive_measurement(max(2, args.steps // 2), outs, img,
+                                                       not args.no_cpu_baseline)
     if not args.no_thick:
         line["thick_disc"] = thick_measurement(max(2, args.steps // 2), not args.no_cpu_baseline)
     if not args.no_scan:

@@ -255,6 +255,45 @@ int rt_image_diagnostics_noalloc(const double *intensity, const rt_image_params 
                                  double bin_width, int32_t n_bins, double *out, double *profile,
                                  void *hip_stream);
 
+/* Rays from listed screen points (the adaptive screen of Sec. 4: the screen
+ * refined where its classification changes, e.g. the subpixels that
+ * rt_refine_points lists).  Ray i starts from the point (X, Y) = (xy[2 i],
+ * xy[2 i + 1]) (units of M) of the observer of `params` and is traced exactly
+ * as a pixel of rt_trace_image (binary64, params->precision RT_FP64); the
+ * screen fields of params (nx, ny, extent) are validated but not used.
+ *   xy: device [n][2], 1 <= n < 2^31.  out: as rt_image_out with the pixel
+ *   index replaced by the point index (ncross, status, attempts, intensity
+ *   [n]; r_em, phi_em, t_em, g_em, intensity_n [3][n], NaN past
+ *   min(N_cross, 3)); any may be NULL, but an emission output (intensity,
+ *   g_em, intensity_n) needs ncross and r_em, and reduce must be NULL.
+ * Stream-ordered (a 256-byte work-queue counter allocated and freed on the
+ * stream).  RT_ERR_ARG for null params/xy/out, n out of range, precision
+ * other than RT_FP64, a non-null reduce, an emission output without ncross
+ * or r_em, or host memory. */
+int rt_trace_points(const rt_image_params *params, const double *xy, int64_t n,
+                    const rt_image_out *out, void *hip_stream);
+
+/* Screen refinement near the lensing-band boundaries (Sec. 4, the adaptive
+ * idea; Sec. 4.2, the bands labelled by N_cross): a pixel of the screen of
+ * `params` is marked when one of its 4-neighbours has another N_cross or
+ * another status in the maps ncross and status (device [ny][nx], as
+ * rt_trace_image writes them), i.e. it straddles a band edge, the shadow
+ * boundary or the critical curve.  *n_marked (device int64) receives the
+ * number of marked pixels; for the marked pixels in pixel order m = 0, 1, ...
+ * with m < max_points / sub^2: pix[m] = the pixel index (device int64 array,
+ * or NULL) and its sub x sub subpixel centres, row by row:
+ *   xy[2 (m sub^2 + b sub + a)]     = x0 + (ix + (a + 1/2) (1/sub)) dX,
+ *   xy[2 (m sub^2 + b sub + a) + 1] = y0 + (iy + (b + 1/2) (1/sub)) dY,
+ * with (x0, dX, y0, dY) the screen's origin and pixel size (sub = 1 gives the
+ * pixel centres of rt_trace_image bit for bit).  1 <= sub <= 16; xy device
+ * [max_points][2] (NULL only when max_points = 0, e.g. to count first).
+ * Stream-ordered (scratch of 8 bytes per 256 pixels allocated and freed on the
+ * stream).  RT_ERR_ARG for null params/ncross/status/n_marked, sub out of
+ * range, max_points < 0, a null xy with max_points > 0, or host memory. */
+int rt_refine_points(const rt_image_params *params, const uint8_t *ncross, const uint8_t *status,
+                     int32_t sub, int64_t max_points, double *xy, int64_t *pix,
+                     int64_t *n_marked, void *hip_stream);
+
 /* Shadow boundary (Sec. 4.1, eqs. (78)-(79)): along each screen direction
  * (cos psi, sin psi), the impact parameter b at which the rays from
  * X = b cos psi, Y = b sin psi turn from captured to escaping (a ray escapes

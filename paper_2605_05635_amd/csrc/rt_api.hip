@@ -14,6 +14,7 @@
 #include "rt.h"
 #include "rt_device.h"
 #include "rt_kernels.h"
+#include "rt_points.h"
 #include "rt_scan.h"
 
 namespace {
@@ -1068,6 +1069,85 @@ int rt_image_diagnostics_noalloc(const double* intensity, const rt_image_params*
     g_last_error.clear();
     return image_diagnostics_noalloc(intensity, params, bin_width, n_bins, out, profile,
                                      hip_stream);
+}
+
+int rt_trace_points(const rt_image_params* params, const double* xy, int64_t n,
+                    const rt_image_out* out, void* hip_stream) {
+    g_last_error.clear();
+    if (!params || !xy || !out) return fail(RT_ERR_ARG, "null params, xy or out");
+    if (n < 1 || n >= (int64_t(1) << 31)) return fail(RT_ERR_ARG, "n must lie in [1, 2^31)");
+    if (params->precision != RT_FP64)
+        return fail(RT_ERR_ARG, "screen points are traced in binary64 (precision RT_FP64)");
+    const rt_image_out& o = *out;
+    if (o.reduce) return fail(RT_ERR_ARG, "reduce is not produced for screen points");
+    const bool emission = o.intensity || o.g_em || o.intensity_n;
+    if (emission && (!o.ncross || !o.r_em))
+        return fail(RT_ERR_ARG, "the emission of screen points needs out->ncross and out->r_em");
+    rt::ImageConst c;
+    int rc = setup_image(params, 0, emission, &c, nullptr);
+    if (rc != RT_OK) return rc;
+    c.n_pix = n;
+    if ((rc = check_device_ptr(xy, "xy", 0)) || (rc = check_device_ptr(o.ncross, "ncross", 0)) ||
+        (rc = check_device_ptr(o.status, "status", 0)) || (rc = check_device_ptr(o.r_em, "r_em", 0)) ||
+        (rc = check_device_ptr(o.phi_em, "phi_em", 0)) || (rc = check_device_ptr(o.t_em, "t_em", 0)) ||
+        (rc = check_device_ptr(o.g_em, "g_em", 0)) || (rc = check_device_ptr(o.intensity, "intensity", 0)) ||
+        (rc = check_device_ptr(o.intensity_n, "intensity_n", 0)) ||
+        (rc = check_device_ptr(o.attempts, "attempts", 0)))
+        return rc;
+    const rt::OutPtrs optrs{o.ncross, o.status, o.r_em, o.phi_em, o.t_em, o.g_em, o.intensity,
+                            o.intensity_n, o.attempts};
+    DeviceInfo info;
+    if ((rc = device_info(&info)) != RT_OK) return rc;
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    void* q = nullptr;
+    hipError_t e = hipMallocAsync(&q, 256, stream);
+    if (e != hipSuccess || !q) {
+        (void)hipGetLastError();
+        return fail(RT_ERR_ALLOC, "stream-ordered allocation of the work queue failed");
+    }
+    auto* queue = static_cast<unsigned long long*>(q);
+    const int64_t want = (n + 255) / 256;
+    const int64_t resident = static_cast<int64_t>(info.cus) * rt::points_blocks_per_cu(c.metric);
+    const int32_t grid = static_cast<int32_t>(std::max<int64_t>(1, std::min(want, resident)));
+    e = rt::launch_zero(queue, 1, stream);
+    if (e == hipSuccess) e = rt::launch_trace_points(c, xy, optrs, queue, grid, stream);
+    const hipError_t ef = hipFreeAsync(q, stream);
+    if (e != hipSuccess) return hip_fail(e, "screen-point kernel launch");
+    if (ef != hipSuccess) return hip_fail(ef, "hipFreeAsync");
+    return RT_OK;
+}
+
+int rt_refine_points(const rt_image_params* params, const uint8_t* ncross, const uint8_t* status,
+                     int32_t sub, int64_t max_points, double* xy, int64_t* pix, int64_t* n_marked,
+                     void* hip_stream) {
+    g_last_error.clear();
+    if (!params || !ncross || !status || !n_marked)
+        return fail(RT_ERR_ARG, "null params, ncross, status or n_marked");
+    if (sub < 1 || sub > 16) return fail(RT_ERR_ARG, "sub must lie in [1, 16]");
+    if (max_points < 0) return fail(RT_ERR_ARG, "max_points must be >= 0");
+    if (max_points > 0 && !xy) return fail(RT_ERR_ARG, "xy is null with max_points > 0");
+    rt::ImageConst c;
+    int rc = setup_image(params, 0, false, &c, nullptr);
+    if (rc != RT_OK) return rc;
+    if ((rc = check_device_ptr(ncross, "ncross", 0)) || (rc = check_device_ptr(status, "status", 0)) ||
+        (rc = check_device_ptr(xy, "xy", 0)) || (rc = check_device_ptr(pix, "pix", 0)) ||
+        (rc = check_device_ptr(n_marked, "n_marked", 0)))
+        return rc;
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    const int64_t blocks = (c.n_pix + rt::kBlock - 1) / rt::kBlock;
+    void* mem = nullptr;
+    hipError_t e = hipMallocAsync(&mem, sizeof(int64_t) * static_cast<size_t>(blocks), stream);
+    if (e != hipSuccess || !mem) {
+        (void)hipGetLastError();
+        return fail(RT_ERR_ALLOC, "stream-ordered allocation of the refinement counts failed");
+    }
+    const int64_t per_pixel = static_cast<int64_t>(sub) * sub;
+    e = rt::launch_refine(c, ncross, status, sub, max_points / per_pixel, xy, pix, n_marked,
+                          static_cast<int64_t*>(mem), stream);
+    const hipError_t ef = hipFreeAsync(mem, stream);
+    if (e != hipSuccess) return hip_fail(e, "refinement kernel launch");
+    if (ef != hipSuccess) return hip_fail(ef, "hipFreeAsync");
+    return RT_OK;
 }
 
 int rt_shadow_boundary(const rt_image_params* params, const double* dirs, int32_t n,

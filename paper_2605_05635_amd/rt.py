@@ -100,6 +100,11 @@ def _load():
                                         C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
                                         C.c_void_p]
     lib.rt_visibility_rings.restype = C.c_int
+    lib.rt_trace_points.argtypes = [P, C.c_void_p, C.c_int64, O, C.c_void_p]
+    lib.rt_trace_points.restype = C.c_int
+    lib.rt_refine_points.argtypes = [P, C.c_void_p, C.c_void_p, C.c_int32, C.c_int64, C.c_void_p,
+                                     C.c_void_p, C.c_void_p, C.c_void_p]
+    lib.rt_refine_points.restype = C.c_int
     lib.rt_trace_thick.argtypes = [P, C.POINTER(rt_thick_disc), O, C.c_void_p]
     lib.rt_trace_thick.restype = C.c_int
     lib.rt_parameter_scan.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]
@@ -411,6 +416,67 @@ def image_diagnostics(img: dict, intensity, bin_width: float, n_bins: int, strea
     return d
 
 
+def rt_trace_points(params: rt_image_params, xy, out: rt_image_out, stream=None) -> None:
+    """Calls rt_trace_points on a device tensor xy [n][2] (f64 screen points)."""
+    n = int(xy.shape[0])
+    _check(_lib.rt_trace_points(C.byref(params), C.c_void_p(xy.data_ptr()), n, C.byref(out),
+                                _stream_handle(stream)))
+
+
+def alloc_point_outputs(n: int, device="cuda", emission: bool = True) -> dict:
+    """Device tensors for every output of n screen points."""
+    import torch
+    d = dict(ncross=torch.empty(n, dtype=torch.uint8, device=device),
+             status=torch.empty(n, dtype=torch.uint8, device=device),
+             r_em=torch.empty((3, n), dtype=torch.float64, device=device),
+             phi_em=torch.empty((3, n), dtype=torch.float64, device=device),
+             t_em=torch.empty((3, n), dtype=torch.float64, device=device),
+             attempts=torch.empty(n, dtype=torch.int32, device=device))
+    if emission:
+        d.update(g_em=torch.empty((3, n), dtype=torch.float64, device=device),
+                 intensity=torch.empty(n, dtype=torch.float64, device=device),
+                 intensity_n=torch.empty((3, n), dtype=torch.float64, device=device))
+    return d
+
+
+def trace_points(img: dict, xy, device="cuda", stream=None, emission: bool = True) -> dict:
+    """Trace the screen points xy ([n][2] f64, a device tensor or array) of the
+    observer of img; returns the outputs as device tensors indexed by point."""
+    import torch
+    xy = torch.as_tensor(xy, dtype=torch.float64, device=device).contiguous()
+    outs = alloc_point_outputs(int(xy.shape[0]), device, emission)
+    rt_trace_points(params_from(img), xy, out_from(outs), stream)
+    return outs
+
+
+def rt_refine_points(params: rt_image_params, ncross, status, sub: int, max_points: int, xy,
+                     pix, n_marked, stream=None) -> None:
+    """Calls rt_refine_points on device tensors: ncross, status [ny][nx] uint8,
+    xy [max_points][2] f64 (or None), pix int64 (or None), n_marked [1] int64."""
+    ptr = lambda t: None if t is None else C.c_void_p(t.data_ptr())  # noqa: E731
+    _check(_lib.rt_refine_points(C.byref(params), ptr(ncross), ptr(status), sub, max_points, ptr(xy),
+                                 ptr(pix), ptr(n_marked), _stream_handle(stream)))
+
+
+def refine_points(img: dict, ncross, status, sub: int, stream=None):
+    """The band-edge pixels of a traced screen and their sub x sub subpixel
+    centres: a counting call, then one that fills buffers of that size.
+    Returns (xy [n sub^2][2], pix [n]) as device tensors."""
+    import torch
+    dev = ncross.device
+    n_marked = torch.zeros(1, dtype=torch.int64, device=dev)
+    p = params_from(img)
+    nc, st = ncross.contiguous(), status.contiguous()
+    rt_refine_points(p, nc, st, sub, 0, None, None, n_marked, stream)
+    torch.cuda.synchronize()
+    n = int(n_marked.item())
+    xy = torch.empty((n * sub * sub, 2), dtype=torch.float64, device=dev)
+    pix = torch.empty(n, dtype=torch.int64, device=dev)
+    if n:
+        rt_refine_points(p, nc, st, sub, n * sub * sub, xy, pix, n_marked, stream)
+    return xy, pix
+
+
 def rt_shadow_boundary(params: rt_image_params, dirs, b_lo: float, b_hi: float, b_tol: float,
                        out, status, attempts=None, stream=None, samples: int = 64) -> None:
     """Calls rt_shadow_boundary on device tensors: dirs [n][2] f64 (cos psi,
@@ -567,6 +633,8 @@ __all__ = ["rt_mixed_stats", "rt_image_vjp", "rt_set_checkpoint_budget", "rt_vjp
            "rt_relative_deviation", "relative_to_reference",
            "rt_parameter_scan", "parameter_scan", "rt_scan_point", "einasto_extremal_spin",
            "rt_trace_thick", "trace_thick", "rt_thick_disc",
+           "rt_trace_points", "trace_points", "alloc_point_outputs", "rt_refine_points",
+           "refine_points",
            "RT_DIAG_COUNT", "RT_DIAG_NOALLOC_MAX_BINS", "DIAG_KEYS",
            "rt_version",
            "rt_last_error", "trace", "trace_many", "params_from", "out_from", "alloc_outputs",

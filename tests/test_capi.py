@@ -310,3 +310,30 @@ def test_thick_disc_argument_errors(rt):
     assert lib.rt_trace_thick(C.byref(p), C.byref(good), C.byref(o2), None) == rt.RT_ERR_ARG
     mixed = rt.params_from(W.image(precision="mixed"))
     assert lib.rt_trace_thick(C.byref(mixed), C.byref(good), C.byref(o), None) == rt.RT_ERR_ARG
+
+
+def test_screen_point_and_refinement_argument_errors(rt):
+    lib = rt.lib()
+    p = rt.params_from(W.kerr_small())
+    d = C.c_void_p(8)
+    o = rt.rt_image_out()
+    o.ncross, o.r_em = 8, 8
+    E = rt.RT_ERR_ARG
+    assert lib.rt_trace_points(None, d, 4, C.byref(o), None) == E
+    assert lib.rt_trace_points(C.byref(p), None, 4, C.byref(o), None) == E
+    assert lib.rt_trace_points(C.byref(p), d, 4, None, None) == E
+    for n in (0, -1, 2**31):
+        assert lib.rt_trace_points(C.byref(p), d, n, C.byref(o), None) == E
+    red = rt.rt_image_out()
+    red.ncross, red.r_em, red.intensity, red.reduce = 8, 8, 8, 8
+    assert lib.rt_trace_points(C.byref(p), d, 4, C.byref(red), None) == E
+    em = rt.rt_image_out()
+    em.intensity = 8                       # emission without ncross and r_em
+    assert lib.rt_trace_points(C.byref(p), d, 4, C.byref(em), None) == E
+    mixed = rt.params_from(W.image(precision="mixed"))
+    assert lib.rt_trace_points(C.byref(mixed), d, 4, C.byref(o), None) == E
+    for sub, mx, xy in ((0, 4, d), (17, 4, d), (2, -1, d), (2, 4, None)):
+        assert lib.rt_refine_points(C.byref(p), d, d, sub, mx, xy, None, d, None) == E
+    assert lib.rt_refine_points(C.byref(p), None, d, 2, 4, d, None, d, None) == E
+    assert lib.rt_refine_points(C.byref(p), d, d, 2, 4, d, None, None, None) == E
+    assert lib.rt_refine_points(None, d, d, 2, 4, d, None, d, None) == E
