@@ -196,8 +196,38 @@ bool finite_all(std::initializer_list<double> v) {
 
 // Outer horizon: the largest root of Delta (eq. (33)) in (0.05, 50]
 // (rt_scan.h).
+// The horizon search walks Delta down from R = 50 in steps of 0.01 (about
+// five thousand evaluations of the mass function, a few hundred microseconds
+// of host time), so each thread keeps the results for its last kHorizonMemo
+// spacetimes, keyed by every value Delta depends on (the same inputs give the
+// same root: the memo changes no result, only the cost of a repeated call).
+struct HorizonMemo {
+    int32_t metric;
+    double chi2, inv_lam, lam_c, inv_lam_c, eta_lc;
+    bool found;
+    double r_plus;
+};
+constexpr int kHorizonMemo = 16;
+thread_local HorizonMemo g_horizon_memo[kHorizonMemo];
+thread_local int g_horizon_used = 0, g_horizon_next = 0;
+
 bool outer_horizon(const rt::ImageConst& c, double* r_plus) {
-    return rt::scan::largest_root(c, c.chi2, r_plus);
+    for (int i = 0; i < g_horizon_used; ++i) {
+        const HorizonMemo& m = g_horizon_memo[i];
+        if (m.metric == c.metric && m.chi2 == c.chi2 && m.inv_lam == c.inv_lam &&
+            m.lam_c == c.lam_c && m.inv_lam_c == c.inv_lam_c && m.eta_lc == c.eta_lc) {
+            if (m.found) *r_plus = m.r_plus;
+            return m.found;
+        }
+    }
+    double r = 0.0;
+    const bool found = rt::scan::largest_root(c, c.chi2, &r);
+    g_horizon_memo[g_horizon_next] =
+        HorizonMemo{c.metric, c.chi2, c.inv_lam, c.lam_c, c.inv_lam_c, c.eta_lc, found, r};
+    g_horizon_next = (g_horizon_next + 1) % kHorizonMemo;
+    if (g_horizon_used < kHorizonMemo) ++g_horizon_used;
+    if (found) *r_plus = r;
+    return found;
 }
 
 // Validates p and fills the image constants.  Returns RT_OK or an error code.

@@ -337,3 +337,28 @@ def test_screen_point_and_refinement_argument_errors(rt):
     assert lib.rt_refine_points(C.byref(p), None, d, 2, 4, d, None, d, None) == E
     assert lib.rt_refine_points(C.byref(p), d, d, 2, 4, d, None, None, None) == E
     assert lib.rt_refine_points(None, d, d, 2, 4, d, None, d, None) == E
+
+
+def test_image_setup_repeats_and_interleaves(rt):
+    """The host keeps the horizons of recent spacetimes: repeated and
+    interleaved set-ups (more spacetimes than it keeps) give the first
+    call's values bit for bit."""
+    lib = rt.lib()
+    imgs = [W.image(metric=m, spin=s, halo=h)
+            for s in (0.1, 0.3, 0.5, 0.7, 0.9, 0.95, 0.2)
+            for m, h in (("kerr", (0.0, 0.0)), ("einasto", (0.2, 0.0)), ("cnfw", (0.02, 10.0)))]
+    def setup(img):
+        buf = (C.c_double * 4)()
+        rc = lib.rt_image_setup(C.byref(rt.params_from(img)), buf)
+        assert rc in (rt.RT_OK, rt.RT_ERR_NO_HORIZON)
+        return rc, list(buf) if rc == rt.RT_OK else None
+
+    first = [setup(img) for img in imgs]
+    assert sum(rc == rt.RT_OK for rc, _ in first) >= 18
+    for rep in range(2):
+        for img, want in zip(imgs[::-1] if rep else imgs, first[::-1] if rep else first):
+            assert setup(img) == want
+    # beyond the extremal spin: no horizon, also when asked again
+    over = rt.params_from(W.image(spin=1.2))
+    for _ in range(2):
+        assert lib.rt_image_setup(C.byref(over), (C.c_double * 4)()) == rt.RT_ERR_NO_HORIZON
