@@ -207,7 +207,7 @@ struct HorizonMemo {
     bool found;
     double r_plus;
 };
-constexpr int kHorizonMemo = 16;
+constexpr int kHorizonMemo = 128;   // a full batch of images
 thread_local HorizonMemo g_horizon_memo[kHorizonMemo];
 thread_local int g_horizon_used = 0, g_horizon_next = 0;
 
