@@ -98,24 +98,30 @@ __global__ __launch_bounds__(kBlock) void refine_count(ImageConst c, const uint8
 }
 
 // Pass 2 (one workgroup): exclusive prefix sums of the counts in place, the
-// total to *n_marked.
+// total to *n_marked.  Each tile of kBlock counts: an inclusive scan within
+// each wavefront by lane shifts, then the wavefronts' totals in order.
 __global__ __launch_bounds__(kBlock) void refine_scan(int64_t* __restrict__ block_count,
                                                       int64_t n_blocks, int64_t* __restrict__ n_marked) {
-    __shared__ int64_t s[kBlock];
-    int64_t carry = 0;
+    __shared__ long long wave_total[kBlock / 64];
+    const int lane = __lane_id(), wave = threadIdx.x / 64;
+    long long carry = 0;
     for (int64_t base = 0; base < n_blocks; base += kBlock) {
         const int64_t i = base + threadIdx.x;
-        const int64_t v = i < n_blocks ? block_count[i] : 0;
-        s[threadIdx.x] = v;
-        __syncthreads();
-        for (int w = 1; w < kBlock; w <<= 1) {   // inclusive scan (Hillis-Steele)
-            const int64_t t = static_cast<int>(threadIdx.x) >= w ? s[threadIdx.x - w] : 0;
-            __syncthreads();
-            s[threadIdx.x] += t;
-            __syncthreads();
+        const long long v = i < n_blocks ? block_count[i] : 0;
+        long long x = v;
+        for (int d = 1; d < 64; d <<= 1) {
+            const long long y = __shfl_up(x, d);
+            if (lane >= d) x += y;
         }
-        if (i < n_blocks) block_count[i] = carry + s[threadIdx.x] - v;
-        carry += s[kBlock - 1];
+        if (lane == 63) wave_total[wave] = x;
+        __syncthreads();
+        long long before = carry, tile = 0;
+        for (int w = 0; w < kBlock / 64; ++w) {
+            if (w < wave) before += wave_total[w];
+            tile += wave_total[w];
+        }
+        if (i < n_blocks) block_count[i] = before + x - v;
+        carry += tile;
         __syncthreads();
     }
     if (threadIdx.x == 0) *n_marked = carry;
